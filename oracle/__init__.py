@@ -1,0 +1,272 @@
+"""Python view of the plain CPU oracle (test infrastructure only).
+
+The oracle is the slow FP64 C library in ``smc_oracle.c``.  Only the test suite, the
+smoke check and the CPU-baseline leg of the benchmark may import this package; the
+product package never does.  ``build()`` compiles the library with gcc.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "smc_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+FEAT_COUNTS_S12, FEAT_ONEHOT_S123 = 0, 1
+ACT_SILU, ACT_IDENTITY, ACT_RELU, ACT_SQUARE = 0, 1, 2, 3
+ORDER_SNAPSHOT, ORDER_FORWARD, ORDER_REVERSE, ORDER_GIVEN = 0, 1, 2, 3
+KB_EV_PER_K = 8.617333262e-5
+
+
+def build(force: bool = True) -> str:
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                               "-Wall", "-Wextra", "-Wno-unused-parameter",
+                               SRC, "-o", LIB + ".tmp", "-lm"], cwd=HERE)
+        os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+class Model(C.Structure):
+    _fields_ = [("feature", C.c_int32), ("hidden", C.c_int32), ("act0", C.c_int32),
+                ("act1", C.c_int32), ("params", C.POINTER(C.c_double))]
+
+
+class TrialRec(C.Structure):
+    _fields_ = [("site", C.c_int64), ("partner", C.c_int64), ("dE", C.c_double),
+                ("theta", C.c_double), ("u", C.c_double), ("dir", C.c_int32),
+                ("same", C.c_int32), ("accept", C.c_int32), ("colour", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("attempts", C.c_uint64), ("diff_species", C.c_uint64),
+                ("accepts", C.c_uint64), ("e_run", C.c_double)]
+
+
+TRIAL_DTYPE = np.dtype([("site", np.int64), ("partner", np.int64), ("dE", np.float64),
+                        ("theta", np.float64), ("u", np.float64), ("dir", np.int32),
+                        ("same", np.int32), ("accept", np.int32), ("colour", np.int32)])
+assert TRIAL_DTYPE.itemsize == C.sizeof(TrialRec)
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = C.CDLL(LIB)
+        i32p, i64p, u8p, f64p = (C.POINTER(C.c_int32), C.POINTER(C.c_int64),
+                                 C.POINTER(C.c_uint8), C.POINTER(C.c_double))
+        u64p = C.POINTER(C.c_uint64)
+        sig = {
+            "or_philox4x64_10": (None, [u64p, u64p, u64p]),
+            "or_n_sites": (C.c_int64, [i32p]),
+            "or_site_pos": (None, [i32p, C.c_int64, i32p]),
+            "or_site_at": (C.c_int64, [i32p, i32p]),
+            "or_shell_table": (None, [i32p, i32p]),
+            "or_neighbor": (C.c_int64, [i32p, C.c_int64, C.c_int32]),
+            "or_n_inputs": (C.c_int32, [C.c_int32]),
+            "or_features": (None, [i32p, C.c_int32, u8p, C.c_int64, C.c_int64, C.c_int64, f64p]),
+            "or_mlp": (C.c_double, [C.POINTER(Model), f64p]),
+            "or_site_energy": (C.c_double, [i32p, C.POINTER(Model), u8p, C.c_int64, C.c_int64,
+                                            C.c_int64]),
+            "or_total_energy": (C.c_double, [i32p, C.POINTER(Model), u8p]),
+            "or_all_site_energies": (None, [i32p, C.POINTER(Model), u8p, f64p]),
+            "or_omega": (C.c_int32, [i32p, C.c_int32, C.c_int64, C.c_int64, i64p]),
+            "or_delta_e": (C.c_double, [i32p, C.POINTER(Model), u8p, C.c_int64, C.c_int64]),
+            "or_n_colours": (C.c_int32, [i32p]),
+            "or_colour_of": (C.c_int32, [i32p, C.c_int64]),
+            "or_propose": (None, [C.c_uint64, C.c_int64, C.c_int64, C.c_int64, i32p, f64p]),
+            "or_theta": (C.c_double, [C.c_double, C.c_double]),
+            "or_accept": (C.c_int32, [C.c_double, C.c_double]),
+            "or_trial": (None, [i32p, C.POINTER(Model), u8p, C.c_double, C.c_uint64, C.c_int64,
+                                C.c_int64, C.c_int64, C.POINTER(TrialRec)]),
+            "or_sweep": (C.c_int, [i32p, C.POINTER(Model), u8p, C.c_double, C.c_uint64, C.c_int64,
+                                   C.c_int64, C.POINTER(Stats), C.c_void_p, C.c_int32, i64p,
+                                   C.c_int32, C.c_int32]),
+            "or_warren_cowley": (None, [i32p, u8p, C.c_int32, f64p]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def _dims(cells) -> np.ndarray:
+    if np.isscalar(cells):
+        cells = (cells, cells, cells)
+    return np.ascontiguousarray(np.asarray(cells, dtype=np.int32))
+
+
+@dataclass
+class MLP:
+    """FP64 view of an FP32 parameter blob (W0, b0, W1, b1, W2, b2; row-major [out][in])."""
+    feature: int
+    hidden: int
+    params: np.ndarray
+    act0: int = ACT_SILU
+    act1: int = ACT_SILU
+
+    def __post_init__(self):
+        self.params = np.ascontiguousarray(np.asarray(self.params, dtype=np.float64))
+        n_in = 12 if self.feature == FEAT_COUNTS_S12 else 108
+        H = self.hidden
+        want = H * n_in + H + H * H + H + H + 1
+        if self.params.size != want:
+            raise ValueError(f"parameter blob has {self.params.size} entries, expected {want}")
+        self._c = Model(self.feature, self.hidden, self.act0, self.act1,
+                        _ptr(self.params, C.c_double))
+
+    @property
+    def c(self):
+        return C.byref(self._c)
+
+    @property
+    def n_in(self) -> int:
+        return 12 if self.feature == FEAT_COUNTS_S12 else 108
+
+
+def philox4x64_10(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(np.asarray(ctr, dtype=np.uint64))
+    k = np.ascontiguousarray(np.asarray(key, dtype=np.uint64))
+    out = np.zeros(4, dtype=np.uint64)
+    lib().or_philox4x64_10(_ptr(c, C.c_uint64), _ptr(k, C.c_uint64), _ptr(out, C.c_uint64))
+    return out
+
+
+def shell_table():
+    off = np.zeros(78, dtype=np.int32)
+    sh = np.zeros(26, dtype=np.int32)
+    lib().or_shell_table(_ptr(off, C.c_int32), _ptr(sh, C.c_int32))
+    return off.reshape(26, 3), sh
+
+
+def n_sites(cells) -> int:
+    return int(lib().or_n_sites(_ptr(_dims(cells), C.c_int32)))
+
+
+def site_pos(cells, s) -> np.ndarray:
+    P = np.zeros(3, dtype=np.int32)
+    lib().or_site_pos(_ptr(_dims(cells), C.c_int32), int(s), _ptr(P, C.c_int32))
+    return P
+
+
+def neighbor(cells, s, k) -> int:
+    return int(lib().or_neighbor(_ptr(_dims(cells), C.c_int32), int(s), int(k)))
+
+
+def features(cells, feature, occ, j, swap=(-1, -1)) -> np.ndarray:
+    occ = np.ascontiguousarray(occ, dtype=np.uint8)
+    x = np.zeros(12 if feature == FEAT_COUNTS_S12 else 108, dtype=np.float64)
+    lib().or_features(_ptr(_dims(cells), C.c_int32), feature, _ptr(occ, C.c_uint8), int(j),
+                      int(swap[0]), int(swap[1]), _ptr(x, C.c_double))
+    return x
+
+
+def mlp(model: MLP, x) -> float:
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    return float(lib().or_mlp(model.c, _ptr(x, C.c_double)))
+
+
+def site_energy(cells, model: MLP, occ, j, swap=(-1, -1)) -> float:
+    occ = np.ascontiguousarray(occ, dtype=np.uint8)
+    return float(lib().or_site_energy(_ptr(_dims(cells), C.c_int32), model.c, _ptr(occ, C.c_uint8),
+                                      int(j), int(swap[0]), int(swap[1])))
+
+
+def total_energy(cells, model: MLP, occ) -> float:
+    occ = np.ascontiguousarray(occ, dtype=np.uint8)
+    return float(lib().or_total_energy(_ptr(_dims(cells), C.c_int32), model.c,
+                                       _ptr(occ, C.c_uint8)))
+
+
+def all_site_energies(cells, model: MLP, occ) -> np.ndarray:
+    occ = np.ascontiguousarray(occ, dtype=np.uint8)
+    e = np.zeros(occ.size, dtype=np.float64)
+    lib().or_all_site_energies(_ptr(_dims(cells), C.c_int32), model.c, _ptr(occ, C.c_uint8),
+                               _ptr(e, C.c_double))
+    return e
+
+
+def omega(cells, feature, i, n) -> np.ndarray:
+    out = np.zeros(54, dtype=np.int64)
+    k = lib().or_omega(_ptr(_dims(cells), C.c_int32), feature, int(i), int(n), _ptr(out, C.c_int64))
+    return out[:k].copy()
+
+
+def delta_e(cells, model: MLP, occ, i, n) -> float:
+    occ = np.ascontiguousarray(occ, dtype=np.uint8)
+    return float(lib().or_delta_e(_ptr(_dims(cells), C.c_int32), model.c, _ptr(occ, C.c_uint8),
+                                  int(i), int(n)))
+
+
+def n_colours(cells) -> int:
+    return int(lib().or_n_colours(_ptr(_dims(cells), C.c_int32)))
+
+
+def colours(cells) -> np.ndarray:
+    d = _dims(cells)
+    n = n_sites(cells)
+    f = lib().or_colour_of
+    dp = _ptr(d, C.c_int32)
+    return np.array([f(dp, s) for s in range(n)], dtype=np.int32)
+
+
+def propose(seed, site, sweep, replica):
+    d = C.c_int32()
+    u = C.c_double()
+    lib().or_propose(seed, site, sweep, replica, C.byref(d), C.byref(u))
+    return d.value, u.value
+
+
+def theta(temperature_K, u) -> float:
+    return float(lib().or_theta(temperature_K, u))
+
+
+def trial(cells, model: MLP, occ, temperature_K, seed, replica, sweep, site) -> np.void:
+    occ = np.ascontiguousarray(occ, dtype=np.uint8)
+    rec = np.zeros(1, dtype=TRIAL_DTYPE)
+    lib().or_trial(_ptr(_dims(cells), C.c_int32), model.c, _ptr(occ, C.c_uint8), temperature_K,
+                   seed, replica, sweep, site, rec.ctypes.data_as(C.POINTER(TrialRec)))
+    return rec[0]
+
+
+def sweep(cells, model: MLP, occ: np.ndarray, temperature_K: float, seed: int, replica: int,
+          sweep_index: int, stats: Stats | None = None, trace: bool = False,
+          order: int = ORDER_SNAPSHOT, given_order=None, nthreads: int = 1,
+          colours_limit: int = -1):
+    """Advance ``occ`` (uint8, modified in place) by one sweep; returns (stats, trace|None)."""
+    assert occ.dtype == np.uint8 and occ.flags.c_contiguous
+    st = stats if stats is not None else Stats()
+    tr = np.zeros(occ.size, dtype=TRIAL_DTYPE) if trace else None
+    go = None
+    if given_order is not None:
+        go = np.ascontiguousarray(given_order, dtype=np.int64)
+    rc = lib().or_sweep(_ptr(_dims(cells), C.c_int32), model.c, _ptr(occ, C.c_uint8),
+                        float(temperature_K), int(seed), int(replica), int(sweep_index),
+                        C.byref(st), tr.ctypes.data if tr is not None else None, order,
+                        _ptr(go, C.c_int64) if go is not None else None, nthreads, colours_limit)
+    if rc != 0:
+        raise MemoryError("oracle sweep failed to allocate")
+    return st, tr
+
+
+def warren_cowley(cells, occ, n_species) -> np.ndarray:
+    occ = np.ascontiguousarray(occ, dtype=np.uint8)
+    a = np.zeros((3, n_species, n_species), dtype=np.float64)
+    lib().or_warren_cowley(_ptr(_dims(cells), C.c_int32), _ptr(occ, C.c_uint8), n_species,
+                           _ptr(a, C.c_double))
+    return a

@@ -1,0 +1,156 @@
+"""Seeded synthetic inputs shared by the oracle tests, the GPU tests and the benchmark.
+
+This module only draws inputs: species placements, compositions, model parameters,
+replica sets and temperatures.  It holds none of the method's arithmetic (no
+geometry, no energies, no random-number stream of the Monte Carlo itself), so the
+CPU oracle and the HIP path can both take their inputs from here without sharing
+any computation.
+
+Workloads (the paper's FCC FeCoNiAlTi systems with trained qSRO/MLPNet models are not
+available, so these synthetic BCC alloys with random-initialised MLPs stand in for
+them; see the paper's Sec. IV-B/IV-C for the originals):
+
+* ``c1``  BCC 8^3 cells (1,024 sites), 4 species equiatomic, 12-input counts
+          features (centre one-hot + shell-1/shell-2 species counts) -> 64 -> 64 -> 1,
+          T = 1000 K, 100 sweeps.
+* ``c2``  BCC 64^3 cells (524,288 sites), 4 species equiatomic, 108-input one-hot
+          features (centre + 26 neighbours of shells 1-3) -> 128 -> 128 -> 1, T = 800 K.
+* ``c3``  BCC 256^3 cells (33,554,432 sites), 5 species equiatomic, same 108-input
+          model, T = 600 K.  One GPU's share of the paper's 1.009e9-atom
+          strong-scaling system on 32 devices (Sec. V-B).
+* ``c4``  96 replicas, cube edges uniform in 16..96 cells, 4 species with random
+          compositions in [0.1, 0.4], temperatures log-spaced 300..3000 K.
+* ``c5``  fit workload: 16^3-cell snapshots, 108-input model.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SEED_LATTICE = 0
+SEED_WEIGHTS = 1
+SEED_PHILOX = 0
+SEED_CE = 3
+SEED_REPLICAS = 4
+SEED_FD = 5
+
+FEAT_COUNTS_S12 = 0   # 12 inputs: centre one-hot(4) + shell-1 counts(4) + shell-2 counts(4)
+FEAT_ONEHOT_S123 = 1  # 108 inputs: one-hot(4) of the centre and of 26 neighbours (shells 1-3)
+
+N_FEATURES = {FEAT_COUNTS_S12: 12, FEAT_ONEHOT_S123: 108}
+
+
+def species_counts(n_sites: int, composition) -> np.ndarray:
+    """Largest-remainder rounding of ``composition * n_sites`` (ties go to the lower species id)."""
+    c = np.asarray(composition, dtype=np.float64)
+    c = c / c.sum()
+    exact = c * n_sites
+    counts = np.floor(exact).astype(np.int64)
+    rem = n_sites - int(counts.sum())
+    frac = exact - counts
+    # stable sort on -frac keeps species order among ties
+    order = np.argsort(-frac, kind="stable")
+    counts[order[:rem]] += 1
+    return counts
+
+
+def random_occupancy(cells, n_species: int = 4, composition=None, seed: int = SEED_LATTICE) -> np.ndarray:
+    """Uniformly random placement of a fixed composition on a BCC lattice of ``cells`` cubic cells.
+
+    Returns uint8 species ids in canonical site order (2 sites per cell)."""
+    lx, ly, lz = (cells, cells, cells) if np.isscalar(cells) else cells
+    n = 2 * int(lx) * int(ly) * int(lz)
+    if composition is None:
+        composition = np.full(n_species, 1.0 / n_species)
+    counts = species_counts(n, composition)
+    base = np.repeat(np.arange(len(counts), dtype=np.uint8), counts)
+    return np.random.default_rng(seed).permutation(base).astype(np.uint8)
+
+
+def mlp_param_sizes(n_in: int, hidden: int) -> list[tuple[str, tuple[int, ...], int]]:
+    """(name, shape, fan_in) of W0, b0, W1, b1, W2, b2 in blob order (row-major [out][in])."""
+    return [("W0", (hidden, n_in), n_in), ("b0", (hidden,), n_in),
+            ("W1", (hidden, hidden), hidden), ("b1", (hidden,), hidden),
+            ("W2", (1, hidden), hidden), ("b2", (1,), hidden)]
+
+
+def mlp_n_params(n_in: int, hidden: int) -> int:
+    return sum(int(np.prod(s)) for _, s, _ in mlp_param_sizes(n_in, hidden))
+
+
+def mlp_params(n_in: int, hidden: int, seed: int = SEED_WEIGHTS, scale: float = 1.0) -> np.ndarray:
+    """FP32 parameter blob, every entry ~ N(0, 1/fan_in) drawn in FP64 then rounded to FP32."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for _, shape, fan_in in mlp_param_sizes(n_in, hidden):
+        parts.append(rng.normal(0.0, math.sqrt(1.0 / fan_in), size=shape).ravel())
+    return (np.concatenate(parts) * scale).astype(np.float32)
+
+
+def dirichlet_composition(rng: np.random.Generator, n_species: int = 4, lo: float = 0.1, hi: float = 0.4):
+    while True:
+        c = rng.dirichlet(np.ones(n_species))
+        if np.all(c >= lo) and np.all(c <= hi):
+            return c
+
+
+@dataclass
+class Workload:
+    name: str
+    cells: list                      # per replica: (Lx, Ly, Lz)
+    n_species: int
+    compositions: list               # per replica
+    temperatures: list               # per replica, kelvin
+    feature: int
+    hidden: int
+    sweeps: int
+    seed: int = SEED_PHILOX
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def n_in(self) -> int:
+        return N_FEATURES[self.feature]
+
+    @property
+    def sites(self) -> list:
+        return [2 * a * b * c for a, b, c in self.cells]
+
+    def occupancy(self) -> np.ndarray:
+        """Concatenated per-replica occupancies (replica r drawn with seed SEED_LATTICE + r)."""
+        parts = [random_occupancy(cl, self.n_species, comp, seed=SEED_LATTICE + r)
+                 for r, (cl, comp) in enumerate(zip(self.cells, self.compositions))]
+        return np.concatenate(parts)
+
+    def params(self) -> np.ndarray:
+        return mlp_params(self.n_in, self.hidden, SEED_WEIGHTS)
+
+
+def replica_set(n_replicas: int = 96, seed: int = SEED_REPLICAS, edge_lo: int = 16, edge_hi: int = 96):
+    rng = np.random.default_rng(seed)
+    edges = rng.integers(edge_lo, edge_hi + 1, size=n_replicas)
+    comps = [dirichlet_composition(rng) for _ in range(n_replicas)]
+    temps = [300.0 * 10.0 ** (r / (n_replicas - 1)) for r in range(n_replicas)]
+    return [int(e) for e in edges], comps, temps
+
+
+def workload(name: str, **over) -> Workload:
+    name = name.lower()
+    if name == "c1":
+        w = Workload("c1", [(8, 8, 8)], 4, [None], [1000.0], FEAT_COUNTS_S12, 64, 100)
+    elif name == "c2":
+        w = Workload("c2", [(64, 64, 64)], 4, [None], [800.0], FEAT_ONEHOT_S123, 128, 1000)
+    elif name == "c3":
+        w = Workload("c3", [(256, 256, 256)], 5, [None], [600.0], FEAT_ONEHOT_S123, 128, 200)
+    elif name == "c4":
+        edges, comps, temps = replica_set()
+        w = Workload("c4", [(e, e, e) for e in edges], 4, comps, temps, FEAT_ONEHOT_S123, 128, 500)
+    elif name == "c5":
+        w = Workload("c5", [(16, 16, 16)], 4, [None], [1000.0], FEAT_ONEHOT_S123, 128, 0,
+                     extra=dict(n_snapshots=65536, batch=1024))
+    else:
+        raise KeyError(name)
+    for k, v in over.items():
+        setattr(w, k, v)
+    return w
