@@ -1,0 +1,156 @@
+/*
+ * libsmc -- swap Monte Carlo on periodic BCC alloys with a local MLP energy, for AMD
+ * Instinct MI355X (gfx950).  C ABI.
+ *
+ * The method is SMC-X/SMC-AI canonical Monte Carlo (arXiv 2604.08250):
+ *   - Algorithm 1 (Sec. III-A): the lattice is cut into link cells; in each sequential
+ *     mini-step every link cell tries one nearest-neighbour species swap at the same
+ *     offset, the local energies of the affected zone Omega are evaluated before and
+ *     after, reduced, and the swap is kept by the Metropolis criterion.
+ *   - Sec. II-A: link cells large enough that concurrent trials are independent, which
+ *     keeps detailed balance; energies are local and their features computed on the fly.
+ *   - Sec. V-A: one MC step (sweep) attempts one swap per site; throughput is counted in
+ *     attempts (atom-steps) per second.
+ *   - Eqs. (4)-(6), Sec. IV-B: the MLP local energy (here SiLU, two hidden layers).
+ *   - Sec. III-A, last paragraphs: the ML model is decoupled from the MC core; here the
+ *     model is a caller-owned parameter blob.
+ *
+ * Conventions shared by every entry point
+ *   - Return value: SMC_OK (0) or a negative smc_status.  Nothing aborts or throws across
+ *     the ABI.  smc_last_error() gives a message for the last failing call on a context.
+ *   - Memory: every large buffer (occupancy, parameters, energy cache, traces) is device
+ *     memory owned by the caller, who keeps it alive until smc_destroy.  The library owns
+ *     only small tables, packed weight copies, counters and scratch, freed by smc_destroy.
+ *   - Streams: all device work is enqueued on the stream given to smc_init.  Calls that
+ *     return host values (smc_energy, smc_sweep with stats) synchronise that stream.
+ *     Asynchronous device faults are reported as SMC_E_DEVICE by the next synchronising call.
+ *   - A context is not thread safe; calls on one context must not overlap.
+ *
+ * Lattice layout (both ways of the ABI): BCC with Lx x Ly x Lz cubic cells and 2 sites
+ * per cell; site index s = ((z*Ly + y)*Lx + x)*2 + b, b = 0 at the cell corner and
+ * b = 1 at the body centre; one uint8 species id per site.  Replicas are concatenated
+ * in replica order.
+ *
+ * Features: species ids 0..3 own one one-hot channel each; a species id of 4 (fifth
+ * species) has none and contributes zeros.  Neighbour slots follow the coordination
+ * shells in ascending distance (8 at a*sqrt(3)/2, 6 at a, 12 at a*sqrt(2)), each shell
+ * in lexicographic order of its doubled-coordinate offset (dx, dy, dz).
+ *   SMC_FEAT_COUNTS_S12: [one-hot(centre), counts per species in shell 1, in shell 2].
+ *   SMC_FEAT_ONEHOT_S123: [one-hot(centre), one-hot(neighbour k) for k = 0..25].
+ *
+ * Parameter blob (FP32, row-major [out][in]): W0[H][F], b0[H], W1[H][H], b1[H], W2[H],
+ * b2[1]; E_j = W2 . silu(W1 . silu(W0 x_j + b0) + b1) + b2 (eV).
+ *
+ * Trial of site i at global sweep t of replica r: Philox4x64-10 with counter
+ * (i, t, r, 0) and key (seed, 0) gives (r0, r1, r2, r3); the partner is the shell-1
+ * neighbour in slot r0 >> 61; u = ((r1 >> 11) + 1) * 2^-53; theta = -kB T ln u with
+ * kB = 8.617333262e-5 eV/K; the swap is accepted iff dE <= theta.  Equal species: no
+ * energy evaluation, not accepted, still an attempt.
+ */
+#ifndef SMC_H
+#define SMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct smc_ctx smc_ctx;
+
+enum smc_status {
+  SMC_OK = 0,
+  SMC_E_INVALID = -1,      /* bad argument or configuration */
+  SMC_E_UNSUPPORTED = -2,  /* valid request this build does not implement */
+  SMC_E_DEVICE = -3,       /* HIP error or device fault */
+  SMC_E_STATE = -4,        /* call not allowed in the context's current state */
+  SMC_E_NOMEM = -5         /* allocation failed */
+};
+
+/* Arithmetic of the energy MLP inside a sweep (pattern: precision). */
+enum smc_prec {
+  SMC_FP32 = 0,      /* FP32 matrix cores, FP32 accumulation */
+  SMC_BF16 = 1,      /* BF16 weights and activations, FP32 accumulation */
+  SMC_BF16X3 = 2,    /* split BF16: hi+lo weights and activations, three products */
+  SMC_FP8_E4M3 = 3,  /* OCP E4M3 with static per-layer scales, FP32 accumulation */
+  SMC_FP64 = 4       /* FP64 throughout (reference mode) */
+};
+
+enum smc_feat { SMC_FEAT_COUNTS_S12 = 0, SMC_FEAT_ONEHOT_S123 = 1 };
+
+typedef struct {
+  int32_t n_replicas;            /* >= 1 */
+  const int32_t *cells;          /* host, [n_replicas][3] cubic cells per axis, each >= 4 */
+  const double *temperature_K;   /* host, [n_replicas]; +inf accepts every swap */
+  int32_t n_species;             /* 2..5 */
+  int32_t feature;               /* smc_feat */
+  int32_t hidden;                /* H: 64 or 128 */
+  int32_t precision;             /* smc_prec */
+  uint64_t seed;                 /* Philox key word 0 */
+  double guard_eV;               /* FP64 re-decision band |dE - theta| < guard; < 0: default */
+} smc_config;
+
+/* Optional outputs of smc_sweep.  Host counters accumulate over the sweeps of one call.
+ * Device traces hold the last sweep of the call, indexed by trial site. */
+typedef struct {
+  uint64_t *attempts;      /* host [n_replicas] or NULL */
+  uint64_t *diff_species;  /* host [n_replicas] or NULL */
+  uint64_t *accepts;       /* host [n_replicas] or NULL */
+  uint64_t *rechecks;      /* host [n_replicas] or NULL: trials re-decided in FP64 */
+  double *trace_dE;        /* device [N_total] or NULL: dE that decided the trial */
+  double *trace_dE_fast;   /* device [N_total] or NULL: dE of the sweep precision */
+  uint8_t *trace_flags;    /* device [N_total] or NULL: 1 accept, 2 same species, 4 FP64 */
+} smc_stats;
+
+/* Create a context (Algorithm 1 inputs: the lattice sigma0, the link-cell partition it
+ * implies, and the model).  occ_dev: uint8 [N_total] occupancy, read and updated in place.
+ * params_dev: FP32 blob, read once here (and by smc_set_params).  ecache_dev: float
+ * [N_total] per-site local energies, filled here and kept equal to the sweep precision's
+ * evaluation of the current occupancy.  hip_stream: hipStream_t or NULL for the null
+ * stream.  Sets the global sweep counter to 0 and the running energies to the FP64 total. */
+int smc_init(const smc_config *cfg, uint8_t *occ_dev, const float *params_dev,
+             float *ecache_dev, void *hip_stream, smc_ctx **out);
+
+/* Run n_sweeps sweeps (Algorithm 1's loop over mini-steps, once per sweep; Sec. V-A).
+ * Asynchronous unless stats is non-NULL. */
+int smc_sweep(smc_ctx *ctx, int32_t n_sweeps, smc_stats *stats);
+
+/* FP64 energies per replica (host arrays [n_replicas], either may be NULL):
+ * e_scratch = sum of FP64 local energies of the current occupancy;
+ * e_running = initial FP64 total plus every accepted dE.  Synchronises. */
+int smc_energy(smc_ctx *ctx, double *e_scratch_host, double *e_running_host);
+
+/* Local energy of every site in the given precision's evaluator: float [N_total] for
+ * SMC_FP32/BF16/BF16X3/FP8_E4M3, double [N_total] for SMC_FP64.  Asynchronous. */
+int smc_site_energies(smc_ctx *ctx, int32_t precision, void *out_dev);
+
+/* Re-read params_dev (FP32 blob), re-pack the low-precision copies, refresh the energy
+ * cache and reset the running energies to the FP64 total.  Asynchronous. */
+int smc_set_params(smc_ctx *ctx, const float *params_dev);
+
+/* Re-derive the energy cache and running energies after the caller rewrote occ_dev
+ * (e.g. a checkpoint restore).  Asynchronous. */
+int smc_refresh(smc_ctx *ctx);
+
+/* Global sweep counter (the Philox counter word 1).  Setting it lets a resumed run
+ * continue the same random stream. */
+int smc_get_sweep(const smc_ctx *ctx, uint64_t *sweep);
+int smc_set_sweep(smc_ctx *ctx, uint64_t sweep);
+
+/* Cumulative counters since smc_init, host array [4][n_replicas]: attempts,
+ * different-species attempts, accepted swaps, FP64 re-decisions.  reset != 0 zeroes them
+ * after reading.  Synchronises. */
+int smc_counters(smc_ctx *ctx, uint64_t *out_host, int32_t reset);
+
+/* Total sites over all replicas, and number of colours (mini-steps) of a replica. */
+int smc_n_sites(const smc_ctx *ctx, int64_t *n);
+int smc_n_colours(const smc_ctx *ctx, int32_t replica, int32_t *n);
+
+void smc_destroy(smc_ctx *ctx);
+const char *smc_last_error(const smc_ctx *ctx);
+const char *smc_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

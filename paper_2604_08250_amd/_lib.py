@@ -1,0 +1,166 @@
+"""ctypes binding of libsmc.so (argument marshalling only; every step runs in HIP kernels).
+
+The functions here carry the names of the C ABI in ``include/smc.h`` and take raw device
+pointers (ints) and host numpy arrays.  There is no fallback: if the library is not built
+or cannot be loaded, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libsmc.so")
+
+SMC_OK, SMC_E_INVALID, SMC_E_UNSUPPORTED, SMC_E_DEVICE, SMC_E_STATE, SMC_E_NOMEM = 0, -1, -2, -3, -4, -5
+SMC_FP32, SMC_BF16, SMC_BF16X3, SMC_FP8_E4M3, SMC_FP64 = 0, 1, 2, 3, 4
+SMC_FEAT_COUNTS_S12, SMC_FEAT_ONEHOT_S123 = 0, 1
+
+PRECISIONS = {"fp32": SMC_FP32, "bf16": SMC_BF16, "bf16x3": SMC_BF16X3, "fp8": SMC_FP8_E4M3,
+              "fp64": SMC_FP64}
+
+EXPORTS = ["smc_init", "smc_sweep", "smc_energy", "smc_site_energies", "smc_set_params",
+           "smc_refresh", "smc_counters", "smc_get_sweep", "smc_set_sweep", "smc_n_sites", "smc_n_colours",
+           "smc_destroy", "smc_last_error", "smc_status_string"]
+
+
+class smc_config(C.Structure):
+    _fields_ = [("n_replicas", C.c_int32), ("cells", C.POINTER(C.c_int32)),
+                ("temperature_K", C.POINTER(C.c_double)), ("n_species", C.c_int32),
+                ("feature", C.c_int32), ("hidden", C.c_int32), ("precision", C.c_int32),
+                ("seed", C.c_uint64), ("guard_eV", C.c_double)]
+
+
+class smc_stats(C.Structure):
+    _fields_ = [("attempts", C.POINTER(C.c_uint64)), ("diff_species", C.POINTER(C.c_uint64)),
+                ("accepts", C.POINTER(C.c_uint64)), ("rechecks", C.POINTER(C.c_uint64)),
+                ("trace_dE", C.c_void_p), ("trace_dE_fast", C.c_void_p),
+                ("trace_flags", C.c_void_p)]
+
+
+class SMCError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """Load libsmc.so (raises if it is missing: there is no other implementation)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise SMCError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        sig = {
+            "smc_init": (C.c_int, [C.POINTER(smc_config), vp, vp, vp, vp, C.POINTER(vp)]),
+            "smc_sweep": (C.c_int, [vp, C.c_int32, C.POINTER(smc_stats)]),
+            "smc_energy": (C.c_int, [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+            "smc_site_energies": (C.c_int, [vp, C.c_int32, vp]),
+            "smc_set_params": (C.c_int, [vp, vp]),
+            "smc_refresh": (C.c_int, [vp]),
+            "smc_counters": (C.c_int, [vp, C.POINTER(C.c_uint64), C.c_int32]),
+            "smc_get_sweep": (C.c_int, [vp, C.POINTER(C.c_uint64)]),
+            "smc_set_sweep": (C.c_int, [vp, C.c_uint64]),
+            "smc_n_sites": (C.c_int, [vp, C.POINTER(C.c_int64)]),
+            "smc_n_colours": (C.c_int, [vp, C.c_int32, C.POINTER(C.c_int32)]),
+            "smc_destroy": (None, [vp]),
+            "smc_last_error": (C.c_char_p, [vp]),
+            "smc_status_string": (C.c_char_p, [C.c_int]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(rc: int, ctx=None):
+    if rc != SMC_OK:
+        msg = lib().smc_status_string(rc).decode()
+        if ctx:
+            msg += ": " + lib().smc_last_error(ctx).decode()
+        raise SMCError(f"libsmc returned {rc} ({msg})")
+
+
+def _u64(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_uint64))
+
+
+def smc_init(cells, temperatures, n_species, feature, hidden, precision, seed, guard_eV,
+             occ_ptr, params_ptr, ecache_ptr, stream_ptr):
+    cells = np.ascontiguousarray(np.asarray(cells, dtype=np.int32).reshape(-1, 3))
+    temps = np.ascontiguousarray(np.asarray(temperatures, dtype=np.float64).reshape(-1))
+    cfg = smc_config(len(temps), cells.ctypes.data_as(C.POINTER(C.c_int32)),
+                     temps.ctypes.data_as(C.POINTER(C.c_double)), n_species, feature, hidden,
+                     precision, seed, guard_eV)
+    ctx = C.c_void_p()
+    rc = lib().smc_init(C.byref(cfg), occ_ptr, params_ptr, ecache_ptr, stream_ptr, C.byref(ctx))
+    check(rc)
+    return ctx.value
+
+
+def smc_sweep(ctx, n_sweeps, attempts=None, diff_species=None, accepts=None, rechecks=None,
+              trace_dE=0, trace_dE_fast=0, trace_flags=0, with_stats=False):
+    st = None
+    if with_stats:
+        st = smc_stats(_u64(attempts), _u64(diff_species), _u64(accepts), _u64(rechecks),
+                       trace_dE or None, trace_dE_fast or None, trace_flags or None)
+    check(lib().smc_sweep(ctx, n_sweeps, C.byref(st) if st is not None else None), ctx)
+
+
+def smc_energy(ctx, n_replicas):
+    es = np.zeros(n_replicas)
+    er = np.zeros(n_replicas)
+    check(lib().smc_energy(ctx, es.ctypes.data_as(C.POINTER(C.c_double)),
+                           er.ctypes.data_as(C.POINTER(C.c_double))), ctx)
+    return es, er
+
+
+def smc_site_energies(ctx, precision, out_ptr):
+    check(lib().smc_site_energies(ctx, precision, out_ptr), ctx)
+
+
+def smc_set_params(ctx, params_ptr):
+    check(lib().smc_set_params(ctx, params_ptr), ctx)
+
+
+def smc_refresh(ctx):
+    check(lib().smc_refresh(ctx), ctx)
+
+
+def smc_counters(ctx, n_replicas, reset=False):
+    out = np.zeros((4, n_replicas), dtype=np.uint64)
+    check(lib().smc_counters(ctx, out.ctypes.data_as(C.POINTER(C.c_uint64)), int(reset)), ctx)
+    return out
+
+
+def smc_get_sweep(ctx) -> int:
+    s = C.c_uint64()
+    check(lib().smc_get_sweep(ctx, C.byref(s)), ctx)
+    return s.value
+
+
+def smc_set_sweep(ctx, sweep):
+    check(lib().smc_set_sweep(ctx, sweep), ctx)
+
+
+def smc_n_sites(ctx) -> int:
+    n = C.c_int64()
+    check(lib().smc_n_sites(ctx, C.byref(n)), ctx)
+    return n.value
+
+
+def smc_n_colours(ctx, replica) -> int:
+    n = C.c_int32()
+    check(lib().smc_n_colours(ctx, replica, C.byref(n)), ctx)
+    return n.value
+
+
+def smc_destroy(ctx):
+    if ctx:
+        lib().smc_destroy(ctx)

@@ -1,0 +1,92 @@
+// Per-lane local-energy evaluator (one site per lane).  Used for the FP64 re-decision
+// of near-threshold trials and for the FP64 reference mode; the sweep precisions use the
+// matrix-core evaluator.
+#pragma once
+#include "lattice.hpp"
+
+namespace smc {
+
+constexpr int kSlots = 27;  // centre + 26 neighbours
+
+template <typename T>
+__device__ inline T silu(T z);
+
+template <>
+__device__ inline double silu<double>(double z) {
+  return z / (1.0 + exp(-z));
+}
+
+template <>
+__device__ inline float silu<float>(float z) {
+  // z * sigmoid(z) with the hardware exp2 and reciprocal (about 1 ulp each)
+  const float e = __builtin_amdgcn_exp2f(-z * 1.44269504088896341f);
+  return z * __builtin_amdgcn_rcpf(1.0f + e);
+}
+
+// Species of the 27 slots of site j (replica-local index), seen with the species of the
+// sites i and n exchanged when swap is true.
+__device__ inline void gather_slots(const uint8_t *occ, int64_t j, int32_t lx, int32_t ly, int32_t lz,
+                                    int n_slots, bool swap, int64_t i, int64_t n, uint8_t si,
+                                    uint8_t sn, uint8_t *slot) {
+  const Pos p = site_pos(j, lx, ly);
+  auto get = [&](int64_t s) -> uint8_t {
+    if (swap) {
+      if (s == i) return sn;
+      if (s == n) return si;
+    }
+    return occ[s];
+  };
+  slot[0] = get(j);
+#pragma unroll
+  for (int k = 0; k < kNbr; ++k)
+    if (k + 1 < n_slots) slot[k + 1] = get(site_at(p, shell_dx(k), shell_dy(k), shell_dz(k), lx, ly, lz));
+}
+
+// E = W2 . silu(W1 . silu(W0 x + b0) + b1) + b2 with x built from the slot species.
+// FEAT 0: x = [onehot(centre), shell-1 counts, shell-2 counts] (12 inputs, 15 slots);
+// FEAT 1: x = one-hot of the 27 slots (108 inputs).  Species >= 4 have no channel.
+template <int FEAT, int H, typename T>
+__device__ inline T mlp_scalar(const uint8_t *slot, const T *W) {
+  constexpr int F = FEAT == 0 ? 12 : 108;
+  const T *W0 = W, *b0 = W0 + H * F, *W1 = b0 + H, *b1 = W1 + H * H, *W2 = b1 + H, *b2 = W2 + H;
+  T h0[H];
+  if (FEAT == 0) {
+    T x[12];
+#pragma unroll
+    for (int f = 0; f < 12; ++f) x[f] = T(0);
+#pragma unroll
+    for (int m = 0; m < 15; ++m) {
+      const int p = slot[m];
+      const int base = m == 0 ? 0 : (m <= 8 ? 4 : 8);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) x[base + c] += (p == c) ? T(1) : T(0);
+    }
+#pragma unroll
+    for (int o = 0; o < H; ++o) {
+      T acc = b0[o];
+#pragma unroll
+      for (int f = 0; f < 12; ++f) acc = fma(W0[o * F + f], x[f], acc);
+      h0[o] = silu<T>(acc);
+    }
+  } else {
+#pragma unroll
+    for (int o = 0; o < H; ++o) {
+      T acc = b0[o];
+      for (int m = 0; m < kSlots; ++m) {
+        const int p = slot[m];
+        if (p < 4) acc += W0[o * F + 4 * m + p];
+      }
+      h0[o] = silu<T>(acc);
+    }
+  }
+  T e = b2[0];
+  for (int o = 0; o < H; ++o) {
+    T acc = b1[o];
+#pragma unroll
+    for (int k = 0; k < H; ++k) acc = fma(W1[o * H + k], h0[k], acc);
+    e = fma(W2[o], silu<T>(acc), e);
+  }
+  return e;
+}
+
+}  // namespace smc

@@ -1,0 +1,194 @@
+// Sweep, energy and bookkeeping kernels of the per-lane path: one trial per lane.
+#pragma once
+#include "scalar_eval.hpp"
+#include "tables.hpp"
+
+namespace smc {
+
+// Flags written to the per-site trace.
+constexpr uint8_t kFlagAccept = 1, kFlagSame = 2, kFlagFp64 = 4;
+
+struct SweepArgs {
+  const Replica *reps;
+  uint8_t *occ;
+  float *ecache;
+  const float *w32;
+  const double *w64;
+  const int8_t *omega;     // [8][kOmegaMax][3]
+  int32_t omega_n;
+  int32_t replica;
+  int32_t colour;
+  int32_t fp64_mode;       // decide every trial with FP64 energies, no cache
+  uint64_t seed;
+  uint64_t sweep;
+  double guard;
+  double *partial;         // one FP64 partial sum of accepted dE per block
+  uint64_t *counters;      // [4][n_replicas]: attempts, diff, accepts, rechecks
+  int32_t n_replicas;
+  double *trace_dE;
+  double *trace_dE_fast;
+  uint8_t *trace_flags;
+};
+
+// Trial site of (colour, trial) inside a replica, or -1 where that link cell is too short
+// to hold the colour's offset.
+__device__ inline int64_t trial_site(const Replica &R, int32_t colour, int64_t t) {
+  const int32_t b = colour & 1;
+  int32_t rest = colour >> 1;
+  const int32_t ox = rest % R.ax[0].big;
+  rest /= R.ax[0].big;
+  const int32_t oy = rest % R.ax[1].big;
+  const int32_t oz = rest / R.ax[1].big;
+  const int32_t cx = (int32_t)(t % R.ax[0].q);
+  const int64_t t1 = t / R.ax[0].q;
+  const int32_t cy = (int32_t)(t1 % R.ax[1].q);
+  const int32_t cz = (int32_t)(t1 / R.ax[1].q);
+  if (ox >= axis_len(R.ax[0], cx) || oy >= axis_len(R.ax[1], cy) || oz >= axis_len(R.ax[2], cz))
+    return -1;
+  const int32_t x = axis_start(R.ax[0], cx) + ox, y = axis_start(R.ax[1], cy) + oy,
+                z = axis_start(R.ax[2], cz) + oz;
+  return (((int64_t)z * R.L[1] + y) * R.L[0] + x) * 2 + b;
+}
+
+template <int FEAT, int H, typename T>
+__device__ inline T site_energy(const uint8_t *occ, const Replica &R, int64_t j, bool swap, int64_t i,
+                                int64_t n, uint8_t si, uint8_t sn, const T *W) {
+  uint8_t slot[kSlots];
+  gather_slots(occ, j, R.L[0], R.L[1], R.L[2], FEAT == 0 ? 15 : kSlots, swap, i, n, si, sn, slot);
+  return mlp_scalar<FEAT, H, T>(slot, W);
+}
+
+// Local energy of every site of one replica (FP32 into the cache, or FP64).
+template <int FEAT, int H, typename T>
+__global__ void k_site_energies(const Replica *reps, int32_t r, const uint8_t *occ, const T *W, T *out) {
+  const Replica R = reps[r];
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= R.n_sites) return;
+  const uint8_t *o = occ + R.site0;
+  out[R.site0 + j] = site_energy<FEAT, H, T>(o, R, j, false, -1, -1, 0, 0, W);
+}
+
+constexpr int kScalarBlock = 64;
+
+// One colour (mini-step) of one replica; one lane per link cell.
+template <int FEAT, int H>
+__global__ __launch_bounds__(kScalarBlock) void k_sweep_colour_scalar(SweepArgs a) {
+  __shared__ float s_e1[kScalarBlock][kOmegaMax];
+  __shared__ double s_de[kScalarBlock];
+  __shared__ uint32_t s_cnt[3];
+  const Replica R = a.reps[a.replica];
+  const int tid = threadIdx.x;
+  const int64_t t = (int64_t)blockIdx.x * kScalarBlock + tid;
+  if (tid < 3) s_cnt[tid] = 0;
+  __syncthreads();
+  double applied = 0.0;
+  const int64_t i = t < R.n_trials ? trial_site(R, a.colour, t) : -1;
+  if (i >= 0) {
+    uint8_t *occ = a.occ + R.site0;
+    float *ec = a.ecache + R.site0;
+    const U64x4 r = philox4x64_10((uint64_t)i, a.sweep, (uint64_t)a.replica, 0, a.seed, 0);
+    const int d = (int)(r.v[0] >> 61);
+    const double u = (double)((r.v[1] >> 11) + 1) * 0x1.0p-53;
+    const double theta = isinf(R.temperature) ? (double)INFINITY
+                                              : -kBoltzmannEvPerK * R.temperature * log(u);
+    const Pos pi = site_pos(i, R.L[0], R.L[1]);
+    const int64_t n = site_at(pi, shell_dx(d), shell_dy(d), shell_dz(d), R.L[0], R.L[1], R.L[2]);
+    const uint8_t si = occ[i], sn = occ[n];
+    uint8_t flags = 0;
+    double dE = 0.0, dE_fast = 0.0;
+    if (si == sn) {
+      flags = kFlagSame;
+    } else {
+      atomicAdd(&s_cnt[0], 1u);
+      const int8_t *om = a.omega + d * kOmegaMax * 3;
+      bool exact = a.fp64_mode != 0;
+      if (!exact) {
+        float acc = 0.0f;
+        for (int k = 0; k < a.omega_n; ++k) {
+          const int64_t j = site_at(pi, om[3 * k], om[3 * k + 1], om[3 * k + 2], R.L[0], R.L[1], R.L[2]);
+          const float e1 = site_energy<FEAT, H, float>(occ, R, j, true, i, n, si, sn, a.w32);
+          s_e1[tid][k] = e1;
+          acc += e1 - ec[j];
+        }
+        dE_fast = (double)acc;
+        dE = dE_fast;
+        if (fabs(dE_fast - theta) < a.guard) exact = true;
+      }
+      if (exact) {
+        double e1 = 0.0, e0 = 0.0;
+        for (int k = 0; k < a.omega_n; ++k) {
+          const int64_t j = site_at(pi, om[3 * k], om[3 * k + 1], om[3 * k + 2], R.L[0], R.L[1], R.L[2]);
+          e1 += site_energy<FEAT, H, double>(occ, R, j, true, i, n, si, sn, a.w64);
+          e0 += site_energy<FEAT, H, double>(occ, R, j, false, i, n, si, sn, a.w64);
+        }
+        dE = e1 - e0;
+        flags |= kFlagFp64;
+        atomicAdd(&s_cnt[2], 1u);
+        if (a.fp64_mode) dE_fast = dE;
+      }
+      if (dE <= theta) {
+        flags |= kFlagAccept;
+        atomicAdd(&s_cnt[1], 1u);
+        applied = dE;
+        occ[i] = sn;
+        occ[n] = si;
+        for (int k = 0; k < a.omega_n; ++k) {
+          const int64_t j = site_at(pi, om[3 * k], om[3 * k + 1], om[3 * k + 2], R.L[0], R.L[1], R.L[2]);
+          if (!a.fp64_mode) ec[j] = s_e1[tid][k];
+        }
+      }
+    }
+    if (a.trace_flags) a.trace_flags[R.site0 + i] = flags;
+    if (a.trace_dE) a.trace_dE[R.site0 + i] = dE;
+    if (a.trace_dE_fast) a.trace_dE_fast[R.site0 + i] = dE_fast;
+  }
+  s_de[tid] = applied;
+  const unsigned long long valid = __ballot(i >= 0);
+  __syncthreads();
+  if (tid == 0) {
+    double s = 0.0;
+    for (int k = 0; k < kScalarBlock; ++k) s += s_de[k];
+    a.partial[blockIdx.x] = s;
+    const int R_ = a.n_replicas;
+    atomicAdd((unsigned long long *)&a.counters[0 * R_ + a.replica], (unsigned long long)__popcll(valid));
+    atomicAdd((unsigned long long *)&a.counters[1 * R_ + a.replica], (unsigned long long)s_cnt[0]);
+    atomicAdd((unsigned long long *)&a.counters[2 * R_ + a.replica], (unsigned long long)s_cnt[1]);
+    atomicAdd((unsigned long long *)&a.counters[3 * R_ + a.replica], (unsigned long long)s_cnt[2]);
+  }
+}
+
+// Deterministic sum of n doubles (fixed per-thread strides, fixed tree); out += sum.
+__global__ void k_sum_into(const double *v, int64_t n, double *out, int accumulate) {
+  __shared__ double s[256];
+  double acc = 0.0;
+  for (int64_t k = threadIdx.x; k < n; k += 256) acc += v[k];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = accumulate ? *out + s[0] : s[0];
+}
+
+__global__ void k_fill_u64(uint64_t *p, int64_t n, uint64_t v) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = v;
+}
+
+__global__ void k_widen(const float *in, double *out, int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) out[k] = (double)in[k];
+}
+
+__global__ void k_copy_f32(const float *in, float *out, int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) out[k] = in[k];
+}
+
+__global__ void k_narrow(const double *in, float *out, int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) out[k] = (float)in[k];
+}
+
+}  // namespace smc

@@ -1,0 +1,39 @@
+// Host-side tables: the affected zone of a swap and the per-replica schedule.
+#pragma once
+#include <stdint.h>
+
+#include <array>
+#include <vector>
+
+#include "lattice.hpp"
+
+namespace smc {
+
+constexpr int kOmegaMax = 40;  // |Omega| with shells 1-3; 22 with shells 1-2
+
+// Affected zone of swapping the site at the origin with its shell-1 neighbour in slot d:
+// the origin, the partner, and every site that has either among the neighbours its
+// features read (the shell set is symmetric, so these are the neighbours of either).
+// Offsets are doubled coordinates, sorted lexicographically, duplicates removed.
+struct OmegaTable {
+  int count = 0;                                  // 22 or 40
+  std::array<std::array<int8_t, 3>, 8 * kOmegaMax> off{};  // [d][k]
+};
+
+OmegaTable build_omega(int n_nbr_used);
+
+// Device-side description of one replica.
+struct Replica {
+  int32_t L[3];         // cubic cells per axis
+  AxisCells ax[3];      // link cells per axis
+  int32_t n_colours;    // 2 * big0 * big1 * big2
+  int32_t pad_;
+  int64_t site0;        // first site of this replica in the concatenated arrays
+  int64_t n_sites;
+  int64_t n_trials;     // link cells = trials per colour (some colours skip short cells)
+  double temperature;   // kelvin
+};
+
+Replica make_replica(const int32_t cells[3], int64_t site0, double temperature);
+
+}  // namespace smc

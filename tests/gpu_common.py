@@ -1,0 +1,81 @@
+"""Shared helpers of the GPU tests: building a context and comparing it with the oracle."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+DECISION_BAND_EV = 1e-9   # disagreements tolerated only this close to the threshold
+FP32_DE_TOL_EV = 1e-5     # |dE_fp32 - dE_fp64| bound for the FP32 sweep precision
+
+
+def need_gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def make(name, precision="fp32", cells=None, temperature=None, n_species=None, seed=None,
+         guard_eV=-1.0, hidden=None, feature=None, params=None, occ=None):
+    import paper_2604_08250_amd as smc
+    w = synth.workload(name)
+    if cells is not None:
+        w.cells = [tuple(cells)]
+    if temperature is not None:
+        w.temperatures = [temperature]
+    if n_species is not None:
+        w.n_species = n_species
+    if hidden is not None:
+        w.hidden = hidden
+    if feature is not None:
+        w.feature = feature
+    occ0 = w.occupancy() if occ is None else np.asarray(occ, dtype=np.uint8)
+    p = w.params() if params is None else np.asarray(params, dtype=np.float32)
+    mc = smc.SwapMC(w.cells, w.temperatures, occ0, p, n_species=w.n_species, feature=w.feature,
+                    hidden=w.hidden, precision=precision, seed=w.seed if seed is None else seed,
+                    guard_eV=guard_eV)
+    model = oracle.MLP(w.feature, w.hidden, p)
+    return w, mc, model, occ0.copy()
+
+
+def compare_sweep(cells, model, occ_oracle, temperature, seed, sweep_index, gpu_trace, gpu_occ,
+                  check_de=True, de_tol=FP32_DE_TOL_EV, nthreads=8):
+    """Advance the oracle one sweep and compare it with the GPU's trace and occupancy.
+
+    Returns the number of tolerated near-threshold disagreements; on one, the GPU's state is
+    copied into the oracle (the chains would otherwise diverge)."""
+    st, tr = oracle.sweep(cells, model, occ_oracle, temperature, seed, 0, sweep_index, trace=True,
+                          nthreads=nthreads)
+    flags = gpu_trace["flags"]
+    acc_gpu = (flags & 1).astype(bool)
+    same_gpu = (flags & 2).astype(bool)
+    assert np.array_equal(same_gpu, tr["same"].astype(bool))
+    acc_or = tr["accept"].astype(bool)
+    diff = np.nonzero(acc_gpu != acc_or)[0]
+    tolerated = 0
+    for s in diff:
+        gap = abs(tr["dE"][s] - tr["theta"][s])
+        assert gap < DECISION_BAND_EV, (
+            f"sweep {sweep_index} site {s}: gpu accept {acc_gpu[s]} oracle {acc_or[s]} "
+            f"dE_oracle {tr['dE'][s]!r} theta {tr['theta'][s]!r} dE_gpu {gpu_trace['dE'][s]!r}")
+        tolerated += 1
+    if tolerated:
+        occ_oracle[:] = gpu_occ
+    else:
+        assert np.array_equal(gpu_occ, occ_oracle), f"occupancy differs after sweep {sweep_index}"
+    if check_de:
+        d = ~tr["same"].astype(bool)
+        err = np.abs(gpu_trace["dE_fast"][d] - tr["dE"][d])
+        assert err.max(initial=0.0) < de_tol, f"max |dE_gpu - dE_oracle| = {err.max()}"
+        err64 = np.abs(gpu_trace["dE"][d] - tr["dE"][d])
+        fp64 = (flags[d] & 4).astype(bool)
+        if fp64.any():
+            assert err64[fp64].max() < 1e-9
+    return tolerated, tr
+
+
+def trace_to_numpy(t):
+    return {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in t.items()}

@@ -1,0 +1,164 @@
+"""GPU sweeps against the CPU oracle, through the C ABI.
+
+Bar: occupancies bit-exact after every sweep under the same Philox stream; FP32 dE within
+1e-5 eV of the oracle's FP64 dE; Metropolis decisions equal except where the oracle's dE
+lies within 1e-9 eV of the threshold; FP64 running totals equal the from-scratch total.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_common import compare_sweep, make, need_gpu, trace_to_numpy
+
+pytestmark = pytest.mark.gpu
+
+
+def _banner(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+
+
+def test_site_energies_match_oracle_c1_c2_shapes():
+    need_gpu()
+    for name, cells in [("c1", None), ("c2", (8, 12, 16))]:
+        _banner(f"site energies {name} {cells}")
+        w, mc, model, occ = make(name, cells=cells)
+        e64 = mc.site_energies("fp64").cpu().numpy()
+        e32 = mc.site_energies("fp32").cpu().numpy()
+        want = oracle.all_site_energies(w.cells[0], model, occ)
+        assert np.max(np.abs(e64 - want)) < 1e-12
+        assert np.max(np.abs(e32 - want)) < 2e-6
+        # the energy cache is the FP32 evaluator's output, bit for bit
+        assert np.array_equal(mc.ecache.cpu().numpy(), e32)
+        es, er = mc.energy()
+        assert es[0] == pytest.approx(want.sum(), abs=1e-9 * abs(want.sum()) + 1e-12)
+        assert er[0] == es[0]
+        mc.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_c1_bit_exact_every_sweep(precision):
+    need_gpu()
+    w, mc, model, occ = make("c1", precision=precision)
+    cells, T = w.cells[0], w.temperatures[0]
+    n_sweeps = 100 if precision == "fp32" else 20
+    _banner(f"c1 {precision} {n_sweeps} sweeps")
+    tolerated = 0
+    accepts = 0
+    max_err = 0.0
+    counts0 = np.bincount(occ, minlength=4)
+    for t in range(n_sweeps):
+        tr = trace_to_numpy(mc.sweep(1, stats=True, trace=True))
+        gocc = mc.occ.cpu().numpy()
+        assert np.array_equal(np.bincount(gocc, minlength=4), counts0)
+        n_tol, otr = compare_sweep(cells, model, occ, T, w.seed, t, tr, gocc)
+        tolerated += n_tol
+        assert tr["attempts"][0] == occ.size
+        assert tr["diff_species"][0] == int((otr["same"] == 0).sum())
+        accepts += int(tr["accepts"][0])
+        d = otr["same"] == 0
+        max_err = max(max_err, float(np.abs(tr["dE"][d] - otr["dE"][d]).max(initial=0.0)))
+    _banner(f"tolerated near-threshold disagreements: {tolerated}; max |dE err| {max_err:.3e}")
+    es, er = mc.energy()
+    # the running total adds the sweep precision's dE of each accepted swap in FP64, so it
+    # drifts from the from-scratch total like a random walk of the per-trial dE error
+    assert abs(es[0] - er[0]) <= 10.0 * max_err * np.sqrt(max(accepts, 1)) + 1e-9 * abs(es[0])
+    assert es[0] == pytest.approx(oracle.total_energy(cells, model, occ), abs=1e-9)
+    assert np.array_equal(mc.ecache.cpu().numpy(), mc.site_energies("fp32").cpu().numpy()) \
+        or precision == "fp64"
+    mc.close()
+
+
+def test_uneven_lattice_and_five_species():
+    """Link cells of 4 and 5 cells, fifth species without a one-hot channel."""
+    need_gpu()
+    cells = (9, 10, 13)
+    _banner(f"uneven lattice {cells} 5 species")
+    w, mc, model, occ = make("c2", cells=cells, n_species=5, hidden=128, temperature=700.0)
+    for t in range(3):
+        tr = trace_to_numpy(mc.sweep(1, stats=True, trace=True))
+        compare_sweep(cells, model, occ, 700.0, w.seed, t, tr, mc.occ.cpu().numpy())
+    mc.close()
+
+
+def test_c2_full_size_sampled():
+    """64^3 cells: the oracle re-decides sampled trials of every colour on the state the
+    GPU's own decisions imply, and the replayed decisions reproduce the GPU lattice."""
+    need_gpu()
+    w, mc, model, occ = make("c2")
+    cells, T = w.cells[0], w.temperatures[0]
+    col = _colours_fast(cells)
+    rng = np.random.default_rng(0)
+    for t in range(2):
+        _banner(f"c2 sampled sweep {t}")
+        tr = trace_to_numpy(mc.sweep(1, stats=True, trace=True))
+        flags = tr["flags"]
+        assert tr["attempts"][0] == occ.size
+        for c in range(oracle.n_colours(cells)):
+            members = np.nonzero(col == c)[0]
+            for s in rng.choice(members, size=3, replace=False):
+                rec = oracle.trial(cells, model, occ, T, w.seed, 0, t, int(s))
+                assert bool(flags[s] & 2) == bool(rec["same"])
+                if not rec["same"]:
+                    assert abs(tr["dE_fast"][s] - rec["dE"]) < 1e-5
+                    if abs(rec["dE"] - rec["theta"]) >= 1e-9:
+                        assert bool(flags[s] & 1) == bool(rec["accept"])
+            acc = members[(flags[members] & 1).astype(bool)]
+            for s in acc:
+                d, _ = oracle.propose(w.seed, int(s), t, 0)
+                n = oracle.neighbor(cells, int(s), d)
+                occ[s], occ[n] = occ[n], occ[s]
+        assert np.array_equal(occ, mc.occ.cpu().numpy())
+    es, er = mc.energy()
+    assert abs(es[0] - er[0]) < 1e-6 * abs(es[0])
+    mc.close()
+
+
+def _colours_fast(cells):
+    """Colour of every site from the schedule rule (link cells of 4 for these sizes)."""
+    lx, ly, lz = cells
+    assert lx % 4 == 0 and ly % 4 == 0 and lz % 4 == 0
+    s = np.arange(2 * lx * ly * lz)
+    b = s % 2
+    c = s // 2
+    x, y, z = c % lx, (c // lx) % ly, c // (lx * ly)
+    col = (((z % 4) * 4 + (y % 4)) * 4 + (x % 4)) * 2 + b
+    # cross-check the rule with the oracle on a few sites
+    for k in range(0, len(s), len(s) // 50):
+        assert col[k] == oracle.lib().or_colour_of(oracle._ptr(oracle._dims(cells), oracle.C.c_int32), k)
+    return col
+
+
+def test_split_run_equals_long_run_and_resume():
+    need_gpu()
+    _banner("split/resume")
+    w, a, _, occ = make("c1")
+    a.sweep(6)
+    w, b, _, _ = make("c1")
+    b.sweep(2)
+    b.sweep(4)
+    assert np.array_equal(a.occ.cpu().numpy(), b.occ.cpu().numpy())
+    # resume from a checkpoint (occupancy + sweep counter) in a fresh context
+    w, c, _, _ = make("c1")
+    c.sweep(3)
+    ck_occ, ck_sweep = c.occ.cpu().numpy().copy(), c.sweep_index
+    w, d, _, _ = make("c1", occ=ck_occ)
+    d.sweep_index = ck_sweep
+    d.sweep(3)
+    assert np.array_equal(a.occ.cpu().numpy(), d.occ.cpu().numpy())
+    for m in (a, b, c, d):
+        m.close()
+
+
+def test_infinite_and_zero_temperature():
+    need_gpu()
+    _banner("T = inf / T = 0")
+    w, mc, model, occ = make("c1", temperature=float("inf"))
+    tr = mc.sweep(1, stats=True)
+    assert tr["accepts"][0] == tr["diff_species"][0]
+    mc.close()
+    w, mc, model, occ = make("c1", temperature=0.0)
+    tr = trace_to_numpy(mc.sweep(1, stats=True, trace=True))
+    acc = (tr["flags"] & 1).astype(bool)
+    assert np.all(tr["dE"][acc] <= 0.0)
+    mc.close()
