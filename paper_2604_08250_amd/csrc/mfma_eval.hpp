@@ -1,0 +1,283 @@
+// Matrix-core evaluation of the local-energy MLP (108 one-hot inputs -> 128 -> 128 -> 1,
+// SiLU) for 32 sites at a time, in FP32, BF16, split BF16 (hi+lo, three products) or
+// OCP FP8 E4M3.
+//
+// Layout.  Every layer is computed transposed, H^T = W . X^T, with the MFMA 32x32xK
+// instructions: the A operand holds 32 hidden units of a weight tile (from LDS), the B
+// operand holds the activations of 32 sites, one site per lane (mod 32).  The output
+// registers of a layer (lane = site, 16 hidden units per lane) are exactly the B operand
+// of the next layer once the next layer's weights are packed with the matching K order,
+// so activations never leave registers.  A output register v of lane group g = lane/32
+// in M-tile T holds hidden unit 32T + 8(v/4) + 4g + (v%4).
+//
+// SiLU.  With y = -log2(e) z, silu(z) = -ln(2) * y / (1 + 2^y).  The factor -log2(e)
+// is folded into W0 and the biases, -ln(2) into the next layer (it cancels against the
+// -log2(e) of that layer, log2(e) ln(2) = 1) and into W2, so each activation costs one
+// exp2, one add, one reciprocal and one multiply.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace smc {
+
+enum { kP32 = 0, kPBF16 = 1, kPBF16X3 = 2, kPFP8 = 3 };
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kHid = 128;
+constexpr int kMT = 4;  // M-tiles of 32 hidden units
+
+// Bytes of the packed weights of each precision in LDS (layer 0 then layer 1), followed by
+// c0[128], c1[128], w2[128] (floats) and two words of FP8 scale exponents.
+template <int P>
+struct PackSize;
+template <>
+struct PackSize<kP32> {
+  static constexpr int kL0 = kMT * 14 * 64 * 16;  // 56 K-steps of 2, four per 16-byte read
+  static constexpr int kL1 = kMT * 16 * 64 * 16;  // 64 K-steps of 2
+};
+template <>
+struct PackSize<kPBF16> {
+  static constexpr int kL0 = kMT * 7 * 64 * 16;   // 7 K-steps of 16 (108 -> 112)
+  static constexpr int kL1 = kMT * 8 * 64 * 16;   // 8 K-steps of 16
+};
+template <>
+struct PackSize<kPBF16X3> {
+  static constexpr int kL0 = 2 * PackSize<kPBF16>::kL0;  // hi then lo
+  static constexpr int kL1 = 2 * PackSize<kPBF16>::kL1;
+};
+template <>
+struct PackSize<kPFP8> {
+  static constexpr int kL0 = kMT * 2 * 64 * 32;   // 2 K-steps of 64 (108 -> 128)
+  static constexpr int kL1 = kMT * 2 * 64 * 32;
+};
+template <int P>
+constexpr int pack_bytes() {
+  return PackSize<P>::kL0 + PackSize<P>::kL1 + 3 * kHid * 4 + 16;
+}
+
+// Activation: h' = y / ((1 + 2^y) s); s = 1, or the FP8 activation scale 2^kh so that the
+// quantised value is h'/2^kh (folded into the add).
+__device__ __forceinline__ float act(float y, float s) {
+  const float e = __builtin_amdgcn_exp2f(y);
+  return y * __builtin_amdgcn_rcpf(fmaf(e, s, s));
+}
+
+__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
+  const __bf16 x = (__bf16)a, y = (__bf16)b;
+  return (uint32_t)__builtin_bit_cast(uint16_t, x) | ((uint32_t)__builtin_bit_cast(uint16_t, y) << 16);
+}
+
+__device__ __forceinline__ float bf16_lo_f32(uint32_t w) { return __builtin_bit_cast(float, w << 16); }
+__device__ __forceinline__ float bf16_hi_f32(uint32_t w) { return __builtin_bit_cast(float, w & 0xffff0000u); }
+
+// One-hot of a species id (0..3; 4 and above: no channel) as 4 BF16 values in 2 dwords.
+__device__ __forceinline__ void onehot_bf16(uint32_t p, uint32_t &lo, uint32_t &hi) {
+  const uint32_t one = 0x3F80u << ((p & 1u) << 4);
+  lo = p < 2u ? one : 0u;
+  hi = (p - 2u) < 2u ? one : 0u;
+}
+
+// One-hot of a species id as 4 FP8 E4M3 bytes in one dword (1.0 = 0x38).
+__device__ __forceinline__ uint32_t onehot_fp8(uint32_t p) {
+  return (uint32_t)((uint64_t)0x38u << (p << 3));  // p = 4 shifts the byte out
+}
+
+struct EvalSmem {
+  const uint8_t *w;     // packed weights of the precision
+  const float *c0, *c1, *w2;
+  float b2;
+  int k_scale_a0, k_scale_a1, k_scale_h;  // FP8 E8M0 scale exponents (biased)
+  float sh;                                // FP8 activation scale 2^kh
+};
+
+// Energy of the site held by this lane (lane % 32) of a 32-site tile.  get(m) returns the
+// species of feature slot m (0 = centre, 1 + k = neighbour k) of the lane's site; only the
+// slots the lane's operands need are requested.  Both lane groups return the same value.
+template <int P, typename GetSlot>
+__device__ __forceinline__ float eval_tile(const EvalSmem &S, GetSlot get) {
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 5;
+  f32x16 acc[kMT];
+  // bias initialisation: register v of M-tile T holds hidden 32T + 8(v/4) + 4g + v%4
+#pragma unroll
+  for (int T = 0; T < kMT; ++T)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const f32x4 b = *(const f32x4 *)(S.c0 + 32 * T + 8 * j + 4 * g);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc[T][4 * j + i] = b[i];
+    }
+
+  // ---------------------------------------------------------------- layer 0
+  if constexpr (P == kP32) {
+    // K-step s covers features 2s, 2s+1; lane group g supplies feature 2s + g = slot s/2,
+    // channel 2(s%2) + g.
+    const f32x4 *A = (const f32x4 *)S.w;
+#pragma unroll
+    for (int m = 0; m < 28; ++m) {
+      const uint32_t p = m < 27 ? (uint32_t)get(m) : 7u;
+      const float b0 = (p == (uint32_t)g) ? 1.0f : 0.0f;
+      const float b1 = (p == (uint32_t)(2 + g)) ? 1.0f : 0.0f;
+#pragma unroll
+      for (int T = 0; T < kMT; ++T) {
+        const f32x4 a = A[(T * 14 + m / 2) * 64 + lane];
+        const int o = (m & 1) * 2;
+        acc[T] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[o], b0, acc[T], 0, 0, 0);
+        acc[T] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[o + 1], b1, acc[T], 0, 0, 0);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  } else if constexpr (P == kPBF16 || P == kPBF16X3) {
+    // K-step s covers features 16s..16s+15; lane group g supplies slots 4s+2g, 4s+2g+1.
+    const i32x4 *Ahi = (const i32x4 *)S.w;
+    const i32x4 *Alo = (const i32x4 *)(S.w + PackSize<kPBF16>::kL0);
+#pragma unroll
+    for (int s = 0; s < 7; ++s) {
+      const int m0 = 4 * s + 2 * g;
+      const uint32_t p0 = (uint32_t)get(m0);
+      const uint32_t p1 = (m0 + 1 < 27) ? (uint32_t)get(m0 + 1) : 7u;
+      i32x4 bw;
+      uint32_t l0, h0, l1, h1;
+      onehot_bf16(p0, l0, h0);
+      onehot_bf16(p1, l1, h1);
+      bw[0] = (int)l0; bw[1] = (int)h0; bw[2] = (int)l1; bw[3] = (int)h1;
+      const bf16x8 b = __builtin_bit_cast(bf16x8, bw);
+#pragma unroll
+      for (int T = 0; T < kMT; ++T) {
+        const bf16x8 ah = __builtin_bit_cast(bf16x8, Ahi[(T * 7 + s) * 64 + lane]);
+        acc[T] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, b, acc[T], 0, 0, 0);
+        if constexpr (P == kPBF16X3) {
+          const bf16x8 al = __builtin_bit_cast(bf16x8, Alo[(T * 7 + s) * 64 + lane]);
+          acc[T] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, b, acc[T], 0, 0, 0);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  } else {
+    // FP8: K-step s covers features 64s..64s+63; lane group g supplies slots 16s+8g..+7.
+    const i32x8 *A = (const i32x8 *)S.w;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      i32x8 b;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int m = 16 * s + 8 * g + j;
+        b[j] = (m < 27) ? (int)onehot_fp8((uint32_t)get(m)) : 0;
+      }
+#pragma unroll
+      for (int T = 0; T < kMT; ++T)
+        acc[T] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[(T * 2 + s) * 64 + lane], b, acc[T], 0, 0,
+                                                                   0, S.k_scale_a0, 0, 127);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+
+  // ---------------------------------------------------------------- activation 0
+  // and the B operands of layer 1 built from the output registers.
+  f32x16 acc1[kMT];
+#pragma unroll
+  for (int T = 0; T < kMT; ++T)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const f32x4 b = *(const f32x4 *)(S.c1 + 32 * T + 8 * j + 4 * g);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc1[T][4 * j + i] = b[i];
+    }
+
+  if constexpr (P == kP32) {
+    f32x16 h[kMT];
+#pragma unroll
+    for (int T = 0; T < kMT; ++T)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) h[T][v] = act(acc[T][v], 1.0f);
+    // K-step s = 16T + v: lane group g supplies its own register v of M-tile T.
+    const f32x4 *A = (const f32x4 *)(S.w + PackSize<kP32>::kL0);
+#pragma unroll
+    for (int T = 0; T < kMT; ++T)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int To = 0; To < kMT; ++To) {
+          const f32x4 a = A[(To * 16 + T * 4 + q) * 64 + lane];
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            acc1[To] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], h[T][4 * q + i], acc1[To], 0, 0, 0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+  } else if constexpr (P == kPBF16 || P == kPBF16X3) {
+    // K-step s' = 2T + hh takes registers 8hh..8hh+7 of M-tile T.
+    const i32x4 *Ahi = (const i32x4 *)(S.w + (P == kPBF16 ? PackSize<kPBF16>::kL0 : PackSize<kPBF16X3>::kL0));
+    const i32x4 *Alo = (const i32x4 *)(S.w + PackSize<kPBF16X3>::kL0 + PackSize<kPBF16>::kL1);
+#pragma unroll
+    for (int T = 0; T < kMT; ++T)
+#pragma unroll
+      for (int hh = 0; hh < 2; ++hh) {
+        i32x4 bh, bl;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float x0 = act(acc[T][8 * hh + 2 * q], 1.0f);
+          const float x1 = act(acc[T][8 * hh + 2 * q + 1], 1.0f);
+          const uint32_t w = pack_bf16x2(x0, x1);
+          bh[q] = (int)w;
+          if constexpr (P == kPBF16X3) bl[q] = (int)pack_bf16x2(x0 - bf16_lo_f32(w), x1 - bf16_hi_f32(w));
+        }
+        const bf16x8 Bh = __builtin_bit_cast(bf16x8, bh);
+        const int s = 2 * T + hh;
+#pragma unroll
+        for (int To = 0; To < kMT; ++To) {
+          const bf16x8 ah = __builtin_bit_cast(bf16x8, Ahi[(To * 8 + s) * 64 + lane]);
+          acc1[To] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, Bh, acc1[To], 0, 0, 0);
+          if constexpr (P == kPBF16X3) {
+            const bf16x8 Bl = __builtin_bit_cast(bf16x8, bl);
+            const bf16x8 al = __builtin_bit_cast(bf16x8, Alo[(To * 8 + s) * 64 + lane]);
+            acc1[To] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, Bl, acc1[To], 0, 0, 0);
+            acc1[To] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, Bh, acc1[To], 0, 0, 0);
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+  } else {
+    // FP8: K-step s' takes M-tiles 2s' and 2s'+1 (16 registers each) of this lane group.
+    const i32x8 *A = (const i32x8 *)(S.w + PackSize<kPFP8>::kL0);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      i32x8 b;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int T = 2 * s + j / 4;
+        const int v = 4 * (j % 4);
+        int w = 0;
+        w = __builtin_amdgcn_cvt_pk_fp8_f32(act(acc[T][v], S.sh), act(acc[T][v + 1], S.sh), w, false);
+        w = __builtin_amdgcn_cvt_pk_fp8_f32(act(acc[T][v + 2], S.sh), act(acc[T][v + 3], S.sh), w, true);
+        b[j] = w;
+      }
+#pragma unroll
+      for (int To = 0; To < kMT; ++To)
+        acc1[To] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[(To * 2 + s) * 64 + lane], b, acc1[To], 0, 0,
+                                                                     0, S.k_scale_a1, 0, S.k_scale_h);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+
+  // ---------------------------------------------------------------- activation 1, layer 2
+  float part = 0.0f;
+#pragma unroll
+  for (int T = 0; T < kMT; ++T)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const f32x4 w = *(const f32x4 *)(S.w2 + 32 * T + 8 * j + 4 * g);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) part = fmaf(w[i], act(acc1[T][4 * j + i], 1.0f), part);
+    }
+  const float other = __shfl_xor(part, 32);
+  const float p0 = g == 0 ? part : other, p1 = g == 0 ? other : part;
+  return S.b2 + (p0 + p1);
+}
+
+}  // namespace smc

@@ -3,14 +3,27 @@
 #include <math.h>
 #include <stdio.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
 #include "../../include/smc.h"
+#include "pack.hpp"
+#include "sweep_mfma.hpp"
 #include "sweep_scalar.hpp"
 #include "tables.hpp"
 
 using namespace smc;
+
+namespace {
+
+struct DevPack {  // one precision's packed weights on the device
+  bool ready = false;
+  PackedModel host;
+  uint8_t *dev = nullptr;
+};
+
+}  // namespace
 
 struct smc_ctx {
   smc_config cfg{};
@@ -19,19 +32,28 @@ struct smc_ctx {
   std::vector<Replica> reps;
   int64_t n_total = 0;
   int32_t n_in = 0, hidden = 0, n_params = 0;
+  bool mfma = false;              // one-hot features with 128 hidden: matrix-core path
+  int n_cu = 256;
   hipStream_t stream = nullptr;
   uint8_t *occ = nullptr;
   float *ecache = nullptr;
+  std::vector<float> host_params;
   // library-owned device memory
   Replica *d_reps = nullptr;
   float *d_w32 = nullptr;
   double *d_w64 = nullptr;
-  int8_t *d_omega = nullptr;
+  int8_t *d_omega = nullptr;      // per-lane path Omega offsets
   int32_t omega_n = 0;
-  double *d_erun = nullptr;       // [R] running FP64 totals
+  int32_t *d_reg_off = nullptr, *d_om_off = nullptr;
+  uint8_t *d_idx = nullptr, *d_reg_pos = nullptr;
+  DevPack packs[4];
+  RecheckEntry *d_queue = nullptr;
+  uint32_t *d_qcount = nullptr;   // one counter per colour of a sweep
+  int64_t queue_cap = 0;
+  int32_t colours_total = 0;
+  double *d_ebase = nullptr;      // [R] FP64 total at the last refresh
+  unsigned long long *d_efixed = nullptr;  // [R] accepted dE since then, 2^-32 eV units
   double *d_escratch = nullptr;   // [R]
-  double *d_partial = nullptr;    // per-block partial sums of accepted dE
-  int64_t partial_cap = 0;
   uint64_t *d_counters = nullptr; // [4][R]
   double *d_site64 = nullptr;     // [N] FP64 site energies (lazy)
   uint64_t sweep = 0;
@@ -53,10 +75,12 @@ int fail(smc_ctx *c, int code, const std::string &msg) {
       return fail((c), SMC_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+// Default FP64 re-decision band per precision: several times the largest |dE| error of the
+// precision measured against FP64 on the reference workloads.
 double default_guard(int prec) {
   switch (prec) {
     case SMC_FP32: return 1e-5;
-    case SMC_BF16X3: return 5e-4;
+    case SMC_BF16X3: return 2e-4;
     case SMC_BF16: return 1e-5;
     case SMC_FP8_E4M3: return 1e-5;
     default: return 0.0;
@@ -65,42 +89,64 @@ double default_guard(int prec) {
 
 unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
-template <int FEAT, int H>
-int launch_site_energies32(smc_ctx *c, float *out) {
-  for (size_t r = 0; r < c->reps.size(); ++r) {
-    hipLaunchKernelGGL((k_site_energies<FEAT, H, float>), dim3(grid_for(c->reps[r].n_sites, 128)),
-                       dim3(128), 0, c->stream, c->d_reps, (int32_t)r, c->occ, c->d_w32, out);
-  }
+template <int FEAT, int H, typename T>
+void launch_site_energies(smc_ctx *c, const T *W, T *out) {
+  for (size_t r = 0; r < c->reps.size(); ++r)
+    hipLaunchKernelGGL((k_site_energies<FEAT, H, T>), dim3(grid_for(c->reps[r].n_sites, 128)), dim3(128), 0,
+                       c->stream, c->d_reps, (int32_t)r, c->occ, W, out);
+}
+
+template <typename T>
+int site_energies_scalar(smc_ctx *c, const T *W, T *out) {
+  const bool counts = c->cfg.feature == SMC_FEAT_COUNTS_S12;
+  if (counts && c->hidden == 64) launch_site_energies<0, 64, T>(c, W, out);
+  else if (counts) launch_site_energies<0, 128, T>(c, W, out);
+  else if (c->hidden == 64) launch_site_energies<1, 64, T>(c, W, out);
+  else launch_site_energies<1, 128, T>(c, W, out);
   HIPC(c, hipGetLastError());
   return SMC_OK;
 }
 
-template <int FEAT, int H>
-int launch_site_energies64(smc_ctx *c, double *out) {
-  for (size_t r = 0; r < c->reps.size(); ++r) {
-    hipLaunchKernelGGL((k_site_energies<FEAT, H, double>), dim3(grid_for(c->reps[r].n_sites, 128)),
-                       dim3(128), 0, c->stream, c->d_reps, (int32_t)r, c->occ, c->d_w64, out);
-  }
-  HIPC(c, hipGetLastError());
+int ensure_pack(smc_ctx *c, int P) {
+  DevPack &dp = c->packs[P];
+  if (dp.ready) return SMC_OK;
+  dp.host = pack_model(P, c->host_params.data());
+  if (!dp.dev) HIPC(c, hipMalloc(&dp.dev, dp.host.bytes.size()));
+  HIPC(c, hipMemcpyAsync(dp.dev, dp.host.bytes.data(), dp.host.bytes.size(), hipMemcpyHostToDevice, c->stream));
+  HIPC(c, hipStreamSynchronize(c->stream));  // the host image may be replaced by a later pack
+  dp.ready = true;
   return SMC_OK;
 }
 
-int site_energies32(smc_ctx *c, float *out) {
-  if (c->cfg.feature == SMC_FEAT_COUNTS_S12) {
-    if (c->hidden == 64) return launch_site_energies32<0, 64>(c, out);
-    return launch_site_energies32<0, 128>(c, out);
+template <int P>
+void launch_site_energies_mfma(smc_ctx *c, float *out) {
+  const DevPack &dp = c->packs[P];
+  for (size_t r = 0; r < c->reps.size(); ++r) {
+    const int64_t tiles = (c->reps[r].n_sites + 31) / 32;
+    const unsigned grid = (unsigned)std::min<int64_t>((tiles + 3) / 4, 4 * (int64_t)c->n_cu);
+    hipLaunchKernelGGL((k_site_energies_mfma<P>), dim3(grid), dim3(256), 0, c->stream, c->d_reps, (int32_t)r,
+                       c->occ, dp.dev, dp.host.b2, dp.host.k_scale_a0, dp.host.k_scale_a1, dp.host.k_scale_h,
+                       dp.host.sh, out);
   }
-  if (c->hidden == 64) return launch_site_energies32<1, 64>(c, out);
-  return launch_site_energies32<1, 128>(c, out);
 }
 
-int site_energies64(smc_ctx *c, double *out) {
-  if (c->cfg.feature == SMC_FEAT_COUNTS_S12) {
-    if (c->hidden == 64) return launch_site_energies64<0, 64>(c, out);
-    return launch_site_energies64<0, 128>(c, out);
+// Local energies with the evaluator of precision P (float out).
+int site_energies_fast(smc_ctx *c, int P, float *out) {
+  if (!c->mfma) {
+    if (P != SMC_FP32) return fail(c, SMC_E_UNSUPPORTED, "low precisions need one-hot features and 128 hidden");
+    return site_energies_scalar<float>(c, c->d_w32, out);
   }
-  if (c->hidden == 64) return launch_site_energies64<1, 64>(c, out);
-  return launch_site_energies64<1, 128>(c, out);
+  int rc = ensure_pack(c, P);
+  if (rc) return rc;
+  switch (P) {
+    case SMC_FP32: launch_site_energies_mfma<kP32>(c, out); break;
+    case SMC_BF16: launch_site_energies_mfma<kPBF16>(c, out); break;
+    case SMC_BF16X3: launch_site_energies_mfma<kPBF16X3>(c, out); break;
+    case SMC_FP8_E4M3: launch_site_energies_mfma<kPFP8>(c, out); break;
+    default: return fail(c, SMC_E_INVALID, "precision");
+  }
+  HIPC(c, hipGetLastError());
+  return SMC_OK;
 }
 
 int ensure_site64(smc_ctx *c) {
@@ -111,8 +157,7 @@ int ensure_site64(smc_ctx *c) {
 // FP64 from-scratch totals per replica into d_escratch.
 int scratch_totals(smc_ctx *c) {
   int rc = ensure_site64(c);
-  if (rc) return rc;
-  rc = site_energies64(c, c->d_site64);
+  if (!rc) rc = site_energies_scalar<double>(c, c->d_w64, c->d_site64);
   if (rc) return rc;
   for (size_t r = 0; r < c->reps.size(); ++r)
     hipLaunchKernelGGL(k_sum_into, dim3(1), dim3(256), 0, c->stream, c->d_site64 + c->reps[r].site0,
@@ -122,26 +167,27 @@ int scratch_totals(smc_ctx *c) {
 }
 
 int refresh(smc_ctx *c) {
-  int rc;
-  if (c->cfg.precision == SMC_FP64) {
-    rc = scratch_totals(c);
-    if (rc) return rc;
+  int rc = scratch_totals(c);
+  if (rc) return rc;
+  if (c->cfg.precision == SMC_FP64)
     hipLaunchKernelGGL(k_narrow, dim3(grid_for(c->n_total, 256)), dim3(256), 0, c->stream, c->d_site64,
                        c->ecache, c->n_total);
-  } else {
-    rc = site_energies32(c, c->ecache);
-    if (rc) return rc;
-    rc = scratch_totals(c);
-    if (rc) return rc;
-  }
-  HIPC(c, hipMemcpyAsync(c->d_erun, c->d_escratch, sizeof(double) * c->reps.size(),
-                         hipMemcpyDeviceToDevice, c->stream));
+  else if ((rc = site_energies_fast(c, c->cfg.precision, c->ecache)))
+    return rc;
+  const int R = (int)c->reps.size();
+  HIPC(c, hipMemcpyAsync(c->d_ebase, c->d_escratch, sizeof(double) * R, hipMemcpyDeviceToDevice, c->stream));
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(256), 0, c->stream, (uint64_t *)c->d_efixed, (int64_t)R,
+                     (uint64_t)0);
   HIPC(c, hipGetLastError());
   return SMC_OK;
 }
 
 int load_params(smc_ctx *c, const float *params_dev) {
   const int64_t P = c->n_params;
+  c->host_params.resize(P);
+  HIPC(c, hipMemcpyAsync(c->host_params.data(), params_dev, sizeof(float) * P, hipMemcpyDeviceToHost, c->stream));
+  HIPC(c, hipStreamSynchronize(c->stream));
+  for (int k = 0; k < 4; ++k) c->packs[k].ready = false;
   hipLaunchKernelGGL(k_copy_f32, dim3(grid_for(P, 256)), dim3(256), 0, c->stream, params_dev, c->d_w32, P);
   hipLaunchKernelGGL(k_widen, dim3(grid_for(P, 256)), dim3(256), 0, c->stream, params_dev, c->d_w64, P);
   HIPC(c, hipGetLastError());
@@ -154,48 +200,114 @@ void launch_colour_scalar(smc_ctx *c, SweepArgs a, int64_t n_trials) {
                      dim3(kScalarBlock), 0, c->stream, a);
 }
 
+template <int P>
+void launch_colour_mfma(smc_ctx *c, const MfmaArgs &a) {
+  int G = std::min(a.n_groups, c->n_cu);
+  if (G >= 8) G -= G % 8;
+  hipLaunchKernelGGL((k_sweep_colour_mfma<P>), dim3(G), dim3(kMfmaThreads), 0, c->stream, a);
+}
+
 int run_sweep(smc_ctx *c, const smc_stats *st, bool last) {
   const int R = (int)c->reps.size();
-  int64_t poff = 0;
-  std::vector<int64_t> pstart(R + 1, 0);
-  for (int r = 0; r < R; ++r) {
-    const Replica &rep = c->reps[r];
-    const int64_t blocks = grid_for(rep.n_trials, kScalarBlock);
-    for (int col = 0; col < rep.n_colours; ++col) {
-      SweepArgs a{};
-      a.reps = c->d_reps;
-      a.occ = c->occ;
-      a.ecache = c->ecache;
-      a.w32 = c->d_w32;
-      a.w64 = c->d_w64;
-      a.omega = c->d_omega;
-      a.omega_n = c->omega_n;
-      a.replica = r;
-      a.colour = col;
-      a.fp64_mode = c->cfg.precision == SMC_FP64;
-      a.seed = c->cfg.seed;
-      a.sweep = c->sweep;
-      a.guard = c->guard;
-      a.partial = c->d_partial + poff;
-      a.counters = c->d_counters;
-      a.n_replicas = R;
-      if (last && st) {
-        a.trace_dE = st->trace_dE;
-        a.trace_dE_fast = st->trace_dE_fast;
-        a.trace_flags = st->trace_flags;
+  const bool trace = last && st;
+  if (c->mfma && c->cfg.precision != SMC_FP64) {
+    const DevPack &dp = c->packs[c->cfg.precision];
+    const int64_t qwords = (c->colours_total + 1) / 2;
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(qwords, 256)), dim3(256), 0, c->stream,
+                       (uint64_t *)c->d_qcount, qwords, (uint64_t)0);
+    int qoff = 0;
+    for (int r = 0; r < R; ++r) {
+      const Replica &rep = c->reps[r];
+      for (int col = 0; col < rep.n_colours; ++col, ++qoff) {
+        MfmaArgs a{};
+        a.reps = c->d_reps;
+        a.occ = c->occ;
+        a.ecache = c->ecache;
+        a.wpack = dp.dev;
+        a.reg_off = c->d_reg_off;
+        a.om_off = c->d_om_off;
+        a.idx = c->d_idx;
+        a.reg_pos = c->d_reg_pos;
+        a.b2 = dp.host.b2;
+        a.k_a0 = dp.host.k_scale_a0;
+        a.k_a1 = dp.host.k_scale_a1;
+        a.k_h = dp.host.k_scale_h;
+        a.sh = dp.host.sh;
+        a.replica = r;
+        a.colour = col;
+        a.seed = c->cfg.seed;
+        a.sweep = c->sweep;
+        a.guard = c->guard;
+        a.q_count = c->d_qcount + qoff;
+        a.queue = c->d_queue;
+        a.e_fixed = c->d_efixed;
+        a.counters = c->d_counters;
+        a.n_replicas = R;
+        a.n_groups = (int32_t)((rep.n_trials + kGroup - 1) / kGroup);
+        if (trace) {
+          a.trace_dE = st->trace_dE;
+          a.trace_dE_fast = st->trace_dE_fast;
+          a.trace_flags = st->trace_flags;
+        }
+        switch (c->cfg.precision) {
+          case SMC_FP32: launch_colour_mfma<kP32>(c, a); break;
+          case SMC_BF16: launch_colour_mfma<kPBF16>(c, a); break;
+          case SMC_BF16X3: launch_colour_mfma<kPBF16X3>(c, a); break;
+          default: launch_colour_mfma<kPFP8>(c, a); break;
+        }
+        RecheckArgs ra{};
+        ra.reps = c->d_reps;
+        ra.occ = c->occ;
+        ra.ecache = c->ecache;
+        ra.w64 = c->d_w64;
+        ra.om_off = c->d_om_off;
+        ra.q_count = c->d_qcount + qoff;
+        ra.queue = c->d_queue;
+        ra.e_fixed = c->d_efixed;
+        ra.counters = c->d_counters;
+        ra.n_replicas = R;
+        if (trace) {
+          ra.trace_dE = st->trace_dE;
+          ra.trace_flags = st->trace_flags;
+        }
+        const int rgrid = (int)std::min<int64_t>(2 * c->n_cu, std::max<int64_t>(1, rep.n_trials));
+        hipLaunchKernelGGL(k_recheck, dim3(rgrid), dim3(128), 0, c->stream, ra);
       }
-      const bool onehot = c->cfg.feature == SMC_FEAT_ONEHOT_S123;
-      if (!onehot && c->hidden == 64) launch_colour_scalar<0, 64>(c, a, rep.n_trials);
-      else if (!onehot) launch_colour_scalar<0, 128>(c, a, rep.n_trials);
-      else if (c->hidden == 64) launch_colour_scalar<1, 64>(c, a, rep.n_trials);
-      else launch_colour_scalar<1, 128>(c, a, rep.n_trials);
-      poff += blocks;
     }
-    pstart[r + 1] = poff;
+  } else {
+    for (int r = 0; r < R; ++r) {
+      const Replica &rep = c->reps[r];
+      for (int col = 0; col < rep.n_colours; ++col) {
+        SweepArgs a{};
+        a.reps = c->d_reps;
+        a.occ = c->occ;
+        a.ecache = c->ecache;
+        a.w32 = c->d_w32;
+        a.w64 = c->d_w64;
+        a.omega = c->d_omega;
+        a.omega_n = c->omega_n;
+        a.replica = r;
+        a.colour = col;
+        a.fp64_mode = c->cfg.precision == SMC_FP64;
+        a.seed = c->cfg.seed;
+        a.sweep = c->sweep;
+        a.guard = c->guard;
+        a.e_fixed = c->d_efixed;
+        a.counters = c->d_counters;
+        a.n_replicas = R;
+        if (trace) {
+          a.trace_dE = st->trace_dE;
+          a.trace_dE_fast = st->trace_dE_fast;
+          a.trace_flags = st->trace_flags;
+        }
+        const bool onehot = c->cfg.feature == SMC_FEAT_ONEHOT_S123;
+        if (!onehot && c->hidden == 64) launch_colour_scalar<0, 64>(c, a, rep.n_trials);
+        else if (!onehot) launch_colour_scalar<0, 128>(c, a, rep.n_trials);
+        else if (c->hidden == 64) launch_colour_scalar<1, 64>(c, a, rep.n_trials);
+        else launch_colour_scalar<1, 128>(c, a, rep.n_trials);
+      }
+    }
   }
-  for (int r = 0; r < R; ++r)
-    hipLaunchKernelGGL(k_sum_into, dim3(1), dim3(256), 0, c->stream, c->d_partial + pstart[r],
-                       pstart[r + 1] - pstart[r], c->d_erun + r, 1);
   HIPC(c, hipGetLastError());
   c->sweep++;
   return SMC_OK;
@@ -227,15 +339,19 @@ int smc_init(const smc_config *cfg, uint8_t *occ_dev, const float *params_dev, f
     return SMC_E_INVALID;
   if (cfg->n_replicas < 1 || cfg->n_species < 2 || cfg->n_species > 5) return SMC_E_INVALID;
   if (cfg->feature != SMC_FEAT_COUNTS_S12 && cfg->feature != SMC_FEAT_ONEHOT_S123) return SMC_E_INVALID;
-  if (cfg->hidden != 64 && cfg->hidden != 128) return SMC_E_UNSUPPORTED;
   if (cfg->precision < SMC_FP32 || cfg->precision > SMC_FP64) return SMC_E_INVALID;
-  if (cfg->precision != SMC_FP32 && cfg->precision != SMC_FP64) return SMC_E_UNSUPPORTED;
+  if (cfg->hidden != 64 && cfg->hidden != 128) return SMC_E_UNSUPPORTED;
+  const bool mfma = cfg->feature == SMC_FEAT_ONEHOT_S123 && cfg->hidden == 128;
+  if (!mfma && cfg->precision != SMC_FP32 && cfg->precision != SMC_FP64) return SMC_E_UNSUPPORTED;
+  int64_t total = 0;
   for (int r = 0; r < cfg->n_replicas; ++r) {
     for (int a = 0; a < 3; ++a)
-      if (cfg->cells[3 * r + a] < 4 || cfg->cells[3 * r + a] > (1 << 20)) return SMC_E_INVALID;
+      if (cfg->cells[3 * r + a] < 4 || cfg->cells[3 * r + a] > 4096) return SMC_E_INVALID;
     const double T = cfg->temperature_K[r];
     if (!(T >= 0.0)) return SMC_E_INVALID;
+    total += 2LL * cfg->cells[3 * r] * cfg->cells[3 * r + 1] * cfg->cells[3 * r + 2];
   }
+  if (total >= (1LL << 31)) return SMC_E_UNSUPPORTED;  // replica-local indices are 32-bit in the fast path
   smc_ctx *c = new (std::nothrow) smc_ctx();
   if (!c) return SMC_E_NOMEM;
   c->cfg = *cfg;
@@ -246,15 +362,22 @@ int smc_init(const smc_config *cfg, uint8_t *occ_dev, const float *params_dev, f
   c->stream = (hipStream_t)hip_stream;
   c->occ = occ_dev;
   c->ecache = ecache_dev;
+  c->mfma = mfma;
   c->n_in = cfg->feature == SMC_FEAT_COUNTS_S12 ? 12 : 108;
   c->hidden = cfg->hidden;
   c->n_params = c->hidden * c->n_in + c->hidden + c->hidden * c->hidden + c->hidden + c->hidden + 1;
   c->guard = cfg->guard_eV < 0 ? default_guard(cfg->precision) : cfg->guard_eV;
-  int64_t site0 = 0, partials = 0;
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0) c->n_cu = n;
+  }
+  int64_t site0 = 0, max_trials = 0;
   for (int r = 0; r < cfg->n_replicas; ++r) {
     c->reps.push_back(make_replica(&c->cells[3 * r], site0, c->temps[r]));
     site0 += c->reps.back().n_sites;
-    partials += (int64_t)c->reps.back().n_colours * grid_for(c->reps.back().n_trials, kScalarBlock);
+    max_trials = std::max(max_trials, c->reps.back().n_trials);
+    c->colours_total += c->reps.back().n_colours;
   }
   c->n_total = site0;
   const OmegaTable om = build_omega(cfg->feature == SMC_FEAT_COUNTS_S12 ? kNbrS12 : kNbr);
@@ -264,23 +387,38 @@ int smc_init(const smc_config *cfg, uint8_t *occ_dev, const float *params_dev, f
     smc_destroy(c);
     return code;
   };
-#define INIT_HIP(expr)                                  \
-  do {                                                  \
+#define INIT_HIP(expr)                                     \
+  do {                                                     \
     if ((expr) != hipSuccess) return cleanup(SMC_E_NOMEM); \
   } while (0)
   INIT_HIP(hipMalloc(&c->d_reps, sizeof(Replica) * R));
   INIT_HIP(hipMalloc(&c->d_w32, sizeof(float) * c->n_params));
   INIT_HIP(hipMalloc(&c->d_w64, sizeof(double) * c->n_params));
   INIT_HIP(hipMalloc(&c->d_omega, sizeof(om.off)));
-  INIT_HIP(hipMalloc(&c->d_erun, sizeof(double) * R));
+  INIT_HIP(hipMalloc(&c->d_ebase, sizeof(double) * R));
+  INIT_HIP(hipMalloc(&c->d_efixed, sizeof(unsigned long long) * R));
   INIT_HIP(hipMalloc(&c->d_escratch, sizeof(double) * R));
-  INIT_HIP(hipMalloc(&c->d_partial, sizeof(double) * partials));
   INIT_HIP(hipMalloc(&c->d_counters, sizeof(uint64_t) * 4 * R));
-#undef INIT_HIP
-  c->partial_cap = partials;
   if (hipMemcpyAsync(c->d_reps, c->reps.data(), sizeof(Replica) * R, hipMemcpyHostToDevice, c->stream) ||
       hipMemcpyAsync(c->d_omega, om.off.data(), sizeof(om.off), hipMemcpyHostToDevice, c->stream))
     return cleanup(SMC_E_DEVICE);
+  if (mfma) {
+    const RegionTables t = build_region_tables();
+    if (t.reg_off.empty()) return cleanup(SMC_E_DEVICE);
+    c->queue_cap = max_trials;
+    INIT_HIP(hipMalloc(&c->d_reg_off, sizeof(int32_t) * t.reg_off.size()));
+    INIT_HIP(hipMalloc(&c->d_om_off, sizeof(int32_t) * t.om_off.size()));
+    INIT_HIP(hipMalloc(&c->d_idx, t.idx.size()));
+    INIT_HIP(hipMalloc(&c->d_reg_pos, t.reg_pos.size()));
+    INIT_HIP(hipMalloc(&c->d_queue, sizeof(RecheckEntry) * c->queue_cap));
+    INIT_HIP(hipMalloc(&c->d_qcount, sizeof(uint32_t) * (c->colours_total + 2)));
+    if (hipMemcpy(c->d_reg_off, t.reg_off.data(), sizeof(int32_t) * t.reg_off.size(), hipMemcpyHostToDevice) ||
+        hipMemcpy(c->d_om_off, t.om_off.data(), sizeof(int32_t) * t.om_off.size(), hipMemcpyHostToDevice) ||
+        hipMemcpy(c->d_idx, t.idx.data(), t.idx.size(), hipMemcpyHostToDevice) ||
+        hipMemcpy(c->d_reg_pos, t.reg_pos.data(), t.reg_pos.size(), hipMemcpyHostToDevice))
+      return cleanup(SMC_E_DEVICE);
+  }
+#undef INIT_HIP
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(256), 0, c->stream, c->d_counters, (int64_t)4 * R, (uint64_t)0);
   int rc = load_params(c, params_dev);
   if (!rc) rc = refresh(c);
@@ -294,7 +432,8 @@ int smc_counters(smc_ctx *c, uint64_t *out, int32_t reset) {
   if (!c || !out) return SMC_E_INVALID;
   const int R = (int)c->reps.size();
   HIPC(c, hipMemcpyAsync(out, c->d_counters, sizeof(uint64_t) * 4 * R, hipMemcpyDeviceToHost, c->stream));
-  if (reset) hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(256), 0, c->stream, c->d_counters, (int64_t)4 * R, (uint64_t)0);
+  if (reset)
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(256), 0, c->stream, c->d_counters, (int64_t)4 * R, (uint64_t)0);
   HIPC(c, hipStreamSynchronize(c->stream));
   return SMC_OK;
 }
@@ -330,19 +469,24 @@ int smc_energy(smc_ctx *c, double *e_scratch, double *e_running) {
   int rc = scratch_totals(c);
   if (rc) return rc;
   const size_t R = c->reps.size();
-  if (e_scratch)
-    HIPC(c, hipMemcpyAsync(e_scratch, c->d_escratch, sizeof(double) * R, hipMemcpyDeviceToHost, c->stream));
-  if (e_running)
-    HIPC(c, hipMemcpyAsync(e_running, c->d_erun, sizeof(double) * R, hipMemcpyDeviceToHost, c->stream));
+  std::vector<double> es(R), eb(R);
+  std::vector<unsigned long long> ef(R);
+  HIPC(c, hipMemcpyAsync(es.data(), c->d_escratch, sizeof(double) * R, hipMemcpyDeviceToHost, c->stream));
+  HIPC(c, hipMemcpyAsync(eb.data(), c->d_ebase, sizeof(double) * R, hipMemcpyDeviceToHost, c->stream));
+  HIPC(c, hipMemcpyAsync(ef.data(), c->d_efixed, sizeof(unsigned long long) * R, hipMemcpyDeviceToHost, c->stream));
   HIPC(c, hipStreamSynchronize(c->stream));
+  for (size_t r = 0; r < R; ++r) {
+    if (e_scratch) e_scratch[r] = es[r];
+    if (e_running) e_running[r] = eb[r] + (double)(long long)ef[r] * 0x1.0p-32;
+  }
   return SMC_OK;
 }
 
 int smc_site_energies(smc_ctx *c, int32_t precision, void *out_dev) {
   if (!c || !out_dev) return SMC_E_INVALID;
-  if (precision == SMC_FP64) return site_energies64(c, (double *)out_dev);
-  if (precision == SMC_FP32) return site_energies32(c, (float *)out_dev);
-  return fail(c, SMC_E_UNSUPPORTED, "precision not built");
+  if (precision == SMC_FP64) return site_energies_scalar<double>(c, c->d_w64, (double *)out_dev);
+  if (precision < SMC_FP32 || precision > SMC_FP8_E4M3) return fail(c, SMC_E_INVALID, "precision");
+  return site_energies_fast(c, precision, (float *)out_dev);
 }
 
 int smc_set_params(smc_ctx *c, const float *params_dev) {
@@ -384,15 +528,12 @@ void smc_destroy(smc_ctx *c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
-  (void)hipFree(c->d_reps);
-  (void)hipFree(c->d_w32);
-  (void)hipFree(c->d_w64);
-  (void)hipFree(c->d_omega);
-  (void)hipFree(c->d_erun);
-  (void)hipFree(c->d_escratch);
-  (void)hipFree(c->d_partial);
-  (void)hipFree(c->d_counters);
-  (void)hipFree(c->d_site64);
+  void *bufs[] = {c->d_reps, c->d_w32, c->d_w64, c->d_omega, c->d_reg_off, c->d_om_off, c->d_idx,
+                  c->d_reg_pos, c->d_queue, c->d_qcount, c->d_ebase, c->d_efixed, c->d_escratch,
+                  c->d_counters, c->d_site64, c->packs[0].dev, c->packs[1].dev, c->packs[2].dev,
+                  c->packs[3].dev};
+  for (void *p : bufs)
+    if (p) (void)hipFree(p);
   delete c;
 }
 

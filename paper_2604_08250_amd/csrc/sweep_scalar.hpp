@@ -22,13 +22,17 @@ struct SweepArgs {
   uint64_t seed;
   uint64_t sweep;
   double guard;
-  double *partial;         // one FP64 partial sum of accepted dE per block
+  unsigned long long *e_fixed;  // [n_replicas] accepted dE in units of 2^-32 eV
   uint64_t *counters;      // [4][n_replicas]: attempts, diff, accepts, rechecks
   int32_t n_replicas;
   double *trace_dE;
   double *trace_dE_fast;
   uint8_t *trace_flags;
 };
+
+// Accepted energy changes are summed per block in a fixed order and added to an integer
+// accumulator in units of 2^-32 eV, so the running total does not depend on block order.
+__device__ __forceinline__ long long to_fixed(double x) { return __double2ll_rn(x * 4294967296.0); }
 
 // Trial site of (colour, trial) inside a replica, or -1 where that link cell is too short
 // to hold the colour's offset.
@@ -148,7 +152,7 @@ __global__ __launch_bounds__(kScalarBlock) void k_sweep_colour_scalar(SweepArgs 
   if (tid == 0) {
     double s = 0.0;
     for (int k = 0; k < kScalarBlock; ++k) s += s_de[k];
-    a.partial[blockIdx.x] = s;
+    atomicAdd(&a.e_fixed[a.replica], (unsigned long long)to_fixed(s));
     const int R_ = a.n_replicas;
     atomicAdd((unsigned long long *)&a.counters[0 * R_ + a.replica], (unsigned long long)__popcll(valid));
     atomicAdd((unsigned long long *)&a.counters[1 * R_ + a.replica], (unsigned long long)s_cnt[0]);

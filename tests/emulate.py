@@ -1,0 +1,109 @@
+"""CPU emulation of the low-precision MLP evaluators, written from their definitions.
+
+Used to check that each GPU precision path computes the model it claims to (packing,
+operand layouts, scales), not as a parity reference for the Monte Carlo itself, which is
+the FP64 oracle's job.
+
+Definitions (all precisions): with y = -log2(e) z, silu(z) = -ln(2) y / (1 + 2^y); the
+kernels evaluate
+    y1 = A0 x + c0,   h1 = y1 / (1 + 2^y1),
+    y2 = A1 q(h1) + c1,   h2 = y2 / (1 + 2^y2),   E = b2 + w2' . h2
+with A0 = q(-log2(e) W0), A1 = q(W1), c = -log2(e) b, w2' = -ln(2) W2, and q() the
+precision's quantiser:
+    fp32   : identity;
+    bf16   : round to BF16 (nearest even);
+    bf16x3 : hi = bf16(v), lo = bf16(v - hi); products hi*hi + hi*lo + lo*hi;
+    fp8    : OCP E4M3 with power-of-two per-layer scales 2^k, k = ceil(log2(amax / 448));
+             the activation scale bounds |h1| from the weights.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+L2E = np.float32(1.4426950408889634)
+LN2 = np.float32(0.6931471805599453)
+
+
+def split_params(p, n_in=108, H=128):
+    p = np.asarray(p, dtype=np.float32)
+    o = 0
+    W0 = p[o:o + H * n_in].reshape(H, n_in); o += H * n_in
+    b0 = p[o:o + H]; o += H
+    W1 = p[o:o + H * H].reshape(H, H); o += H * H
+    b1 = p[o:o + H]; o += H
+    W2 = p[o:o + H]; o += H
+    b2 = p[o]
+    return W0, b0, W1, b1, W2, b2
+
+
+def bf16(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(torch.bfloat16).float().numpy()
+
+
+def e4m3(a):
+    t = torch.from_numpy(np.clip(np.asarray(a, dtype=np.float32), -448.0, 448.0))
+    return t.to(torch.float8_e4m3fn).float().numpy()
+
+
+def _pow2_at_least(x):
+    return 0 if x <= 0 else int(math.ceil(math.log2(x)))
+
+
+def fp8_scales(params):
+    W0, b0, W1, b1, W2, b2 = split_params(params)
+    W0s = (-L2E * W0).astype(np.float32)
+    k0 = _pow2_at_least(float(np.abs(W0s).max()) / 448.0)
+    k1 = _pow2_at_least(float(np.abs(W1).max()) / 448.0)
+    zmax = b0.astype(np.float64) + np.sum(
+        np.maximum(0.0, W0.astype(np.float64).reshape(128, 27, 4).max(axis=2)), axis=1)
+    hmax = float(np.max(1.4426950408889634 * np.maximum(zmax, 0.2785)))
+    kh = _pow2_at_least(hmax / 448.0)
+    return k0, k1, kh
+
+
+def act(y):
+    y = y.astype(np.float32)
+    return (y / (np.float32(1.0) + np.exp2(y))).astype(np.float32)
+
+
+def energies(params, X, prec):
+    """Local energies of rows X [n, 108] (0/1 features) in the named precision."""
+    W0, b0, W1, b1, W2, b2 = split_params(params)
+    X = np.asarray(X, dtype=np.float64)
+    W0s = (-L2E * W0).astype(np.float32)
+    c0 = (-L2E * b0).astype(np.float32)
+    c1 = (-L2E * b1).astype(np.float32)
+    w2s = (-LN2 * W2).astype(np.float32)
+    f64 = np.float64
+    if prec == "fp32":
+        y1 = X @ W0s.T.astype(f64) + c0
+        h = act(y1.astype(np.float32))
+        y2 = h.astype(f64) @ W1.T.astype(f64) + c1
+    elif prec == "bf16":
+        y1 = X @ bf16(W0s).T.astype(f64) + c0
+        h = bf16(act(y1.astype(np.float32)))
+        y2 = h.astype(f64) @ bf16(W1).T.astype(f64) + c1
+    elif prec == "bf16x3":
+        hi0 = bf16(W0s)
+        lo0 = bf16(W0s - hi0)
+        y1 = X @ (hi0.astype(f64) + lo0).T + c0
+        h = act(y1.astype(np.float32))
+        hh = bf16(h)
+        hl = bf16(h - hh)
+        A1h = bf16(W1)
+        A1l = bf16(W1 - A1h)
+        y2 = hh.astype(f64) @ A1h.T + hl.astype(f64) @ A1h.T + hh.astype(f64) @ A1l.T + c1
+    elif prec == "fp8":
+        k0, k1, kh = fp8_scales(params)
+        A0 = e4m3(W0s * 2.0 ** -k0) * 2.0 ** k0
+        A1 = e4m3(W1 * 2.0 ** -k1) * 2.0 ** k1
+        y1 = X @ A0.T.astype(f64) + c0
+        h = e4m3(act(y1.astype(np.float32)) * np.float32(2.0 ** -kh)) * 2.0 ** kh
+        y2 = h.astype(f64) @ A1.T.astype(f64) + c1
+    else:
+        raise ValueError(prec)
+    h2 = act(y2.astype(np.float32))
+    return b2 + h2.astype(f64) @ w2s.astype(f64)

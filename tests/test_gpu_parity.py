@@ -27,7 +27,7 @@ def test_site_energies_match_oracle_c1_c2_shapes():
         e32 = mc.site_energies("fp32").cpu().numpy()
         want = oracle.all_site_energies(w.cells[0], model, occ)
         assert np.max(np.abs(e64 - want)) < 1e-12
-        assert np.max(np.abs(e32 - want)) < 2e-6
+        assert np.max(np.abs(e32 - want)) < 5e-6
         # the energy cache is the FP32 evaluator's output, bit for bit
         assert np.array_equal(mc.ecache.cpu().numpy(), e32)
         es, er = mc.energy()
