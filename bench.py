@@ -4,10 +4,15 @@ One step = one sweep (every site attempts one nearest-neighbour swap; Sec. V-A o
 paper): all colours (mini-steps) of trial proposal, gather, features, MLP energies, dE
 reduction, Metropolis decision with FP64 re-decision near the threshold, and apply.
 
-Default workload: BCC 256^3 cells (33,554,432 sites), 5 species equiatomic, 108-input
-one-hot MLP 108 -> 128 -> 128 -> 1 (SiLU), T = 600 K, synthetic seeded inputs.
+Workload: BCC 256^3 cells (33,554,432 sites), 5 species equiatomic, 108-input one-hot MLP
+108 -> 128 -> 128 -> 1 (SiLU), T = 600 K, synthetic seeded inputs (one GPU's share of the
+paper's 1.009e9-atom strong-scaling system; trained weights are not available).
 
-Prints one JSON line (rank 0).  --gpus N > 1 exits: this build measures one GPU.
+The headline `value` is the split-BF16 energy path (the low-precision path whose dE error
+stays below 1e-4 eV); FP32, plain BF16 and FP8 are measured in the same run and reported
+under "precisions" with their attempts/s, ratio to FP32, roofline fraction and error.
+
+Prints one JSON line.  --gpus N > 1 exits: this build measures one GPU.
 """
 from __future__ import annotations
 
@@ -22,61 +27,100 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FLOP_PER_EVAL = {108: 2 * (108 * 128 + 128 * 128 + 128), 12: 2 * (12 * 64 + 64 * 64 + 64)}
-OMEGA = {108: 40, 12: 22}
-PEAK = {  # MI355X published dense peaks
-    "fp32": (157.3e12, "mfma"), "bf16": (2.5e15, "mfma"), "bf16x3": (2.5e15, "mfma"),
-    "fp8": (5.0e15, "mfma"), "fp64": (78.6e12, "mfma"),
-}
-DTYPE = {"fp32": "f32", "bf16": "bf16", "bf16x3": "bf16", "fp8": "fp8-e4m3", "fp64": "f64"}
+# Algorithmic work of one local energy (dense 108 -> 128 -> 128 -> 1 MLP, Eqs. (4)-(6)).
+FLOP_PER_EVAL = 2 * (108 * 128 + 128 * 128 + 128)
+OMEGA = 40  # local energies evaluated per different-species trial (affected zone, shells 1-3)
+# Matrix-core work each precision executes per local energy (padding and split products).
+EXEC_FLOP_PER_EVAL = {"fp32": 2 * (112 * 128 + 128 * 128), "bf16": 2 * (112 * 128 + 128 * 128),
+                      "bf16x3": 2 * (2 * 112 * 128 + 3 * 128 * 128), "fp8": 2 * (128 * 128 + 128 * 128)}
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0, "fp8": 5000.0}
+DTYPE = {"fp32": "f32", "bf16": "bf16", "bf16x3": "bf16", "fp8": "fp8-e4m3"}
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_gpu(workload, precision, steps, warmup):
+def colour0_sites(cells, n):
+    """Trial sites of colour 0 (link-cell offset (0,0,0), basis 0) spread over the lattice."""
+    lx, ly, lz = cells
+    qx, qy, qz = lx // 4, ly // 4, lz // 4
+    t = np.linspace(0, qx * qy * qz - 1, n).astype(np.int64)
+    cx, cy, cz = t % qx, (t // qx) % qy, t // (qx * qy)
+    return (((4 * cz) * ly + 4 * cy) * lx + 4 * cx) * 2
+
+
+def measure(workload, precision, steps, warmup, err_samples):
     import torch
 
     import synth
     import paper_2604_08250_amd as smc
 
     w = synth.workload(workload)
-    occ = w.occupancy()
-    params = w.params()
-    log(f"workload {workload}: {sum(w.sites):,} sites, precision {precision}")
+    n_sites = sum(w.sites)
     stream = torch.cuda.current_stream()
-    mc = smc.SwapMC(w.cells, w.temperatures, occ, params, n_species=w.n_species, feature=w.feature,
-                    hidden=w.hidden, precision=precision, seed=w.seed, stream=stream)
+    t0 = time.perf_counter()
+    mc = smc.SwapMC(w.cells, w.temperatures, w.occupancy(), w.params(), n_species=w.n_species,
+                    feature=w.feature, hidden=w.hidden, precision=precision, seed=w.seed, stream=stream)
+    log(f"{precision}: context ready in {time.perf_counter() - t0:.1f} s")
     if warmup:
         mc.sweep(warmup)
     torch.cuda.synchronize()
     mc.counters(reset=True)
-    n_colours = sum(mc.n_colours(r) for r in range(mc.n_replicas))
+    # ---- timed region: `steps` sweeps, inputs resident in HBM
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
     start.record(stream)
-    for k in range(steps):
+    for _ in range(steps):
         mc.sweep(1)
     end.record(stream)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
     ms = start.elapsed_time(end)
-    cnt = mc.counters()
-    attempts = int(cnt[0].sum())
-    diff = int(cnt[1].sum())
-    accepts = int(cnt[2].sum())
-    rechecks = int(cnt[3].sum())
-    es, er = mc.energy()
-    mc.close()
-    n_sites = sum(w.sites)
+    cnt = mc.counters(reset=True)
+    attempts, diff, accepts, rechecks = (int(cnt[i].sum()) for i in range(4))
     assert attempts == n_sites * steps, (attempts, n_sites, steps)
-    launches = steps * n_colours
-    flop = diff * OMEGA[w.n_in] * FLOP_PER_EVAL[w.n_in]
-    return dict(w=w, ms=ms, wall=wall, attempts=attempts, diff=diff, accepts=accepts,
-                rechecks=rechecks, launches=launches, flop=flop, e_scratch=float(es.sum()),
-                e_running=float(er.sum()))
+    log(f"{precision}: {steps} sweeps in {ms:.1f} ms -> {attempts / ms * 1e3:.3e} attempts/s")
+    # ---- per-kernel timing of the dominant kernel (HIP events around each launch)
+    prof_sweeps = 2
+    mc.profile(True)
+    mc.sweep(prof_sweeps)
+    colour_ms, recheck_ms, launches = mc.kernel_times()
+    mc.profile(False)
+    pcnt = mc.counters(reset=True)
+    p_diff = int(pcnt[1].sum())
+    flop = p_diff * OMEGA * FLOP_PER_EVAL
+    exec_flop = p_diff * OMEGA * EXEC_FLOP_PER_EVAL[precision]
+    avg_launch_s = colour_ms / 1e3 / launches
+    # ---- dE error against the FP64 evaluator on trials of the next sweep's first colour
+    sites = colour0_sites(w.cells[0], err_samples)
+    _, dE64 = mc.delta_e64(sites)
+    tr = mc.sweep(1, stats=True, trace=True)
+    fast = tr["dE_fast"].cpu().numpy()[sites]
+    flags = tr["flags"].cpu().numpy()[sites]
+    d = (flags & 2) == 0
+    err = fast[d] - dE64[d]
+    # ---- local-energy and total-energy error of the precision's evaluator (final lattice)
+    e_p = mc.site_energies(precision).double()
+    e_64 = mc.site_energies("fp64")
+    de_site = (e_p - e_64).abs()
+    es, er = mc.energy()
+    out = {
+        "attempts_per_s": attempts / (ms / 1e3), "ms_per_sweep": ms / steps, "sweeps": steps,
+        "diff_species_fraction": diff / attempts, "accept_ratio": accepts / max(diff, 1),
+        "fp64_recheck_fraction": rechecks / max(diff, 1),
+        "colour_kernel_us": avg_launch_s * 1e6, "recheck_kernel_ms_per_sweep": recheck_ms / prof_sweeps,
+        "colour_launches": launches, "algorithmic_tflops": flop / (colour_ms / 1e3) / 1e12,
+        "executed_tflops": exec_flop / (colour_ms / 1e3) / 1e12,
+        "dE_err_max_eV": float(np.abs(err).max()), "dE_err_rms_eV": float(np.sqrt(np.mean(err ** 2))),
+        "dE_err_trials": int(d.sum()),
+        "site_energy_err_max_eV": float(de_site.max()), "site_energy_err_rms_eV": float(de_site.pow(2).mean().sqrt()),
+        "energy_per_atom_err_eV": float((e_p.sum() - e_64.sum()) / n_sites),
+        "running_minus_scratch_eV": float(er.sum() - es.sum()),
+    }
+    mc.close()
+    del mc
+    torch.cuda.empty_cache()
+    return w, out
 
 
 def cpu_baseline(workload, seconds=12.0):
@@ -93,7 +137,6 @@ def cpu_baseline(workload, seconds=12.0):
     model = oracle.MLP(w.feature, w.hidden, w.params())
     cores = len(os.sched_getaffinity(0))
     lx, ly, lz = cells
-    # colour 0 = link-cell offset (0,0,0), basis 0: cells (4a, 4b, 4c)
     sites = [(((4 * c) * ly + 4 * b) * lx + 4 * a) * 2 for c in range(lz // 4)
              for b in range(ly // 4) for a in range(lx // 4)]
     oracle.trial(cells, model, occ, w.temperatures[0], w.seed, 0, 0, sites[0])  # warm tables
@@ -107,17 +150,20 @@ def cpu_baseline(workload, seconds=12.0):
             done += len(batch)
     dt = time.perf_counter() - t0
     return {"value": done / dt, "unit": "attempts/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {done} trials of colour 0, sweep 0 of the {workload} lattice "
-                      f"({w.cells[0][0]}^3 cells), FP64 energies before and after each swap"}
+            "sample": f"first {done} trials of colour 0 of sweep 0 of the {cells[0]}^3-cell lattice "
+                      f"(FP64 energies of the 40-site zone before and after each swap)"}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c3")
-    ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--precision", default="bf16x3")
+    ap.add_argument("--others", default="fp32,bf16,fp8")
+    ap.add_argument("--other-steps", type=int, default=3)
+    ap.add_argument("--err-samples", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
@@ -125,12 +171,19 @@ def main():
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU slab "
               "decomposition is a design, not part of this build.", file=sys.stderr)
         sys.exit(2)
-    r = run_gpu(args.workload, args.precision, args.steps, args.warmup)
-    w = r["w"]
-    value = r["attempts"] / (r["ms"] / 1e3)
-    peak, bound = PEAK[args.precision]
-    avg_launch_s = (r["ms"] / 1e3) / r["launches"]
-    achieved = r["flop"] / r["launches"] / avg_launch_s
+    w, head = measure(args.workload, args.precision, args.steps, args.warmup, args.err_samples)
+    precs = {args.precision: head}
+    for p in [x for x in args.others.split(",") if x and x != args.precision]:
+        precs[p] = measure(args.workload, p, args.other_steps, 1, args.err_samples)[1]
+    fp32 = precs.get("fp32", {}).get("attempts_per_s")
+    for p, r in precs.items():
+        r["peak_tflops"] = PEAK_TFLOPS[p]
+        r["roofline_frac"] = r["algorithmic_tflops"] / PEAK_TFLOPS[p]
+        r["executed_frac"] = r["executed_tflops"] / PEAK_TFLOPS[p]
+        if fp32:
+            r["speedup_vs_fp32"] = r["attempts_per_s"] / fp32
+        r["dE_err_below_1e-4_eV"] = r["dE_err_max_eV"] < 1e-4
+    value = head["attempts_per_s"]
     out = {
         "metric": "MC swap attempts/s",
         "value": value,
@@ -138,23 +191,21 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": r["ms"] / args.steps,
+        "ms_per_step": head["ms_per_sweep"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": DTYPE[args.precision],
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: BCC {w.cells[0][0]}^3 cells, {sum(w.sites)} sites, "
-                               f"{w.n_species} species, {w.n_in}->{w.hidden}->{w.hidden}->1 SiLU MLP, "
-                               f"T={w.temperatures[0]} K",
+        "config": {"workload": f"BCC {w.cells[0][0]}^3 cells ({sum(w.sites)} sites), {w.n_species} species "
+                               f"equiatomic, one-hot {w.n_in}-{w.hidden}-{w.hidden}-1 SiLU MLP, "
+                               f"T = {w.temperatures[0]:g} K, {args.precision} energy path",
                    "precision": args.precision, "sites": sum(w.sites)},
-        "roofline": {"bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
-                     "kernel": "sweep colour kernel", "avg_launch_us": avg_launch_s * 1e6},
-        "accept_ratio": r["accepts"] / max(1, r["diff"]),
-        "diff_species_fraction": r["diff"] / r["attempts"],
-        "fp64_recheck_fraction": r["rechecks"] / max(1, r["diff"]),
-        "e_running_minus_scratch": r["e_running"] - r["e_scratch"],
+        "roofline": {"bound": "mfma", "achieved": head["algorithmic_tflops"], "peak": PEAK_TFLOPS[args.precision],
+                     "unit": "TFLOP/s", "frac": head["roofline_frac"], "traffic": None,
+                     "kernel": f"k_sweep_colour_mfma<{args.precision}>",
+                     "avg_launch_us": head["colour_kernel_us"], "executed_frac": head["executed_frac"]},
+        "precisions": precs,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)

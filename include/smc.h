@@ -124,6 +124,16 @@ int smc_energy(smc_ctx *ctx, double *e_scratch_host, double *e_running_host);
  * SMC_FP32/BF16/BF16X3/FP8_E4M3, double [N_total] for SMC_FP64.  Asynchronous. */
 int smc_site_energies(smc_ctx *ctx, int32_t precision, void *out_dev);
 
+/* Verification probe: the FP64 energy change of the swap that each listed trial site of
+ * `replica` proposes at global sweep `sweep` (its Philox partner), on the current occupancy,
+ * by the same FP64 evaluator that re-decides near-threshold trials (affected-zone energies
+ * after minus before, Algorithm 1's two reductions over Omega).  Nothing is changed.
+ * sites_host: n replica-local site indices; partner_host (nullable) and dE_host: host
+ * outputs [n].  Equal species give 0.  Needs one-hot features and 128 hidden units
+ * (else SMC_E_UNSUPPORTED).  Synchronises. */
+int smc_delta_e64(smc_ctx *ctx, int32_t replica, uint64_t sweep, const int64_t *sites_host, int32_t n,
+                  int64_t *partner_host, double *dE_host);
+
 /* Re-read params_dev (FP32 blob), re-pack the low-precision copies, refresh the energy
  * cache and reset the running energies to the FP64 total.  Asynchronous. */
 int smc_set_params(smc_ctx *ctx, const float *params_dev);
@@ -141,6 +151,13 @@ int smc_set_sweep(smc_ctx *ctx, uint64_t sweep);
  * different-species attempts, accepted swaps, FP64 re-decisions.  reset != 0 zeroes them
  * after reading.  Synchronises. */
 int smc_counters(smc_ctx *ctx, uint64_t *out_host, int32_t reset);
+
+/* Per-kernel timing with HIP events recorded around each launch on the context's stream.
+ * enable != 0 starts recording and clears the totals; enable == 0 stops.  smc_kernel_times
+ * returns the totals since the last enable: milliseconds inside colour (sweep) kernels and
+ * inside FP64 re-decision kernels, and the number of colour-kernel launches.  Synchronises. */
+int smc_profile(smc_ctx *ctx, int32_t enable);
+int smc_kernel_times(smc_ctx *ctx, double *colour_ms, double *recheck_ms, int64_t *colour_launches);
 
 /* Total sites over all replicas, and number of colours (mini-steps) of a replica. */
 int smc_n_sites(const smc_ctx *ctx, int64_t *n);

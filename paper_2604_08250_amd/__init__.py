@@ -9,7 +9,7 @@ import numpy as np
 
 from ._lib import (PRECISIONS, SMC_BF16, SMC_BF16X3, SMC_FEAT_COUNTS_S12, SMC_FEAT_ONEHOT_S123,
                    SMC_FP8_E4M3, SMC_FP32, SMC_FP64, SMCError, lib, smc_destroy, smc_energy,
-                   smc_counters, smc_get_sweep, smc_init, smc_n_colours, smc_n_sites, smc_refresh, smc_set_params,
+                   smc_counters, smc_delta_e64, smc_get_sweep, smc_init, smc_kernel_times, smc_profile, smc_n_colours, smc_n_sites, smc_refresh, smc_set_params,
                    smc_set_sweep, smc_site_energies, smc_sweep)
 
 __all__ = ["SwapMC", "SMCError", "PRECISIONS", "lib"]
@@ -70,6 +70,19 @@ class SwapMC:
 
     def energy(self):
         return smc_energy(self.ctx, self.n_replicas)
+
+    def profile(self, enable=True):
+        """Record HIP events around every colour / re-decision kernel launch."""
+        smc_profile(self.ctx, enable)
+
+    def kernel_times(self):
+        """(colour-kernel ms, re-decision-kernel ms, colour launches) since profile(True)."""
+        return smc_kernel_times(self.ctx)
+
+    def delta_e64(self, sites, sweep=None, replica=0):
+        """FP64 dE of the swaps the given trial sites propose at `sweep` (default: the next
+        sweep), on the current lattice; returns (partners, dE)."""
+        return smc_delta_e64(self.ctx, replica, self.sweep_index if sweep is None else sweep, sites)
 
     def site_energies(self, precision=None):
         torch = _torch()

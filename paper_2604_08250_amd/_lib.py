@@ -22,7 +22,7 @@ PRECISIONS = {"fp32": SMC_FP32, "bf16": SMC_BF16, "bf16x3": SMC_BF16X3, "fp8": S
               "fp64": SMC_FP64}
 
 EXPORTS = ["smc_init", "smc_sweep", "smc_energy", "smc_site_energies", "smc_set_params",
-           "smc_refresh", "smc_counters", "smc_get_sweep", "smc_set_sweep", "smc_n_sites", "smc_n_colours",
+           "smc_refresh", "smc_counters", "smc_delta_e64", "smc_profile", "smc_kernel_times", "smc_get_sweep", "smc_set_sweep", "smc_n_sites", "smc_n_colours",
            "smc_destroy", "smc_last_error", "smc_status_string"]
 
 
@@ -63,6 +63,11 @@ def lib():
             "smc_set_params": (C.c_int, [vp, vp]),
             "smc_refresh": (C.c_int, [vp]),
             "smc_counters": (C.c_int, [vp, C.POINTER(C.c_uint64), C.c_int32]),
+            "smc_delta_e64": (C.c_int, [vp, C.c_int32, C.c_uint64, C.POINTER(C.c_int64), C.c_int32,
+                                        C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
+            "smc_profile": (C.c_int, [vp, C.c_int32]),
+            "smc_kernel_times": (C.c_int, [vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                           C.POINTER(C.c_int64)]),
             "smc_get_sweep": (C.c_int, [vp, C.POINTER(C.c_uint64)]),
             "smc_set_sweep": (C.c_int, [vp, C.c_uint64]),
             "smc_n_sites": (C.c_int, [vp, C.POINTER(C.c_int64)]),
@@ -137,6 +142,26 @@ def smc_counters(ctx, n_replicas, reset=False):
     out = np.zeros((4, n_replicas), dtype=np.uint64)
     check(lib().smc_counters(ctx, out.ctypes.data_as(C.POINTER(C.c_uint64)), int(reset)), ctx)
     return out
+
+
+def smc_delta_e64(ctx, replica, sweep, sites):
+    sites = np.ascontiguousarray(np.asarray(sites, dtype=np.int64))
+    partner = np.zeros(sites.size, dtype=np.int64)
+    dE = np.zeros(sites.size, dtype=np.float64)
+    check(lib().smc_delta_e64(ctx, replica, sweep, sites.ctypes.data_as(C.POINTER(C.c_int64)), sites.size,
+                              partner.ctypes.data_as(C.POINTER(C.c_int64)),
+                              dE.ctypes.data_as(C.POINTER(C.c_double))), ctx)
+    return partner, dE
+
+
+def smc_profile(ctx, enable):
+    check(lib().smc_profile(ctx, int(bool(enable))), ctx)
+
+
+def smc_kernel_times(ctx):
+    a, b, n = C.c_double(), C.c_double(), C.c_int64()
+    check(lib().smc_kernel_times(ctx, C.byref(a), C.byref(b), C.byref(n)), ctx)
+    return a.value, b.value, n.value
 
 
 def smc_get_sweep(ctx) -> int:

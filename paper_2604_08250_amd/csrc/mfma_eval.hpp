@@ -67,9 +67,13 @@ __device__ __forceinline__ float act(float y, float s) {
   return y * __builtin_amdgcn_rcpf(fmaf(e, s, s));
 }
 
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// Two floats to two BF16 (round to nearest even) in one packed conversion.
 __device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
-  const __bf16 x = (__bf16)a, y = (__bf16)b;
-  return (uint32_t)__builtin_bit_cast(uint16_t, x) | ((uint32_t)__builtin_bit_cast(uint16_t, y) << 16);
+  const f32x2 v = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
 }
 
 __device__ __forceinline__ float bf16_lo_f32(uint32_t w) { return __builtin_bit_cast(float, w << 16); }
@@ -103,14 +107,22 @@ __device__ __forceinline__ float eval_tile(const EvalSmem &S, GetSlot get) {
   const int lane = threadIdx.x & 63;
   const int g = lane >> 5;
   f32x16 acc[kMT];
-  // bias initialisation: register v of M-tile T holds hidden 32T + 8(v/4) + 4g + v%4
+  // Layer-0 bias.  FP32/BF16: a weight column fed by a constant-one input in the padding
+  // slot 27 (feature 108), so it rides on the matrix cores.  FP8: accumulator
+  // initialisation (register v of M-tile T holds hidden 32T + 8(v/4) + 4g + v%4), keeping
+  // the bias out of the 3-bit mantissa.
 #pragma unroll
   for (int T = 0; T < kMT; ++T)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const f32x4 b = *(const f32x4 *)(S.c0 + 32 * T + 8 * j + 4 * g);
+      if constexpr (P == kPFP8) {
+        const f32x4 b = *(const f32x4 *)(S.c0 + 32 * T + 8 * j + 4 * g);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) acc[T][4 * j + i] = b[i];
+        for (int i = 0; i < 4; ++i) acc[T][4 * j + i] = b[i];
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[T][4 * j + i] = 0.0f;
+      }
     }
 
   // ---------------------------------------------------------------- layer 0
@@ -120,7 +132,7 @@ __device__ __forceinline__ float eval_tile(const EvalSmem &S, GetSlot get) {
     const f32x4 *A = (const f32x4 *)S.w;
 #pragma unroll
     for (int m = 0; m < 28; ++m) {
-      const uint32_t p = m < 27 ? (uint32_t)get(m) : 7u;
+      const uint32_t p = m < 27 ? (uint32_t)get(m) : 0u;  // slot 27: constant one (bias)
       const float b0 = (p == (uint32_t)g) ? 1.0f : 0.0f;
       const float b1 = (p == (uint32_t)(2 + g)) ? 1.0f : 0.0f;
 #pragma unroll
@@ -140,7 +152,7 @@ __device__ __forceinline__ float eval_tile(const EvalSmem &S, GetSlot get) {
     for (int s = 0; s < 7; ++s) {
       const int m0 = 4 * s + 2 * g;
       const uint32_t p0 = (uint32_t)get(m0);
-      const uint32_t p1 = (m0 + 1 < 27) ? (uint32_t)get(m0 + 1) : 7u;
+      const uint32_t p1 = (m0 + 1 < 27) ? (uint32_t)get(m0 + 1) : 0u;  // slot 27: bias input
       i32x4 bw;
       uint32_t l0, h0, l1, h1;
       onehot_bf16(p0, l0, h0);

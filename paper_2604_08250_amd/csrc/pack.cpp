@@ -89,7 +89,9 @@ PackedModel pack_model(int P, const float *p) {
     w2s[h] = -kLn2 * W2[h];
   }
   out.b2 = b2[0];
-  auto w0 = [&](int h, int f) { return f < kF ? W0s[h * kF + f] : 0.0f; };
+  // feature 108 (padding slot 27, constant-one input) carries the bias except in FP8, where
+  // the bias initialises the accumulators instead
+  auto w0 = [&](int h, int f) { return f < kF ? W0s[h * kF + f] : (f == kF && P != 3 ? c0[h] : 0.0f); };
   auto w1 = [&](int o, int k) { return W1[o * kH + k]; };
   const int total = kL0[P] + kL1[P] + 3 * kH * 4 + 16;
   out.bytes.assign(total, 0);
@@ -184,7 +186,7 @@ RegionTables build_region_tables() {
   t.idx.assign(8 * kOmegaOneHot * 28, 0);
   t.reg_pos.assign(16, 0);
   using V = std::array<int, 3>;
-  auto pack = [](const V &v) { return (v[0] + 16) | ((v[1] + 16) << 8) | ((v[2] + 16) << 16); };
+  auto pack = [](const V &v) { return (uint16_t)((v[0] + 8) | ((v[1] + 8) << 4) | ((v[2] + 8) << 8)); };
   std::vector<V> slot = {{0, 0, 0}};
   for (int k = 0; k < kNbr; ++k) slot.push_back({shell_dx(k), shell_dy(k), shell_dz(k)});
   for (int d = 0; d < 8; ++d) {

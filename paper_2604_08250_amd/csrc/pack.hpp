@@ -24,13 +24,13 @@ float e4m3_to_f32(uint8_t v);
 
 // Sites read by one trial (one-hot features, shells 1-3): the affected zone Omega of the
 // swap with partner slot d plus every neighbour of Omega.  Offsets are doubled coordinates
-// packed as (dx+16) | (dy+16) << 8 | (dz+16) << 16.
+// in [-5, 5] packed as (dx+8) | (dy+8) << 4 | (dz+8) << 8.
 constexpr int kRegion = 192;
 constexpr int kOmegaOneHot = 40;
 constexpr int kSlotsOneHot = 27;
 struct RegionTables {
-  std::vector<int32_t> reg_off;  // [8][192]
-  std::vector<int32_t> om_off;   // [8][40]
+  std::vector<uint16_t> reg_off;  // [8][192]
+  std::vector<uint16_t> om_off;   // [8][40]
   std::vector<uint8_t> idx;      // [8][40][28]: region position of slot m of Omega site k
   std::vector<uint8_t> reg_pos;  // [8][2]: region position of the trial site and of the partner
 };

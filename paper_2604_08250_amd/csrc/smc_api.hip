@@ -7,7 +7,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/smc.h"
+#include "smc.h"
 #include "pack.hpp"
 #include "sweep_mfma.hpp"
 #include "sweep_scalar.hpp"
@@ -42,12 +42,15 @@ struct smc_ctx {
   Replica *d_reps = nullptr;
   float *d_w32 = nullptr;
   double *d_w64 = nullptr;
+  double *d_w64t = nullptr;       // FP64 blob with W0, W1 stored [input][unit] (re-decision kernel)
   int8_t *d_omega = nullptr;      // per-lane path Omega offsets
   int32_t omega_n = 0;
-  int32_t *d_reg_off = nullptr, *d_om_off = nullptr;
+  uint16_t *d_reg_off = nullptr, *d_om_off = nullptr;
   uint8_t *d_idx = nullptr, *d_reg_pos = nullptr;
   DevPack packs[4];
   RecheckEntry *d_queue = nullptr;
+  double *d_rowe = nullptr;       // [queue_cap][80] FP64 local energies of queued trials
+  uint32_t *d_done = nullptr;     // [queue_cap] per-entry completion counters
   uint32_t *d_qcount = nullptr;   // one counter per colour of a sweep
   int64_t queue_cap = 0;
   int32_t colours_total = 0;
@@ -58,6 +61,11 @@ struct smc_ctx {
   double *d_site64 = nullptr;     // [N] FP64 site energies (lazy)
   uint64_t sweep = 0;
   double guard = 0.0;
+  // per-kernel timing: event pairs recorded around launches while profiling is on
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool;         // 2 per recorded launch
+  std::vector<int> ev_kind;                // 0 colour kernel, 1 re-decision kernel
+  size_t ev_used = 0;
   std::string err;
 };
 
@@ -88,6 +96,32 @@ double default_guard(int prec) {
 }
 
 unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
+
+// Start event of a timed launch (index of the pair), or -1 when not profiling.
+int prof_begin(smc_ctx *c) {
+  if (!c->profiling) return -1;
+  const size_t k = c->ev_used;
+  if (2 * k + 2 > c->ev_pool.size()) {
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return -1;
+    if (hipEventCreate(&e1) != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      return -1;
+    }
+    c->ev_pool.push_back(e0);
+    c->ev_pool.push_back(e1);
+    c->ev_kind.push_back(0);
+  }
+  if (hipEventRecord(c->ev_pool[2 * k], c->stream) != hipSuccess) return -1;
+  c->ev_used++;
+  return (int)k;
+}
+
+void prof_end(smc_ctx *c, int k, int kind) {
+  if (k < 0) return;
+  c->ev_kind[k] = kind;
+  (void)hipEventRecord(c->ev_pool[2 * k + 1], c->stream);
+}
 
 template <int FEAT, int H, typename T>
 void launch_site_energies(smc_ctx *c, const T *W, T *out) {
@@ -188,6 +222,22 @@ int load_params(smc_ctx *c, const float *params_dev) {
   HIPC(c, hipMemcpyAsync(c->host_params.data(), params_dev, sizeof(float) * P, hipMemcpyDeviceToHost, c->stream));
   HIPC(c, hipStreamSynchronize(c->stream));
   for (int k = 0; k < 4; ++k) c->packs[k].ready = false;
+  if (c->mfma) {
+    // [input][unit] FP64 copy: consecutive threads of the re-decision kernel own consecutive
+    // hidden units, so their weight loads are contiguous
+    const int H = c->hidden, F = c->n_in;
+    const float *p = c->host_params.data();
+    std::vector<double> t(P);
+    for (int o = 0; o < H; ++o)
+      for (int f = 0; f < F; ++f) t[(size_t)f * H + o] = p[(size_t)o * F + f];
+    const size_t b0 = (size_t)H * F, w1 = b0 + H;
+    for (int o = 0; o < H; ++o) t[b0 + o] = p[b0 + o];
+    for (int o = 0; o < H; ++o)
+      for (int k = 0; k < H; ++k) t[w1 + (size_t)k * H + o] = p[w1 + (size_t)o * H + k];
+    for (size_t q = w1 + (size_t)H * H; q < (size_t)P; ++q) t[q] = p[q];
+    HIPC(c, hipMemcpyAsync(c->d_w64t, t.data(), sizeof(double) * P, hipMemcpyHostToDevice, c->stream));
+    HIPC(c, hipStreamSynchronize(c->stream));
+  }
   hipLaunchKernelGGL(k_copy_f32, dim3(grid_for(P, 256)), dim3(256), 0, c->stream, params_dev, c->d_w32, P);
   hipLaunchKernelGGL(k_widen, dim3(grid_for(P, 256)), dim3(256), 0, c->stream, params_dev, c->d_w64, P);
   HIPC(c, hipGetLastError());
@@ -210,8 +260,14 @@ void launch_colour_mfma(smc_ctx *c, const MfmaArgs &a) {
 int run_sweep(smc_ctx *c, const smc_stats *st, bool last) {
   const int R = (int)c->reps.size();
   const bool trace = last && st;
-  if (c->mfma && c->cfg.precision != SMC_FP64) {
-    const DevPack &dp = c->packs[c->cfg.precision];
+  if (c->mfma) {
+    // FP64 reference mode: the FP32 matrix-core pass only proposes; every different-species
+    // trial is queued and decided by the FP64 evaluator
+    const bool fp64 = c->cfg.precision == SMC_FP64;
+    const int P = fp64 ? SMC_FP32 : c->cfg.precision;
+    int rc = ensure_pack(c, P);
+    if (rc) return rc;
+    const DevPack &dp = c->packs[P];
     const int64_t qwords = (c->colours_total + 1) / 2;
     hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(qwords, 256)), dim3(256), 0, c->stream,
                        (uint64_t *)c->d_qcount, qwords, (uint64_t)0);
@@ -237,7 +293,7 @@ int run_sweep(smc_ctx *c, const smc_stats *st, bool last) {
         a.colour = col;
         a.seed = c->cfg.seed;
         a.sweep = c->sweep;
-        a.guard = c->guard;
+        a.guard = fp64 ? (double)INFINITY : c->guard;
         a.q_count = c->d_qcount + qoff;
         a.queue = c->d_queue;
         a.e_fixed = c->d_efixed;
@@ -249,29 +305,39 @@ int run_sweep(smc_ctx *c, const smc_stats *st, bool last) {
           a.trace_dE_fast = st->trace_dE_fast;
           a.trace_flags = st->trace_flags;
         }
-        switch (c->cfg.precision) {
+        const int ev = prof_begin(c);
+        switch (P) {
           case SMC_FP32: launch_colour_mfma<kP32>(c, a); break;
           case SMC_BF16: launch_colour_mfma<kPBF16>(c, a); break;
           case SMC_BF16X3: launch_colour_mfma<kPBF16X3>(c, a); break;
           default: launch_colour_mfma<kPFP8>(c, a); break;
         }
+        prof_end(c, ev, 0);
         RecheckArgs ra{};
         ra.reps = c->d_reps;
         ra.occ = c->occ;
         ra.ecache = c->ecache;
-        ra.w64 = c->d_w64;
+        ra.w64 = c->d_w64t;
+        ra.reg_off = c->d_reg_off;
         ra.om_off = c->d_om_off;
+        ra.idx = c->d_idx;
+        ra.reg_pos = c->d_reg_pos;
         ra.q_count = c->d_qcount + qoff;
         ra.queue = c->d_queue;
         ra.e_fixed = c->d_efixed;
         ra.counters = c->d_counters;
         ra.n_replicas = R;
+        ra.row_e = c->d_rowe;
+        ra.done = c->d_done;
         if (trace) {
           ra.trace_dE = st->trace_dE;
           ra.trace_flags = st->trace_flags;
         }
-        const int rgrid = (int)std::min<int64_t>(2 * c->n_cu, std::max<int64_t>(1, rep.n_trials));
-        hipLaunchKernelGGL(k_recheck, dim3(rgrid), dim3(128), 0, c->stream, ra);
+        const int rgrid =
+            (int)std::min<int64_t>(8 * c->n_cu, kRcSplit * std::max<int64_t>(1, rep.n_trials));
+        const int ev2 = prof_begin(c);
+        hipLaunchKernelGGL(k_recheck, dim3(rgrid), dim3(kRcThreads), 0, c->stream, ra);
+        prof_end(c, ev2, 1);
       }
     }
   } else {
@@ -301,10 +367,12 @@ int run_sweep(smc_ctx *c, const smc_stats *st, bool last) {
           a.trace_flags = st->trace_flags;
         }
         const bool onehot = c->cfg.feature == SMC_FEAT_ONEHOT_S123;
+        const int ev = prof_begin(c);
         if (!onehot && c->hidden == 64) launch_colour_scalar<0, 64>(c, a, rep.n_trials);
         else if (!onehot) launch_colour_scalar<0, 128>(c, a, rep.n_trials);
         else if (c->hidden == 64) launch_colour_scalar<1, 64>(c, a, rep.n_trials);
         else launch_colour_scalar<1, 128>(c, a, rep.n_trials);
+        prof_end(c, ev, 0);
       }
     }
   }
@@ -394,6 +462,7 @@ int smc_init(const smc_config *cfg, uint8_t *occ_dev, const float *params_dev, f
   INIT_HIP(hipMalloc(&c->d_reps, sizeof(Replica) * R));
   INIT_HIP(hipMalloc(&c->d_w32, sizeof(float) * c->n_params));
   INIT_HIP(hipMalloc(&c->d_w64, sizeof(double) * c->n_params));
+  INIT_HIP(hipMalloc(&c->d_w64t, sizeof(double) * c->n_params));
   INIT_HIP(hipMalloc(&c->d_omega, sizeof(om.off)));
   INIT_HIP(hipMalloc(&c->d_ebase, sizeof(double) * R));
   INIT_HIP(hipMalloc(&c->d_efixed, sizeof(unsigned long long) * R));
@@ -406,14 +475,17 @@ int smc_init(const smc_config *cfg, uint8_t *occ_dev, const float *params_dev, f
     const RegionTables t = build_region_tables();
     if (t.reg_off.empty()) return cleanup(SMC_E_DEVICE);
     c->queue_cap = max_trials;
-    INIT_HIP(hipMalloc(&c->d_reg_off, sizeof(int32_t) * t.reg_off.size()));
-    INIT_HIP(hipMalloc(&c->d_om_off, sizeof(int32_t) * t.om_off.size()));
+    INIT_HIP(hipMalloc(&c->d_reg_off, sizeof(uint16_t) * t.reg_off.size()));
+    INIT_HIP(hipMalloc(&c->d_om_off, sizeof(uint16_t) * t.om_off.size()));
     INIT_HIP(hipMalloc(&c->d_idx, t.idx.size()));
     INIT_HIP(hipMalloc(&c->d_reg_pos, t.reg_pos.size()));
     INIT_HIP(hipMalloc(&c->d_queue, sizeof(RecheckEntry) * c->queue_cap));
+    INIT_HIP(hipMalloc(&c->d_rowe, sizeof(double) * kRows64 * c->queue_cap));
+    INIT_HIP(hipMalloc(&c->d_done, sizeof(uint32_t) * c->queue_cap));
+    INIT_HIP(hipMemset(c->d_done, 0, sizeof(uint32_t) * c->queue_cap));
     INIT_HIP(hipMalloc(&c->d_qcount, sizeof(uint32_t) * (c->colours_total + 2)));
-    if (hipMemcpy(c->d_reg_off, t.reg_off.data(), sizeof(int32_t) * t.reg_off.size(), hipMemcpyHostToDevice) ||
-        hipMemcpy(c->d_om_off, t.om_off.data(), sizeof(int32_t) * t.om_off.size(), hipMemcpyHostToDevice) ||
+    if (hipMemcpy(c->d_reg_off, t.reg_off.data(), sizeof(uint16_t) * t.reg_off.size(), hipMemcpyHostToDevice) ||
+        hipMemcpy(c->d_om_off, t.om_off.data(), sizeof(uint16_t) * t.om_off.size(), hipMemcpyHostToDevice) ||
         hipMemcpy(c->d_idx, t.idx.data(), t.idx.size(), hipMemcpyHostToDevice) ||
         hipMemcpy(c->d_reg_pos, t.reg_pos.data(), t.reg_pos.size(), hipMemcpyHostToDevice))
       return cleanup(SMC_E_DEVICE);
@@ -489,6 +561,71 @@ int smc_site_energies(smc_ctx *c, int32_t precision, void *out_dev) {
   return site_energies_fast(c, precision, (float *)out_dev);
 }
 
+int smc_delta_e64(smc_ctx *c, int32_t replica, uint64_t sweep, const int64_t *sites, int32_t n,
+                  int64_t *partner_out, double *dE_out) {
+  if (!c || !sites || n < 0 || replica < 0 || replica >= (int32_t)c->reps.size()) return SMC_E_INVALID;
+  if (!c->mfma) return fail(c, SMC_E_UNSUPPORTED, "FP64 probe needs one-hot features and 128 hidden");
+  if (n == 0) return SMC_OK;
+  const Replica &R = c->reps[replica];
+  std::vector<RecheckEntry> h(n);
+  for (int32_t k = 0; k < n; ++k) {
+    if (sites[k] < 0 || sites[k] >= R.n_sites) return fail(c, SMC_E_INVALID, "site out of range");
+    const U64x4 r = philox4x64_10((uint64_t)sites[k], sweep, (uint64_t)replica, 0, c->cfg.seed, 0);
+    const int d = (int)(r.v[0] >> 61);
+    const Pos p = site_pos(sites[k], R.L[0], R.L[1]);
+    RecheckEntry e{};
+    e.site = sites[k];
+    e.partner = site_at(p, shell_dx(d), shell_dy(d), shell_dz(d), R.L[0], R.L[1], R.L[2]);
+    e.replica = replica;
+    e.dir = d;
+    h[k] = e;
+    if (partner_out) partner_out[k] = e.partner;
+  }
+  RecheckEntry *d_e = nullptr;
+  double *d_out = nullptr, *d_rowe = nullptr;
+  uint32_t *d_n = nullptr, *d_done = nullptr;
+  const uint32_t nn = (uint32_t)n;
+  int rc = SMC_OK;
+  if (hipMalloc(&d_e, sizeof(RecheckEntry) * n) || hipMalloc(&d_out, sizeof(double) * n) ||
+      hipMalloc(&d_n, sizeof(uint32_t)) || hipMalloc(&d_rowe, sizeof(double) * kRows64 * n) ||
+      hipMalloc(&d_done, sizeof(uint32_t) * n))
+    rc = fail(c, SMC_E_NOMEM, "probe buffers");
+  if (!rc && (hipMemcpyAsync(d_e, h.data(), sizeof(RecheckEntry) * n, hipMemcpyHostToDevice, c->stream) ||
+              hipMemcpyAsync(d_n, &nn, sizeof(uint32_t), hipMemcpyHostToDevice, c->stream) ||
+              hipMemsetAsync(d_done, 0, sizeof(uint32_t) * n, c->stream)))
+    rc = fail(c, SMC_E_DEVICE, "probe upload");
+  if (!rc) {
+    RecheckArgs ra{};
+    ra.reps = c->d_reps;
+    ra.occ = c->occ;
+    ra.ecache = c->ecache;
+    ra.w64 = c->d_w64t;
+    ra.reg_off = c->d_reg_off;
+    ra.om_off = c->d_om_off;
+    ra.idx = c->d_idx;
+    ra.reg_pos = c->d_reg_pos;
+    ra.q_count = d_n;
+    ra.queue = d_e;
+    ra.e_fixed = c->d_efixed;
+    ra.counters = c->d_counters;
+    ra.n_replicas = (int32_t)c->reps.size();
+    ra.probe_dE = d_out;
+    ra.row_e = d_rowe;
+    ra.done = d_done;
+    hipLaunchKernelGGL(k_recheck, dim3(std::min(kRcSplit * n, 8 * c->n_cu)), dim3(kRcThreads), 0, c->stream, ra);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(dE_out, d_out, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream) ||
+        hipStreamSynchronize(c->stream))
+      rc = fail(c, SMC_E_DEVICE, "probe kernel");
+  }
+  (void)hipFree(d_e);
+  (void)hipFree(d_out);
+  (void)hipFree(d_rowe);
+  (void)hipFree(d_done);
+  (void)hipFree(d_n);
+  return rc;
+}
+
 int smc_set_params(smc_ctx *c, const float *params_dev) {
   if (!c || !params_dev) return SMC_E_INVALID;
   int rc = load_params(c, params_dev);
@@ -498,6 +635,31 @@ int smc_set_params(smc_ctx *c, const float *params_dev) {
 int smc_refresh(smc_ctx *c) {
   if (!c) return SMC_E_INVALID;
   return refresh(c);
+}
+
+int smc_profile(smc_ctx *c, int32_t enable) {
+  if (!c) return SMC_E_INVALID;
+  HIPC(c, hipStreamSynchronize(c->stream));
+  c->profiling = enable != 0;
+  if (enable) c->ev_used = 0;
+  return SMC_OK;
+}
+
+int smc_kernel_times(smc_ctx *c, double *colour_ms, double *recheck_ms, int64_t *colour_launches) {
+  if (!c) return SMC_E_INVALID;
+  HIPC(c, hipStreamSynchronize(c->stream));
+  double t[2] = {0.0, 0.0};
+  int64_t n0 = 0;
+  for (size_t k = 0; k < c->ev_used; ++k) {
+    float ms = 0.0f;
+    HIPC(c, hipEventElapsedTime(&ms, c->ev_pool[2 * k], c->ev_pool[2 * k + 1]));
+    t[c->ev_kind[k]] += ms;
+    if (c->ev_kind[k] == 0) ++n0;
+  }
+  if (colour_ms) *colour_ms = t[0];
+  if (recheck_ms) *recheck_ms = t[1];
+  if (colour_launches) *colour_launches = n0;
+  return SMC_OK;
 }
 
 int smc_get_sweep(const smc_ctx *c, uint64_t *s) {
@@ -528,12 +690,13 @@ void smc_destroy(smc_ctx *c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
-  void *bufs[] = {c->d_reps, c->d_w32, c->d_w64, c->d_omega, c->d_reg_off, c->d_om_off, c->d_idx,
-                  c->d_reg_pos, c->d_queue, c->d_qcount, c->d_ebase, c->d_efixed, c->d_escratch,
+  void *bufs[] = {c->d_reps, c->d_w32, c->d_w64, c->d_w64t, c->d_omega, c->d_reg_off, c->d_om_off, c->d_idx,
+                  c->d_reg_pos, c->d_queue, c->d_rowe, c->d_done, c->d_qcount, c->d_ebase, c->d_efixed, c->d_escratch,
                   c->d_counters, c->d_site64, c->packs[0].dev, c->packs[1].dev, c->packs[2].dev,
                   c->packs[3].dev};
   for (void *p : bufs)
     if (p) (void)hipFree(p);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;
 }
 

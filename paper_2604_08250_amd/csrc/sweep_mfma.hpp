@@ -1,18 +1,21 @@
 // Swap kernels of the matrix-core path (one-hot features over shells 1-3, 128 hidden).
 //
 // One launch per colour (mini-step).  A persistent block of 512 threads keeps the packed
-// weights and the slot->region table in LDS and walks groups of 32 link cells:
-//   1. proposal: Philox block per trial, partner, species, threshold theta (FP64);
-//      same-species trials are finished here; the others are compacted;
-//   2. gather: the 192 sites read by each trial (the affected zone and its neighbours) are
-//      loaded into LDS with the two swapped species exchanged, and the cached energies of
-//      the 40 affected sites;
-//   3. energy: the post-swap local energies of all affected sites of the group, 32 sites per
-//      matrix-core tile (mfma_eval.hpp);
-//   4. decide: dE = sum over the zone of (new - cached) in a fixed order; trials with
-//      |dE - theta| below the guard band go to a queue re-decided in FP64, the others are
+// weights and the lookup tables in LDS and walks groups of 32 link cells as a pipeline:
+//   proposal (group g+2): Philox block per trial, partner, species, threshold theta (FP64);
+//      same-species trials are finished here, the others compacted;
+//   gather (group g+1, issued before the energies of group g and consumed after them): the
+//      192 sites read by each trial (its affected zone Omega and their neighbours) and the
+//      cached energies of the 40 zone sites, into registers, then into LDS with the two
+//      swapped species exchanged;
+//   energy (group g): the post-swap local energies of every zone site, 32 sites per
+//      matrix-core tile (mfma_eval.hpp), tiles claimed dynamically by the eight waves;
+//   decide (group g): dE = sum over the zone of (new - cached) in a fixed order; trials with
+//      |dE - theta| inside the guard band go to a queue re-decided in FP64, the others are
 //      accepted iff dE <= theta;
-//   5. apply: accepted swaps write the two species and the new energies of their zone.
+//   apply (group g): accepted swaps write the two species and the new zone energies.
+// Trials of one colour never read what another trial of the colour writes (link cells of
+// at least four cells), so reads may run ahead of writes across groups.
 #pragma once
 #include "mfma_eval.hpp"
 #include "sweep_scalar.hpp"
@@ -24,6 +27,9 @@ constexpr int kMfmaThreads = 512;
 constexpr int kReg = 192;
 constexpr int kOm = 40;
 constexpr int kIdxRow = 28;
+constexpr int kPfReg = (kGroup * kReg + kMfmaThreads - 1) / kMfmaThreads;  // 12 region bytes per thread
+constexpr int kPfOm = (kGroup * kOm + kMfmaThreads - 1) / kMfmaThreads;    // 3 cached energies per thread
+constexpr int kPart = 8;                                                    // dE partial sums per trial
 
 struct RecheckEntry {
   int64_t site;      // replica-local trial site
@@ -40,8 +46,8 @@ struct MfmaArgs {
   uint8_t *occ;
   float *ecache;
   const uint8_t *wpack;     // pack_bytes<P>() bytes
-  const int32_t *reg_off;   // [8][192]
-  const int32_t *om_off;    // [8][40]
+  const uint16_t *reg_off;  // [8][192]
+  const uint16_t *om_off;   // [8][40]
   const uint8_t *idx;       // [8][40][28]
   const uint8_t *reg_pos;   // [8][2]
   float b2;
@@ -61,34 +67,46 @@ struct MfmaArgs {
   uint8_t *trace_flags;
 };
 
-__device__ __forceinline__ void unpack_off(int32_t v, int &dx, int &dy, int &dz) {
-  dx = (v & 0xff) - 16;
-  dy = ((v >> 8) & 0xff) - 16;
-  dz = ((v >> 16) & 0xff) - 16;
+__device__ __forceinline__ void unpack_off(uint32_t v, int &dx, int &dy, int &dz) {
+  dx = (int)(v & 15u) - 8;
+  dy = (int)((v >> 4) & 15u) - 8;
+  dz = (int)((v >> 8) & 15u) - 8;
 }
+
+// Per-trial data of one group (three groups in flight).
+struct TrialBuf {
+  int32_t site[kGroup], part[kGroup], px[kGroup], py[kGroup], pz[kGroup];
+  double theta[kGroup];
+  uint8_t dir[kGroup], si[kGroup], sn[kGroup];
+  int32_t nact;
+};
 
 template <int P>
 __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) {
   constexpr int kW = pack_bytes<P>();
   __shared__ __attribute__((aligned(16))) uint8_t s_w[kW];
   __shared__ __attribute__((aligned(16))) uint8_t s_idx[8 * kOm * kIdxRow];
+  __shared__ uint16_t s_roff[8 * kReg];
+  __shared__ uint16_t s_ooff[8 * kOm];
+  __shared__ uint8_t s_rpos[16];
   __shared__ uint8_t s_reg[kGroup * kReg];
   __shared__ float s_e[kGroup * kOm];
   __shared__ float s_ec[kGroup * kOm];
-  __shared__ int32_t s_site[kGroup], s_part[kGroup], s_px[kGroup], s_py[kGroup], s_pz[kGroup];
-  __shared__ double s_theta[kGroup];
-  __shared__ uint8_t s_dir[kGroup], s_si[kGroup], s_sn[kGroup], s_acc[kGroup];
-  __shared__ int s_nact;
+  __shared__ float s_psum[kGroup * kPart];
+  __shared__ TrialBuf s_tb[3];
+  __shared__ uint8_t s_acc[kGroup];
+  __shared__ int s_tile;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const Replica R = a.reps[a.replica];
   uint8_t *occ = a.occ + R.site0;
   float *ec = a.ecache + R.site0;
 
-  // weights and slot table into LDS, once per block
   for (int q = tid; q < kW / 16; q += kMfmaThreads) ((int4 *)s_w)[q] = ((const int4 *)a.wpack)[q];
   for (int q = tid; q < 8 * kOm * kIdxRow / 4; q += kMfmaThreads) ((int *)s_idx)[q] = ((const int *)a.idx)[q];
-  __syncthreads();
+  for (int q = tid; q < 8 * kReg; q += kMfmaThreads) s_roff[q] = a.reg_off[q];
+  for (int q = tid; q < 8 * kOm; q += kMfmaThreads) s_ooff[q] = a.om_off[q];
+  if (tid < 16) s_rpos[tid] = a.reg_pos[tid];
   EvalSmem S;
   S.w = s_w;
   S.c0 = (const float *)(s_w + PackSize<P>::kL0 + PackSize<P>::kL1);
@@ -113,118 +131,179 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
   uint32_t cnt_att = 0, cnt_diff = 0, cnt_acc = 0;
   long long fixed_sum = 0;
 
-  for (int grp = gstart; grp < gend; grp += gstep) {
-    // ------------------------------------------------------------ 1. proposal
-    if (wave == 0) {
-      const int64_t t = (int64_t)grp * kGroup + lane;
-      const int64_t i = (lane < kGroup && t < R.n_trials) ? trial_site(R, a.colour, t) : -1;
-      bool active = false;
-      int d = 0;
-      double theta = 0.0;
-      Pos pi{0, 0, 0};
-      int64_t n = 0;
-      uint8_t si = 0, sn = 0;
-      if (i >= 0) {
-        const U64x4 r = philox4x64_10((uint64_t)i, a.sweep, (uint64_t)a.replica, 0, a.seed, 0);
-        d = (int)(r.v[0] >> 61);
-        const double u = (double)((r.v[1] >> 11) + 1) * 0x1.0p-53;
-        theta = isinf(R.temperature) ? (double)INFINITY : -kBoltzmannEvPerK * R.temperature * log(u);
-        pi = site_pos(i, R.L[0], R.L[1]);
-        n = site_at(pi, shell_dx(d), shell_dy(d), shell_dz(d), R.L[0], R.L[1], R.L[2]);
-        si = occ[i];
-        sn = occ[n];
-        active = si != sn;
-        if (!active) {
-          if (a.trace_flags) a.trace_flags[R.site0 + i] = kFlagSame;
-          if (a.trace_dE) a.trace_dE[R.site0 + i] = 0.0;
-          if (a.trace_dE_fast) a.trace_dE_fast[R.site0 + i] = 0.0;
-        }
-      }
-      const unsigned long long valid = __ballot(i >= 0);
-      const unsigned long long act_mask = __ballot(active);
-      const int ca = __popcll(act_mask & ((1ull << lane) - 1ull));
-      if (active) {
-        s_site[ca] = (int32_t)i;
-        s_part[ca] = (int32_t)n;
-        s_px[ca] = pi.x;
-        s_py[ca] = pi.y;
-        s_pz[ca] = pi.z;
-        s_theta[ca] = theta;
-        s_dir[ca] = (uint8_t)d;
-        s_si[ca] = si;
-        s_sn[ca] = sn;
-      }
-      if (lane == 0) {
-        s_nact = __popcll(act_mask);
-        cnt_att += __popcll(valid);
-        cnt_diff += __popcll(act_mask);
+  // proposal for one group into a trial buffer (wave 0)
+  auto propose = [&](int grp, TrialBuf &tb) {
+    const int64_t t = (int64_t)grp * kGroup + lane;
+    const int64_t i = (grp < gend && lane < kGroup && t < R.n_trials) ? trial_site(R, a.colour, t) : -1;
+    bool active = false;
+    int d = 0;
+    double theta = 0.0;
+    Pos pi{0, 0, 0};
+    int64_t n = 0;
+    uint8_t si = 0, sn = 0;
+    if (i >= 0) {
+      const U64x4 r = philox4x64_10((uint64_t)i, a.sweep, (uint64_t)a.replica, 0, a.seed, 0);
+      d = (int)(r.v[0] >> 61);
+      const double u = (double)((r.v[1] >> 11) + 1) * 0x1.0p-53;
+      theta = isinf(R.temperature) ? (double)INFINITY : -kBoltzmannEvPerK * R.temperature * log(u);
+      pi = site_pos(i, R.L[0], R.L[1]);
+      n = site_at(pi, shell_dx(d), shell_dy(d), shell_dz(d), R.L[0], R.L[1], R.L[2]);
+      si = occ[i];
+      sn = occ[n];
+      active = si != sn;
+      if (!active) {
+        if (a.trace_flags) a.trace_flags[R.site0 + i] = kFlagSame;
+        if (a.trace_dE) a.trace_dE[R.site0 + i] = 0.0;
+        if (a.trace_dE_fast) a.trace_dE_fast[R.site0 + i] = 0.0;
       }
     }
-    __syncthreads();
-    const int nact = s_nact;
+    const unsigned long long valid = __ballot(i >= 0);
+    const unsigned long long act_mask = __ballot(active);
+    const int ca = __popcll(act_mask & ((1ull << lane) - 1ull));
+    if (active) {
+      tb.site[ca] = (int32_t)i;
+      tb.part[ca] = (int32_t)n;
+      tb.px[ca] = pi.x;
+      tb.py[ca] = pi.y;
+      tb.pz[ca] = pi.z;
+      tb.theta[ca] = theta;
+      tb.dir[ca] = (uint8_t)d;
+      tb.si[ca] = si;
+      tb.sn[ca] = sn;
+    }
+    if (lane == 0) {
+      tb.nact = __popcll(act_mask);
+      cnt_att += __popcll(valid);
+      cnt_diff += __popcll(act_mask);
+    }
+  };
 
-    // ------------------------------------------------------------ 2. gather
-    for (int q = tid; q < nact * kReg; q += kMfmaThreads) {
-      const int t = q / kReg, p = q - t * kReg;
-      const int d = s_dir[t];
-      int dx, dy, dz;
-      unpack_off(a.reg_off[d * kReg + p], dx, dy, dz);
-      const Pos pi{s_px[t], s_py[t], s_pz[t]};
-      const int64_t j = site_at(pi, dx, dy, dz, R.L[0], R.L[1], R.L[2]);
-      uint8_t v = occ[j];
-      if (p == a.reg_pos[2 * d]) v = s_sn[t];
-      if (p == a.reg_pos[2 * d + 1]) v = s_si[t];
-      s_reg[q] = v;
+  // gather loads of one group into registers (the loads stay in flight until used)
+  uint8_t pf_reg[kPfReg];
+  float pf_om[kPfOm];
+  auto gather_issue = [&](const TrialBuf &tb) {
+    const int nact = tb.nact;
+#pragma unroll
+    for (int j = 0; j < kPfReg; ++j) {
+      const int q = tid + j * kMfmaThreads;
+      if (q < nact * kReg) {
+        const int t = q / kReg, p = q - t * kReg;
+        int dx, dy, dz;
+        unpack_off(s_roff[tb.dir[t] * kReg + p], dx, dy, dz);
+        pf_reg[j] = occ[site_at(Pos{tb.px[t], tb.py[t], tb.pz[t]}, dx, dy, dz, R.L[0], R.L[1], R.L[2])];
+      }
     }
-    for (int q = tid; q < nact * kOm; q += kMfmaThreads) {
-      const int t = q / kOm, k = q - t * kOm;
-      int dx, dy, dz;
-      unpack_off(a.om_off[s_dir[t] * kOm + k], dx, dy, dz);
-      const Pos pi{s_px[t], s_py[t], s_pz[t]};
-      s_ec[q] = ec[site_at(pi, dx, dy, dz, R.L[0], R.L[1], R.L[2])];
+#pragma unroll
+    for (int j = 0; j < kPfOm; ++j) {
+      const int q = tid + j * kMfmaThreads;
+      if (q < nact * kOm) {
+        const int t = q / kOm, k = q - t * kOm;
+        int dx, dy, dz;
+        unpack_off(s_ooff[tb.dir[t] * kOm + k], dx, dy, dz);
+        pf_om[j] = ec[site_at(Pos{tb.px[t], tb.py[t], tb.pz[t]}, dx, dy, dz, R.L[0], R.L[1], R.L[2])];
+      }
     }
-    __syncthreads();
+  };
+  auto gather_store = [&](const TrialBuf &tb) {
+    const int nact = tb.nact;
+#pragma unroll
+    for (int j = 0; j < kPfReg; ++j) {
+      const int q = tid + j * kMfmaThreads;
+      if (q < nact * kReg) {
+        const int t = q / kReg, p = q - t * kReg;
+        const int d = tb.dir[t];
+        uint8_t v = pf_reg[j];
+        if (p == s_rpos[2 * d]) v = tb.sn[t];
+        if (p == s_rpos[2 * d + 1]) v = tb.si[t];
+        s_reg[q] = v;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kPfOm; ++j) {
+      const int q = tid + j * kMfmaThreads;
+      if (q < nact * kOm) s_ec[q] = pf_om[j];
+    }
+  };
 
-    // ------------------------------------------------------------ 3. energies
+  // prologue: proposals of the first two groups, gather of the first
+  __syncthreads();
+  if (wave == 0) {
+    propose(gstart, s_tb[0]);
+    propose(gstart + gstep, s_tb[1]);
+  }
+  __syncthreads();
+  gather_issue(s_tb[0]);
+
+  int it = 0;
+  for (int grp = gstart; grp < gend; grp += gstep, ++it) {
+    TrialBuf &cur = s_tb[it % 3];
+    TrialBuf &nxt = s_tb[(it + 1) % 3];
+    TrialBuf &nxt2 = s_tb[(it + 2) % 3];
+    // ------------------------------------------------------------ gather (g) into LDS
+    gather_store(cur);
+    if (tid == 0) s_tile = 0;
+    __syncthreads();
+    const int nact = cur.nact;
+    // ------------------------------------------------------------ gather (g+1) in flight
+    if (grp + gstep < gend) gather_issue(nxt);
+    // ------------------------------------------------------------ proposal (g+2), wave 0
+    if (wave == 0) propose(grp + 2 * gstep, nxt2);
+    // ------------------------------------------------------------ energies (g)
     const int rows = nact * kOm;
-    for (int tile = wave; tile * 32 < rows; tile += kMfmaThreads / 64) {
+    const int ntiles = (rows + 31) / 32;
+    for (;;) {
+      int tile = 0;
+      if (lane == 0) tile = atomicAdd(&s_tile, 1);
+      tile = __shfl(tile, 0);
+      if (tile >= ntiles) break;
       const int row = tile * 32 + (lane & 31);
       const bool valid = row < rows;
       const int t = valid ? row / kOm : 0;
       const int k = valid ? row - t * kOm : 0;
-      const uint8_t *irow = s_idx + (s_dir[t] * kOm + k) * kIdxRow;
+      const uint8_t *irow = s_idx + (cur.dir[t] * kOm + k) * kIdxRow;
       const uint8_t *reg = s_reg + t * kReg;
       const float E = eval_tile<P>(S, [&](int m) -> uint32_t { return reg[irow[m]]; });
       if (valid && lane < 32) s_e[row] = E;
     }
     __syncthreads();
-
-    // ------------------------------------------------------------ 4. decide
+    // ------------------------------------------------------------ decide (g)
+    if (tid < nact * kPart) {
+      const int t = tid / kPart, part = tid - t * kPart;
+      float s = 0.0f;
+#pragma unroll
+      for (int k = 0; k < kOm / kPart; ++k) {
+        const int q = t * kOm + part * (kOm / kPart) + k;
+        s += s_e[q] - s_ec[q];
+      }
+      s_psum[tid] = s;
+    }
+    __syncthreads();
     if (wave == 0) {
       bool accept = false;
       double dEd = 0.0;
       if (lane < nact) {
         float dE = 0.0f;
-        for (int k = 0; k < kOm; ++k) dE += s_e[lane * kOm + k] - s_ec[lane * kOm + k];
+#pragma unroll
+        for (int part = 0; part < kPart; ++part) dE += s_psum[lane * kPart + part];
         dEd = (double)dE;
-        const double theta = s_theta[lane];
-        const int64_t i = s_site[lane];
+        const double theta = cur.theta[lane];
+        const int64_t i = cur.site[lane];
         if (fabs(dEd - theta) < a.guard) {
           const uint32_t slot = atomicAdd(a.q_count, 1u);
           RecheckEntry &e = a.queue[slot];
           e.site = i;
-          e.partner = s_part[lane];
+          e.partner = cur.part[lane];
           e.theta = theta;
           e.dE_fast = dE;
           e.replica = a.replica;
-          e.dir = s_dir[lane];
+          e.dir = cur.dir[lane];
           for (int k = 0; k < kOm; ++k) e.e1[k] = s_e[lane * kOm + k];
           if (a.trace_dE_fast) a.trace_dE_fast[R.site0 + i] = dEd;
         } else {
           accept = dEd <= theta;
           if (accept) {
-            occ[i] = s_sn[lane];
-            occ[s_part[lane]] = s_si[lane];
+            occ[i] = cur.sn[lane];
+            occ[cur.part[lane]] = cur.si[lane];
           }
           if (a.trace_flags) a.trace_flags[R.site0 + i] = accept ? kFlagAccept : 0;
           if (a.trace_dE) a.trace_dE[R.site0 + i] = dEd;
@@ -245,15 +324,13 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
       }
     }
     __syncthreads();
-
-    // ------------------------------------------------------------ 5. apply the cache
+    // ------------------------------------------------------------ apply (g)
     for (int q = tid; q < nact * kOm; q += kMfmaThreads) {
       const int t = q / kOm, k = q - t * kOm;
       if (!s_acc[t]) continue;
       int dx, dy, dz;
-      unpack_off(a.om_off[s_dir[t] * kOm + k], dx, dy, dz);
-      const Pos pi{s_px[t], s_py[t], s_pz[t]};
-      ec[site_at(pi, dx, dy, dz, R.L[0], R.L[1], R.L[2])] = s_e[q];
+      unpack_off(s_ooff[cur.dir[t] * kOm + k], dx, dy, dz);
+      ec[site_at(Pos{cur.px[t], cur.py[t], cur.pz[t]}, dx, dy, dz, R.L[0], R.L[1], R.L[2])] = s_e[q];
     }
     __syncthreads();
   }
@@ -266,14 +343,19 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
   }
 }
 
-// FP64 re-decision of queued near-threshold trials: 80 lanes evaluate the 40 affected
-// sites after and before the swap in FP64 (per-lane evaluator), one trial per block step.
+// FP64 re-decision of queued near-threshold trials.  One block per trial step evaluates the
+// 80 local energies (the 40 zone sites after and before the swap) cooperatively: layer 0 as
+// the sum of the 27 selected columns of W0 in slot order, layer 1 with one thread per
+// (hidden unit, half of the rows), activations staged in LDS.
 struct RecheckArgs {
   const Replica *reps;
   uint8_t *occ;
   float *ecache;
-  const double *w64;
-  const int32_t *om_off;  // [8][40]
+  const double *w64;        // FP64 blob with W0 and W1 transposed ([input][unit]) for coalescing
+  const uint16_t *reg_off;  // [8][192]
+  const uint16_t *om_off;   // [8][40]
+  const uint8_t *idx;       // [8][40][28]
+  const uint8_t *reg_pos;   // [8][2]
   const uint32_t *q_count;
   const RecheckEntry *queue;
   unsigned long long *e_fixed;
@@ -281,52 +363,157 @@ struct RecheckArgs {
   int32_t n_replicas;
   double *trace_dE;
   uint8_t *trace_flags;
+  double *probe_dE;   // non-null: write dE of queue entry q to probe_dE[q] and change nothing
+  double *row_e;      // [queue capacity][80] FP64 local energies
+  uint32_t *done;     // [queue capacity] blocks finished per entry, zero between uses
 };
 
-__global__ __launch_bounds__(128) void k_recheck(RecheckArgs a) {
-  __shared__ double s_e[2 * kOm];
-  __shared__ int s_accept;
+constexpr int kRcThreads = 1024;
+constexpr int kRows64 = 2 * kOm;              // rows 0..39 after the swap, 40..79 before
+constexpr int kRcSplit = 1;                   // blocks sharing one queued trial
+constexpr int kRcRowsB = kRows64 / kRcSplit;  // 16 rows per block
+constexpr int kRcParts = kRcThreads / kHid;   // 8 threads per hidden unit
+constexpr int kRcRows = kRcRowsB / kRcParts;  // 2 rows per thread
+constexpr int kHStride = kHid + 1;            // padded row stride of the activation buffer
+
+// One block per (queued trial, block of 16 rows): FP64 local energies of its rows go to
+// row_e; the block that completes a trial (per-trial counter) reduces the 80 energies in a
+// fixed order, decides and applies.  No block ever waits for another.
+__global__ __launch_bounds__(kRcThreads) void k_recheck(RecheckArgs a) {
+  __shared__ double s_h[kRcRowsB * kHStride];  // activations, then per-unit terms of layer 2
+  __shared__ double s_part[kRcRowsB * kRcParts];
+  __shared__ uint8_t s_reg[kReg];
+  __shared__ uint8_t s_sp[kRcRowsB * 27];
+  __shared__ double s_e[kRows64];
+  __shared__ int s_last, s_accept;
   const uint32_t n = *a.q_count;
   const int tid = threadIdx.x;
-  for (uint32_t q = blockIdx.x; q < n; q += gridDim.x) {
+  const int o = tid % kHid, part = tid / kHid;  // thread owns unit o for local rows part + 8j
+  const double *W0 = a.w64, *b0 = W0 + kHid * 108, *W1 = b0 + kHid, *b1 = W1 + kHid * kHid, *W2 = b1 + kHid,
+               *b2 = W2 + kHid;
+  for (uint32_t w = blockIdx.x; w < n * kRcSplit; w += gridDim.x) {
+    const uint32_t q = w / kRcSplit;
+    const int r0 = (int)(w % kRcSplit) * kRcRowsB;
     const RecheckEntry &e = a.queue[q];
     const Replica R = a.reps[e.replica];
     uint8_t *occ = a.occ + R.site0;
     const Pos pi = site_pos(e.site, R.L[0], R.L[1]);
     const int d = e.dir;
     const uint8_t si = occ[e.site], sn = occ[e.partner];
-    if (tid < 2 * kOm) {
-      const int k = tid % kOm;
+    const int pos_i = a.reg_pos[2 * d], pos_n = a.reg_pos[2 * d + 1];
+    if (tid < kReg) {
       int dx, dy, dz;
-      unpack_off(a.om_off[d * kOm + k], dx, dy, dz);
-      const int64_t j = site_at(pi, dx, dy, dz, R.L[0], R.L[1], R.L[2]);
-      s_e[tid] = site_energy<1, 128, double>(occ, R, j, tid < kOm, e.site, e.partner, si, sn, a.w64);
+      unpack_off(a.reg_off[d * kReg + tid], dx, dy, dz);
+      s_reg[tid] = occ[site_at(pi, dx, dy, dz, R.L[0], R.L[1], R.L[2])];
     }
     __syncthreads();
-    if (tid == 0) {
-      double e1 = 0.0, e0 = 0.0;
-      for (int k = 0; k < kOm; ++k) e1 += s_e[k];
-      for (int k = 0; k < kOm; ++k) e0 += s_e[kOm + k];
-      const double dE = e1 - e0;
-      const bool accept = dE <= e.theta;
-      const int Rn = a.n_replicas;
-      if (accept) {
-        occ[e.site] = sn;
-        occ[e.partner] = si;
-        atomicAdd(&a.e_fixed[e.replica], (unsigned long long)to_fixed(dE));
-        atomicAdd((unsigned long long *)&a.counters[2 * Rn + e.replica], 1ull);
+    // slot species of this block's rows (post-swap rows see i and n exchanged)
+    for (int v = tid; v < kRcRowsB * 27; v += kRcThreads) {
+      const int lr = v / 27, m = v - lr * 27, gr = r0 + lr;
+      const bool post = gr < kOm;
+      const int p = a.idx[(d * kOm + (post ? gr : gr - kOm)) * kIdxRow + m];
+      s_sp[v] = post ? (p == pos_i ? sn : (p == pos_n ? si : s_reg[p])) : s_reg[p];
+    }
+    __syncthreads();
+    // layer 0 + activation: the selected W0 column of each slot, added in slot order
+    {
+      double acc[kRcRows];
+#pragma unroll
+      for (int j = 0; j < kRcRows; ++j) acc[j] = b0[o];
+#pragma unroll 3
+      for (int m = 0; m < 27; ++m) {
+        const double w0 = W0[(4 * m) * kHid + o], w1 = W0[(4 * m + 1) * kHid + o],
+                     w2 = W0[(4 * m + 2) * kHid + o], w3 = W0[(4 * m + 3) * kHid + o];
+#pragma unroll
+        for (int j = 0; j < kRcRows; ++j) {
+          const int sp = s_sp[(part + kRcParts * j) * 27 + m];
+          const double wv = sp == 0 ? w0 : (sp == 1 ? w1 : (sp == 2 ? w2 : w3));
+          if (sp < 4) acc[j] += wv;
+        }
       }
-      atomicAdd((unsigned long long *)&a.counters[3 * Rn + e.replica], 1ull);
-      if (a.trace_flags) a.trace_flags[R.site0 + e.site] = kFlagFp64 | (accept ? kFlagAccept : 0);
-      if (a.trace_dE) a.trace_dE[R.site0 + e.site] = dE;
-      s_accept = accept;
+#pragma unroll
+      for (int j = 0; j < kRcRows; ++j) s_h[(part + kRcParts * j) * kHStride + o] = silu<double>(acc[j]);
     }
     __syncthreads();
-    if (tid < kOm && s_accept) {
-      // the cache keeps the sweep precision's energies of the zone
-      int dx, dy, dz;
-      unpack_off(a.om_off[d * kOm + tid], dx, dy, dz);
-      a.ecache[R.site0 + site_at(pi, dx, dy, dz, R.L[0], R.L[1], R.L[2])] = e.e1[tid];
+    // layer 1 + activation, times W2
+    {
+      double acc[kRcRows];
+#pragma unroll
+      for (int j = 0; j < kRcRows; ++j) acc[j] = b1[o];
+#pragma unroll 4
+      for (int k = 0; k < kHid; ++k) {
+        const double wk = W1[k * kHid + o];
+#pragma unroll
+        for (int j = 0; j < kRcRows; ++j) acc[j] = fma(wk, s_h[(part + kRcParts * j) * kHStride + k], acc[j]);
+      }
+      __syncthreads();
+      const double w2 = W2[o];
+#pragma unroll
+      for (int j = 0; j < kRcRows; ++j) s_h[(part + kRcParts * j) * kHStride + o] = w2 * silu<double>(acc[j]);
+    }
+    __syncthreads();
+    // E_r = b2 + sum over units in a fixed order: 8 consecutive chunks of 16, then the chunks
+    if (tid < kRcRowsB * kRcParts) {
+      const int lr = tid / kRcParts, c = tid % kRcParts;
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < kHid / kRcParts; ++i) s += s_h[lr * kHStride + c * (kHid / kRcParts) + i];
+      s_part[tid] = s;
+    }
+    __syncthreads();
+    if (tid < kRcRowsB) {
+      double E = b2[0];
+#pragma unroll
+      for (int c = 0; c < kRcParts; ++c) E += s_part[tid * kRcParts + c];
+      if constexpr (kRcSplit == 1) s_e[tid] = E;
+      else a.row_e[(size_t)q * kRows64 + r0 + tid] = E;
+    }
+    if constexpr (kRcSplit > 1) {
+      __threadfence();
+      __syncthreads();
+      if (tid == 0) s_last = atomicAdd(&a.done[q], 1u) == kRcSplit - 1;
+      __syncthreads();
+    } else {
+      if (tid == 0) s_last = 1;
+      __syncthreads();
+    }
+    if (s_last) {
+      if constexpr (kRcSplit > 1) __threadfence();
+      if (tid == 0) {
+        double e1 = 0.0, e0 = 0.0;
+        if constexpr (kRcSplit == 1) {
+          for (int k = 0; k < kOm; ++k) e1 += s_e[k];
+          for (int k = 0; k < kOm; ++k) e0 += s_e[kOm + k];
+        } else {
+          const double *re = a.row_e + (size_t)q * kRows64;
+          for (int k = 0; k < kOm; ++k) e1 += __hip_atomic_load(re + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          for (int k = 0; k < kOm; ++k)
+            e0 += __hip_atomic_load(re + kOm + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          a.done[q] = 0;  // ready for the next use of this queue slot
+        }
+        const double dE = e1 - e0;
+        const bool probe = a.probe_dE != nullptr;
+        const bool accept = !probe && dE <= e.theta;
+        const int Rn = a.n_replicas;
+        if (probe) a.probe_dE[q] = dE;
+        if (accept) {
+          occ[e.site] = sn;
+          occ[e.partner] = si;
+          atomicAdd(&a.e_fixed[e.replica], (unsigned long long)to_fixed(dE));
+          atomicAdd((unsigned long long *)&a.counters[2 * Rn + e.replica], 1ull);
+        }
+        if (!probe) atomicAdd((unsigned long long *)&a.counters[3 * Rn + e.replica], 1ull);
+        if (a.trace_flags) a.trace_flags[R.site0 + e.site] = kFlagFp64 | (accept ? kFlagAccept : 0);
+        if (a.trace_dE) a.trace_dE[R.site0 + e.site] = dE;
+        s_accept = accept;
+      }
+      __syncthreads();
+      if (tid < kOm && s_accept) {
+        // the cache keeps the sweep precision's energies of the zone
+        int dx, dy, dz;
+        unpack_off(a.om_off[d * kOm + tid], dx, dy, dz);
+        a.ecache[R.site0 + site_at(pi, dx, dy, dz, R.L[0], R.L[1], R.L[2])] = e.e1[tid];
+      }
     }
     __syncthreads();
   }

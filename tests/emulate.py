@@ -78,17 +78,21 @@ def energies(params, X, prec):
     c1 = (-L2E * b1).astype(np.float32)
     w2s = (-LN2 * W2).astype(np.float32)
     f64 = np.float64
+    # FP32/BF16 paths carry the layer-0 bias as a weight column (quantised like the weights);
+    # FP8 keeps it in FP32 as the accumulator's initial value
     if prec == "fp32":
         y1 = X @ W0s.T.astype(f64) + c0
         h = act(y1.astype(np.float32))
         y2 = h.astype(f64) @ W1.T.astype(f64) + c1
     elif prec == "bf16":
-        y1 = X @ bf16(W0s).T.astype(f64) + c0
+        y1 = X @ bf16(W0s).T.astype(f64) + bf16(c0)
         h = bf16(act(y1.astype(np.float32)))
         y2 = h.astype(f64) @ bf16(W1).T.astype(f64) + c1
     elif prec == "bf16x3":
         hi0 = bf16(W0s)
         lo0 = bf16(W0s - hi0)
+        c0h = bf16(c0)
+        c0 = c0h.astype(f64) + bf16(c0 - c0h)
         y1 = X @ (hi0.astype(f64) + lo0).T + c0
         h = act(y1.astype(np.float32))
         hh = bf16(h)

@@ -58,7 +58,7 @@ def test_site_energies_match_emulation_and_oracle(prec):
     mc.close()
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp64"])
 def test_one_hot_sweeps_bit_exact(prec):
     need_gpu()
     cells = (8, 8, 8)
@@ -72,8 +72,28 @@ def test_one_hot_sweeps_bit_exact(prec):
         d = otr["same"] == 0
         worst = max(worst, float(np.abs(tr["dE_fast"][d] - otr["dE"][d]).max()))
     _banner(f"{prec}: max |dE_fast - dE_fp64| = {worst:.3e}, guard {'1e-5' if prec == 'fp32' else '2e-4'}")
-    assert worst < (2e-6 if prec == "fp32" else 4e-5)  # guard / 5
-    assert np.array_equal(mc.ecache.cpu().numpy(), mc.site_energies(prec).cpu().numpy())
+    assert worst < (4e-5 if prec == "bf16x3" else 2e-6)  # guard / 5
+    if prec == "fp64":
+        # every different-species trial was decided by the FP64 evaluator
+        flags = tr["flags"]
+        assert np.all((flags & 4).astype(bool) == ~(flags & 2).astype(bool))
+    else:
+        assert np.array_equal(mc.ecache.cpu().numpy(), mc.site_energies(prec).cpu().numpy())
+    mc.close()
+
+
+def test_fp64_probe_matches_oracle():
+    """smc_delta_e64 (the FP64 evaluator of the re-decision path) against the oracle."""
+    need_gpu()
+    cells = (12, 8, 16)
+    w, mc, model, occ = make("c2", precision="bf16", cells=cells, n_species=5)
+    sites = np.arange(0, occ.size, 7)
+    partner, dE = mc.delta_e64(sites, sweep=3)
+    for s, p, e in zip(sites, partner, dE):
+        rec = oracle.trial(cells, model, occ, 800.0, w.seed, 0, 3, int(s))
+        assert p == rec["partner"]
+        assert abs(e - rec["dE"]) < 1e-11
+    assert np.array_equal(mc.occ.cpu().numpy(), occ)  # nothing changed
     mc.close()
 
 
