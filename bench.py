@@ -41,6 +41,21 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def measured_traffic(precision):
+    """HBM bytes per colour-kernel launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, or None when the kernel sources changed since those counters were taken."""
+    import glob
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"sweep_colour_{precision}_bcc256_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2604_08250_amd", "csrc", "*"))):
+        h.update(open(f, "rb").read())
+    return rec["traffic_bytes_per_launch"] if rec.get("kernel_source_sha256") == h.hexdigest() else None
+
+
 def colour0_sites(cells, n):
     """Trial sites of colour 0 (link-cell offset (0,0,0), basis 0) spread over the lattice."""
     lx, ly, lz = cells
@@ -166,7 +181,19 @@ def main():
     ap.add_argument("--err-samples", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-calibration", type=float, default=0.0,
+                    help="only run 4 plain device copies of this many GiB (scale for the HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration > 0:
+        import torch
+        n = int(args.copy_calibration * 2**30) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each": n * 4, "copies": 4}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU slab "
               "decomposition is a design, not part of this build.", file=sys.stderr)
@@ -202,7 +229,8 @@ def main():
                                f"T = {w.temperatures[0]:g} K, {args.precision} energy path",
                    "precision": args.precision, "sites": sum(w.sites)},
         "roofline": {"bound": "mfma", "achieved": head["algorithmic_tflops"], "peak": PEAK_TFLOPS[args.precision],
-                     "unit": "TFLOP/s", "frac": head["roofline_frac"], "traffic": None,
+                     "unit": "TFLOP/s", "frac": head["roofline_frac"],
+                     "traffic": measured_traffic(args.precision) if args.workload == "c3" else None,
                      "kernel": f"k_sweep_colour_mfma<{args.precision}>",
                      "avg_launch_us": head["colour_kernel_us"], "executed_frac": head["executed_frac"]},
         "precisions": precs,
