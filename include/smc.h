@@ -159,6 +159,23 @@ int smc_counters(smc_ctx *ctx, uint64_t *out_host, int32_t reset);
 int smc_profile(smc_ctx *ctx, int32_t enable);
 int smc_kernel_times(smc_ctx *ctx, double *colour_ms, double *recheck_ms, int64_t *colour_launches);
 
+/* Batched sweeps.  One launch per colour index covers that colour of every replica whose
+ * schedule has it (replicas are independent chains; a replica's colours still run in
+ * order).  Without stats, traces or profiling a sweep is replayed from a hipGraph captured
+ * once (one host submission per sweep); the sweep counter then advances on the device.
+ * smc_use_graph(ctx, 0) forces per-launch submission (results are identical).
+ * Kernel variants (link cells per group: 32 or 16; XCD-contiguous or strided group order)
+ * give bit-identical results; smc_autotune times all of them on one sweep of the context's
+ * current state (restored afterwards), fails with SMC_E_STATE if any variant differs bit for
+ * bit, keeps the fastest, and appends it to the JSON-lines cache at cache_path (nullable),
+ * where a later call with the same device, precision and replica shapes finds it without
+ * timing.  chosen (nullable) receives the variant, ms_per_variant (nullable, [4]) the
+ * timings.  Synchronises. */
+int smc_use_graph(smc_ctx *ctx, int32_t enable);
+int smc_set_variant(smc_ctx *ctx, int32_t variant);
+int smc_get_variant(const smc_ctx *ctx, int32_t *variant);
+int smc_autotune(smc_ctx *ctx, const char *cache_path, int32_t *chosen, float *ms_per_variant);
+
 /* Total sites over all replicas, and number of colours (mini-steps) of a replica. */
 int smc_n_sites(const smc_ctx *ctx, int64_t *n);
 int smc_n_colours(const smc_ctx *ctx, int32_t replica, int32_t *n);

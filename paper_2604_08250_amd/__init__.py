@@ -8,9 +8,11 @@ from __future__ import annotations
 import numpy as np
 
 from ._lib import (PRECISIONS, SMC_BF16, SMC_BF16X3, SMC_FEAT_COUNTS_S12, SMC_FEAT_ONEHOT_S123,
-                   SMC_FP8_E4M3, SMC_FP32, SMC_FP64, SMCError, lib, smc_destroy, smc_energy,
-                   smc_counters, smc_delta_e64, smc_get_sweep, smc_init, smc_kernel_times, smc_profile, smc_n_colours, smc_n_sites, smc_refresh, smc_set_params,
-                   smc_set_sweep, smc_site_energies, smc_sweep)
+                   SMC_FP8_E4M3, SMC_FP32, SMC_FP64, SMCError, lib, smc_autotune, smc_counters,
+                   smc_delta_e64, smc_destroy, smc_energy, smc_get_sweep, smc_get_variant, smc_init,
+                   smc_kernel_times, smc_n_colours, smc_n_sites, smc_profile, smc_refresh,
+                   smc_set_params, smc_set_sweep, smc_set_variant, smc_site_energies, smc_sweep,
+                   smc_use_graph)
 
 __all__ = ["SwapMC", "SMCError", "PRECISIONS", "lib"]
 
@@ -107,6 +109,23 @@ class SwapMC:
     @sweep_index.setter
     def sweep_index(self, v):
         smc_set_sweep(self.ctx, int(v))
+
+    def use_graph(self, enable=True):
+        """Replay plain sweeps from a captured hipGraph (default on); results are identical."""
+        smc_use_graph(self.ctx, enable)
+
+    @property
+    def variant(self):
+        return smc_get_variant(self.ctx)
+
+    @variant.setter
+    def variant(self, v):
+        smc_set_variant(self.ctx, v)
+
+    def autotune(self, cache_path=None):
+        """Time every colour-kernel variant on one sweep of the current state (restored
+        afterwards), keep the fastest; returns (variant, ms per variant)."""
+        return smc_autotune(self.ctx, cache_path)
 
     def n_colours(self, replica=0):
         return smc_n_colours(self.ctx, replica)

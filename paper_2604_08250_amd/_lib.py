@@ -22,8 +22,9 @@ PRECISIONS = {"fp32": SMC_FP32, "bf16": SMC_BF16, "bf16x3": SMC_BF16X3, "fp8": S
               "fp64": SMC_FP64}
 
 EXPORTS = ["smc_init", "smc_sweep", "smc_energy", "smc_site_energies", "smc_set_params",
-           "smc_refresh", "smc_counters", "smc_delta_e64", "smc_profile", "smc_kernel_times", "smc_get_sweep", "smc_set_sweep", "smc_n_sites", "smc_n_colours",
-           "smc_destroy", "smc_last_error", "smc_status_string"]
+           "smc_refresh", "smc_counters", "smc_delta_e64", "smc_profile", "smc_kernel_times", "smc_get_sweep",
+           "smc_set_sweep", "smc_use_graph", "smc_set_variant", "smc_get_variant", "smc_autotune",
+           "smc_n_sites", "smc_n_colours", "smc_destroy", "smc_last_error", "smc_status_string"]
 
 
 class smc_config(C.Structure):
@@ -70,6 +71,10 @@ def lib():
                                            C.POINTER(C.c_int64)]),
             "smc_get_sweep": (C.c_int, [vp, C.POINTER(C.c_uint64)]),
             "smc_set_sweep": (C.c_int, [vp, C.c_uint64]),
+            "smc_use_graph": (C.c_int, [vp, C.c_int32]),
+            "smc_set_variant": (C.c_int, [vp, C.c_int32]),
+            "smc_get_variant": (C.c_int, [vp, C.POINTER(C.c_int32)]),
+            "smc_autotune": (C.c_int, [vp, C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
             "smc_n_sites": (C.c_int, [vp, C.POINTER(C.c_int64)]),
             "smc_n_colours": (C.c_int, [vp, C.c_int32, C.POINTER(C.c_int32)]),
             "smc_destroy": (None, [vp]),
@@ -172,6 +177,28 @@ def smc_get_sweep(ctx) -> int:
 
 def smc_set_sweep(ctx, sweep):
     check(lib().smc_set_sweep(ctx, sweep), ctx)
+
+
+def smc_use_graph(ctx, enable):
+    check(lib().smc_use_graph(ctx, int(bool(enable))), ctx)
+
+
+def smc_set_variant(ctx, variant):
+    check(lib().smc_set_variant(ctx, int(variant)), ctx)
+
+
+def smc_get_variant(ctx) -> int:
+    v = C.c_int32()
+    check(lib().smc_get_variant(ctx, C.byref(v)), ctx)
+    return v.value
+
+
+def smc_autotune(ctx, cache_path=None):
+    chosen = C.c_int32()
+    ms = np.zeros(4, dtype=np.float32)
+    check(lib().smc_autotune(ctx, cache_path.encode() if cache_path else None, C.byref(chosen),
+                             ms.ctypes.data_as(C.POINTER(C.c_float))), ctx)
+    return chosen.value, ms
 
 
 def smc_n_sites(ctx) -> int:

@@ -51,9 +51,23 @@ struct smc_ctx {
   RecheckEntry *d_queue = nullptr;
   double *d_rowe = nullptr;       // [queue_cap][80] FP64 local energies of queued trials
   uint32_t *d_done = nullptr;     // [queue_cap] per-entry completion counters
-  uint32_t *d_qcount = nullptr;   // one counter per colour of a sweep
+  uint32_t *d_qcount = nullptr;   // one counter per colour index of a sweep
   int64_t queue_cap = 0;
   int32_t colours_total = 0;
+  int32_t max_colours = 0;        // colour indices per sweep (largest replica schedule)
+  // per colour index: the replicas that have it and their flattened group offsets, for
+  // groups of 32 [0] and 16 [1] link cells
+  std::vector<int32_t> seg_off;               // [max_colours + 1] into the segment lists
+  std::vector<int32_t> seg_groups[2];         // [max_colours] total groups
+  std::vector<int64_t> col_trials;            // [max_colours] link cells over all replicas
+  int32_t *d_seg_rep = nullptr;               // [segments]
+  int32_t *d_seg_start[2] = {nullptr, nullptr};  // [segments + max_colours]
+  uint64_t *d_sweep = nullptr;                // device sweep counter
+  int variant = 0;                            // kernel variant (autotuner)
+  bool use_graph = true;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
   double *d_ebase = nullptr;      // [R] FP64 total at the last refresh
   unsigned long long *d_efixed = nullptr;  // [R] accepted dE since then, 2^-32 eV units
   double *d_escratch = nullptr;   // [R]
@@ -75,6 +89,8 @@ int fail(smc_ctx *c, int code, const std::string &msg) {
   if (c) c->err = msg;
   return code;
 }
+
+void drop_graph(smc_ctx *c);
 
 #define HIPC(c, expr)                                                                   \
   do {                                                                                  \
@@ -222,6 +238,7 @@ int load_params(smc_ctx *c, const float *params_dev) {
   HIPC(c, hipMemcpyAsync(c->host_params.data(), params_dev, sizeof(float) * P, hipMemcpyDeviceToHost, c->stream));
   HIPC(c, hipStreamSynchronize(c->stream));
   for (int k = 0; k < 4; ++k) c->packs[k].ready = false;
+  drop_graph(c);  // the captured sweep holds the packed scales and output bias by value
   if (c->mfma) {
     // [input][unit] FP64 copy: consecutive threads of the re-decision kernel own consecutive
     // hidden units, so their weight loads are contiguous
@@ -250,95 +267,156 @@ void launch_colour_scalar(smc_ctx *c, SweepArgs a, int64_t n_trials) {
                      dim3(kScalarBlock), 0, c->stream, a);
 }
 
-template <int P>
-void launch_colour_mfma(smc_ctx *c, const MfmaArgs &a) {
-  int G = std::min(a.n_groups, c->n_cu);
+// Kernel variants picked by the autotuner: link cells per group and XCD-contiguous order.
+constexpr int kNumVariants = 4;
+constexpr int kVariantGroup[kNumVariants] = {32, 32, 16, 16};
+constexpr int kVariantXcd[kNumVariants] = {1, 0, 1, 0};
+
+template <int P, int GROUP>
+void launch_colour_mfma_g(smc_ctx *c, const MfmaArgs &a, int n_groups) {
+  int G = std::min(n_groups, c->n_cu);
   if (G >= 8) G -= G % 8;
-  hipLaunchKernelGGL((k_sweep_colour_mfma<P>), dim3(G), dim3(kMfmaThreads), 0, c->stream, a);
+  hipLaunchKernelGGL((k_sweep_colour_mfma<P, GROUP>), dim3(std::max(G, 1)), dim3(kMfmaThreads), 0, c->stream, a);
+}
+
+template <int P>
+void launch_colour_mfma(smc_ctx *c, const MfmaArgs &a, int n_groups, int group) {
+  if (group == 16) launch_colour_mfma_g<P, 16>(c, a, n_groups);
+  else launch_colour_mfma_g<P, 32>(c, a, n_groups);
+}
+
+// Enqueue one sweep of the matrix-core path on c->stream (also used under graph capture):
+// clear the per-colour queue counters, then per colour index one batched colour kernel over
+// every replica that has that colour and one FP64 re-decision kernel; finally advance the
+// device sweep counter.
+int enqueue_sweep_mfma(smc_ctx *c, const smc_stats *st, bool trace) {
+  const int R = (int)c->reps.size();
+  const bool fp64 = c->cfg.precision == SMC_FP64;
+  const int P = fp64 ? SMC_FP32 : c->cfg.precision;
+  const DevPack &dp = c->packs[P];
+  const int group = kVariantGroup[c->variant];
+  const int gi = group == 16 ? 1 : 0;
+  const int64_t qwords = (c->max_colours + 1) / 2;
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(qwords, 256)), dim3(256), 0, c->stream, (uint64_t *)c->d_qcount,
+                     qwords, (uint64_t)0);
+  for (int col = 0; col < c->max_colours; ++col) {
+    const int so = c->seg_off[col], ns = c->seg_off[col + 1] - so;
+    MfmaArgs a{};
+    a.reps = c->d_reps;
+    a.occ = c->occ;
+    a.ecache = c->ecache;
+    a.wpack = dp.dev;
+    a.reg_off = c->d_reg_off;
+    a.om_off = c->d_om_off;
+    a.idx = c->d_idx;
+    a.reg_pos = c->d_reg_pos;
+    a.b2 = dp.host.b2;
+    a.k_a0 = dp.host.k_scale_a0;
+    a.k_a1 = dp.host.k_scale_a1;
+    a.k_h = dp.host.k_scale_h;
+    a.sh = dp.host.sh;
+    a.colour = col;
+    a.seg_rep = c->d_seg_rep + so;
+    a.seg_start = c->d_seg_start[gi] + so + col;  // ns + 1 entries per colour
+    a.nseg = ns;
+    a.xcd_order = kVariantXcd[c->variant];
+    a.seed = c->cfg.seed;
+    a.sweep = c->d_sweep;
+    a.guard = fp64 ? (double)INFINITY : c->guard;
+    a.q_count = c->d_qcount + col;
+    a.queue = c->d_queue;
+    a.e_fixed = c->d_efixed;
+    a.counters = c->d_counters;
+    a.n_replicas = R;
+    if (trace) {
+      a.trace_dE = st->trace_dE;
+      a.trace_dE_fast = st->trace_dE_fast;
+      a.trace_flags = st->trace_flags;
+    }
+    const int n_groups = c->seg_groups[gi][col];
+    const int ev = prof_begin(c);
+    switch (P) {
+      case SMC_FP32: launch_colour_mfma<kP32>(c, a, n_groups, group); break;
+      case SMC_BF16: launch_colour_mfma<kPBF16>(c, a, n_groups, group); break;
+      case SMC_BF16X3: launch_colour_mfma<kPBF16X3>(c, a, n_groups, group); break;
+      default: launch_colour_mfma<kPFP8>(c, a, n_groups, group); break;
+    }
+    prof_end(c, ev, 0);
+    RecheckArgs ra{};
+    ra.reps = c->d_reps;
+    ra.occ = c->occ;
+    ra.ecache = c->ecache;
+    ra.w64 = c->d_w64t;
+    ra.reg_off = c->d_reg_off;
+    ra.om_off = c->d_om_off;
+    ra.idx = c->d_idx;
+    ra.reg_pos = c->d_reg_pos;
+    ra.q_count = c->d_qcount + col;
+    ra.queue = c->d_queue;
+    ra.e_fixed = c->d_efixed;
+    ra.counters = c->d_counters;
+    ra.n_replicas = R;
+    ra.row_e = c->d_rowe;
+    ra.done = c->d_done;
+    if (trace) {
+      ra.trace_dE = st->trace_dE;
+      ra.trace_flags = st->trace_flags;
+    }
+    const int rgrid = (int)std::min<int64_t>(8 * c->n_cu, kRcSplit * std::max<int64_t>(1, c->col_trials[col]));
+    const int ev2 = prof_begin(c);
+    hipLaunchKernelGGL(k_recheck, dim3(rgrid), dim3(kRcThreads), 0, c->stream, ra);
+    prof_end(c, ev2, 1);
+  }
+  hipLaunchKernelGGL(k_next_sweep, dim3(1), dim3(64), 0, c->stream, c->d_sweep);
+  HIPC(c, hipGetLastError());
+  return SMC_OK;
+}
+
+void drop_graph(smc_ctx *c) {
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->graph_exec = nullptr;
+  c->graph = nullptr;
+}
+
+// Capture one sweep into a graph on the internal capture stream (the caller's stream may be
+// the null stream, which cannot be captured); replays run on the caller's stream.
+int build_graph(smc_ctx *c) {
+  if (!c->cap_stream) HIPC(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  hipStream_t user = c->stream;
+  c->stream = c->cap_stream;
+  const bool prof = c->profiling;
+  c->profiling = false;
+  hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+  int rc = e == hipSuccess ? enqueue_sweep_mfma(c, nullptr, false) : SMC_E_DEVICE;
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
+  c->stream = user;
+  c->profiling = prof;
+  if (rc || e2 != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail(c, SMC_E_DEVICE, std::string("graph capture failed: ") + hipGetErrorString(e2));
+  }
+  c->graph = g;
+  if (hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0) != hipSuccess) {
+    drop_graph(c);
+    return fail(c, SMC_E_DEVICE, "graph instantiation failed");
+  }
+  return SMC_OK;
 }
 
 int run_sweep(smc_ctx *c, const smc_stats *st, bool last) {
   const int R = (int)c->reps.size();
   const bool trace = last && st;
   if (c->mfma) {
-    // FP64 reference mode: the FP32 matrix-core pass only proposes; every different-species
-    // trial is queued and decided by the FP64 evaluator
-    const bool fp64 = c->cfg.precision == SMC_FP64;
-    const int P = fp64 ? SMC_FP32 : c->cfg.precision;
+    const int P = c->cfg.precision == SMC_FP64 ? SMC_FP32 : c->cfg.precision;
     int rc = ensure_pack(c, P);
     if (rc) return rc;
-    const DevPack &dp = c->packs[P];
-    const int64_t qwords = (c->colours_total + 1) / 2;
-    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(qwords, 256)), dim3(256), 0, c->stream,
-                       (uint64_t *)c->d_qcount, qwords, (uint64_t)0);
-    int qoff = 0;
-    for (int r = 0; r < R; ++r) {
-      const Replica &rep = c->reps[r];
-      for (int col = 0; col < rep.n_colours; ++col, ++qoff) {
-        MfmaArgs a{};
-        a.reps = c->d_reps;
-        a.occ = c->occ;
-        a.ecache = c->ecache;
-        a.wpack = dp.dev;
-        a.reg_off = c->d_reg_off;
-        a.om_off = c->d_om_off;
-        a.idx = c->d_idx;
-        a.reg_pos = c->d_reg_pos;
-        a.b2 = dp.host.b2;
-        a.k_a0 = dp.host.k_scale_a0;
-        a.k_a1 = dp.host.k_scale_a1;
-        a.k_h = dp.host.k_scale_h;
-        a.sh = dp.host.sh;
-        a.replica = r;
-        a.colour = col;
-        a.seed = c->cfg.seed;
-        a.sweep = c->sweep;
-        a.guard = fp64 ? (double)INFINITY : c->guard;
-        a.q_count = c->d_qcount + qoff;
-        a.queue = c->d_queue;
-        a.e_fixed = c->d_efixed;
-        a.counters = c->d_counters;
-        a.n_replicas = R;
-        a.n_groups = (int32_t)((rep.n_trials + kGroup - 1) / kGroup);
-        if (trace) {
-          a.trace_dE = st->trace_dE;
-          a.trace_dE_fast = st->trace_dE_fast;
-          a.trace_flags = st->trace_flags;
-        }
-        const int ev = prof_begin(c);
-        switch (P) {
-          case SMC_FP32: launch_colour_mfma<kP32>(c, a); break;
-          case SMC_BF16: launch_colour_mfma<kPBF16>(c, a); break;
-          case SMC_BF16X3: launch_colour_mfma<kPBF16X3>(c, a); break;
-          default: launch_colour_mfma<kPFP8>(c, a); break;
-        }
-        prof_end(c, ev, 0);
-        RecheckArgs ra{};
-        ra.reps = c->d_reps;
-        ra.occ = c->occ;
-        ra.ecache = c->ecache;
-        ra.w64 = c->d_w64t;
-        ra.reg_off = c->d_reg_off;
-        ra.om_off = c->d_om_off;
-        ra.idx = c->d_idx;
-        ra.reg_pos = c->d_reg_pos;
-        ra.q_count = c->d_qcount + qoff;
-        ra.queue = c->d_queue;
-        ra.e_fixed = c->d_efixed;
-        ra.counters = c->d_counters;
-        ra.n_replicas = R;
-        ra.row_e = c->d_rowe;
-        ra.done = c->d_done;
-        if (trace) {
-          ra.trace_dE = st->trace_dE;
-          ra.trace_flags = st->trace_flags;
-        }
-        const int rgrid =
-            (int)std::min<int64_t>(8 * c->n_cu, kRcSplit * std::max<int64_t>(1, rep.n_trials));
-        const int ev2 = prof_begin(c);
-        hipLaunchKernelGGL(k_recheck, dim3(rgrid), dim3(kRcThreads), 0, c->stream, ra);
-        prof_end(c, ev2, 1);
-      }
+    if (c->use_graph && !trace && !c->profiling) {
+      if (!c->graph_exec && (rc = build_graph(c))) return rc;
+      HIPC(c, hipGraphLaunch(c->graph_exec, c->stream));
+    } else if ((rc = enqueue_sweep_mfma(c, st, trace))) {
+      return rc;
     }
   } else {
     for (int r = 0; r < R; ++r) {
@@ -375,6 +453,7 @@ int run_sweep(smc_ctx *c, const smc_stats *st, bool last) {
         prof_end(c, ev, 0);
       }
     }
+    hipLaunchKernelGGL(k_next_sweep, dim3(1), dim3(64), 0, c->stream, c->d_sweep);
   }
   HIPC(c, hipGetLastError());
   c->sweep++;
@@ -448,6 +527,33 @@ int smc_init(const smc_config *cfg, uint8_t *occ_dev, const float *params_dev, f
     c->colours_total += c->reps.back().n_colours;
   }
   c->n_total = site0;
+  // batched schedule: colour index -> replicas that have it, with flattened group offsets
+  std::vector<int32_t> seg_rep, seg_start[2];
+  for (const Replica &rp : c->reps) c->max_colours = std::max(c->max_colours, rp.n_colours);
+  c->seg_off.assign(c->max_colours + 1, 0);
+  c->seg_groups[0].assign(c->max_colours, 0);
+  c->seg_groups[1].assign(c->max_colours, 0);
+  c->col_trials.assign(c->max_colours, 0);
+  for (int col = 0; col < c->max_colours; ++col) {
+    c->seg_off[col] = (int32_t)seg_rep.size();
+    int32_t g32 = 0, g16 = 0;
+    seg_start[0].push_back(0);
+    seg_start[1].push_back(0);
+    for (int r = 0; r < cfg->n_replicas; ++r) {
+      const Replica &rp = c->reps[r];
+      if (rp.n_colours <= col) continue;
+      seg_rep.push_back(r);
+      g32 += (int32_t)((rp.n_trials + 31) / 32);
+      g16 += (int32_t)((rp.n_trials + 15) / 16);
+      seg_start[0].push_back(g32);
+      seg_start[1].push_back(g16);
+      c->col_trials[col] += rp.n_trials;
+    }
+    c->seg_groups[0][col] = g32;
+    c->seg_groups[1][col] = g16;
+    max_trials = std::max(max_trials, c->col_trials[col]);
+  }
+  c->seg_off[c->max_colours] = (int32_t)seg_rep.size();
   const OmegaTable om = build_omega(cfg->feature == SMC_FEAT_COUNTS_S12 ? kNbrS12 : kNbr);
   c->omega_n = om.count;
   const int R = cfg->n_replicas;
@@ -468,6 +574,8 @@ int smc_init(const smc_config *cfg, uint8_t *occ_dev, const float *params_dev, f
   INIT_HIP(hipMalloc(&c->d_efixed, sizeof(unsigned long long) * R));
   INIT_HIP(hipMalloc(&c->d_escratch, sizeof(double) * R));
   INIT_HIP(hipMalloc(&c->d_counters, sizeof(uint64_t) * 4 * R));
+  INIT_HIP(hipMalloc(&c->d_sweep, sizeof(uint64_t)));
+  INIT_HIP(hipMemset(c->d_sweep, 0, sizeof(uint64_t)));
   if (hipMemcpyAsync(c->d_reps, c->reps.data(), sizeof(Replica) * R, hipMemcpyHostToDevice, c->stream) ||
       hipMemcpyAsync(c->d_omega, om.off.data(), sizeof(om.off), hipMemcpyHostToDevice, c->stream))
     return cleanup(SMC_E_DEVICE);
@@ -483,7 +591,15 @@ int smc_init(const smc_config *cfg, uint8_t *occ_dev, const float *params_dev, f
     INIT_HIP(hipMalloc(&c->d_rowe, sizeof(double) * kRows64 * c->queue_cap));
     INIT_HIP(hipMalloc(&c->d_done, sizeof(uint32_t) * c->queue_cap));
     INIT_HIP(hipMemset(c->d_done, 0, sizeof(uint32_t) * c->queue_cap));
-    INIT_HIP(hipMalloc(&c->d_qcount, sizeof(uint32_t) * (c->colours_total + 2)));
+    INIT_HIP(hipMalloc(&c->d_qcount, sizeof(uint32_t) * (c->max_colours + 2)));
+    INIT_HIP(hipMalloc(&c->d_seg_rep, sizeof(int32_t) * std::max<size_t>(1, seg_rep.size())));
+    for (int k = 0; k < 2; ++k) {
+      INIT_HIP(hipMalloc(&c->d_seg_start[k], sizeof(int32_t) * seg_start[k].size()));
+      INIT_HIP(hipMemcpy(c->d_seg_start[k], seg_start[k].data(), sizeof(int32_t) * seg_start[k].size(),
+                         hipMemcpyHostToDevice));
+    }
+    if (!seg_rep.empty())
+      INIT_HIP(hipMemcpy(c->d_seg_rep, seg_rep.data(), sizeof(int32_t) * seg_rep.size(), hipMemcpyHostToDevice));
     if (hipMemcpy(c->d_reg_off, t.reg_off.data(), sizeof(uint16_t) * t.reg_off.size(), hipMemcpyHostToDevice) ||
         hipMemcpy(c->d_om_off, t.om_off.data(), sizeof(uint16_t) * t.om_off.size(), hipMemcpyHostToDevice) ||
         hipMemcpy(c->d_idx, t.idx.data(), t.idx.size(), hipMemcpyHostToDevice) ||
@@ -670,7 +786,149 @@ int smc_get_sweep(const smc_ctx *c, uint64_t *s) {
 
 int smc_set_sweep(smc_ctx *c, uint64_t s) {
   if (!c) return SMC_E_INVALID;
+  HIPC(c, hipMemcpyAsync(c->d_sweep, &s, sizeof(uint64_t), hipMemcpyHostToDevice, c->stream));
+  HIPC(c, hipStreamSynchronize(c->stream));
   c->sweep = s;
+  return SMC_OK;
+}
+
+int smc_set_variant(smc_ctx *c, int32_t variant) {
+  if (!c || variant < 0 || variant >= kNumVariants) return SMC_E_INVALID;
+  if (variant != c->variant) drop_graph(c);
+  c->variant = variant;
+  return SMC_OK;
+}
+
+int smc_get_variant(const smc_ctx *c, int32_t *variant) {
+  if (!c || !variant) return SMC_E_INVALID;
+  *variant = c->variant;
+  return SMC_OK;
+}
+
+int smc_use_graph(smc_ctx *c, int32_t enable) {
+  if (!c) return SMC_E_INVALID;
+  c->use_graph = enable != 0;
+  if (!c->use_graph) drop_graph(c);
+  return SMC_OK;
+}
+
+int smc_autotune(smc_ctx *c, const char *cache_path, int32_t *chosen, float *ms_per_variant) {
+  if (!c) return SMC_E_INVALID;
+  if (!c->mfma) {
+    if (chosen) *chosen = c->variant;
+    return SMC_OK;  // the per-lane path has a single variant
+  }
+  // cache key: device, precision and the replica shapes
+  hipDeviceProp_t prop{};
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipGetDeviceProperties(&prop, dev);
+  std::string key = std::string(prop.gcnArchName) + "/p" + std::to_string(c->cfg.precision);
+  for (size_t r = 0; r < c->reps.size(); ++r)
+    key += "/" + std::to_string(c->cells[3 * r]) + "x" + std::to_string(c->cells[3 * r + 1]) + "x" +
+           std::to_string(c->cells[3 * r + 2]);
+  if (key.size() > 200) key = key.substr(0, 120) + "/n" + std::to_string(c->reps.size()) + "/s" + std::to_string(c->n_total);
+  if (cache_path) {
+    FILE *f = fopen(cache_path, "r");
+    if (f) {
+      char line[512];
+      while (fgets(line, sizeof line, f)) {
+        int v = -1;
+        char k[400];
+        if (sscanf(line, "{\"key\": \"%399[^\"]\", \"variant\": %d", k, &v) == 2 && key == k && v >= 0 &&
+            v < kNumVariants) {
+          fclose(f);
+          if (chosen) *chosen = v;
+          return smc_set_variant(c, v);
+        }
+      }
+      fclose(f);
+    }
+  }
+  // time every variant on the same sweep from the same state; all must agree bit for bit
+  const size_t R = c->reps.size(), N = (size_t)c->n_total;
+  uint8_t *occ0 = nullptr, *occ1 = nullptr;
+  float *ec0 = nullptr;
+  unsigned long long *ef0 = nullptr;
+  uint64_t *cnt0 = nullptr;
+  int rc = SMC_OK;
+  if (hipMalloc(&occ0, N) || hipMalloc(&occ1, N) || hipMalloc(&ec0, 4 * N) || hipMalloc(&ef0, 8 * R) ||
+      hipMalloc(&cnt0, 32 * R))
+    rc = fail(c, SMC_E_NOMEM, "autotune buffers");
+  const uint64_t sweep0 = c->sweep;
+  const int v0 = c->variant;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (!rc && (hipEventCreate(&e0) || hipEventCreate(&e1))) rc = fail(c, SMC_E_DEVICE, "autotune events");
+  if (!rc && (hipMemcpyAsync(occ0, c->occ, N, hipMemcpyDeviceToDevice, c->stream) ||
+              hipMemcpyAsync(ec0, c->ecache, 4 * N, hipMemcpyDeviceToDevice, c->stream) ||
+              hipMemcpyAsync(ef0, c->d_efixed, 8 * R, hipMemcpyDeviceToDevice, c->stream) ||
+              hipMemcpyAsync(cnt0, c->d_counters, 32 * R, hipMemcpyDeviceToDevice, c->stream)))
+    rc = fail(c, SMC_E_DEVICE, "autotune save");
+  int best = v0;
+  float best_ms = 1e30f;
+  std::vector<uint8_t> ref, got;
+  for (int v = 0; v < kNumVariants && !rc; ++v) {
+    if ((rc = smc_set_variant(c, v)) || (rc = smc_set_sweep(c, sweep0))) break;
+    if (hipMemcpyAsync(c->occ, occ0, N, hipMemcpyDeviceToDevice, c->stream) ||
+        hipMemcpyAsync(c->ecache, ec0, 4 * N, hipMemcpyDeviceToDevice, c->stream)) {
+      rc = fail(c, SMC_E_DEVICE, "autotune restore");
+      break;
+    }
+    if ((rc = run_sweep(c, nullptr, false))) break;  // warm (graph build); same sweep replayed below
+    if ((rc = smc_set_sweep(c, sweep0))) break;
+    if (hipMemcpyAsync(c->occ, occ0, N, hipMemcpyDeviceToDevice, c->stream) ||
+        hipMemcpyAsync(c->ecache, ec0, 4 * N, hipMemcpyDeviceToDevice, c->stream) ||
+        hipEventRecord(e0, c->stream)) {
+      rc = fail(c, SMC_E_DEVICE, "autotune restore");
+      break;
+    }
+    if ((rc = run_sweep(c, nullptr, false))) break;
+    float ms = 0.0f;
+    if (hipEventRecord(e1, c->stream) || hipEventSynchronize(e1) || hipEventElapsedTime(&ms, e0, e1)) {
+      rc = fail(c, SMC_E_DEVICE, "autotune timing");
+      break;
+    }
+    if (ms_per_variant) ms_per_variant[v] = ms;
+    // bit-exactness gate against the first variant
+    got.resize(N);
+    if (hipMemcpy(got.data(), c->occ, N, hipMemcpyDeviceToHost)) {
+      rc = fail(c, SMC_E_DEVICE, "autotune compare");
+      break;
+    }
+    if (v == 0) ref = got;
+    else if (got != ref) {
+      rc = fail(c, SMC_E_STATE, "kernel variant " + std::to_string(v) + " is not bit-identical to variant 0");
+      break;
+    }
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = v;
+    }
+  }
+  // restore the caller's state and the chosen variant
+  if (occ0 && ec0) {
+    (void)hipMemcpyAsync(c->occ, occ0, N, hipMemcpyDeviceToDevice, c->stream);
+    (void)hipMemcpyAsync(c->ecache, ec0, 4 * N, hipMemcpyDeviceToDevice, c->stream);
+    (void)hipMemcpyAsync(c->d_efixed, ef0, 8 * R, hipMemcpyDeviceToDevice, c->stream);
+    (void)hipMemcpyAsync(c->d_counters, cnt0, 32 * R, hipMemcpyDeviceToDevice, c->stream);
+  }
+  const int rc2 = smc_set_sweep(c, sweep0);
+  (void)smc_set_variant(c, rc ? v0 : best);
+  (void)hipStreamSynchronize(c->stream);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  for (void *p : {(void *)occ0, (void *)occ1, (void *)ec0, (void *)ef0, (void *)cnt0})
+    if (p) (void)hipFree(p);
+  if (rc) return rc;
+  if (rc2) return rc2;
+  if (chosen) *chosen = best;
+  if (cache_path) {
+    FILE *f = fopen(cache_path, "a");
+    if (f) {
+      fprintf(f, "{\"key\": \"%s\", \"variant\": %d, \"ms\": %.4f}\n", key.c_str(), best, best_ms);
+      fclose(f);
+    }
+  }
   return SMC_OK;
 }
 
@@ -690,10 +948,12 @@ void smc_destroy(smc_ctx *c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
+  drop_graph(c);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   void *bufs[] = {c->d_reps, c->d_w32, c->d_w64, c->d_w64t, c->d_omega, c->d_reg_off, c->d_om_off, c->d_idx,
                   c->d_reg_pos, c->d_queue, c->d_rowe, c->d_done, c->d_qcount, c->d_ebase, c->d_efixed, c->d_escratch,
                   c->d_counters, c->d_site64, c->packs[0].dev, c->packs[1].dev, c->packs[2].dev,
-                  c->packs[3].dev};
+                  c->packs[3].dev, c->d_seg_rep, c->d_seg_start[0], c->d_seg_start[1], c->d_sweep};
   for (void *p : bufs)
     if (p) (void)hipFree(p);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);

@@ -1,7 +1,9 @@
 // Swap kernels of the matrix-core path (one-hot features over shells 1-3, 128 hidden).
 //
-// One launch per colour (mini-step).  A persistent block of 512 threads keeps the packed
-// weights and the lookup tables in LDS and walks groups of 32 link cells as a pipeline:
+// One launch per colour index (mini-step) processes that colour of every replica whose
+// schedule has it (replicas of uneven size are independent and share the launch).  A
+// persistent block of 512 threads keeps the packed weights and the lookup tables in LDS and
+// walks groups of GROUP link cells as a pipeline:
 //   proposal (group g+2): Philox block per trial, partner, species, threshold theta (FP64);
 //      same-species trials are finished here, the others compacted;
 //   gather (group g+1, issued before the energies of group g and consumed after them): the
@@ -22,14 +24,11 @@
 
 namespace smc {
 
-constexpr int kGroup = 32;
 constexpr int kMfmaThreads = 512;
 constexpr int kReg = 192;
 constexpr int kOm = 40;
 constexpr int kIdxRow = 28;
-constexpr int kPfReg = (kGroup * kReg + kMfmaThreads - 1) / kMfmaThreads;  // 12 region bytes per thread
-constexpr int kPfOm = (kGroup * kOm + kMfmaThreads - 1) / kMfmaThreads;    // 3 cached energies per thread
-constexpr int kPart = 8;                                                    // dE partial sums per trial
+constexpr int kPart = 8;  // dE partial sums per trial
 
 struct RecheckEntry {
   int64_t site;      // replica-local trial site
@@ -53,15 +52,19 @@ struct MfmaArgs {
   float b2;
   int32_t k_a0, k_a1, k_h;
   float sh;
-  int32_t replica, colour;
-  uint64_t seed, sweep;
+  int32_t colour;           // colour index of this launch
+  const int32_t *seg_rep;   // [nseg] replicas that have this colour
+  const int32_t *seg_start; // [nseg + 1] first flattened group of each replica
+  int32_t nseg;
+  int32_t xcd_order;        // 1: each XCD walks a contiguous range of groups
+  uint64_t seed;
+  const uint64_t *sweep;    // device sweep counter (graph replays advance it)
   double guard;
   uint32_t *q_count;        // queue length of this colour
   RecheckEntry *queue;
   unsigned long long *e_fixed;  // [R] accepted dE in units of 2^-32 eV
   uint64_t *counters;           // [4][R]
   int32_t n_replicas;
-  int32_t n_groups;
   double *trace_dE;
   double *trace_dE_fast;
   uint8_t *trace_flags;
@@ -74,33 +77,33 @@ __device__ __forceinline__ void unpack_off(uint32_t v, int &dx, int &dy, int &dz
 }
 
 // Per-trial data of one group (three groups in flight).
+template <int GROUP>
 struct TrialBuf {
-  int32_t site[kGroup], part[kGroup], px[kGroup], py[kGroup], pz[kGroup];
-  double theta[kGroup];
-  uint8_t dir[kGroup], si[kGroup], sn[kGroup];
-  int32_t nact;
+  int32_t site[GROUP], part[GROUP], px[GROUP], py[GROUP], pz[GROUP];
+  double theta[GROUP];
+  uint8_t dir[GROUP], si[GROUP], sn[GROUP];
+  int32_t nact, nvalid, rep;
 };
 
-template <int P>
+template <int P, int GROUP>
 __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) {
   constexpr int kW = pack_bytes<P>();
+  constexpr int kPfReg = (GROUP * kReg + kMfmaThreads - 1) / kMfmaThreads;  // region bytes per thread
+  constexpr int kPfOm = (GROUP * kOm + kMfmaThreads - 1) / kMfmaThreads;    // cached energies per thread
   __shared__ __attribute__((aligned(16))) uint8_t s_w[kW];
   __shared__ __attribute__((aligned(16))) uint8_t s_idx[8 * kOm * kIdxRow];
   __shared__ uint16_t s_roff[8 * kReg];
   __shared__ uint16_t s_ooff[8 * kOm];
   __shared__ uint8_t s_rpos[16];
-  __shared__ uint8_t s_reg[kGroup * kReg];
-  __shared__ float s_e[kGroup * kOm];
-  __shared__ float s_ec[kGroup * kOm];
-  __shared__ float s_psum[kGroup * kPart];
-  __shared__ TrialBuf s_tb[3];
-  __shared__ uint8_t s_acc[kGroup];
+  __shared__ uint8_t s_reg[GROUP * kReg];
+  __shared__ float s_e[GROUP * kOm];
+  __shared__ float s_ec[GROUP * kOm];
+  __shared__ float s_psum[GROUP * kPart];
+  __shared__ TrialBuf<GROUP> s_tb[3];
+  __shared__ uint8_t s_acc[GROUP];
   __shared__ int s_tile;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const Replica R = a.reps[a.replica];
-  uint8_t *occ = a.occ + R.site0;
-  float *ec = a.ecache + R.site0;
 
   for (int q = tid; q < kW / 16; q += kMfmaThreads) ((int4 *)s_w)[q] = ((const int4 *)a.wpack)[q];
   for (int q = tid; q < 8 * kOm * kIdxRow / 4; q += kMfmaThreads) ((int *)s_idx)[q] = ((const int *)a.idx)[q];
@@ -117,24 +120,56 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
   S.k_scale_a1 = a.k_a1;
   S.k_scale_h = a.k_h;
   S.sh = a.sh;
+  const uint64_t sweep = *a.sweep;
 
-  // XCD-aware group order: blocks b and b+8k share an XCD (round-robin dispatch), so each
-  // XCD walks one contiguous eighth of the colour's link cells.
+  // Flattened groups of all participating replicas.  XCD-aware order: blocks b and b+8k
+  // share an XCD (round-robin dispatch), so each XCD walks one contiguous eighth.
+  const int n_groups = a.seg_start[a.nseg];
   const int G = gridDim.x;
-  int gstart = blockIdx.x, gstep = G, gend = a.n_groups;
-  if (G % 8 == 0 && G >= 8) {
-    const int x = blockIdx.x & 7, j = blockIdx.x >> 3, per = (a.n_groups + 7) / 8;
+  int gstart = blockIdx.x, gstep = G, gend = n_groups;
+  if (a.xcd_order && G % 8 == 0 && G >= 8) {
+    const int x = blockIdx.x & 7, j = blockIdx.x >> 3, per = (n_groups + 7) / 8;
     gstart = x * per + j;
     gstep = G / 8;
-    gend = min(a.n_groups, (x + 1) * per);
+    gend = min(n_groups, (x + 1) * per);
   }
+  // per-replica statistics, flushed when the block moves to another replica
+  int stat_rep = -1;
   uint32_t cnt_att = 0, cnt_diff = 0, cnt_acc = 0;
   long long fixed_sum = 0;
+  auto flush = [&]() {
+    if (tid == 0 && stat_rep >= 0) {
+      const int Rn = a.n_replicas;
+      atomicAdd(&a.e_fixed[stat_rep], (unsigned long long)fixed_sum);
+      atomicAdd((unsigned long long *)&a.counters[0 * Rn + stat_rep], (unsigned long long)cnt_att);
+      atomicAdd((unsigned long long *)&a.counters[1 * Rn + stat_rep], (unsigned long long)cnt_diff);
+      atomicAdd((unsigned long long *)&a.counters[2 * Rn + stat_rep], (unsigned long long)cnt_acc);
+    }
+    cnt_att = cnt_diff = cnt_acc = 0;
+    fixed_sum = 0;
+  };
+
+  // replica and replica-local group of a flattened group (binary search over the segments)
+  auto locate = [&](int grp, int &rep, int &lgrp) {
+    int lo = 0, hi = a.nseg - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (a.seg_start[mid] <= grp) lo = mid;
+      else hi = mid - 1;
+    }
+    rep = a.seg_rep[lo];
+    lgrp = grp - a.seg_start[lo];
+  };
 
   // proposal for one group into a trial buffer (wave 0)
-  auto propose = [&](int grp, TrialBuf &tb) {
-    const int64_t t = (int64_t)grp * kGroup + lane;
-    const int64_t i = (grp < gend && lane < kGroup && t < R.n_trials) ? trial_site(R, a.colour, t) : -1;
+  auto propose = [&](int grp, TrialBuf<GROUP> &tb) {
+    int rep = 0, lgrp = 0;
+    const bool live = grp < gend;
+    if (live) locate(grp, rep, lgrp);
+    const Replica &R = a.reps[rep];
+    const uint8_t *occ = a.occ + R.site0;
+    const int64_t t = (int64_t)lgrp * GROUP + lane;
+    const int64_t i = (live && lane < GROUP && t < R.n_trials) ? trial_site(R, a.colour, t) : -1;
     bool active = false;
     int d = 0;
     double theta = 0.0;
@@ -142,7 +177,7 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
     int64_t n = 0;
     uint8_t si = 0, sn = 0;
     if (i >= 0) {
-      const U64x4 r = philox4x64_10((uint64_t)i, a.sweep, (uint64_t)a.replica, 0, a.seed, 0);
+      const U64x4 r = philox4x64_10((uint64_t)i, sweep, (uint64_t)rep, 0, a.seed, 0);
       d = (int)(r.v[0] >> 61);
       const double u = (double)((r.v[1] >> 11) + 1) * 0x1.0p-53;
       theta = isinf(R.temperature) ? (double)INFINITY : -kBoltzmannEvPerK * R.temperature * log(u);
@@ -173,16 +208,19 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
     }
     if (lane == 0) {
       tb.nact = __popcll(act_mask);
-      cnt_att += __popcll(valid);
-      cnt_diff += __popcll(act_mask);
+      tb.nvalid = __popcll(valid);
+      tb.rep = rep;
     }
   };
 
   // gather loads of one group into registers (the loads stay in flight until used)
   uint8_t pf_reg[kPfReg];
   float pf_om[kPfOm];
-  auto gather_issue = [&](const TrialBuf &tb) {
+  auto gather_issue = [&](const TrialBuf<GROUP> &tb) {
     const int nact = tb.nact;
+    const Replica &R = a.reps[tb.rep];
+    const uint8_t *occ = a.occ + R.site0;
+    const float *ec = a.ecache + R.site0;
 #pragma unroll
     for (int j = 0; j < kPfReg; ++j) {
       const int q = tid + j * kMfmaThreads;
@@ -204,7 +242,7 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
       }
     }
   };
-  auto gather_store = [&](const TrialBuf &tb) {
+  auto gather_store = [&](const TrialBuf<GROUP> &tb) {
     const int nact = tb.nact;
 #pragma unroll
     for (int j = 0; j < kPfReg; ++j) {
@@ -236,14 +274,17 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
 
   int it = 0;
   for (int grp = gstart; grp < gend; grp += gstep, ++it) {
-    TrialBuf &cur = s_tb[it % 3];
-    TrialBuf &nxt = s_tb[(it + 1) % 3];
-    TrialBuf &nxt2 = s_tb[(it + 2) % 3];
+    TrialBuf<GROUP> &cur = s_tb[it % 3];
+    TrialBuf<GROUP> &nxt = s_tb[(it + 1) % 3];
+    TrialBuf<GROUP> &nxt2 = s_tb[(it + 2) % 3];
     // ------------------------------------------------------------ gather (g) into LDS
     gather_store(cur);
     if (tid == 0) s_tile = 0;
     __syncthreads();
     const int nact = cur.nact;
+    const Replica &R = a.reps[cur.rep];
+    uint8_t *occ = a.occ + R.site0;
+    float *ec = a.ecache + R.site0;
     // ------------------------------------------------------------ gather (g+1) in flight
     if (grp + gstep < gend) gather_issue(nxt);
     // ------------------------------------------------------------ proposal (g+2), wave 0
@@ -295,7 +336,7 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
           e.partner = cur.part[lane];
           e.theta = theta;
           e.dE_fast = dE;
-          e.replica = a.replica;
+          e.replica = cur.rep;
           e.dir = cur.dir[lane];
           for (int k = 0; k < kOm; ++k) e.e1[k] = s_e[lane * kOm + k];
           if (a.trace_dE_fast) a.trace_dE_fast[R.site0 + i] = dEd;
@@ -319,7 +360,13 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
         v += (lane + off < 32) ? o : 0.0;
       }
       if (lane == 0) {
+        if (cur.rep != stat_rep) {
+          flush();
+          stat_rep = cur.rep;
+        }
         fixed_sum += to_fixed(v);
+        cnt_att += cur.nvalid;
+        cnt_diff += nact;
         cnt_acc += __popcll(acc_mask);
       }
     }
@@ -334,19 +381,14 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
     }
     __syncthreads();
   }
-  if (tid == 0) {
-    const int Rn = a.n_replicas;
-    atomicAdd(&a.e_fixed[a.replica], (unsigned long long)fixed_sum);
-    atomicAdd((unsigned long long *)&a.counters[0 * Rn + a.replica], (unsigned long long)cnt_att);
-    atomicAdd((unsigned long long *)&a.counters[1 * Rn + a.replica], (unsigned long long)cnt_diff);
-    atomicAdd((unsigned long long *)&a.counters[2 * Rn + a.replica], (unsigned long long)cnt_acc);
-  }
+  flush();
 }
 
-// FP64 re-decision of queued near-threshold trials.  One block per trial step evaluates the
-// 80 local energies (the 40 zone sites after and before the swap) cooperatively: layer 0 as
-// the sum of the 27 selected columns of W0 in slot order, layer 1 with one thread per
-// (hidden unit, half of the rows), activations staged in LDS.
+// Advance the device sweep counter (last node of a sweep).
+__global__ void k_next_sweep(uint64_t *sweep) {
+  if (threadIdx.x == 0) *sweep += 1;
+}
+
 struct RecheckArgs {
   const Replica *reps;
   uint8_t *occ;
