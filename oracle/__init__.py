@@ -15,6 +15,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "smc_oracle.c")
+SOURCES = [SRC, os.path.join(HERE, "fit_oracle.c")]
 LIB = os.path.join(HERE, "liboracle.so")
 
 FEAT_COUNTS_S12, FEAT_ONEHOT_S123 = 0, 1
@@ -24,10 +25,11 @@ KB_EV_PER_K = 8.617333262e-5
 
 
 def build(force: bool = True) -> str:
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+    stale = not os.path.exists(LIB) or any(os.path.getmtime(LIB) < os.path.getmtime(f) for f in SOURCES)
+    if force or stale:
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
                                "-Wall", "-Wextra", "-Wno-unused-parameter",
-                               SRC, "-o", LIB + ".tmp", "-lm"], cwd=HERE)
+                               *SOURCES, "-o", LIB + ".tmp", "-lm"], cwd=HERE)
         os.replace(LIB + ".tmp", LIB)
     return LIB
 
@@ -35,6 +37,12 @@ def build(force: bool = True) -> str:
 class Model(C.Structure):
     _fields_ = [("feature", C.c_int32), ("hidden", C.c_int32), ("act0", C.c_int32),
                 ("act1", C.c_int32), ("params", C.POINTER(C.c_double))]
+
+
+class CE(C.Structure):
+    _fields_ = [("n_species", C.c_int32), ("pair", C.POINTER(C.c_double)), ("n_items", C.c_int32),
+                ("offsets", C.POINTER(C.c_int32)), ("species", C.POINTER(C.c_uint8)),
+                ("J", C.POINTER(C.c_double))]
 
 
 class TrialRec(C.Structure):
@@ -92,6 +100,16 @@ def lib():
                                    C.c_int64, C.POINTER(Stats), C.c_void_p, C.c_int32, i64p,
                                    C.c_int32, C.c_int32]),
             "or_warren_cowley": (None, [i32p, u8p, C.c_int32, f64p]),
+            "or_ce_triangles": (C.c_int32, [i32p, C.c_int32]),
+            "or_ce_site_energy": (C.c_double, [i32p, C.POINTER(CE), u8p, C.c_int64]),
+            "or_ce_total_local": (C.c_double, [i32p, C.POINTER(CE), u8p]),
+            "or_ce_total_brute": (C.c_double, [i32p, C.POINTER(CE), u8p]),
+            "or_n_params": (C.c_int64, [C.POINTER(Model)]),
+            "or_energy_grad": (None, [i32p, C.POINTER(Model), u8p, C.c_int32, f64p, f64p, f64p, C.c_int32]),
+            "or_fit_loss_grad": (C.c_double, [i32p, C.POINTER(Model), u8p, C.c_int32, f64p, f64p, f64p,
+                                              C.c_int32]),
+            "or_fit_fd": (None, [i32p, C.POINTER(Model), u8p, C.c_int32, f64p, i64p, C.c_int32, C.c_double,
+                                 f64p, C.c_int32]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -270,3 +288,83 @@ def warren_cowley(cells, occ, n_species) -> np.ndarray:
     lib().or_warren_cowley(_ptr(_dims(cells), C.c_int32), _ptr(occ, C.c_uint8), n_species,
                            _ptr(a, C.c_double))
     return a
+
+
+# ---------------------------------------------------------------- differentiation pattern
+
+class CEModel:
+    """FP64 view of a cluster-expansion Hamiltonian: pair[3][S][S], and items of
+    (canonical triangle offsets [6], species triple [3], J)."""
+
+    def __init__(self, n_species, pair, offsets, species, J):
+        self.n_species = int(n_species)
+        self.pair = np.ascontiguousarray(np.asarray(pair, dtype=np.float64).reshape(3, n_species, n_species))
+        self.offsets = np.ascontiguousarray(np.asarray(offsets, dtype=np.int32).reshape(-1, 6))
+        self.species = np.ascontiguousarray(np.asarray(species, dtype=np.uint8).reshape(-1, 3))
+        self.J = np.ascontiguousarray(np.asarray(J, dtype=np.float64).reshape(-1))
+        self._c = CE(self.n_species, _ptr(self.pair, C.c_double), len(self.J), _ptr(self.offsets, C.c_int32),
+                     _ptr(self.species, C.c_uint8), _ptr(self.J, C.c_double))
+
+    @property
+    def c(self):
+        return C.byref(self._c)
+
+
+def ce_triangles() -> np.ndarray:
+    out = np.zeros((1024, 6), dtype=np.int32)
+    n = lib().or_ce_triangles(_ptr(out, C.c_int32), 1024)
+    return out[:n].copy()
+
+
+def ce_site_energy(cells, ce: CEModel, occ, s) -> float:
+    occ = np.ascontiguousarray(occ, dtype=np.uint8)
+    return float(lib().or_ce_site_energy(_ptr(_dims(cells), C.c_int32), ce.c, _ptr(occ, C.c_uint8), int(s)))
+
+
+def ce_total(cells, ce: CEModel, occ, brute=False) -> float:
+    occ = np.ascontiguousarray(occ, dtype=np.uint8)
+    f = lib().or_ce_total_brute if brute else lib().or_ce_total_local
+    return float(f(_ptr(_dims(cells), C.c_int32), ce.c, _ptr(occ, C.c_uint8)))
+
+
+def snapshot_energies(cells, model: MLP, snaps, nthreads=8) -> np.ndarray:
+    snaps = np.ascontiguousarray(snaps, dtype=np.uint8)
+    B = snaps.shape[0]
+    S = np.zeros(B)
+    lib().or_energy_grad(_ptr(_dims(cells), C.c_int32), model.c, _ptr(snaps, C.c_uint8), B,
+                         _ptr(S, C.c_double), None, None, nthreads)
+    return S
+
+
+def energy_grad(cells, model: MLP, snaps, gE, nthreads=8) -> np.ndarray:
+    """sum_b gE[b] dS_b/dparams (FP64)."""
+    snaps = np.ascontiguousarray(snaps, dtype=np.uint8)
+    gE = np.ascontiguousarray(gE, dtype=np.float64)
+    g = np.zeros(model.params.size)
+    lib().or_energy_grad(_ptr(_dims(cells), C.c_int32), model.c, _ptr(snaps, C.c_uint8), snaps.shape[0],
+                         None, _ptr(gE, C.c_double), _ptr(g, C.c_double), nthreads)
+    return g
+
+
+def fit_loss_grad(cells, model: MLP, snaps, labels, nthreads=8, want_grad=True):
+    """(loss, S[batch], grad|None) of loss = mean_b ((S_b - E_b)/N)^2."""
+    snaps = np.ascontiguousarray(snaps, dtype=np.uint8)
+    labels = np.ascontiguousarray(labels, dtype=np.float64)
+    B = snaps.shape[0]
+    S = np.zeros(B)
+    g = np.zeros(model.params.size) if want_grad else None
+    loss = lib().or_fit_loss_grad(_ptr(_dims(cells), C.c_int32), model.c, _ptr(snaps, C.c_uint8), B,
+                                  _ptr(labels, C.c_double), _ptr(S, C.c_double),
+                                  _ptr(g, C.c_double) if g is not None else None, nthreads)
+    return float(loss), S, g
+
+
+def fit_fd(cells, model: MLP, snaps, labels, idx, h=1e-6, nthreads=8) -> np.ndarray:
+    snaps = np.ascontiguousarray(snaps, dtype=np.uint8)
+    labels = np.ascontiguousarray(labels, dtype=np.float64)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    out = np.zeros(idx.size)
+    lib().or_fit_fd(_ptr(_dims(cells), C.c_int32), model.c, _ptr(snaps, C.c_uint8), snaps.shape[0],
+                    _ptr(labels, C.c_double), _ptr(idx, C.c_int64), idx.size, float(h), _ptr(out, C.c_double),
+                    nthreads)
+    return out

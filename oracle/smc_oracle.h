@@ -92,6 +92,28 @@ int or_sweep(const int32_t L[3], const or_model *m, uint8_t *occ, double tempera
 /* Observables. alpha is [3][S][S]. */
 void or_warren_cowley(const int32_t L[3], const uint8_t *occ, int32_t n_species, double *alpha);
 
+/* Differentiation pattern (fit_oracle.c). */
+typedef struct {
+  int32_t n_species;
+  const double *pair;      /* [3][S][S], symmetric; shell m = 1..3 at index m - 1 */
+  int32_t n_items;
+  const int32_t *offsets;  /* [n_items][6]: canonical triangle, vertices 1 and 2 relative to vertex 0 */
+  const uint8_t *species;  /* [n_items][3]: species at vertices 0, 1, 2 */
+  const double *J;         /* [n_items] eV */
+} or_ce;
+
+int32_t or_ce_triangles(int32_t *out, int32_t max);
+double or_ce_site_energy(const int32_t L[3], const or_ce *ce, const uint8_t *occ, int64_t s);
+double or_ce_total_local(const int32_t L[3], const or_ce *ce, const uint8_t *occ);
+double or_ce_total_brute(const int32_t L[3], const or_ce *ce, const uint8_t *occ);
+int64_t or_n_params(const or_model *m);
+void or_energy_grad(const int32_t L[3], const or_model *m, const uint8_t *snaps, int32_t batch, double *S,
+                    const double *gE, double *grad, int32_t nthreads);
+double or_fit_loss_grad(const int32_t L[3], const or_model *m, const uint8_t *snaps, int32_t batch,
+                        const double *labels, double *S_out, double *grad, int32_t nthreads);
+void or_fit_fd(const int32_t L[3], const or_model *m, const uint8_t *snaps, int32_t batch, const double *labels,
+               const int64_t *idx, int32_t n, double h, double *out, int32_t nthreads);
+
 #ifdef __cplusplus
 }
 #endif

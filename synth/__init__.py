@@ -20,7 +20,8 @@ them; see the paper's Sec. IV-B/IV-C for the originals):
           strong-scaling system on 32 devices (Sec. V-B).
 * ``c4``  96 replicas, cube edges uniform in 16..96 cells, 4 species with random
           compositions in [0.1, 0.4], temperatures log-spaced 300..3000 K.
-* ``c5``  fit workload: 16^3-cell snapshots, 108-input model.
+* ``c5``  fit workload: 16^3-cell snapshots, 108-input model, labels from a seeded
+          cluster-expansion Hamiltonian (``ce_params``), batches of 1,024 snapshots.
 """
 from __future__ import annotations
 
@@ -133,6 +134,51 @@ def replica_set(n_replicas: int = 96, seed: int = SEED_REPLICAS, edge_lo: int = 
     comps = [dirichlet_composition(rng) for _ in range(n_replicas)]
     temps = [300.0 * 10.0 ** (r / (n_replicas - 1)) for r in range(n_replicas)]
     return [int(e) for e in edges], comps, temps
+
+
+N_CE_TRIANGLES = 44  # distinct BCC triangle shapes with all three edges within shell 3
+
+
+def ce_params(n_species: int = 4, n_items: int = 200, n_triangles: int = N_CE_TRIANGLES,
+              seed: int = SEED_CE) -> dict:
+    """Random draws of the reference cluster-expansion Hamiltonian.
+
+    pair[m][p][q] = pair[m][q][p] ~ N(0, 0.03 eV) for shells m = 0..2 (drawn for p <= q in
+    order m, p, q); then ``n_items`` distinct (triangle index, species triple) items, the
+    triangle index uniform over the ``n_triangles`` canonical shapes (numbered in the
+    lexicographic order of their canonical offsets) and each species uniform, duplicates
+    redrawn; then J ~ N(0, 0.01 eV) per item."""
+    rng = np.random.default_rng(seed)
+    S = n_species
+    pair = np.zeros((3, S, S))
+    for m in range(3):
+        for p in range(S):
+            for q in range(p, S):
+                pair[m, p, q] = pair[m, q, p] = rng.normal(0.0, 0.03)
+    seen, tri, sp = set(), [], []
+    while len(tri) < n_items:
+        t = int(rng.integers(n_triangles))
+        trip = tuple(int(v) for v in rng.integers(0, S, size=3))
+        if (t, trip) in seen:
+            continue
+        seen.add((t, trip))
+        tri.append(t)
+        sp.append(trip)
+    J = rng.normal(0.0, 0.01, size=n_items)
+    return {"n_species": S, "pair": pair, "triangle": np.asarray(tri, dtype=np.int32),
+            "species": np.asarray(sp, dtype=np.uint8), "J": J}
+
+
+def snapshots(n: int, cells: int = 16, n_species: int = 4, seed: int = SEED_LATTICE + 100) -> np.ndarray:
+    """``n`` snapshots (uint8 [n][2 cells^3]) with compositions drawn like the replica set
+    (Dirichlet, every species in [0.1, 0.4]) and uniformly random placement."""
+    rng = np.random.default_rng(seed)
+    N = 2 * cells ** 3
+    out = np.empty((n, N), dtype=np.uint8)
+    for b in range(n):
+        counts = species_counts(N, dirichlet_composition(rng, n_species))
+        out[b] = rng.permutation(np.repeat(np.arange(n_species, dtype=np.uint8), counts))
+    return out
 
 
 def workload(name: str, **over) -> Workload:
