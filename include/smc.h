@@ -176,6 +176,63 @@ int smc_set_variant(smc_ctx *ctx, int32_t variant);
 int smc_get_variant(const smc_ctx *ctx, int32_t *variant);
 int smc_autotune(smc_ctx *ctx, const char *cache_path, int32_t *chosen, float *ms_per_variant);
 
+/* ---- Differentiation (Sec. IV-B: the energy model is trained by gradient descent with
+ * backpropagation; here it is fitted to a synthetic reference Hamiltonian).
+ * Snapshots: uint8 device [batch][2 L^3], each a periodic BCC lattice of L cells per axis
+ * (4 <= L <= 1024) in the sweep lattice's layout.  Model: the FP32 blob params_dev (same
+ * layout as smc_init's), one-hot features, 128 hidden units (else SMC_E_UNSUPPORTED).
+ * Arithmetic follows the context's precision: SMC_BF16 runs the matrix cores (BF16 operands,
+ * FP32 accumulation); SMC_FP32 and SMC_FP64 run plain per-row evaluators in that precision
+ * (reference mode); other precisions give SMC_E_UNSUPPORTED.  Sums over rows are taken in a
+ * fixed order, so repeated calls give identical results.  All asynchronous on the context's
+ * stream unless stated; work buffers are allocated on first use and kept until smc_destroy. */
+
+/* e_out_dev: double device [batch], S_b = sum over the sites of snapshot b of the local
+ * energy (Eqs. (4)-(6)). */
+int smc_energy_fwd(smc_ctx *ctx, const uint8_t *snap_dev, int32_t batch, int32_t cells_per_axis,
+                   const float *params_dev, double *e_out_dev);
+
+/* Backward of smc_energy_fwd: grad_params_dev (float device [n_params], overwritten) =
+ * sum_b grad_e_dev[b] * dS_b/dparams, grad_e_dev double device [batch].  The hand-written
+ * reverse pass of the MLP (no autodiff). */
+int smc_energy_bwd(smc_ctx *ctx, const uint8_t *snap_dev, int32_t batch, int32_t cells_per_axis,
+                   const float *params_dev, const double *grad_e_dev, float *grad_params_dev);
+
+/* One training step on a batch: S = smc_energy_fwd(...); loss = mean_b ((S_b - E_b)/N)^2
+ * with labels E (label_dev, double device [batch]) and N = 2 L^3; gradient by the backward
+ * pass; Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected with step >= 1, learning rate
+ * lr > 0) updating params_dev (FP32 masters) and the moments adam_m_dev, adam_v_dev (float
+ * device [n_params], zero before step 1) in place.  loss_host (nullable): the loss before
+ * the update; giving it synchronises.  Low-precision copies used by sweeps are not touched:
+ * call smc_set_params after fitting to sweep with the new model. */
+int smc_fit_step(smc_ctx *ctx, const uint8_t *snap_dev, int32_t batch, int32_t cells_per_axis,
+                 const double *label_dev, float *params_dev, float *adam_m_dev, float *adam_v_dev,
+                 float lr, int32_t step, double *loss_host);
+
+/* Cluster-expansion reference Hamiltonian (the labels of the fit):
+ * E = sum over shells m = 1..3 and unordered site pairs at that distance of pair[m-1][p][q]
+ *   + sum over items k of J[k] * #{translations of triangle shape triangle[k] whose vertices
+ *     0, 1, 2 carry species species[k][0..2]}.
+ * Triangle shapes: every point set {0, a, b} with a, b and a - b among the 26 shell-1..3
+ * vectors, translated so that its lexicographically smallest point is the origin, written
+ * (a, b) with a < b in doubled coordinates, numbered in lexicographic order of (a, b);
+ * smc_ce_triangles lists them (44). */
+typedef struct {
+  int32_t n_species;        /* 2..5 */
+  const double *pair;       /* host [3][S][S], symmetric, eV */
+  int32_t n_items;
+  const int32_t *triangle;  /* host [n_items], index into the shape list */
+  const uint8_t *species;   /* host [n_items][3] */
+  const double *J;          /* host [n_items], eV */
+} smc_ce;
+
+/* e_out_dev: double device [batch], CE energy of each snapshot.  Synchronises. */
+int smc_ce_energy(smc_ctx *ctx, const smc_ce *ce, const uint8_t *snap_dev, int32_t batch,
+                  int32_t cells_per_axis, double *e_out_dev);
+
+/* Triangle shapes: out_host [max][6] (nullable), count (nullable) = number of shapes. */
+int smc_ce_triangles(int32_t *out_host, int32_t max, int32_t *count);
+
 /* Total sites over all replicas, and number of colours (mini-steps) of a replica. */
 int smc_n_sites(const smc_ctx *ctx, int64_t *n);
 int smc_n_colours(const smc_ctx *ctx, int32_t replica, int32_t *n);

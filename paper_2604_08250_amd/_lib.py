@@ -24,6 +24,7 @@ PRECISIONS = {"fp32": SMC_FP32, "bf16": SMC_BF16, "bf16x3": SMC_BF16X3, "fp8": S
 EXPORTS = ["smc_init", "smc_sweep", "smc_energy", "smc_site_energies", "smc_set_params",
            "smc_refresh", "smc_counters", "smc_delta_e64", "smc_profile", "smc_kernel_times", "smc_get_sweep",
            "smc_set_sweep", "smc_use_graph", "smc_set_variant", "smc_get_variant", "smc_autotune",
+           "smc_energy_fwd", "smc_energy_bwd", "smc_fit_step", "smc_ce_energy", "smc_ce_triangles",
            "smc_n_sites", "smc_n_colours", "smc_destroy", "smc_last_error", "smc_status_string"]
 
 
@@ -39,6 +40,12 @@ class smc_stats(C.Structure):
                 ("accepts", C.POINTER(C.c_uint64)), ("rechecks", C.POINTER(C.c_uint64)),
                 ("trace_dE", C.c_void_p), ("trace_dE_fast", C.c_void_p),
                 ("trace_flags", C.c_void_p)]
+
+
+class smc_ce(C.Structure):
+    _fields_ = [("n_species", C.c_int32), ("pair", C.POINTER(C.c_double)), ("n_items", C.c_int32),
+                ("triangle", C.POINTER(C.c_int32)), ("species", C.POINTER(C.c_uint8)),
+                ("J", C.POINTER(C.c_double))]
 
 
 class SMCError(RuntimeError):
@@ -75,6 +82,12 @@ def lib():
             "smc_set_variant": (C.c_int, [vp, C.c_int32]),
             "smc_get_variant": (C.c_int, [vp, C.POINTER(C.c_int32)]),
             "smc_autotune": (C.c_int, [vp, C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
+            "smc_energy_fwd": (C.c_int, [vp, vp, C.c_int32, C.c_int32, vp, vp]),
+            "smc_energy_bwd": (C.c_int, [vp, vp, C.c_int32, C.c_int32, vp, vp, vp]),
+            "smc_fit_step": (C.c_int, [vp, vp, C.c_int32, C.c_int32, vp, vp, vp, vp, C.c_float, C.c_int32,
+                                       C.POINTER(C.c_double)]),
+            "smc_ce_energy": (C.c_int, [vp, C.POINTER(smc_ce), vp, C.c_int32, C.c_int32, vp]),
+            "smc_ce_triangles": (C.c_int, [C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32)]),
             "smc_n_sites": (C.c_int, [vp, C.POINTER(C.c_int64)]),
             "smc_n_colours": (C.c_int, [vp, C.c_int32, C.POINTER(C.c_int32)]),
             "smc_destroy": (None, [vp]),
@@ -199,6 +212,42 @@ def smc_autotune(ctx, cache_path=None):
     check(lib().smc_autotune(ctx, cache_path.encode() if cache_path else None, C.byref(chosen),
                              ms.ctypes.data_as(C.POINTER(C.c_float))), ctx)
     return chosen.value, ms
+
+
+def smc_energy_fwd(ctx, snap_ptr, batch, cells_per_axis, params_ptr, e_out_ptr):
+    check(lib().smc_energy_fwd(ctx, snap_ptr, batch, cells_per_axis, params_ptr, e_out_ptr), ctx)
+
+
+def smc_energy_bwd(ctx, snap_ptr, batch, cells_per_axis, params_ptr, grad_e_ptr, grad_params_ptr):
+    check(lib().smc_energy_bwd(ctx, snap_ptr, batch, cells_per_axis, params_ptr, grad_e_ptr, grad_params_ptr), ctx)
+
+
+def smc_fit_step(ctx, snap_ptr, batch, cells_per_axis, label_ptr, params_ptr, m_ptr, v_ptr, lr, step,
+                 want_loss=True):
+    loss = C.c_double(float("nan"))
+    check(lib().smc_fit_step(ctx, snap_ptr, batch, cells_per_axis, label_ptr, params_ptr, m_ptr, v_ptr, lr, step,
+                             C.byref(loss) if want_loss else None), ctx)
+    return loss.value if want_loss else None
+
+
+def smc_ce_triangles() -> np.ndarray:
+    n = C.c_int32()
+    check(lib().smc_ce_triangles(None, 0, C.byref(n)))
+    out = np.zeros((n.value, 6), dtype=np.int32)
+    check(lib().smc_ce_triangles(out.ctypes.data_as(C.POINTER(C.c_int32)), n.value, None))
+    return out
+
+
+def smc_ce_energy(ctx, ce: dict, snap_ptr, batch, cells_per_axis, e_out_ptr):
+    """ce: dict with n_species, pair [3][S][S], triangle [n], species [n][3], J [n]."""
+    pair = np.ascontiguousarray(ce["pair"], dtype=np.float64)
+    tri = np.ascontiguousarray(ce["triangle"], dtype=np.int32)
+    sp = np.ascontiguousarray(ce["species"], dtype=np.uint8)
+    J = np.ascontiguousarray(ce["J"], dtype=np.float64)
+    s = smc_ce(int(ce["n_species"]), pair.ctypes.data_as(C.POINTER(C.c_double)), len(J),
+               tri.ctypes.data_as(C.POINTER(C.c_int32)), sp.ctypes.data_as(C.POINTER(C.c_uint8)),
+               J.ctypes.data_as(C.POINTER(C.c_double)))
+    check(lib().smc_ce_energy(ctx, C.byref(s), snap_ptr, batch, cells_per_axis, e_out_ptr), ctx)
 
 
 def smc_n_sites(ctx) -> int:

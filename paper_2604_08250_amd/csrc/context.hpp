@@ -1,0 +1,121 @@
+// Library state behind the opaque smc_ctx handle, shared by the sweep and the fit entry
+// points.  Host-only declarations: no kernels live here.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "pack.hpp"
+#include "smc.h"
+#include "tables.hpp"
+
+namespace smc {
+
+struct RecheckEntry;
+
+struct DevPack {  // one precision's packed weights on the device
+  bool ready = false;
+  PackedModel host;
+  uint8_t *dev = nullptr;
+};
+
+// Buffers of the differentiation entry points (allocated on first use, grown on demand).
+struct FitState {
+  uint8_t *pack = nullptr;     // BF16 forward images (layer 0, layer 1) + c1 + w2
+  uint8_t *w1t = nullptr;      // BF16 image of W1 transposed (backward through layer 1)
+  float *partial = nullptr;    // [blocks][params] per-block gradient partials
+  int partial_blocks = 0;
+  double *row_e = nullptr;     // [rows] local energies of the last forward
+  int64_t row_cap = 0;
+  double *S = nullptr, *gs = nullptr, *loss = nullptr;  // [batch], [batch], [1]
+  int32_t batch_cap = 0;
+  float *grad = nullptr;       // [params]
+  void *ref = nullptr;         // reference-precision scratch (per-row layer values)
+  size_t ref_bytes = 0;
+  double *ce_table = nullptr;  // CE lookup tables
+  size_t ce_bytes = 0;
+};
+
+void fit_release(smc_ctx *c);
+
+}  // namespace smc
+
+struct smc_ctx {
+  smc_config cfg{};
+  std::vector<int32_t> cells;
+  std::vector<double> temps;
+  std::vector<smc::Replica> reps;
+  int64_t n_total = 0;
+  int32_t n_in = 0, hidden = 0, n_params = 0;
+  bool mfma = false;              // one-hot features with 128 hidden: matrix-core path
+  int n_cu = 256;
+  hipStream_t stream = nullptr;
+  uint8_t *occ = nullptr;
+  float *ecache = nullptr;
+  std::vector<float> host_params;
+  // library-owned device memory
+  smc::Replica *d_reps = nullptr;
+  float *d_w32 = nullptr;
+  double *d_w64 = nullptr;
+  double *d_w64t = nullptr;       // FP64 blob with W0, W1 stored [input][unit] (re-decision kernel)
+  int8_t *d_omega = nullptr;      // per-lane path Omega offsets
+  int32_t omega_n = 0;
+  uint16_t *d_reg_off = nullptr, *d_om_off = nullptr;
+  uint8_t *d_idx = nullptr, *d_reg_pos = nullptr;
+  smc::DevPack packs[4];
+  smc::RecheckEntry *d_queue = nullptr;
+  double *d_rowe = nullptr;       // [queue_cap][80] FP64 local energies of queued trials
+  uint32_t *d_done = nullptr;     // [queue_cap] per-entry completion counters
+  uint32_t *d_qcount = nullptr;   // one counter per colour index of a sweep
+  int64_t queue_cap = 0;
+  int32_t colours_total = 0;
+  int32_t max_colours = 0;        // colour indices per sweep (largest replica schedule)
+  // per colour index: the replicas that have it and their flattened group offsets, for
+  // groups of 32 [0] and 16 [1] link cells
+  std::vector<int32_t> seg_off;               // [max_colours + 1] into the segment lists
+  std::vector<int32_t> seg_groups[2];         // [max_colours] total groups
+  std::vector<int64_t> col_trials;            // [max_colours] link cells over all replicas
+  int32_t *d_seg_rep = nullptr;               // [segments]
+  int32_t *d_seg_start[2] = {nullptr, nullptr};  // [segments + max_colours]
+  uint64_t *d_sweep = nullptr;                // device sweep counter
+  int variant = 0;                            // kernel variant (autotuner)
+  bool use_graph = true;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  double *d_ebase = nullptr;      // [R] FP64 total at the last refresh
+  unsigned long long *d_efixed = nullptr;  // [R] accepted dE since then, 2^-32 eV units
+  double *d_escratch = nullptr;   // [R]
+  uint64_t *d_counters = nullptr; // [4][R]
+  double *d_site64 = nullptr;     // [N] FP64 site energies (lazy)
+  uint64_t sweep = 0;
+  double guard = 0.0;
+  // per-kernel timing: event pairs recorded around launches while profiling is on
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool;         // 2 per recorded launch
+  std::vector<int> ev_kind;                // 0 colour kernel, 1 re-decision kernel
+  size_t ev_used = 0;
+  smc::FitState fit;
+  std::string err;
+};
+
+namespace smc {
+
+inline int fail(smc_ctx *c, int code, const std::string &msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
+
+// Return SMC_E_DEVICE with the failing call and HIP's message.
+#define HIPC(c, expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail((c), SMC_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+
+}  // namespace smc

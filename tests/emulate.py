@@ -111,3 +111,50 @@ def energies(params, X, prec):
         raise ValueError(prec)
     h2 = act(y2.astype(np.float32))
     return b2 + h2.astype(f64) @ w2s.astype(f64)
+
+
+def dsilu_from_y(y):
+    """silu'(z) with z = -ln(2) y: sigma (1 + z (1 - sigma)), sigma = 1 / (1 + 2^y)."""
+    y = np.asarray(y, dtype=np.float32)
+    sg = (np.float32(1.0) / (np.float32(1.0) + np.exp2(y))).astype(np.float32)
+    z = (-LN2 * y).astype(np.float32)
+    return (sg * (np.float32(1.0) + z * (np.float32(1.0) - sg))).astype(np.float32)
+
+
+def fit_grad_bf16(params, X, g_rows):
+    """Gradient sum_r g_r dE_r/dparams as the BF16 matrix-core backward defines it: the
+    forward of energies(..., "bf16"); gz2 = q(g W2 silu'(z2)); gh1 = q(W1)^T gz2;
+    gz1 = q(gh1 silu'(z1)); dW1 = sum gz2 (x) q(h1) (h1 as the forward feeds layer 1);
+    dW0, db0 = sum gz1 (x) x; db1 = sum gz2; dW2 = sum g silu(z2); db2 = sum g; q = BF16."""
+    W0, b0, W1, b1, W2, b2 = split_params(params)
+    X = np.asarray(X, dtype=np.float64)
+    g = np.asarray(g_rows, dtype=np.float64)[:, None]
+    f64 = np.float64
+    W0s = (-L2E * W0).astype(np.float32)
+    c0 = (-L2E * b0).astype(np.float32)
+    c1 = (-L2E * b1).astype(np.float32)
+    y1 = (X @ bf16(W0s).T.astype(f64) + bf16(c0)).astype(np.float32)
+    a1 = bf16(act(y1))                                   # -log2(e) h1, as staged
+    y2 = (a1.astype(f64) @ bf16(W1).T.astype(f64) + c1).astype(np.float32)
+    z2 = (-LN2 * y2).astype(np.float32)
+    sg2 = (np.float32(1.0) / (np.float32(1.0) + np.exp2(y2))).astype(np.float32)
+    w2 = (-L2E * (-LN2 * W2).astype(np.float32)).astype(np.float32)
+    gz2 = bf16((g * w2[None, :] * dsilu_from_y(y2)).astype(np.float32))
+    hg = (g * (z2 * sg2)).astype(np.float64)
+    gh1 = (gz2.astype(f64) @ bf16(W1).astype(f64)).astype(np.float32)
+    gz1 = bf16((gh1 * dsilu_from_y(y1)).astype(np.float32))
+    dW1 = -np.float64(LN2) * (gz2.astype(f64).T @ a1.astype(f64))
+    dW0 = gz1.astype(f64).T @ X
+    out = np.concatenate([dW0.ravel(), gz1.astype(f64).sum(axis=0), dW1.ravel(), gz2.astype(f64).sum(axis=0),
+                          hg.sum(axis=0), [g.sum()]])
+    return out
+
+
+def snapshot_rows(cells, snaps):
+    """One-hot feature rows [batch * N, 108] of every site of every snapshot (oracle features)."""
+    import oracle
+    rows = []
+    for s in snaps:
+        for j in range(s.size):
+            rows.append(oracle.features(cells, 1, s, j))
+    return np.asarray(rows)

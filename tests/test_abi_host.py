@@ -74,3 +74,19 @@ def test_null_arguments():
     assert lib.smc_autotune(None, None, None, None) == -1
     assert lib.smc_status_string(-3) == b"device error"
     lib.smc_destroy(None)
+
+
+def test_library_triangle_shapes_equal_oracle():
+    """The CE triangle-shape list is index data shared by contract: bit-exact equality."""
+    L = _lib()
+    import oracle
+    assert np.array_equal(L.smc_ce_triangles(), oracle.ce_triangles())
+
+
+def test_fit_entry_points_reject_null_context():
+    L = _lib()
+    lib = L.lib()
+    assert lib.smc_energy_fwd(None, None, 1, 4, None, None) == -1
+    assert lib.smc_energy_bwd(None, None, 1, 4, None, None, None) == -1
+    assert lib.smc_fit_step(None, None, 1, 4, None, None, None, None, 1e-3, 1, None) == -1
+    assert lib.smc_ce_energy(None, None, None, 1, 4, None) == -1
