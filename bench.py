@@ -138,6 +138,121 @@ def measure(workload, precision, steps, warmup, err_samples):
     return w, out
 
 
+def measure_batched(precision="bf16", steps=3, warmup=1):
+    """The 96-replica workload: one graph-replayed launch sequence per sweep over every
+    replica, with the colour-kernel variant picked by the autotuner first."""
+    import torch
+
+    import synth
+    import paper_2604_08250_amd as smc
+
+    w = synth.workload("c4")
+    n_sites = sum(w.sites)
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    mc = smc.SwapMC(w.cells, w.temperatures, w.occupancy(), w.params(), n_species=w.n_species,
+                    feature=w.feature, hidden=w.hidden, precision=precision, seed=w.seed, stream=stream)
+    log(f"c4 {precision}: context ready in {time.perf_counter() - t0:.1f} s ({n_sites} sites)")
+    variant, ms_var = mc.autotune()
+    log(f"c4 autotune: variant {variant}, ms per variant {np.round(ms_var, 2).tolist()}")
+    if warmup:
+        mc.sweep(warmup)
+    mc.counters(reset=True)
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(steps):
+        mc.sweep(1)
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    cnt = mc.counters(reset=True)
+    attempts = int(cnt[0].sum())
+    assert attempts == n_sites * steps, (attempts, n_sites, steps)
+    es, er = mc.energy()
+    out = {"workload": f"{len(w.cells)} replicas, cube edges {min(c[0] for c in w.cells)}..{max(c[0] for c in w.cells)}, "
+                       f"{n_sites} sites, T {min(w.temperatures):.0f}..{max(w.temperatures):.0f} K",
+           "precision": precision, "attempts_per_s": attempts / (ms / 1e3), "ms_per_sweep": ms / steps, "sweeps": steps,
+           "graph_replay": True, "variant": int(variant), "ms_per_variant": [float(x) for x in ms_var],
+           "accept_ratio": int(cnt[2].sum()) / max(int(cnt[1].sum()), 1),
+           "running_minus_scratch_eV_max": float(np.abs(er - es).max())}
+    log(f"c4: {out['attempts_per_s']:.3e} attempts/s, {out['ms_per_sweep']:.1f} ms per sweep")
+    mc.close()
+    del mc
+    torch.cuda.empty_cache()
+    return out
+
+
+# Algorithmic work of one fit row: forward (Eqs. (4)-(6)) plus the backward products
+# dL/dh1 = W1^T dL/dz2 (2*128*128), dW1 (2*128*128), dW0 over the 108 one-hot inputs (2*128*108)
+# and the bias/output terms.
+FIT_FLOP_PER_ROW = FLOP_PER_EVAL + 2 * 128 * 128 + 2 * 128 * 128 + 2 * 128 * 108 + 4 * 128
+
+
+def measure_fit(steps=5, warmup=1):
+    """Fit workload: 1,024 snapshots of 16^3 cells (8.4 M rows) per step, labels from the CE
+    reference Hamiltonian (computed on the GPU), BF16 forward and backward, Adam on FP32
+    masters; one step = smc_fit_step (forward, loss, backward, Adam)."""
+    import torch
+
+    import synth
+    import paper_2604_08250_amd as smc
+    from paper_2604_08250_amd.fit import Fitter, ce_energy
+    from paper_2604_08250_amd._lib import smc_energy_bwd, smc_energy_fwd
+
+    w = synth.workload("c5")
+    L, B = w.cells[0][0], w.extra["batch"]
+    params0 = w.params()
+    mc = smc.SwapMC([(4, 4, 4)], [1000.0], synth.random_occupancy(4, 4), params0, n_species=4,
+                    feature=w.feature, hidden=w.hidden, precision="bf16", seed=0)
+    snaps = torch.from_numpy(synth.snapshots(B, L)).cuda()
+    labels = ce_energy(mc, synth.ce_params(), snaps, L)
+    params = torch.from_numpy(params0).cuda()
+    fit = Fitter(mc, params, lr=1e-3)
+    loss0 = fit.step(snaps, labels, L)
+    for _ in range(max(0, warmup - 1)):
+        fit.step(snaps, labels, L, want_loss=False)
+    stream = torch.cuda.current_stream()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(steps):
+        fit.step(snaps, labels, L, want_loss=False)
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    loss1 = fit.step(snaps, labels, L)
+    rows = B * 2 * L ** 3
+    # forward and backward timed on their own (same inputs)
+    S = torch.empty(B, dtype=torch.float64, device="cuda")
+    gE = torch.full((B,), 1.0 / B, dtype=torch.float64, device="cuda")
+    grad = torch.empty_like(params)
+    t = {}
+    for name in ("fwd", "bwd"):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(3):
+            if name == "fwd":
+                smc_energy_fwd(mc.ctx, snaps.data_ptr(), B, L, params.data_ptr(), S.data_ptr())
+            else:
+                smc_energy_bwd(mc.ctx, snaps.data_ptr(), B, L, params.data_ptr(), gE.data_ptr(), grad.data_ptr())
+        b.record(stream)
+        torch.cuda.synchronize()
+        t[name] = a.elapsed_time(b) / 3
+    out = {"workload": f"{B} snapshots of BCC {L}^3 cells ({rows} rows), CE labels, BF16 fwd/bwd, Adam",
+           "rows_per_s": rows * steps / (ms / 1e3), "ms_per_step": ms / steps, "steps": steps,
+           "fwd_ms": t["fwd"], "bwd_ms": t["bwd"],
+           "algorithmic_tflops": rows * FIT_FLOP_PER_ROW / (ms / steps / 1e3) / 1e12,
+           "loss_first": loss0, "loss_after": loss1}
+    out["roofline_frac"] = out["algorithmic_tflops"] / PEAK_TFLOPS["bf16"]
+    log(f"c5 fit: {out['ms_per_step']:.2f} ms per step (fwd {t['fwd']:.2f} ms, bwd {t['bwd']:.2f} ms), "
+        f"loss {loss0:.3e} -> {loss1:.3e}")
+    mc.close()
+    del mc
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(workload, seconds=12.0):
     """The FP64 oracle, unchanged, on a bounded sample: the first trials of colour 0 of
     sweep 0 of the same workload, run on all host cores through a thread pool."""
@@ -180,6 +295,8 @@ def main():
     ap.add_argument("--other-steps", type=int, default=3)
     ap.add_argument("--err-samples", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 96-replica measurement")
+    ap.add_argument("--no-fit", action="store_true", help="skip the fit-step measurement")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="only run 4 plain device copies of this many GiB (scale for the HBM byte counters)")
@@ -235,6 +352,10 @@ def main():
                      "avg_launch_us": head["colour_kernel_us"], "executed_frac": head["executed_frac"]},
         "precisions": precs,
     }
+    if not args.no_batched:
+        out["batched"] = measure_batched()
+    if not args.no_fit:
+        out["fit"] = measure_fit()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -145,7 +145,7 @@ int refresh(smc_ctx *c) {
     return rc;
   const int R = (int)c->reps.size();
   HIPC(c, hipMemcpyAsync(c->d_ebase, c->d_escratch, sizeof(double) * R, hipMemcpyDeviceToDevice, c->stream));
-  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(256), 0, c->stream, (uint64_t *)c->d_efixed, (int64_t)R,
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(R, 256)), dim3(256), 0, c->stream, (uint64_t *)c->d_efixed, (int64_t)R,
                      (uint64_t)0);
   HIPC(c, hipGetLastError());
   return SMC_OK;
@@ -526,7 +526,8 @@ int smc_init(const smc_config *cfg, uint8_t *occ_dev, const float *params_dev, f
       return cleanup(SMC_E_DEVICE);
   }
 #undef INIT_HIP
-  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(256), 0, c->stream, c->d_counters, (int64_t)4 * R, (uint64_t)0);
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(4 * R, 256)), dim3(256), 0, c->stream, c->d_counters, (int64_t)4 * R,
+                     (uint64_t)0);
   int rc = load_params(c, params_dev);
   if (!rc) rc = refresh(c);
   if (!rc && hipStreamSynchronize(c->stream) != hipSuccess) rc = SMC_E_DEVICE;
@@ -540,7 +541,8 @@ int smc_counters(smc_ctx *c, uint64_t *out, int32_t reset) {
   const int R = (int)c->reps.size();
   HIPC(c, hipMemcpyAsync(out, c->d_counters, sizeof(uint64_t) * 4 * R, hipMemcpyDeviceToHost, c->stream));
   if (reset)
-    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(256), 0, c->stream, c->d_counters, (int64_t)4 * R, (uint64_t)0);
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(4 * R, 256)), dim3(256), 0, c->stream, c->d_counters, (int64_t)4 * R,
+                     (uint64_t)0);
   HIPC(c, hipStreamSynchronize(c->stream));
   return SMC_OK;
 }

@@ -175,9 +175,10 @@ __global__ void k_sum_into(const double *v, int64_t n, double *out, int accumula
   if (threadIdx.x == 0) *out = accumulate ? *out + s[0] : s[0];
 }
 
+// Fill n words with v (grid-stride, so any launch shape covers all of them).
 __global__ void k_fill_u64(uint64_t *p, int64_t n, uint64_t v) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) p[k] = v;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    p[k] = v;
 }
 
 __global__ void k_widen(const float *in, double *out, int64_t n) {

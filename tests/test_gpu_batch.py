@@ -197,3 +197,36 @@ def test_c4_batched_sampled():
             f"max {np.abs(errs).max():.3e}")
     assert np.sqrt((errs ** 2).mean()) < 0.02
     e.close()
+
+
+def test_many_replicas_counters_and_parity():
+    """70 replicas (more counters than one block of threads): every replica's counters are
+    consistent from the first sweep, and sampled replicas match the oracle bit for bit."""
+    need_gpu()
+    import paper_2604_08250_amd as smc
+    R = 70
+    edges = [4 + (r % 3) for r in range(R)]
+    temps = [300.0 + 40.0 * r for r in range(R)]
+    params = synth.mlp_params(108, 128)
+    occs = [synth.random_occupancy(e, 4, None, seed=200 + r) for r, e in enumerate(edges)]
+    cells = [(e, e, e) for e in edges]
+    _banner(f"{R} replicas")
+    mc = smc.SwapMC(cells, temps, np.concatenate(occs), params, n_species=4, feature=1, hidden=128,
+                    precision="fp32", seed=9)
+    st = mc.sweep(2, stats=True)
+    sizes = np.array([o.size for o in occs], dtype=np.uint64)
+    assert np.array_equal(st["attempts"], 2 * sizes)
+    assert np.all(st["diff_species"] <= st["attempts"])
+    assert np.all(st["accepts"] <= st["diff_species"])
+    assert np.all(st["rechecks"] <= st["diff_species"])
+    cnt = mc.counters()
+    assert np.array_equal(cnt[0], st["attempts"]) and np.array_equal(cnt[2], st["accepts"])
+    got = mc.occ.cpu().numpy()
+    model = oracle.MLP(1, 128, params)
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    for r in (0, 64, 69):
+        ref = occs[r].copy()
+        for t in range(2):
+            oracle.sweep(cells[r], model, ref, temps[r], 9, r, t, nthreads=8)
+        assert np.array_equal(got[offs[r]:offs[r + 1]], ref), f"replica {r}"
+    mc.close()
