@@ -297,6 +297,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 96-replica measurement")
     ap.add_argument("--no-fit", action="store_true", help="skip the fit-step measurement")
+    ap.add_argument("--only", choices=["batched", "fit"], default=None,
+                    help="run only this measurement and print its object (for profiling)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="only run 4 plain device copies of this many GiB (scale for the HBM byte counters)")
@@ -315,6 +317,11 @@ def main():
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU slab "
               "decomposition is a design, not part of this build.", file=sys.stderr)
         sys.exit(2)
+    if args.only:
+        res = measure_batched(steps=args.steps, warmup=args.warmup) if args.only == "batched" else \
+            measure_fit(steps=args.steps, warmup=args.warmup)
+        print(json.dumps({args.only: res}), flush=True)
+        return
     w, head = measure(args.workload, args.precision, args.steps, args.warmup, args.err_samples)
     precs = {args.precision: head}
     for p in [x for x in args.others.split(",") if x and x != args.precision]:

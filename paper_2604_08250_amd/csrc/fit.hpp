@@ -186,6 +186,12 @@ __global__ void k_fit_loss(const double *S, const double *label, int32_t batch, 
 
 __device__ __forceinline__ bf16x8 fit_ld8(const uint16_t *p) { return __builtin_bit_cast(bf16x8, *(const i32x4 *)p); }
 
+// Offset of (unit u, row r) in a [unit][row] BF16 staging tile.  Rows come in 16-byte chunks
+// of 8; the chunk index is XOR-ed with the unit so that lanes reading the same chunk of
+// consecutive units (the matrix-core operand reads) hit different LDS banks instead of the
+// same four (a 256-byte row stride maps every unit to the same banks).
+__device__ __forceinline__ int fit_off(int u, int r) { return u * kFitRows + ((((r >> 3) ^ u) & 15) << 3) + (r & 7); }
+
 __device__ __forceinline__ float fit_sum8(const uint16_t *p) {
   const i32x4 w = *(const i32x4 *)p;
   float s = 0.0f;
@@ -252,12 +258,25 @@ __global__ __launch_bounds__(kFitThreads) void k_fit_bwd_bf16(FitArgs a) {
 
   const int64_t n_chunks = (a.n_rows + kFitRows - 1) / kFitRows;
   const int rl = 32 * wave + l32;  // row within the chunk
-  // stage one BF16 value per (unit, row): register pair q of (T, hh) holds units of 8hh+2q+e
+  // Stage one BF16 value per (unit, row): register pair q of (T, hh) holds units
+  // u = 32T + 8j + 4g + i with j = 2hh + q/2, i = 2(q%2) + e.  In fit_off the swizzle term
+  // (row chunk) ^ (u & 15) splits into a per-lane part (chunk ^ 4g) and K = 8(j%2) + i, which
+  // takes eight values; their offsets are computed once, so each write is base + constant.
+  int sbase[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int K = 8 * (k >> 2) + (k & 3);
+    sbase[k] = 128 * (4 * g) + 8 * (((rl >> 3) ^ (4 * g) ^ K) & 15) + (rl & 7);
+  }
   auto stage = [&](uint16_t *dst, int T, int hh, const i32x4 &p) {
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
-      for (int e = 0; e < 2; ++e) dst[fit_hid(T, 8 * hh + 2 * q + e, g) * kFitRows + rl] = (uint16_t)((uint32_t)p[q] >> (16 * e));
+      for (int e = 0; e < 2; ++e) {
+        const int j = 2 * hh + (q >> 1), i = 2 * (q & 1) + e;
+        const int k = 4 * (j & 1) + i;  // K = 8 (j % 2) + i
+        dst[sbase[k] + kFitRows * (32 * T + 8 * j + i)] = (uint16_t)((uint32_t)p[q] >> (16 * e));
+      }
   };
   for (int64_t chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x) {
     for (int q = tid; q < 27 * (kFitRows / 8); q += kFitThreads) s_sp[q] = 0u;
@@ -383,16 +402,16 @@ __global__ __launch_bounds__(kFitThreads) void k_fit_bwd_bf16(FitArgs a) {
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kFitRows / 16; ++k) {
-      const bf16x8 A = fit_ld8(s_b + (32 * wave + l32) * kFitRows + 16 * k + 8 * g);
+      const bf16x8 A = fit_ld8(s_b + fit_off(32 * wave + l32, 16 * k + 8 * g));
 #pragma unroll
       for (int nt = 0; nt < kMT; ++nt)
-        accW1[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, fit_ld8(s_a + (32 * nt + l32) * kFitRows + 16 * k + 8 * g),
+        accW1[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, fit_ld8(s_a + fit_off(32 * nt + l32, 16 * k + 8 * g)),
                                                             accW1[nt], 0, 0, 0);
     }
     {
       const int o = tid >> 1, half = tid & 1;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) db1 += fit_sum8(s_b + o * kFitRows + 64 * half + 8 * q);
+      for (int q = 0; q < 8; ++q) db1 += fit_sum8(s_b + fit_off(o, 64 * half + 8 * q));
     }
     __syncthreads();
     // ---------------------------------------------------------------- phase B: dW0 (+db0)
@@ -421,7 +440,7 @@ __global__ __launch_bounds__(kFitThreads) void k_fit_bwd_bf16(FitArgs a) {
         const bf16x8 B = __builtin_bit_cast(bf16x8, bw);
 #pragma unroll
         for (int mt = 0; mt < kMT; ++mt)
-          accW0[mt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fit_ld8(s_a + (32 * mt + l32) * kFitRows + 16 * k + 8 * g),
+          accW0[mt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fit_ld8(s_a + fit_off(32 * mt + l32, 16 * k + 8 * g)),
                                                               B, accW0[mt], 0, 0, 0);
       }
     }
