@@ -41,19 +41,27 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+# Sources that define the colour kernel; the committed traffic counters are used only while
+# these files are byte-identical to the ones profiled.
+KERNEL_SOURCES = ["sweep_mfma.hpp", "mfma_eval.hpp", "sweep_scalar.hpp", "lattice.hpp", "tables.hpp"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2604_08250_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(precision):
     """HBM bytes per colour-kernel launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
     summary, or None when the kernel sources changed since those counters were taken."""
-    import glob
-    import hashlib
     path = os.path.join(ROOT, "profiles", f"sweep_colour_{precision}_bcc256_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2604_08250_amd", "csrc", "*"))):
-        h.update(open(f, "rb").read())
-    return rec["traffic_bytes_per_launch"] if rec.get("kernel_source_sha256") == h.hexdigest() else None
+    return rec["traffic_bytes_per_launch"] if rec.get("kernel_source_sha256") == kernel_source_hash() else None
 
 
 def colour0_sites(cells, n):
@@ -302,7 +310,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="only run 4 plain device copies of this many GiB (scale for the HBM byte counters)")
+    ap.add_argument("--print-kernel-hash", action="store_true",
+                    help="print the hash of the colour-kernel sources (recorded with traffic counters)")
     args = ap.parse_args()
+    if args.print_kernel_hash:
+        print(kernel_source_hash())
+        return
     if args.copy_calibration > 0:
         import torch
         n = int(args.copy_calibration * 2**30) // 4
