@@ -191,6 +191,45 @@ def measure_batched(precision="bf16", steps=3, warmup=1):
     return out
 
 
+def measure_double_lattice(workload, precision, steps=1, warmup=0):
+    """Algorithm 1 as written (sigma0/sigma1, every site evaluated before and after each
+    mini-step) on the headline workload: same trajectory as the zone strategy, more work."""
+    import torch
+
+    import synth
+    import paper_2604_08250_amd as smc
+
+    w = synth.workload(workload)
+    n_sites = sum(w.sites)
+    stream = torch.cuda.current_stream()
+    mc = smc.SwapMC(w.cells, w.temperatures, w.occupancy(), w.params(), n_species=w.n_species,
+                    feature=w.feature, hidden=w.hidden, precision=precision, seed=w.seed, stream=stream)
+    mc.strategy = "double_lattice"
+    if warmup:
+        mc.sweep(warmup)
+    mc.counters(reset=True)
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(steps):
+        mc.sweep(1)
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    cnt = mc.counters(reset=True)
+    attempts, diff = int(cnt[0].sum()), int(cnt[1].sum())
+    assert attempts == n_sites * steps
+    colours = mc.n_colours(0)
+    out = {"precision": precision, "attempts_per_s": attempts / (ms / 1e3), "ms_per_sweep": ms / steps,
+           "sweeps": steps, "evaluations_per_attempt": 2.0 * colours,
+           "zone_evaluations_per_attempt": 40.0 * diff / attempts}
+    log(f"double lattice {precision}: {out['attempts_per_s']:.3e} attempts/s, {out['ms_per_sweep']:.0f} ms per sweep")
+    mc.close()
+    del mc
+    torch.cuda.empty_cache()
+    return out
+
+
 # Algorithmic work of one fit row: forward (Eqs. (4)-(6)) plus the backward products
 # dL/dh1 = W1^T dL/dz2 (2*128*128), dW1 (2*128*128), dW0 over the 108 one-hot inputs (2*128*108)
 # and the bias/output terms.
@@ -305,6 +344,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 96-replica measurement")
     ap.add_argument("--no-fit", action="store_true", help="skip the fit-step measurement")
+    ap.add_argument("--no-double-lattice", action="store_true", help="skip the double-lattice measurement")
     ap.add_argument("--only", choices=["batched", "fit"], default=None,
                     help="run only this measurement and print its object (for profiling)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -372,6 +412,10 @@ def main():
                      "avg_launch_us": head["colour_kernel_us"], "executed_frac": head["executed_frac"]},
         "precisions": precs,
     }
+    if not args.no_double_lattice:
+        dl = measure_double_lattice(args.workload, args.precision)
+        dl["zone_over_double_lattice"] = head["attempts_per_s"] / dl["attempts_per_s"]
+        out["double_lattice"] = dl
     if not args.no_batched:
         out["batched"] = measure_batched()
     if not args.no_fit:

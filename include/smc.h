@@ -159,6 +159,22 @@ int smc_counters(smc_ctx *ctx, uint64_t *out_host, int32_t reset);
 int smc_profile(smc_ctx *ctx, int32_t enable);
 int smc_kernel_times(smc_ctx *ctx, double *colour_ms, double *recheck_ms, int64_t *colour_launches);
 
+/* Sweep strategy (Algorithm 1, Sec. III-A).
+ * SMC_STRATEGY_ZONE (default): each trial evaluates the post-swap local energies of its
+ *   affected zone Omega (40 sites) and takes the pre-swap ones from the energy cache.
+ * SMC_STRATEGY_DOUBLE_LATTICE: the algorithm as the paper writes it: per mini-step the
+ *   whole lattice is evaluated before (E0, from sigma0) and after (E1, from the auxiliary
+ *   lattice sigma1 in which every trial of the colour has swapped its pair), E1 - E0 is
+ *   reduced over each trial's Omega, and accepted pairs are copied from sigma1 to sigma0.
+ *   The zone sums keep the zone strategy's order, so both strategies give the same
+ *   occupancies and energy cache bit for bit; the double lattice evaluates every site twice
+ *   per mini-step.  Needs one-hot features, 128 hidden units and a matrix-core precision (not
+ *   SMC_FP64), else SMC_E_UNSUPPORTED; allocates the auxiliary lattice and two energy arrays.
+ *   Sweeps with it are submitted per launch (no graph). */
+enum smc_strategy { SMC_STRATEGY_ZONE = 0, SMC_STRATEGY_DOUBLE_LATTICE = 1 };
+int smc_set_strategy(smc_ctx *ctx, int32_t strategy);
+int smc_get_strategy(const smc_ctx *ctx, int32_t *strategy);
+
 /* Batched sweeps.  One launch per colour index covers that colour of every replica whose
  * schedule has it (replicas are independent chains; a replica's colours still run in
  * order).  Without stats, traces or profiling a sweep is replayed from a hipGraph captured

@@ -12,7 +12,7 @@ from ._lib import (PRECISIONS, SMC_BF16, SMC_BF16X3, SMC_FEAT_COUNTS_S12, SMC_FE
                    smc_delta_e64, smc_destroy, smc_energy, smc_get_sweep, smc_get_variant, smc_init,
                    smc_kernel_times, smc_n_colours, smc_n_sites, smc_profile, smc_refresh,
                    smc_set_params, smc_set_sweep, smc_set_variant, smc_site_energies, smc_sweep,
-                   smc_use_graph)
+                   smc_use_graph, smc_set_strategy, smc_get_strategy, STRATEGIES)
 
 __all__ = ["SwapMC", "SMCError", "PRECISIONS", "lib"]
 
@@ -109,6 +109,17 @@ class SwapMC:
     @sweep_index.setter
     def sweep_index(self, v):
         smc_set_sweep(self.ctx, int(v))
+
+    @property
+    def strategy(self):
+        """'zone' (default) or 'double_lattice' (Algorithm 1 with sigma0/sigma1 and all-site
+        energies; same trajectory, about 10x the evaluations)."""
+        v = smc_get_strategy(self.ctx)
+        return {b: a for a, b in STRATEGIES.items()}[v]
+
+    @strategy.setter
+    def strategy(self, name):
+        smc_set_strategy(self.ctx, STRATEGIES[name] if isinstance(name, str) else int(name))
 
     def use_graph(self, enable=True):
         """Replay plain sweeps from a captured hipGraph (default on); results are identical."""

@@ -13,6 +13,7 @@
 namespace smc {
 
 struct RecheckEntry;
+struct DlTrial;
 
 struct DevPack {  // one precision's packed weights on the device
   bool ready = false;
@@ -96,6 +97,11 @@ struct smc_ctx {
   std::vector<hipEvent_t> ev_pool;         // 2 per recorded launch
   std::vector<int> ev_kind;                // 0 colour kernel, 1 re-decision kernel
   size_t ev_used = 0;
+  // double-lattice strategy (Algorithm 1 as written)
+  int strategy = 0;                  // smc_strategy
+  uint8_t *d_sigma1 = nullptr;       // [N] auxiliary lattice
+  float *d_E0 = nullptr, *d_E1 = nullptr;  // [N] all-site energies before / after
+  smc::DlTrial *d_dltrials = nullptr;      // [largest colour of a replica]
   smc::FitState fit;
   std::string err;
 };

@@ -10,6 +10,7 @@
 #include "context.hpp"
 #include "smc.h"
 #include "pack.hpp"
+#include "double_lattice.hpp"
 #include "sweep_mfma.hpp"
 #include "sweep_scalar.hpp"
 #include "tables.hpp"
@@ -88,14 +89,15 @@ int ensure_pack(smc_ctx *c, int P) {
 }
 
 template <int P>
-void launch_site_energies_mfma(smc_ctx *c, float *out) {
+void launch_site_energies_mfma(smc_ctx *c, float *out, const uint8_t *occ = nullptr, int only = -1) {
   const DevPack &dp = c->packs[P];
   for (size_t r = 0; r < c->reps.size(); ++r) {
+    if (only >= 0 && (int)r != only) continue;
     const int64_t tiles = (c->reps[r].n_sites + 31) / 32;
     const unsigned grid = (unsigned)std::min<int64_t>((tiles + 3) / 4, 4 * (int64_t)c->n_cu);
     hipLaunchKernelGGL((k_site_energies_mfma<P>), dim3(grid), dim3(256), 0, c->stream, c->d_reps, (int32_t)r,
-                       c->occ, dp.dev, dp.host.b2, dp.host.k_scale_a0, dp.host.k_scale_a1, dp.host.k_scale_h,
-                       dp.host.sh, out);
+                       occ ? occ : c->occ, dp.dev, dp.host.b2, dp.host.k_scale_a0, dp.host.k_scale_a1,
+                       dp.host.k_scale_h, dp.host.sh, out);
   }
 }
 
@@ -324,6 +326,98 @@ int build_graph(smc_ctx *c) {
   return SMC_OK;
 }
 
+// One sweep with the double-lattice strategy: per replica and colour, proposals into sigma1,
+// all-site energies of sigma0 and sigma1, zone reductions and decisions, FP64 re-decisions,
+// and sigma1 brought back to sigma0 at the trial pairs.
+int enqueue_sweep_dl(smc_ctx *c, const smc_stats *st, bool trace) {
+  const int R = (int)c->reps.size();
+  const int P = c->cfg.precision;
+  HIPC(c, hipMemcpyAsync(c->d_sigma1, c->occ, (size_t)c->n_total, hipMemcpyDeviceToDevice, c->stream));
+  const int qslot = (c->max_colours + 1) & ~1;  // a 64-bit word of the counter array no colour uses
+  for (int r = 0; r < R; ++r) {
+    const Replica &rep = c->reps[r];
+    for (int col = 0; col < rep.n_colours; ++col) {
+      DlArgs a{};
+      a.reps = c->d_reps;
+      a.r = r;
+      a.colour = col;
+      a.sweep = c->d_sweep;
+      a.seed = c->cfg.seed;
+      a.occ = c->occ;
+      a.sigma1 = c->d_sigma1;
+      a.trials = c->d_dltrials;
+      a.E0 = c->d_E0;
+      a.E1 = c->d_E1;
+      a.ecache = c->ecache;
+      a.om_off = c->d_om_off;
+      a.guard = c->guard;
+      a.q_count = c->d_qcount + qslot;
+      a.queue = c->d_queue;
+      a.e_fixed = c->d_efixed;
+      a.counters = c->d_counters;
+      a.n_replicas = R;
+      if (trace) {
+        a.trace_dE = st->trace_dE;
+        a.trace_dE_fast = st->trace_dE_fast;
+        a.trace_flags = st->trace_flags;
+      }
+      const unsigned tg = grid_for(std::max<int64_t>(1, rep.n_trials), 256);
+      hipLaunchKernelGGL(k_dl_propose, dim3(tg), dim3(256), 0, c->stream, a);
+      switch (P) {
+        case SMC_FP32:
+          launch_site_energies_mfma<kP32>(c, c->d_E0, c->occ, r);
+          launch_site_energies_mfma<kP32>(c, c->d_E1, c->d_sigma1, r);
+          break;
+        case SMC_BF16:
+          launch_site_energies_mfma<kPBF16>(c, c->d_E0, c->occ, r);
+          launch_site_energies_mfma<kPBF16>(c, c->d_E1, c->d_sigma1, r);
+          break;
+        case SMC_BF16X3:
+          launch_site_energies_mfma<kPBF16X3>(c, c->d_E0, c->occ, r);
+          launch_site_energies_mfma<kPBF16X3>(c, c->d_E1, c->d_sigma1, r);
+          break;
+        default:
+          launch_site_energies_mfma<kPFP8>(c, c->d_E0, c->occ, r);
+          launch_site_energies_mfma<kPFP8>(c, c->d_E1, c->d_sigma1, r);
+          break;
+      }
+      hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, c->stream, (uint64_t *)(c->d_qcount + qslot), (int64_t)1,
+                         (uint64_t)0);
+      const int ev = prof_begin(c);
+      hipLaunchKernelGGL(k_dl_decide, dim3(tg), dim3(256), 0, c->stream, a);
+      prof_end(c, ev, 0);
+      RecheckArgs ra{};
+      ra.reps = c->d_reps;
+      ra.occ = c->occ;
+      ra.ecache = c->ecache;
+      ra.w64 = c->d_w64t;
+      ra.reg_off = c->d_reg_off;
+      ra.om_off = c->d_om_off;
+      ra.idx = c->d_idx;
+      ra.reg_pos = c->d_reg_pos;
+      ra.q_count = c->d_qcount + qslot;
+      ra.queue = c->d_queue;
+      ra.e_fixed = c->d_efixed;
+      ra.counters = c->d_counters;
+      ra.n_replicas = R;
+      ra.row_e = c->d_rowe;
+      ra.done = c->d_done;
+      if (trace) {
+        ra.trace_dE = st->trace_dE;
+        ra.trace_flags = st->trace_flags;
+      }
+      const int rgrid = (int)std::min<int64_t>(8 * c->n_cu, kRcSplit * std::max<int64_t>(1, rep.n_trials));
+      const int ev2 = prof_begin(c);
+      hipLaunchKernelGGL(k_recheck, dim3(rgrid), dim3(kRcThreads), 0, c->stream, ra);
+      prof_end(c, ev2, 1);
+      hipLaunchKernelGGL(k_dl_sync, dim3(tg), dim3(256), 0, c->stream, a);
+    }
+  }
+  hipLaunchKernelGGL(k_next_sweep, dim3(1), dim3(64), 0, c->stream, c->d_sweep);
+  HIPC(c, hipGetLastError());
+  return SMC_OK;
+}
+
 int run_sweep(smc_ctx *c, const smc_stats *st, bool last) {
   const int R = (int)c->reps.size();
   const bool trace = last && st;
@@ -331,7 +425,9 @@ int run_sweep(smc_ctx *c, const smc_stats *st, bool last) {
     const int P = c->cfg.precision == SMC_FP64 ? SMC_FP32 : c->cfg.precision;
     int rc = ensure_pack(c, P);
     if (rc) return rc;
-    if (c->use_graph && !trace && !c->profiling) {
+    if (c->strategy == SMC_STRATEGY_DOUBLE_LATTICE) {
+      if ((rc = enqueue_sweep_dl(c, st, trace))) return rc;
+    } else if (c->use_graph && !trace && !c->profiling) {
       if (!c->graph_exec && (rc = build_graph(c))) return rc;
       HIPC(c, hipGraphLaunch(c->graph_exec, c->stream));
     } else if ((rc = enqueue_sweep_mfma(c, st, trace))) {
@@ -510,7 +606,7 @@ int smc_init(const smc_config *cfg, uint8_t *occ_dev, const float *params_dev, f
     INIT_HIP(hipMalloc(&c->d_rowe, sizeof(double) * kRows64 * c->queue_cap));
     INIT_HIP(hipMalloc(&c->d_done, sizeof(uint32_t) * c->queue_cap));
     INIT_HIP(hipMemset(c->d_done, 0, sizeof(uint32_t) * c->queue_cap));
-    INIT_HIP(hipMalloc(&c->d_qcount, sizeof(uint32_t) * (c->max_colours + 2)));
+    INIT_HIP(hipMalloc(&c->d_qcount, sizeof(uint32_t) * (c->max_colours + 4)));
     INIT_HIP(hipMalloc(&c->d_seg_rep, sizeof(int32_t) * std::max<size_t>(1, seg_rep.size())));
     for (int k = 0; k < 2; ++k) {
       INIT_HIP(hipMalloc(&c->d_seg_start[k], sizeof(int32_t) * seg_start[k].size()));
@@ -726,6 +822,32 @@ int smc_get_variant(const smc_ctx *c, int32_t *variant) {
   return SMC_OK;
 }
 
+int smc_set_strategy(smc_ctx *c, int32_t strategy) {
+  if (!c) return SMC_E_INVALID;
+  if (strategy != SMC_STRATEGY_ZONE && strategy != SMC_STRATEGY_DOUBLE_LATTICE)
+    return fail(c, SMC_E_INVALID, "unknown strategy");
+  if (strategy == SMC_STRATEGY_DOUBLE_LATTICE) {
+    if (!c->mfma || c->cfg.precision == SMC_FP64)
+      return fail(c, SMC_E_UNSUPPORTED, "the double-lattice strategy needs one-hot features, 128 hidden units "
+                                        "and a matrix-core precision");
+    int64_t most = 1;
+    for (const Replica &rp : c->reps) most = std::max(most, rp.n_trials);
+    if (!c->d_sigma1 && hipMalloc(&c->d_sigma1, (size_t)c->n_total) != hipSuccess) return fail(c, SMC_E_NOMEM, "sigma1");
+    if (!c->d_E0 && hipMalloc(&c->d_E0, sizeof(float) * c->n_total) != hipSuccess) return fail(c, SMC_E_NOMEM, "E0");
+    if (!c->d_E1 && hipMalloc(&c->d_E1, sizeof(float) * c->n_total) != hipSuccess) return fail(c, SMC_E_NOMEM, "E1");
+    if (!c->d_dltrials && hipMalloc(&c->d_dltrials, sizeof(DlTrial) * most) != hipSuccess)
+      return fail(c, SMC_E_NOMEM, "trial records");
+  }
+  c->strategy = strategy;
+  return SMC_OK;
+}
+
+int smc_get_strategy(const smc_ctx *c, int32_t *strategy) {
+  if (!c || !strategy) return SMC_E_INVALID;
+  *strategy = c->strategy;
+  return SMC_OK;
+}
+
 int smc_use_graph(smc_ctx *c, int32_t enable) {
   if (!c) return SMC_E_INVALID;
   c->use_graph = enable != 0;
@@ -739,6 +861,7 @@ int smc_autotune(smc_ctx *c, const char *cache_path, int32_t *chosen, float *ms_
     if (chosen) *chosen = c->variant;
     return SMC_OK;  // the per-lane path has a single variant
   }
+  if (c->strategy != SMC_STRATEGY_ZONE) return fail(c, SMC_E_STATE, "the autotuner tunes the zone strategy's kernel");
   // cache key: device, precision and the replica shapes
   hipDeviceProp_t prop{};
   int dev = 0;
@@ -874,7 +997,8 @@ void smc_destroy(smc_ctx *c) {
   void *bufs[] = {c->d_reps, c->d_w32, c->d_w64, c->d_w64t, c->d_omega, c->d_reg_off, c->d_om_off, c->d_idx,
                   c->d_reg_pos, c->d_queue, c->d_rowe, c->d_done, c->d_qcount, c->d_ebase, c->d_efixed, c->d_escratch,
                   c->d_counters, c->d_site64, c->packs[0].dev, c->packs[1].dev, c->packs[2].dev,
-                  c->packs[3].dev, c->d_seg_rep, c->d_seg_start[0], c->d_seg_start[1], c->d_sweep};
+                  c->packs[3].dev, c->d_seg_rep, c->d_seg_start[0], c->d_seg_start[1], c->d_sweep,
+                  c->d_sigma1, c->d_E0, c->d_E1, c->d_dltrials};
   for (void *p : bufs)
     if (p) (void)hipFree(p);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
