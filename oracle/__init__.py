@@ -18,7 +18,7 @@ SRC = os.path.join(HERE, "smc_oracle.c")
 SOURCES = [SRC, os.path.join(HERE, "fit_oracle.c")]
 LIB = os.path.join(HERE, "liboracle.so")
 
-FEAT_COUNTS_S12, FEAT_ONEHOT_S123 = 0, 1
+FEAT_COUNTS_S12, FEAT_ONEHOT_S123, FEAT_QSRO_S123 = 0, 1, 2
 ACT_SILU, ACT_IDENTITY, ACT_RELU, ACT_SQUARE = 0, 1, 2, 3
 ORDER_SNAPSHOT, ORDER_FORWARD, ORDER_REVERSE, ORDER_GIVEN = 0, 1, 2, 3
 KB_EV_PER_K = 8.617333262e-5
@@ -155,6 +155,23 @@ class MLP:
     @property
     def n_in(self) -> int:
         return 12 if self.feature == FEAT_COUNTS_S12 else 108
+
+
+class QSRO:
+    """FP64 view of a qSRO parameter blob (Eq. 2): V[3][5][5] (symmetric), W[3][5], lambda, C."""
+
+    feature = FEAT_QSRO_S123
+    hidden = 0
+
+    def __init__(self, params):
+        self.params = np.ascontiguousarray(np.asarray(params, dtype=np.float64))
+        if self.params.size != 92:
+            raise ValueError(f"qSRO blob has {self.params.size} entries, expected 92")
+        self._c = Model(FEAT_QSRO_S123, 0, 0, 0, _ptr(self.params, C.c_double))
+
+    @property
+    def c(self):
+        return C.byref(self._c)
 
 
 def philox4x64_10(ctr, key) -> np.ndarray:

@@ -204,8 +204,40 @@ double or_mlp(const or_model *m, const double *x) {
   return e;
 }
 
+/* qSRO local energy (Eq. 2).  Pairs of site j with its neighbours in coordination shell m
+ * (m = 1..3) are counted per unordered species pair: n_m^{pp'}; pi_m^{pp'} = n_m^{pp'} divided
+ * by the number of pairs in the shell.  E_j = sum_{m, p' < p} V_m^{pp'} pi_m^{pp'}
+ * + sum_{m, p} W_m^p (pi_m^{pp})^2 + lambda sum_{m, p} (W_m^p)^2 + C, over species 0..4. */
+double or_qsro(const int32_t L[3], const double *P, const uint8_t *occ, int64_t j, int64_t swap_i,
+               int64_t swap_n) {
+  or_tables();
+  const double *V = P, *W = P + 75, lambda = P[90], C = P[91];
+  double e = C;
+  const uint8_t c = or_species(occ, j, swap_i, swap_n);
+  for (int m = 1; m <= 3; ++m) {
+    double n[5][5] = {{0}};
+    double pairs = 0.0;
+    for (int k = 0; k < 26; ++k) {
+      if (g_shell[k] != m) continue;
+      const uint8_t q = or_species(occ, or_neighbor(L, j, k), swap_i, swap_n);
+      const int hi = c > q ? c : q, lo = c > q ? q : c;
+      n[hi][lo] += 1.0;
+      pairs += 1.0;
+    }
+    for (int p = 0; p < 5; ++p)
+      for (int pp = 0; pp < p; ++pp) e += V[((m - 1) * 5 + p) * 5 + pp] * (n[p][pp] / pairs);
+    for (int p = 0; p < 5; ++p) {
+      const double pi = n[p][p] / pairs;
+      e += W[(m - 1) * 5 + p] * pi * pi;
+    }
+  }
+  for (int q = 0; q < 15; ++q) e += lambda * W[q] * W[q];
+  return e;
+}
+
 double or_site_energy(const int32_t L[3], const or_model *m, const uint8_t *occ, int64_t j,
                       int64_t swap_i, int64_t swap_n) {
+  if (m->feature == OR_FEAT_QSRO_S123) return or_qsro(L, m->params, occ, j, swap_i, swap_n);
   double x[108];
   or_features(L, m->feature, occ, j, swap_i, swap_n, x);
   return or_mlp(m, x);

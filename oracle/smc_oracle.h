@@ -27,7 +27,7 @@
 extern "C" {
 #endif
 
-enum { OR_FEAT_COUNTS_S12 = 0, OR_FEAT_ONEHOT_S123 = 1 };
+enum { OR_FEAT_COUNTS_S12 = 0, OR_FEAT_ONEHOT_S123 = 1, OR_FEAT_QSRO_S123 = 2 };
 enum { OR_ACT_SILU = 0, OR_ACT_IDENTITY = 1, OR_ACT_RELU = 2, OR_ACT_SQUARE = 3 };
 enum { OR_ORDER_SNAPSHOT = 0, OR_ORDER_FORWARD = 1, OR_ORDER_REVERSE = 2, OR_ORDER_GIVEN = 3 };
 
@@ -35,7 +35,8 @@ typedef struct {
   int32_t feature;        /* OR_FEAT_* */
   int32_t hidden;         /* H */
   int32_t act0, act1;     /* activation after layer 0 and layer 1 (OR_ACT_*) */
-  const double *params;   /* W0[H][F], b0[H], W1[H][H], b1[H], W2[H], b2 */
+  const double *params;   /* MLP: W0[H][F], b0[H], W1[H][H], b1[H], W2[H], b2.
+                             qSRO: V[3][5][5] (symmetric), W[3][5], lambda, C (92 values). */
 } or_model;
 
 typedef struct {
@@ -65,6 +66,8 @@ int32_t or_n_neighbors_used(int32_t feature);
 void or_features(const int32_t L[3], int32_t feature, const uint8_t *occ, int64_t j,
                  int64_t swap_i, int64_t swap_n, double *x);
 double or_mlp(const or_model *m, const double *x);
+double or_qsro(const int32_t L[3], const double *params, const uint8_t *occ, int64_t j, int64_t swap_i,
+               int64_t swap_n);
 double or_site_energy(const int32_t L[3], const or_model *m, const uint8_t *occ, int64_t j,
                       int64_t swap_i, int64_t swap_n);
 double or_total_energy(const int32_t L[3], const or_model *m, const uint8_t *occ);

@@ -169,6 +169,25 @@ def ce_params(n_species: int = 4, n_items: int = 200, n_triangles: int = N_CE_TR
             "species": np.asarray(sp, dtype=np.uint8), "J": J}
 
 
+SEED_QSRO = 6
+
+
+def qsro_params(n_species: int = 4, seed: int = SEED_QSRO) -> np.ndarray:
+    """Synthetic qSRO coefficients (Eq. 2; trained ones are not available), FP32 blob
+    [V[3][5][5], W[3][5], lambda, C]: V_m^{pp'} = V_m^{p'p} ~ N(0, 0.05 eV) for p' < p <
+    n_species (drawn in order m, p, p'), W_m^p ~ N(0, 0.02 eV) for p < n_species, lambda =
+    0.01, C = -0.1 eV; entries of absent species are zero."""
+    rng = np.random.default_rng(seed)
+    V = np.zeros((3, 5, 5))
+    for m in range(3):
+        for p in range(n_species):
+            for q in range(p):
+                V[m, p, q] = V[m, q, p] = rng.normal(0.0, 0.05)
+    W = np.zeros((3, 5))
+    W[:, :n_species] = rng.normal(0.0, 0.02, size=(3, n_species))
+    return np.concatenate([V.ravel(), W.ravel(), [0.01, -0.1]]).astype(np.float32)
+
+
 def snapshots(n: int, cells: int = 16, n_species: int = 4, seed: int = SEED_LATTICE + 100) -> np.ndarray:
     """``n`` snapshots (uint8 [n][2 cells^3]) with compositions drawn like the replica set
     (Dirichlet, every species in [0.1, 0.4]) and uniformly random placement."""
