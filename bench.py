@@ -230,6 +230,45 @@ def measure_double_lattice(workload, precision, steps=1, warmup=0):
     return out
 
 
+def measure_qsro(workload, steps=2, warmup=1):
+    """The qSRO model (Eq. 2) on the headline lattice: per-lane evaluator (neighbour counts
+    and a quadratic per site, no matrix products), FP32 with the FP64 re-decision band."""
+    import torch
+
+    import synth
+    import paper_2604_08250_amd as smc
+
+    w = synth.workload(workload)
+    n_sites = sum(w.sites)
+    stream = torch.cuda.current_stream()
+    mc = smc.SwapMC(w.cells, w.temperatures, w.occupancy(), synth.qsro_params(w.n_species), n_species=w.n_species,
+                    feature=2, hidden=0, precision="fp32", seed=w.seed, stream=stream)
+    if warmup:
+        mc.sweep(warmup)
+    mc.counters(reset=True)
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(steps):
+        mc.sweep(1)
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    cnt = mc.counters(reset=True)
+    attempts = int(cnt[0].sum())
+    assert attempts == n_sites * steps
+    es, er = mc.energy()
+    out = {"model": "qSRO (Eq. 2), shells 1-3", "precision": "fp32", "attempts_per_s": attempts / (ms / 1e3),
+           "ms_per_sweep": ms / steps, "sweeps": steps,
+           "accept_ratio": int(cnt[2].sum()) / max(int(cnt[1].sum()), 1),
+           "running_minus_scratch_eV": float(er.sum() - es.sum())}
+    log(f"qSRO fp32: {out['attempts_per_s']:.3e} attempts/s, {out['ms_per_sweep']:.1f} ms per sweep")
+    mc.close()
+    del mc
+    torch.cuda.empty_cache()
+    return out
+
+
 # Algorithmic work of one fit row: forward (Eqs. (4)-(6)) plus the backward products
 # dL/dh1 = W1^T dL/dz2 (2*128*128), dW1 (2*128*128), dW0 over the 108 one-hot inputs (2*128*108)
 # and the bias/output terms.
@@ -345,7 +384,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 96-replica measurement")
     ap.add_argument("--no-fit", action="store_true", help="skip the fit-step measurement")
     ap.add_argument("--no-double-lattice", action="store_true", help="skip the double-lattice measurement")
-    ap.add_argument("--only", choices=["batched", "fit"], default=None,
+    ap.add_argument("--no-qsro", action="store_true", help="skip the qSRO-model measurement")
+    ap.add_argument("--only", choices=["batched", "fit", "qsro"], default=None,
                     help="run only this measurement and print its object (for profiling)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", type=float, default=0.0,
@@ -371,8 +411,12 @@ def main():
               "decomposition is a design, not part of this build.", file=sys.stderr)
         sys.exit(2)
     if args.only:
-        res = measure_batched(steps=args.steps, warmup=args.warmup) if args.only == "batched" else \
-            measure_fit(steps=args.steps, warmup=args.warmup)
+        if args.only == "batched":
+            res = measure_batched(steps=args.steps, warmup=args.warmup)
+        elif args.only == "fit":
+            res = measure_fit(steps=args.steps, warmup=args.warmup)
+        else:
+            res = measure_qsro(args.workload, steps=args.steps, warmup=args.warmup)
         print(json.dumps({args.only: res}), flush=True)
         return
     w, head = measure(args.workload, args.precision, args.steps, args.warmup, args.err_samples)
@@ -416,6 +460,8 @@ def main():
         dl = measure_double_lattice(args.workload, args.precision)
         dl["zone_over_double_lattice"] = head["attempts_per_s"] / dl["attempts_per_s"]
         out["double_lattice"] = dl
+    if not args.no_qsro:
+        out["qsro"] = measure_qsro(args.workload)
     if not args.no_batched:
         out["batched"] = measure_batched()
     if not args.no_fit:

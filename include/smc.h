@@ -40,6 +40,11 @@
  *
  * Parameter blob (FP32, row-major [out][in]): W0[H][F], b0[H], W1[H][H], b1[H], W2[H],
  * b2[1]; E_j = W2 . silu(W1 . silu(W0 x_j + b0) + b1) + b2 (eV).
+ * qSRO blob (FP32, 92 values): V[3][5][5], W[3][5], lambda, C; with n_m^{pp'} the number of
+ * pairs of site j with its shell-m neighbours whose species are {p, p'} and pi = n / (pairs in
+ * the shell), E_j = sum_{m, p' < p} V[m][p][p'] pi_m^{pp'} + sum_{m, p} W[m][p] (pi_m^{pp})^2
+ * + lambda sum_{m, p} W[m][p]^2 + C over species 0..4 (entries of absent species should be 0,
+ * they still enter the lambda term).
  *
  * Trial of site i at global sweep t of replica r: Philox4x64-10 with counter
  * (i, t, r, 0) and key (seed, 0) gives (r0, r1, r2, r3); the partner is the shell-1
@@ -76,7 +81,10 @@ enum smc_prec {
   SMC_FP64 = 4       /* FP64 throughout (reference mode) */
 };
 
-enum smc_feat { SMC_FEAT_COUNTS_S12 = 0, SMC_FEAT_ONEHOT_S123 = 1 };
+/* Energy model and its inputs.  SMC_FEAT_COUNTS_S12 and SMC_FEAT_ONEHOT_S123 select the MLP
+ * (Eqs. (4)-(6)) with those features; SMC_FEAT_QSRO_S123 selects the qSRO model (Eq. 2) over
+ * coordination shells 1..3 (hidden is ignored; FP32 or FP64 only). */
+enum smc_feat { SMC_FEAT_COUNTS_S12 = 0, SMC_FEAT_ONEHOT_S123 = 1, SMC_FEAT_QSRO_S123 = 2 };
 
 typedef struct {
   int32_t n_replicas;            /* >= 1 */

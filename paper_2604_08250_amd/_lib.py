@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(PKG, "libsmc.so")
 
 SMC_OK, SMC_E_INVALID, SMC_E_UNSUPPORTED, SMC_E_DEVICE, SMC_E_STATE, SMC_E_NOMEM = 0, -1, -2, -3, -4, -5
 SMC_FP32, SMC_BF16, SMC_BF16X3, SMC_FP8_E4M3, SMC_FP64 = 0, 1, 2, 3, 4
-SMC_FEAT_COUNTS_S12, SMC_FEAT_ONEHOT_S123 = 0, 1
+SMC_FEAT_COUNTS_S12, SMC_FEAT_ONEHOT_S123, SMC_FEAT_QSRO_S123 = 0, 1, 2
 
 PRECISIONS = {"fp32": SMC_FP32, "bf16": SMC_BF16, "bf16x3": SMC_BF16X3, "fp8": SMC_FP8_E4M3,
               "fp64": SMC_FP64}

@@ -89,4 +89,39 @@ __device__ inline T mlp_scalar(const uint8_t *slot, const T *W) {
   return e;
 }
 
+// qSRO local energy (Eq. 2) from the slot species (centre + shells 1..3), with the host-folded
+// coefficients Vf[m][c][q] = V_m^{max(c,q) min(c,q)} / z_m (0 for q = c), Wf[m][c] =
+// W_m^c / z_m^2 and K = C + lambda sum W^2:  E = K + sum_m (sum_q Vf[m][c][q] n_m[q] +
+// Wf[m][c] n_m[c]^2), n_m[q] the number of shell-m neighbours of species q.
+constexpr int kQsroPacked = 3 * 25 + 15 + 1;
+
+template <typename T>
+__device__ inline T qsro_scalar(const uint8_t *slot, const T *F) {
+  const T *Vf = F, *Wf = F + 75;
+  const int c = slot[0];
+  T cnt[3][5];
+#pragma unroll
+  for (int m = 0; m < 3; ++m)
+#pragma unroll
+    for (int q = 0; q < 5; ++q) cnt[m][q] = T(0);
+#pragma unroll
+  for (int k = 0; k < kNbr; ++k) {
+    const int m = shell_of(k) - 1, q = slot[k + 1];
+#pragma unroll
+    for (int p = 0; p < 5; ++p) cnt[m][p] += (q == p) ? T(1) : T(0);
+  }
+  T e = F[90];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    T acc = T(0);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) acc = fma(Vf[(m * 5 + c) * 5 + q], cnt[m][q], acc);
+    T self = T(0);
+#pragma unroll
+    for (int p = 0; p < 5; ++p) self += (p == c) ? cnt[m][p] : T(0);
+    e += acc + Wf[m * 5 + c] * self * self;
+  }
+  return e;
+}
+
 }  // namespace smc

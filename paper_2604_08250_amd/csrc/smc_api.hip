@@ -69,7 +69,8 @@ void launch_site_energies(smc_ctx *c, const T *W, T *out) {
 template <typename T>
 int site_energies_scalar(smc_ctx *c, const T *W, T *out) {
   const bool counts = c->cfg.feature == SMC_FEAT_COUNTS_S12;
-  if (counts && c->hidden == 64) launch_site_energies<0, 64, T>(c, W, out);
+  if (c->cfg.feature == SMC_FEAT_QSRO_S123) launch_site_energies<2, 0, T>(c, W, out);
+  else if (counts && c->hidden == 64) launch_site_energies<0, 64, T>(c, W, out);
   else if (counts) launch_site_energies<0, 128, T>(c, W, out);
   else if (c->hidden == 64) launch_site_energies<1, 64, T>(c, W, out);
   else launch_site_energies<1, 128, T>(c, W, out);
@@ -175,6 +176,27 @@ int load_params(smc_ctx *c, const float *params_dev) {
     for (size_t q = w1 + (size_t)H * H; q < (size_t)P; ++q) t[q] = p[q];
     HIPC(c, hipMemcpyAsync(c->d_w64t, t.data(), sizeof(double) * P, hipMemcpyHostToDevice, c->stream));
     HIPC(c, hipStreamSynchronize(c->stream));
+  }
+  if (c->cfg.feature == SMC_FEAT_QSRO_S123) {
+    // folded coefficients of the per-lane qSRO evaluator (FP64 and its FP32 rounding)
+    const float *p = c->host_params.data();
+    const double z[3] = {8.0, 6.0, 12.0};
+    std::vector<double> f(kQsroPacked, 0.0);
+    std::vector<float> f32(kQsroPacked);
+    for (int m = 0; m < 3; ++m)
+      for (int cc = 0; cc < 5; ++cc) {
+        for (int q = 0; q < 5; ++q)
+          if (q != cc) f[(m * 5 + cc) * 5 + q] = (double)p[(m * 5 + std::max(cc, q)) * 5 + std::min(cc, q)] / z[m];
+        f[75 + m * 5 + cc] = (double)p[75 + m * 5 + cc] / (z[m] * z[m]);
+      }
+    double K = (double)p[91];
+    for (int q = 0; q < 15; ++q) K += (double)p[90] * (double)p[75 + q] * (double)p[75 + q];
+    f[90] = K;
+    for (int q = 0; q < kQsroPacked; ++q) f32[q] = (float)f[q];
+    HIPC(c, hipMemcpyAsync(c->d_w64, f.data(), sizeof(double) * kQsroPacked, hipMemcpyHostToDevice, c->stream));
+    HIPC(c, hipMemcpyAsync(c->d_w32, f32.data(), sizeof(float) * kQsroPacked, hipMemcpyHostToDevice, c->stream));
+    HIPC(c, hipStreamSynchronize(c->stream));
+    return SMC_OK;
   }
   hipLaunchKernelGGL(k_copy_f32, dim3(grid_for(P, 256)), dim3(256), 0, c->stream, params_dev, c->d_w32, P);
   hipLaunchKernelGGL(k_widen, dim3(grid_for(P, 256)), dim3(256), 0, c->stream, params_dev, c->d_w64, P);
@@ -461,7 +483,8 @@ int run_sweep(smc_ctx *c, const smc_stats *st, bool last) {
         }
         const bool onehot = c->cfg.feature == SMC_FEAT_ONEHOT_S123;
         const int ev = prof_begin(c);
-        if (!onehot && c->hidden == 64) launch_colour_scalar<0, 64>(c, a, rep.n_trials);
+        if (c->cfg.feature == SMC_FEAT_QSRO_S123) launch_colour_scalar<2, 0>(c, a, rep.n_trials);
+        else if (!onehot && c->hidden == 64) launch_colour_scalar<0, 64>(c, a, rep.n_trials);
         else if (!onehot) launch_colour_scalar<0, 128>(c, a, rep.n_trials);
         else if (c->hidden == 64) launch_colour_scalar<1, 64>(c, a, rep.n_trials);
         else launch_colour_scalar<1, 128>(c, a, rep.n_trials);
@@ -500,9 +523,12 @@ int smc_init(const smc_config *cfg, uint8_t *occ_dev, const float *params_dev, f
   if (!cfg || !occ_dev || !params_dev || !ecache_dev || !cfg->cells || !cfg->temperature_K)
     return SMC_E_INVALID;
   if (cfg->n_replicas < 1 || cfg->n_species < 2 || cfg->n_species > 5) return SMC_E_INVALID;
-  if (cfg->feature != SMC_FEAT_COUNTS_S12 && cfg->feature != SMC_FEAT_ONEHOT_S123) return SMC_E_INVALID;
+  if (cfg->feature != SMC_FEAT_COUNTS_S12 && cfg->feature != SMC_FEAT_ONEHOT_S123 &&
+      cfg->feature != SMC_FEAT_QSRO_S123)
+    return SMC_E_INVALID;
   if (cfg->precision < SMC_FP32 || cfg->precision > SMC_FP64) return SMC_E_INVALID;
-  if (cfg->hidden != 64 && cfg->hidden != 128) return SMC_E_UNSUPPORTED;
+  const bool qsro = cfg->feature == SMC_FEAT_QSRO_S123;
+  if (!qsro && cfg->hidden != 64 && cfg->hidden != 128) return SMC_E_UNSUPPORTED;
   const bool mfma = cfg->feature == SMC_FEAT_ONEHOT_S123 && cfg->hidden == 128;
   if (!mfma && cfg->precision != SMC_FP32 && cfg->precision != SMC_FP64) return SMC_E_UNSUPPORTED;
   int64_t total = 0;
@@ -528,6 +554,11 @@ int smc_init(const smc_config *cfg, uint8_t *occ_dev, const float *params_dev, f
   c->n_in = cfg->feature == SMC_FEAT_COUNTS_S12 ? 12 : 108;
   c->hidden = cfg->hidden;
   c->n_params = c->hidden * c->n_in + c->hidden + c->hidden * c->hidden + c->hidden + c->hidden + 1;
+  if (qsro) {
+    c->n_in = 0;
+    c->hidden = 0;
+    c->n_params = 92;  // V[3][5][5], W[3][5], lambda, C
+  }
   c->guard = cfg->guard_eV < 0 ? default_guard(cfg->precision) : cfg->guard_eV;
   int dev = 0;
   if (hipGetDevice(&dev) == hipSuccess) {

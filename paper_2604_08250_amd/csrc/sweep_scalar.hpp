@@ -59,7 +59,8 @@ __device__ inline T site_energy(const uint8_t *occ, const Replica &R, int64_t j,
                                 int64_t n, uint8_t si, uint8_t sn, const T *W) {
   uint8_t slot[kSlots];
   gather_slots(occ, j, R.L[0], R.L[1], R.L[2], FEAT == 0 ? 15 : kSlots, swap, i, n, si, sn, slot);
-  return mlp_scalar<FEAT, H, T>(slot, W);
+  if constexpr (FEAT == 2) return qsro_scalar<T>(slot, W);
+  else return mlp_scalar<FEAT, H, T>(slot, W);
 }
 
 // Local energy of every site of one replica (FP32 into the cache, or FP64).
