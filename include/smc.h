@@ -167,6 +167,19 @@ int smc_counters(smc_ctx *ctx, uint64_t *out_host, int32_t reset);
 int smc_profile(smc_ctx *ctx, int32_t enable);
 int smc_kernel_times(smc_ctx *ctx, double *colour_ms, double *recheck_ms, int64_t *colour_launches);
 
+/* New temperatures (host [n_replicas], >= 0 or +inf) for the following sweeps, e.g. an
+ * annealing schedule (the paper's runs anneal its alloys at fixed T; Sec. IV-C).  The
+ * replica table is read by the kernels at run time, so captured sweeps follow the change.
+ * Synchronises. */
+int smc_set_temperatures(smc_ctx *ctx, const double *temperature_K_host);
+
+/* Warren-Cowley short-range order of one replica's current occupancy: alpha_host [3][S][S]
+ * (S = n_species) with alpha_m^{pq} = 1 - P(neighbour in shell m has species q | site has
+ * species p) / c_q, c_q the concentration of q; 0 where p or q is absent.  The pair fractions
+ * of the qSRO model (Eq. 3) averaged over the lattice.  Pair counts are integers summed on
+ * the device; synchronises. */
+int smc_warren_cowley(smc_ctx *ctx, int32_t replica, double *alpha_host);
+
 /* Sweep strategy (Algorithm 1, Sec. III-A).
  * SMC_STRATEGY_ZONE (default): each trial evaluates the post-swap local energies of its
  *   affected zone Omega (40 sites) and takes the pre-swap ones from the energy cache.

@@ -7,12 +7,13 @@ from __future__ import annotations
 
 import numpy as np
 
-from ._lib import (PRECISIONS, SMC_BF16, SMC_BF16X3, SMC_FEAT_COUNTS_S12, SMC_FEAT_ONEHOT_S123,
+from ._lib import (PRECISIONS, SMC_BF16, SMC_BF16X3, SMC_FEAT_COUNTS_S12, SMC_FEAT_ONEHOT_S123, SMC_FEAT_QSRO_S123,
                    SMC_FP8_E4M3, SMC_FP32, SMC_FP64, SMCError, lib, smc_autotune, smc_counters,
                    smc_delta_e64, smc_destroy, smc_energy, smc_get_sweep, smc_get_variant, smc_init,
                    smc_kernel_times, smc_n_colours, smc_n_sites, smc_profile, smc_refresh,
                    smc_set_params, smc_set_sweep, smc_set_variant, smc_site_energies, smc_sweep,
-                   smc_use_graph, smc_set_strategy, smc_get_strategy, STRATEGIES)
+                   smc_use_graph, smc_set_strategy, smc_get_strategy, STRATEGIES, smc_set_temperatures,
+                   smc_warren_cowley)
 
 __all__ = ["SwapMC", "SMCError", "PRECISIONS", "lib"]
 
@@ -42,6 +43,7 @@ class SwapMC:
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         self.n_sites = n_total
+        self.n_species = int(n_species)
         self.ctx = None
         self.ctx = smc_init(cells, self.temperatures, n_species, feature, hidden, self.precision,
                             seed, guard_eV, self.occ.data_ptr(), self.params.data_ptr(),
@@ -109,6 +111,22 @@ class SwapMC:
     @sweep_index.setter
     def sweep_index(self, v):
         smc_set_sweep(self.ctx, int(v))
+
+    def set_temperatures(self, temperatures):
+        """Temperatures (K) of every replica for the following sweeps (scalar: all replicas)."""
+        t = np.broadcast_to(np.asarray(temperatures, dtype=np.float64), (self.n_replicas,)).copy()
+        smc_set_temperatures(self.ctx, t)
+        self.temperatures = t
+
+    def anneal(self, schedule, sweeps_per_temperature):
+        """Run sweeps_per_temperature sweeps at each temperature of the schedule (K)."""
+        for T in schedule:
+            self.set_temperatures(T)
+            self.sweep(sweeps_per_temperature)
+
+    def warren_cowley(self, replica=0):
+        """Warren-Cowley alpha[shell][p][q] of the replica's current occupancy."""
+        return smc_warren_cowley(self.ctx, replica, self.n_species)
 
     @property
     def strategy(self):

@@ -23,7 +23,7 @@ PRECISIONS = {"fp32": SMC_FP32, "bf16": SMC_BF16, "bf16x3": SMC_BF16X3, "fp8": S
 
 EXPORTS = ["smc_init", "smc_sweep", "smc_energy", "smc_site_energies", "smc_set_params",
            "smc_refresh", "smc_counters", "smc_delta_e64", "smc_profile", "smc_kernel_times", "smc_get_sweep",
-           "smc_set_sweep", "smc_set_strategy", "smc_get_strategy", "smc_use_graph", "smc_set_variant", "smc_get_variant", "smc_autotune",
+           "smc_set_sweep", "smc_set_temperatures", "smc_warren_cowley", "smc_set_strategy", "smc_get_strategy", "smc_use_graph", "smc_set_variant", "smc_get_variant", "smc_autotune",
            "smc_energy_fwd", "smc_energy_bwd", "smc_fit_step", "smc_ce_energy", "smc_ce_triangles",
            "smc_n_sites", "smc_n_colours", "smc_destroy", "smc_last_error", "smc_status_string"]
 
@@ -78,6 +78,8 @@ def lib():
                                            C.POINTER(C.c_int64)]),
             "smc_get_sweep": (C.c_int, [vp, C.POINTER(C.c_uint64)]),
             "smc_set_sweep": (C.c_int, [vp, C.c_uint64]),
+            "smc_set_temperatures": (C.c_int, [vp, C.POINTER(C.c_double)]),
+            "smc_warren_cowley": (C.c_int, [vp, C.c_int32, C.POINTER(C.c_double)]),
             "smc_set_strategy": (C.c_int, [vp, C.c_int32]),
             "smc_get_strategy": (C.c_int, [vp, C.POINTER(C.c_int32)]),
             "smc_use_graph": (C.c_int, [vp, C.c_int32]),
@@ -192,6 +194,17 @@ def smc_get_sweep(ctx) -> int:
 
 def smc_set_sweep(ctx, sweep):
     check(lib().smc_set_sweep(ctx, sweep), ctx)
+
+
+def smc_set_temperatures(ctx, temperatures):
+    t = np.ascontiguousarray(np.asarray(temperatures, dtype=np.float64).reshape(-1))
+    check(lib().smc_set_temperatures(ctx, t.ctypes.data_as(C.POINTER(C.c_double))), ctx)
+
+
+def smc_warren_cowley(ctx, replica, n_species):
+    a = np.zeros((3, n_species, n_species), dtype=np.float64)
+    check(lib().smc_warren_cowley(ctx, int(replica), a.ctypes.data_as(C.POINTER(C.c_double))), ctx)
+    return a
 
 
 SMC_STRATEGY_ZONE, SMC_STRATEGY_DOUBLE_LATTICE = 0, 1

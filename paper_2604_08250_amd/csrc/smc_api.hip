@@ -853,6 +853,49 @@ int smc_get_variant(const smc_ctx *c, int32_t *variant) {
   return SMC_OK;
 }
 
+int smc_set_temperatures(smc_ctx *c, const double *temperature_K) {
+  if (!c || !temperature_K) return SMC_E_INVALID;
+  const int R = (int)c->reps.size();
+  for (int r = 0; r < R; ++r)
+    if (!(temperature_K[r] >= 0.0)) return fail(c, SMC_E_INVALID, "temperatures must be >= 0 or +inf");
+  for (int r = 0; r < R; ++r) {
+    c->temps[r] = temperature_K[r];
+    c->reps[r].temperature = temperature_K[r];
+  }
+  // kernels (and replays of the captured sweep) read the replica table at run time
+  HIPC(c, hipMemcpyAsync(c->d_reps, c->reps.data(), sizeof(Replica) * R, hipMemcpyHostToDevice, c->stream));
+  HIPC(c, hipStreamSynchronize(c->stream));
+  return SMC_OK;
+}
+
+int smc_warren_cowley(smc_ctx *c, int32_t replica, double *alpha) {
+  if (!c || !alpha || replica < 0 || replica >= (int32_t)c->reps.size()) return SMC_E_INVALID;
+  const int S = c->cfg.n_species;
+  unsigned long long *d = nullptr;
+  if (hipMalloc(&d, sizeof(unsigned long long) * (3 * S * S + S)) != hipSuccess) return fail(c, SMC_E_NOMEM, "counts");
+  std::vector<unsigned long long> h(3 * S * S + S);
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(256), 0, c->stream, (uint64_t *)d, (int64_t)(3 * S * S + S), (uint64_t)0);
+  const int64_t n = c->reps[replica].n_sites;
+  const unsigned grid = (unsigned)std::min<int64_t>(grid_for(n, 256), 4 * (int64_t)c->n_cu);
+  hipLaunchKernelGGL(k_pair_counts, dim3(grid), dim3(256), 0, c->stream, c->d_reps, replica, c->occ, S, d,
+                     d + 3 * S * S);
+  const hipError_t e1 = hipMemcpyAsync(h.data(), d, sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost,
+                                       c->stream);
+  const hipError_t e2 = hipStreamSynchronize(c->stream);
+  (void)hipFree(d);
+  if (e1 != hipSuccess || e2 != hipSuccess) return fail(c, SMC_E_DEVICE, "pair counts");
+  const unsigned long long *cnt = h.data(), *nsp = h.data() + 3 * S * S;
+  const double z[3] = {8.0, 6.0, 12.0};
+  for (int m = 0; m < 3; ++m)
+    for (int p = 0; p < S; ++p)
+      for (int q = 0; q < S; ++q) {
+        const double cq = (double)nsp[q] / (double)n;
+        const double pq = nsp[p] > 0 ? (double)cnt[(m * S + p) * S + q] / ((double)nsp[p] * z[m]) : 0.0;
+        alpha[(m * S + p) * S + q] = (cq > 0 && nsp[p] > 0) ? 1.0 - pq / cq : 0.0;
+      }
+  return SMC_OK;
+}
+
 int smc_set_strategy(smc_ctx *c, int32_t strategy) {
   if (!c) return SMC_E_INVALID;
   if (strategy != SMC_STRATEGY_ZONE && strategy != SMC_STRATEGY_DOUBLE_LATTICE)

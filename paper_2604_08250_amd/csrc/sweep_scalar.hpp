@@ -176,6 +176,38 @@ __global__ void k_sum_into(const double *v, int64_t n, double *out, int accumula
   if (threadIdx.x == 0) *out = accumulate ? *out + s[0] : s[0];
 }
 
+// Pair counts for short-range order: per coordination shell m (1..3) and ordered species pair
+// (p, q), the number of (site, shell-m neighbour) pairs with those species, and the number of
+// sites of each species; per-block LDS histograms, then one global add per counter.
+__global__ void k_pair_counts(const Replica *reps, int32_t r, const uint8_t *occ_all, int32_t S,
+                              unsigned long long *cnt, unsigned long long *nsp) {
+  __shared__ unsigned int s_cnt[3 * 5 * 5 + 5];
+  for (int q = threadIdx.x; q < 3 * 25 + 5; q += blockDim.x) s_cnt[q] = 0u;
+  __syncthreads();
+  const Replica R = reps[r];
+  const uint8_t *occ = occ_all + R.site0;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < R.n_sites; j += (int64_t)gridDim.x * blockDim.x) {
+    const int p = occ[j];
+    if (p >= S) continue;  // occupancies are validated on entry; never index past the histogram
+    atomicAdd(&s_cnt[75 + p], 1u);
+    const Pos pos = site_pos(j, R.L[0], R.L[1]);
+    for (int k = 0; k < kNbr; ++k) {
+      const int q = occ[site_at(pos, shell_dx(k), shell_dy(k), shell_dz(k), R.L[0], R.L[1], R.L[2])];
+      if (q < S) atomicAdd(&s_cnt[((shell_of(k) - 1) * 5 + p) * 5 + q], 1u);
+    }
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < 3 * 25 + 5; q += blockDim.x) {
+    if (!s_cnt[q]) continue;
+    if (q < 75) {
+      const int m = q / 25, p = (q / 5) % 5, qq = q % 5;
+      if (p < S && qq < S) atomicAdd(&cnt[(m * S + p) * S + qq], (unsigned long long)s_cnt[q]);
+    } else if (q - 75 < S) {
+      atomicAdd(&nsp[q - 75], (unsigned long long)s_cnt[q]);
+    }
+  }
+}
+
 // Fill n words with v (grid-stride, so any launch shape covers all of them).
 __global__ void k_fill_u64(uint64_t *p, int64_t n, uint64_t v) {
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)

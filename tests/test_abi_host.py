@@ -68,6 +68,8 @@ def test_null_arguments():
     assert lib.smc_init(None, None, None, None, None, None) == -1
     assert lib.smc_sweep(None, 1, None) == -1
     assert lib.smc_energy(None, None, None) == -1
+    assert lib.smc_set_temperatures(None, None) == -1
+    assert lib.smc_warren_cowley(None, 0, None) == -1
     assert lib.smc_set_strategy(None, 1) == -1
     assert lib.smc_get_strategy(None, None) == -1
     assert lib.smc_use_graph(None, 1) == -1
