@@ -1,6 +1,7 @@
 """Python view of the plain CPU oracle (test infrastructure only).
 
-The oracle is the slow FP64 C library in ``smc_oracle.c``.  Only the test suite, the
+The oracle is the slow FP64 C library in ``smc_oracle.c`` (BCC), ``fcc_oracle.c`` (FCC, see
+``oracle.fcc``) and ``fit_oracle.c`` (the fit).  Only the test suite, the
 smoke check and the CPU-baseline leg of the benchmark may import this package; the
 product package never does.  ``build()`` compiles the library with gcc.
 """
@@ -15,7 +16,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "smc_oracle.c")
-SOURCES = [SRC, os.path.join(HERE, "fit_oracle.c")]
+SOURCES = [SRC, os.path.join(HERE, "fit_oracle.c"), os.path.join(HERE, "fcc_oracle.c")]
 LIB = os.path.join(HERE, "liboracle.so")
 
 FEAT_COUNTS_S12, FEAT_ONEHOT_S123, FEAT_QSRO_S123 = 0, 1, 2

@@ -95,6 +95,43 @@ int or_sweep(const int32_t L[3], const or_model *m, uint8_t *occ, double tempera
 /* Observables. alpha is [3][S][S]. */
 void or_warren_cowley(const int32_t L[3], const uint8_t *occ, int32_t n_species, double *alpha);
 
+/* FCC lattice with the MLPNet and qSRO models (fcc_oracle.c).  Sites s = ((z*Ly + y)*Lx + x)*4 + b,
+ * shells 1-3 = 12 / 6 / 24 neighbours; the MLPNet reads shells 1-2 (76 inputs), qSRO shells 1-3. */
+enum { OR_FCC_MLPNET_S12 = 0, OR_FCC_QSRO_S123 = 1 };
+typedef struct {
+  int32_t model;          /* OR_FCC_* */
+  int32_t hidden;         /* H of every hidden layer (MLPNet) */
+  const double *params;   /* MLPNet: W0[H][76], b0[H], W1[H][H], b1[H], W2[H][H], b2[H], W3[H], b3.
+                             qSRO: V[3][5][5], W[3][5], lambda, C (92 values). */
+} or_fcc_model;
+
+int64_t or_fcc_n_sites(const int32_t L[3]);
+void or_fcc_site_pos(const int32_t L[3], int64_t s, int32_t P[3]);
+int64_t or_fcc_site_at(const int32_t L[3], const int32_t P[3]);
+void or_fcc_shell_table(int32_t off[42 * 3], int32_t shell[42]);
+int64_t or_fcc_neighbor(const int32_t L[3], int64_t s, int32_t k);
+int32_t or_fcc_n_neighbors_used(int32_t model);
+int32_t or_fcc_n_inputs(void);
+int64_t or_fcc_n_params(const or_fcc_model *m);
+void or_fcc_features(const int32_t L[3], const uint8_t *occ, int64_t j, int64_t swap_i, int64_t swap_n,
+                     double *x);
+double or_fcc_mlpnet(const or_fcc_model *m, const double *x);
+double or_fcc_qsro(const int32_t L[3], const double *params, const uint8_t *occ, int64_t j, int64_t swap_i,
+                   int64_t swap_n);
+double or_fcc_site_energy(const int32_t L[3], const or_fcc_model *m, const uint8_t *occ, int64_t j,
+                          int64_t swap_i, int64_t swap_n);
+void or_fcc_all_site_energies(const int32_t L[3], const or_fcc_model *m, const uint8_t *occ, double *e);
+double or_fcc_total_energy(const int32_t L[3], const or_fcc_model *m, const uint8_t *occ);
+int32_t or_fcc_omega(const int32_t L[3], int32_t model, int64_t i, int64_t n, int64_t *omega);
+double or_fcc_delta_e(const int32_t L[3], const or_fcc_model *m, const uint8_t *occ, int64_t i, int64_t n);
+int32_t or_fcc_n_colours(const int32_t L[3]);
+int32_t or_fcc_colour_of(const int32_t L[3], int64_t s);
+void or_fcc_propose(uint64_t seed, int64_t site, int64_t sweep, int64_t replica, int32_t *dir, double *u);
+int or_fcc_sweep(const int32_t L[3], const or_fcc_model *m, uint8_t *occ, double temperature_K, uint64_t seed,
+                 int64_t replica, int64_t sweep, or_stats *st, or_trial_rec *trace, int32_t order,
+                 const int64_t *given_order, int32_t nthreads, int32_t colours_limit);
+void or_fcc_warren_cowley(const int32_t L[3], const uint8_t *occ, int32_t n_species, double *alpha);
+
 /* Differentiation pattern (fit_oracle.c). */
 typedef struct {
   int32_t n_species;

@@ -22,6 +22,12 @@ them; see the paper's Sec. IV-B/IV-C for the originals):
           compositions in [0.1, 0.4], temperatures log-spaced 300..3000 K.
 * ``c5``  fit workload: 16^3-cell snapshots, 108-input model, labels from a seeded
           cluster-expansion Hamiltonian (``ce_params``), batches of 1,024 snapshots.
+* ``fcc`` FCC 200^3 cells (32,000,000 sites, about one GPU's share of the paper's
+          1.009e9-atom system on 32 devices), five species in the paper's
+          Fe29Co29Ni28Al7Ti7 proportions (Sec. IV-C), the MLPNet shape of Eqs. (4)-(6)
+          (76 one-hot inputs of the centre and its 18 shell-1/2 neighbours -> 96 -> 96
+          -> 96 -> 1, ReLU) with random weights, T = 1000 K (the end of the paper's
+          annealing schedule).
 """
 from __future__ import annotations
 
@@ -40,6 +46,9 @@ SEED_FD = 5
 FEAT_COUNTS_S12 = 0   # 12 inputs: centre one-hot(4) + shell-1 counts(4) + shell-2 counts(4)
 FEAT_ONEHOT_S123 = 1  # 108 inputs: one-hot(4) of the centre and of 26 neighbours (shells 1-3)
 
+FEAT_QSRO_S123 = 2    # qSRO (Eq. 2) over shells 1-3
+FEAT_FCC_MLPNET_S12 = 3  # FCC: one-hot(4) of the centre and 18 shell-1/2 neighbours, MLPNet
+
 N_FEATURES = {FEAT_COUNTS_S12: 12, FEAT_ONEHOT_S123: 108}
 
 
@@ -57,12 +66,14 @@ def species_counts(n_sites: int, composition) -> np.ndarray:
     return counts
 
 
-def random_occupancy(cells, n_species: int = 4, composition=None, seed: int = SEED_LATTICE) -> np.ndarray:
-    """Uniformly random placement of a fixed composition on a BCC lattice of ``cells`` cubic cells.
+def random_occupancy(cells, n_species: int = 4, composition=None, seed: int = SEED_LATTICE,
+                     basis: int = 2) -> np.ndarray:
+    """Uniformly random placement of a fixed composition on a lattice of ``cells`` cubic cells
+    with ``basis`` sites per cell (2: BCC, 4: FCC).
 
-    Returns uint8 species ids in canonical site order (2 sites per cell)."""
+    Returns uint8 species ids in canonical site order."""
     lx, ly, lz = (cells, cells, cells) if np.isscalar(cells) else cells
-    n = 2 * int(lx) * int(ly) * int(lz)
+    n = int(basis) * int(lx) * int(ly) * int(lz)
     if composition is None:
         composition = np.full(n_species, 1.0 / n_species)
     counts = species_counts(n, composition)
@@ -109,22 +120,29 @@ class Workload:
     sweeps: int
     seed: int = SEED_PHILOX
     extra: dict = field(default_factory=dict)
+    lattice: str = "bcc"
+
+    @property
+    def basis(self) -> int:
+        return 4 if self.lattice == "fcc" else 2
 
     @property
     def n_in(self) -> int:
-        return N_FEATURES[self.feature]
+        return FCC_N_INPUTS if self.lattice == "fcc" else N_FEATURES[self.feature]
 
     @property
     def sites(self) -> list:
-        return [2 * a * b * c for a, b, c in self.cells]
+        return [self.basis * a * b * c for a, b, c in self.cells]
 
     def occupancy(self) -> np.ndarray:
         """Concatenated per-replica occupancies (replica r drawn with seed SEED_LATTICE + r)."""
-        parts = [random_occupancy(cl, self.n_species, comp, seed=SEED_LATTICE + r)
+        parts = [random_occupancy(cl, self.n_species, comp, seed=SEED_LATTICE + r, basis=self.basis)
                  for r, (cl, comp) in enumerate(zip(self.cells, self.compositions))]
         return np.concatenate(parts)
 
     def params(self) -> np.ndarray:
+        if self.lattice == "fcc":
+            return mlpnet_params(self.hidden, SEED_WEIGHTS)
         return mlp_params(self.n_in, self.hidden, SEED_WEIGHTS)
 
 
@@ -171,6 +189,25 @@ def ce_params(n_species: int = 4, n_items: int = 200, n_triangles: int = N_CE_TR
 
 SEED_QSRO = 6
 
+# The paper's alloy, Fe29Co29Ni28Al7Ti7 (Sec. IV-C), as species 0..4.
+HEA_COMPOSITION = (0.29, 0.29, 0.28, 0.07, 0.07)
+FCC_N_INPUTS = 76  # one-hot(4) of the centre and of the 18 shell-1/2 FCC neighbours
+
+
+def mlpnet_param_sizes(hidden: int = 96, n_in: int = FCC_N_INPUTS):
+    """(name, shape, fan_in) of the MLPNet blob (Eqs. (4)-(6)): W0, b0, W1, b1, W2, b2, W3, b3."""
+    return [("W0", (hidden, n_in), n_in), ("b0", (hidden,), n_in),
+            ("W1", (hidden, hidden), hidden), ("b1", (hidden,), hidden),
+            ("W2", (hidden, hidden), hidden), ("b2", (hidden,), hidden),
+            ("W3", (1, hidden), hidden), ("b3", (1,), hidden)]
+
+
+def mlpnet_params(hidden: int = 96, seed: int = SEED_WEIGHTS, n_in: int = FCC_N_INPUTS) -> np.ndarray:
+    """FP32 MLPNet blob, every entry ~ N(0, 1/fan_in) drawn in FP64 then rounded to FP32."""
+    rng = np.random.default_rng(seed)
+    parts = [rng.normal(0.0, math.sqrt(1.0 / f), size=s).ravel() for _, s, f in mlpnet_param_sizes(hidden, n_in)]
+    return np.concatenate(parts).astype(np.float32)
+
 
 def qsro_params(n_species: int = 4, seed: int = SEED_QSRO) -> np.ndarray:
     """Synthetic qSRO coefficients (Eq. 2; trained ones are not available), FP32 blob
@@ -211,6 +248,9 @@ def workload(name: str, **over) -> Workload:
     elif name == "c4":
         edges, comps, temps = replica_set()
         w = Workload("c4", [(e, e, e) for e in edges], 4, comps, temps, FEAT_ONEHOT_S123, 128, 500)
+    elif name == "fcc":
+        w = Workload("fcc", [(200, 200, 200)], 5, [HEA_COMPOSITION], [1000.0], FEAT_FCC_MLPNET_S12, 96, 100,
+                     lattice="fcc")
     elif name == "c5":
         w = Workload("c5", [(16, 16, 16)], 4, [None], [1000.0], FEAT_ONEHOT_S123, 128, 0,
                      extra=dict(n_snapshots=65536, batch=1024))
