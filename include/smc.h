@@ -51,6 +51,18 @@
  * neighbour in slot r0 >> 61; u = ((r1 >> 11) + 1) * 2^-53; theta = -kB T ln u with
  * kB = 8.617333262e-5 eV/K; the swap is accepted iff dE <= theta.  Equal species: no
  * energy evaluation, not accepted, still an attempt.
+ *
+ * FCC lattice (the paper's physical system, Sec. IV-C; smc_config.lattice = SMC_LATTICE_FCC):
+ * cell (x,y,z) holds four sites at doubled coordinates (2x,2y,2z) + (0,0,0), (0,1,1),
+ * (1,0,1), (1,1,0) for b = 0..3; s = ((z*Ly + y)*Lx + x)*4 + b.  Shells: 12 at a/sqrt(2),
+ * 6 at a, 24 at a*sqrt(3/2), lexicographic within a shell.  Link cells as on BCC with the
+ * basis index in the colour: 4 e_x e_y e_z colours (256 for 4x4x4 link cells).  The partner
+ * is nearest-neighbour slot floor((r0 >> 32) * 12 / 2^32).
+ *   SMC_FEAT_MLPNET_S12: [one-hot(centre), one-hot(neighbour k) for k = 0..17] (76 inputs)
+ *   into the MLPNet of Eqs. (4)-(6): h1 = relu(W0 x + b0), h2 = relu(W1 h1 + b1),
+ *   h3 = relu(W2 h2 + b2), E = W3 . h3 + b3, hidden = 96; blob W0[96][76], b0[96],
+ *   W1[96][96], b1[96], W2[96][96], b2[96], W3[96], b3 (26,113 floats).
+ *   SMC_FEAT_QSRO_S123: the qSRO blob above over the FCC shells 1..3.
  */
 #ifndef SMC_H
 #define SMC_H
@@ -84,7 +96,15 @@ enum smc_prec {
 /* Energy model and its inputs.  SMC_FEAT_COUNTS_S12 and SMC_FEAT_ONEHOT_S123 select the MLP
  * (Eqs. (4)-(6)) with those features; SMC_FEAT_QSRO_S123 selects the qSRO model (Eq. 2) over
  * coordination shells 1..3 (hidden is ignored; FP32 or FP64 only). */
-enum smc_feat { SMC_FEAT_COUNTS_S12 = 0, SMC_FEAT_ONEHOT_S123 = 1, SMC_FEAT_QSRO_S123 = 2 };
+enum smc_feat {
+  SMC_FEAT_COUNTS_S12 = 0,
+  SMC_FEAT_ONEHOT_S123 = 1,
+  SMC_FEAT_QSRO_S123 = 2,
+  SMC_FEAT_MLPNET_S12 = 3  /* FCC only: the MLPNet of Eqs. (4)-(6), 96 hidden, FP32/BF16/BF16X3/FP64 */
+};
+
+/* Lattice of every replica of a context. */
+enum smc_lattice { SMC_LATTICE_BCC = 0, SMC_LATTICE_FCC = 1 };
 
 typedef struct {
   int32_t n_replicas;            /* >= 1 */
@@ -92,10 +112,11 @@ typedef struct {
   const double *temperature_K;   /* host, [n_replicas]; +inf accepts every swap */
   int32_t n_species;             /* 2..5 */
   int32_t feature;               /* smc_feat */
-  int32_t hidden;                /* H: 64 or 128 */
+  int32_t hidden;                /* H: 64 or 128 (BCC MLP), 96 (FCC MLPNet) */
   int32_t precision;             /* smc_prec */
   uint64_t seed;                 /* Philox key word 0 */
   double guard_eV;               /* FP64 re-decision band |dE - theta| < guard; < 0: default */
+  int32_t lattice;               /* smc_lattice; 0 (BCC) for a zero-initialised config */
 } smc_config;
 
 /* Optional outputs of smc_sweep.  Host counters accumulate over the sweeps of one call.
@@ -179,6 +200,11 @@ int smc_set_temperatures(smc_ctx *ctx, const double *temperature_K_host);
  * of the qSRO model (Eq. 3) averaged over the lattice.  Pair counts are integers summed on
  * the device; synchronises. */
 int smc_warren_cowley(smc_ctx *ctx, int32_t replica, double *alpha_host);
+
+/* Neighbour shells of a lattice (smc_lattice): writes up to max_slots offsets (doubled
+ * coordinates, [k][3]) and shell numbers (1-based) in slot order to the host arrays and
+ * returns the slot count (26 for BCC, 42 for FCC), or a negative status.  Host only. */
+int smc_lattice_shells(int32_t lattice, int32_t *offsets_host, int32_t *shells_host, int32_t max_slots);
 
 /* Sweep strategy (Algorithm 1, Sec. III-A).
  * SMC_STRATEGY_ZONE (default): each trial evaluates the post-swap local energies of its

@@ -1,4 +1,4 @@
-"""Swap Monte Carlo on periodic BCC alloys with a local MLP energy, for MI355X (gfx950).
+"""Swap Monte Carlo on periodic BCC and FCC alloys with local MLP or qSRO energies, for MI355X (gfx950).
 
 The compute path is the HIP library ``libsmc.so`` behind the C ABI of ``include/smc.h``;
 this package only marshals arguments.  PyTorch provides device memory and streams.
@@ -7,8 +7,9 @@ from __future__ import annotations
 
 import numpy as np
 
-from ._lib import (PRECISIONS, SMC_BF16, SMC_BF16X3, SMC_FEAT_COUNTS_S12, SMC_FEAT_ONEHOT_S123, SMC_FEAT_QSRO_S123,
-                   SMC_FP8_E4M3, SMC_FP32, SMC_FP64, SMCError, lib, smc_autotune, smc_counters,
+from ._lib import (PRECISIONS, SMC_BF16, SMC_BF16X3, SMC_FEAT_COUNTS_S12, SMC_FEAT_ONEHOT_S123,
+                   SMC_FEAT_QSRO_S123, SMC_FEAT_MLPNET_S12, SMC_LATTICE_BCC, SMC_LATTICE_FCC, LATTICES, BASIS,
+                   smc_lattice_shells, SMC_FP8_E4M3, SMC_FP32, SMC_FP64, SMCError, lib, smc_autotune, smc_counters,
                    smc_delta_e64, smc_destroy, smc_energy, smc_get_sweep, smc_get_variant, smc_init,
                    smc_kernel_times, smc_n_colours, smc_n_sites, smc_profile, smc_refresh,
                    smc_set_params, smc_set_sweep, smc_set_variant, smc_site_energies, smc_sweep,
@@ -27,7 +28,7 @@ class SwapMC:
     """One libsmc context over caller-owned torch tensors (occupancy, parameters, cache)."""
 
     def __init__(self, cells, temperatures, occ, params, *, n_species, feature, hidden,
-                 precision="fp32", seed=0, guard_eV=-1.0, device="cuda:0", stream=None):
+                 precision="fp32", seed=0, guard_eV=-1.0, device="cuda:0", stream=None, lattice="bcc"):
         torch = _torch()
         cells = np.asarray(cells, dtype=np.int32).reshape(-1, 3)
         self.cells = cells
@@ -36,7 +37,8 @@ class SwapMC:
         self.device = torch.device(device)
         self.occ = torch.as_tensor(np.asarray(occ, dtype=np.uint8)).to(self.device).contiguous()
         self.params = torch.as_tensor(np.asarray(params, dtype=np.float32)).to(self.device).contiguous()
-        n_total = int(sum(2 * int(np.prod(c)) for c in cells))
+        self.lattice = LATTICES[lattice] if isinstance(lattice, str) else int(lattice)
+        n_total = int(sum(BASIS[self.lattice] * int(np.prod(c)) for c in cells))
         if self.occ.numel() != n_total:
             raise ValueError(f"occupancy has {self.occ.numel()} sites, cells imply {n_total}")
         self.ecache = torch.empty(n_total, dtype=torch.float32, device=self.device)
@@ -47,7 +49,7 @@ class SwapMC:
         self.ctx = None
         self.ctx = smc_init(cells, self.temperatures, n_species, feature, hidden, self.precision,
                             seed, guard_eV, self.occ.data_ptr(), self.params.data_ptr(),
-                            self.ecache.data_ptr(), self.stream.cuda_stream)
+                            self.ecache.data_ptr(), self.stream.cuda_stream, self.lattice)
 
     def sweep(self, n=1, stats=False, trace=False):
         torch = _torch()

@@ -16,7 +16,10 @@ LIB_PATH = os.path.join(PKG, "libsmc.so")
 
 SMC_OK, SMC_E_INVALID, SMC_E_UNSUPPORTED, SMC_E_DEVICE, SMC_E_STATE, SMC_E_NOMEM = 0, -1, -2, -3, -4, -5
 SMC_FP32, SMC_BF16, SMC_BF16X3, SMC_FP8_E4M3, SMC_FP64 = 0, 1, 2, 3, 4
-SMC_FEAT_COUNTS_S12, SMC_FEAT_ONEHOT_S123, SMC_FEAT_QSRO_S123 = 0, 1, 2
+SMC_FEAT_COUNTS_S12, SMC_FEAT_ONEHOT_S123, SMC_FEAT_QSRO_S123, SMC_FEAT_MLPNET_S12 = 0, 1, 2, 3
+SMC_LATTICE_BCC, SMC_LATTICE_FCC = 0, 1
+LATTICES = {"bcc": SMC_LATTICE_BCC, "fcc": SMC_LATTICE_FCC}
+BASIS = {SMC_LATTICE_BCC: 2, SMC_LATTICE_FCC: 4}
 
 PRECISIONS = {"fp32": SMC_FP32, "bf16": SMC_BF16, "bf16x3": SMC_BF16X3, "fp8": SMC_FP8_E4M3,
               "fp64": SMC_FP64}
@@ -24,7 +27,7 @@ PRECISIONS = {"fp32": SMC_FP32, "bf16": SMC_BF16, "bf16x3": SMC_BF16X3, "fp8": S
 EXPORTS = ["smc_init", "smc_sweep", "smc_energy", "smc_site_energies", "smc_set_params",
            "smc_refresh", "smc_counters", "smc_delta_e64", "smc_profile", "smc_kernel_times", "smc_get_sweep",
            "smc_set_sweep", "smc_set_temperatures", "smc_warren_cowley", "smc_set_strategy", "smc_get_strategy", "smc_use_graph", "smc_set_variant", "smc_get_variant", "smc_autotune",
-           "smc_energy_fwd", "smc_energy_bwd", "smc_fit_step", "smc_ce_energy", "smc_ce_triangles",
+           "smc_energy_fwd", "smc_energy_bwd", "smc_fit_step", "smc_ce_energy", "smc_ce_triangles", "smc_lattice_shells",
            "smc_n_sites", "smc_n_colours", "smc_destroy", "smc_last_error", "smc_status_string"]
 
 
@@ -32,7 +35,7 @@ class smc_config(C.Structure):
     _fields_ = [("n_replicas", C.c_int32), ("cells", C.POINTER(C.c_int32)),
                 ("temperature_K", C.POINTER(C.c_double)), ("n_species", C.c_int32),
                 ("feature", C.c_int32), ("hidden", C.c_int32), ("precision", C.c_int32),
-                ("seed", C.c_uint64), ("guard_eV", C.c_double)]
+                ("seed", C.c_uint64), ("guard_eV", C.c_double), ("lattice", C.c_int32)]
 
 
 class smc_stats(C.Structure):
@@ -92,6 +95,7 @@ def lib():
                                        C.POINTER(C.c_double)]),
             "smc_ce_energy": (C.c_int, [vp, C.POINTER(smc_ce), vp, C.c_int32, C.c_int32, vp]),
             "smc_ce_triangles": (C.c_int, [C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32)]),
+            "smc_lattice_shells": (C.c_int, [C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32]),
             "smc_n_sites": (C.c_int, [vp, C.POINTER(C.c_int64)]),
             "smc_n_colours": (C.c_int, [vp, C.c_int32, C.POINTER(C.c_int32)]),
             "smc_destroy": (None, [vp]),
@@ -119,12 +123,12 @@ def _u64(a):
 
 
 def smc_init(cells, temperatures, n_species, feature, hidden, precision, seed, guard_eV,
-             occ_ptr, params_ptr, ecache_ptr, stream_ptr):
+             occ_ptr, params_ptr, ecache_ptr, stream_ptr, lattice=SMC_LATTICE_BCC):
     cells = np.ascontiguousarray(np.asarray(cells, dtype=np.int32).reshape(-1, 3))
     temps = np.ascontiguousarray(np.asarray(temperatures, dtype=np.float64).reshape(-1))
     cfg = smc_config(len(temps), cells.ctypes.data_as(C.POINTER(C.c_int32)),
                      temps.ctypes.data_as(C.POINTER(C.c_double)), n_species, feature, hidden,
-                     precision, seed, guard_eV)
+                     precision, seed, guard_eV, lattice)
     ctx = C.c_void_p()
     rc = lib().smc_init(C.byref(cfg), occ_ptr, params_ptr, ecache_ptr, stream_ptr, C.byref(ctx))
     check(rc)
@@ -194,6 +198,17 @@ def smc_get_sweep(ctx) -> int:
 
 def smc_set_sweep(ctx, sweep):
     check(lib().smc_set_sweep(ctx, sweep), ctx)
+
+
+def smc_lattice_shells(lattice):
+    """(offsets [k][3], shells [k]) of the neighbour slots of a lattice, in slot order."""
+    off = np.zeros((64, 3), dtype=np.int32)
+    sh = np.zeros(64, dtype=np.int32)
+    n = lib().smc_lattice_shells(int(lattice), off.ctypes.data_as(C.POINTER(C.c_int32)),
+                                 sh.ctypes.data_as(C.POINTER(C.c_int32)), 64)
+    if n < 0:
+        check(n)
+    return off[:n].copy(), sh[:n].copy()
 
 
 def smc_set_temperatures(ctx, temperatures):

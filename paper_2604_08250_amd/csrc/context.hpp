@@ -14,6 +14,27 @@ namespace smc {
 
 struct RecheckEntry;
 struct DlTrial;
+namespace fcc {
+struct Trial;
+struct QEntry;
+}
+
+// Buffers of the FCC lattice path.
+struct FccState {
+  bool on = false;
+  int model = 0;                     // 0: MLPNet (shells 1-2), 1: qSRO (shells 1-3)
+  int om_n = 0;                      // zone size: 28 or 60
+  int8_t *d_om = nullptr;            // [12][60][3] zone offsets per partner slot
+  fcc::Trial *d_trials = nullptr;    // [cap]
+  int32_t *d_active = nullptr;       // [cap]
+  float *d_e1 = nullptr;             // [cap][om_n]
+  fcc::QEntry *d_queue = nullptr;    // [cap]
+  uint32_t *d_counts = nullptr;      // active trials, queued trials (one 64-bit word)
+  int64_t cap = 0;                   // largest trial count of a colour
+  uint8_t *d_pack[3] = {nullptr, nullptr, nullptr};  // FP32, BF16, split BF16 weight images
+  bool pack_ready[3] = {false, false, false};
+  float b3 = 0.0f;
+};
 
 struct DevPack {  // one precision's packed weights on the device
   bool ready = false;
@@ -103,6 +124,7 @@ struct smc_ctx {
   float *d_E0 = nullptr, *d_E1 = nullptr;  // [N] all-site energies before / after
   smc::DlTrial *d_dltrials = nullptr;      // [largest colour of a replica]
   smc::FitState fit;
+  smc::FccState fcc;
   std::string err;
 };
 
@@ -114,6 +136,33 @@ inline int fail(smc_ctx *c, int code, const std::string &msg) {
 }
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
+
+// Start event of a timed launch (index of the pair), or -1 when not profiling.
+inline int prof_begin(smc_ctx *c) {
+  if (!c->profiling) return -1;
+  const size_t k = c->ev_used;
+  if (2 * k + 2 > c->ev_pool.size()) {
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return -1;
+    if (hipEventCreate(&e1) != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      return -1;
+    }
+    c->ev_pool.push_back(e0);
+    c->ev_pool.push_back(e1);
+    c->ev_kind.push_back(0);
+  }
+  if (hipEventRecord(c->ev_pool[2 * k], c->stream) != hipSuccess) return -1;
+  c->ev_used++;
+  return (int)k;
+}
+
+inline void prof_end(smc_ctx *c, int k, int kind) {
+  if (k < 0) return;
+  c->ev_kind[k] = kind;
+  (void)hipEventRecord(c->ev_pool[2 * k + 1], c->stream);
+}
+
 
 // Return SMC_E_DEVICE with the failing call and HIP's message.
 #define HIPC(c, expr)                                                                   \

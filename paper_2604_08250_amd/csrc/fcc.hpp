@@ -1,0 +1,744 @@
+// FCC lattice path: geometry, the MLPNet evaluator on the matrix cores and the per-colour
+// phase kernels of a sweep.
+//
+// Geometry.  Cell (x,y,z) holds four basis sites at doubled coordinates (2x,2y,2z) +
+// {(0,0,0), (0,1,1), (1,0,1), (1,1,0)} for b = 0..3; site index s = ((z*Ly + y)*Lx + x)*4 + b;
+// periodic modulo 2L per axis.  Neighbour slots: shell 1 (12 vectors, permutations of
+// (+-1,+-1,0), distance a/sqrt2), shell 2 (6, (+-2,0,0)), shell 3 (24, permutations of
+// (+-2,+-1,+-1)), each shell in lexicographic order of (dx,dy,dz).  The MLPNet reads shells
+// 1-2 (the site and 18 neighbours, 76 one-hot inputs); qSRO reads shells 1-3.
+//
+// MLPNet (Eqs. (4)-(6)): E = W3 . relu(W2 relu(W1 relu(W0 x + b0) + b1) + b2) + b3 with
+// 96 units per hidden layer.  Evaluated transposed, 32 sites per tile, exactly like the BCC
+// evaluator: three M-tiles of 32 hidden units, the output registers of one layer are the B
+// operand of the next, and the layer-0 bias rides on a constant-one input (slot 19,
+// feature 76).  ReLU needs no folding of constants.
+//
+// A sweep runs, per replica and colour: k_propose (Philox proposals, same-species trials
+// set aside, active trials appended to a list), k_rows_net / k_rows_qsro (post-swap local
+// energies of every zone site of every active trial), k_decide (zone sums against the energy
+// cache, Metropolis decision or a place in the FP64 queue, apply) and k_recheck (FP64 zone
+// energies before and after for queued trials, decide, apply).
+#pragma once
+#include "mfma_eval.hpp"
+#include "scalar_eval.hpp"
+#include "sweep_scalar.hpp"
+
+namespace smc {
+namespace fcc {
+
+constexpr int kNbr = 42;        // shells 1-3
+constexpr int kNbrMlp = 18;     // shells 1-2
+constexpr int kDirs = 12;       // nearest neighbours = swap partners
+constexpr int kOmMlp = 28;      // |Omega| with shells 1-2
+constexpr int kOmQsro = 60;     // |Omega| with shells 1-3
+constexpr int kOmMax = 60;
+constexpr int kHid = 96;
+constexpr int kMT = 3;          // M-tiles of 32 hidden units
+constexpr int kIn = 76;         // 19 slots x 4 channels
+constexpr int kSlots = 19;
+
+__host__ __device__ constexpr int8_t dx(int k) {
+  constexpr int8_t t[kNbr] = {-1, -1, -1, -1, 0,  0,  0,  0,  1,  1,  1,  1,  -2, 0,
+                              0,  0,  0,  2,  -2, -2, -2, -2, -1, -1, -1, -1, -1, -1,
+                              -1, -1, 1,  1,  1,  1,  1,  1,  1,  1,  2,  2,  2,  2};
+  return t[k];
+}
+__host__ __device__ constexpr int8_t dy(int k) {
+  constexpr int8_t t[kNbr] = {-1, 0,  0,  1,  -1, -1, 1,  1,  -1, 0,  0,  1,  0,  -2,
+                              0,  0,  2,  0,  -1, -1, 1,  1,  -2, -2, -1, -1, 1,  1,
+                              2,  2,  -2, -2, -1, -1, 1,  1,  2,  2,  -1, -1, 1,  1};
+  return t[k];
+}
+__host__ __device__ constexpr int8_t dz(int k) {
+  constexpr int8_t t[kNbr] = {0,  -1, 1,  0,  -1, 1,  -1, 1,  0,  -1, 1,  0,  0,  0,
+                              -2, 2,  0,  0,  -1, 1,  -1, 1,  -1, 1,  -2, 2,  -2, 2,
+                              -1, 1,  -1, 1,  -2, 2,  -2, 2,  -1, 1,  -1, 1,  -1, 1};
+  return t[k];
+}
+__host__ __device__ constexpr int shell_of(int k) { return k < 12 ? 1 : (k < 18 ? 2 : 3); }
+
+__host__ __device__ inline Pos pos(int64_t s, int32_t lx, int32_t ly) {
+  const int32_t b = (int32_t)(s & 3);
+  const int64_t c = s >> 2;
+  const int32_t x = (int32_t)(c % lx);
+  const int64_t r = c / lx;
+  const int32_t y = (int32_t)(r % ly);
+  const int32_t z = (int32_t)(r / ly);
+  // basis offsets (0,0,0), (0,1,1), (1,0,1), (1,1,0): x parity is bit 1 of b, y parity bit 0
+  const int32_t bx = b >> 1, by = b & 1, bz = bx ^ by;
+  return Pos{2 * x + bx, 2 * y + by, 2 * z + bz};
+}
+
+__host__ __device__ inline int64_t index(Pos p, int32_t lx, int32_t ly) {
+  const int32_t b = ((p.x & 1) << 1) | (p.y & 1);
+  return (((int64_t)(p.z >> 1) * ly + (p.y >> 1)) * lx + (p.x >> 1)) * 4 + b;
+}
+
+__host__ __device__ inline int64_t at(Pos p, int ddx, int ddy, int ddz, int32_t lx, int32_t ly, int32_t lz) {
+  Pos q{wrap1(p.x + ddx, 2 * lx), wrap1(p.y + ddy, 2 * ly), wrap1(p.z + ddz, 2 * lz)};
+  return index(q, lx, ly);
+}
+
+// Partner slot from the first Philox word: floor((r0 >> 32) * 12 / 2^32).
+__host__ __device__ inline int dir_of(uint64_t r0) { return (int)(((r0 >> 32) * 12ull) >> 32); }
+
+// Trial site of (colour, link cell t) of a replica with four basis sites, or -1 where that
+// link cell is too short to hold the colour's offset.
+__device__ inline int64_t trial_site(const Replica &R, int32_t colour, int64_t t) {
+  const int32_t b = colour & 3;
+  int32_t rest = colour >> 2;
+  const int32_t ox = rest % R.ax[0].big;
+  rest /= R.ax[0].big;
+  const int32_t oy = rest % R.ax[1].big;
+  const int32_t oz = rest / R.ax[1].big;
+  const int32_t cx = (int32_t)(t % R.ax[0].q);
+  const int64_t t1 = t / R.ax[0].q;
+  const int32_t cy = (int32_t)(t1 % R.ax[1].q);
+  const int32_t cz = (int32_t)(t1 / R.ax[1].q);
+  if (ox >= axis_len(R.ax[0], cx) || oy >= axis_len(R.ax[1], cy) || oz >= axis_len(R.ax[2], cz)) return -1;
+  const int32_t x = axis_start(R.ax[0], cx) + ox, y = axis_start(R.ax[1], cy) + oy, z = axis_start(R.ax[2], cz) + oz;
+  return (((int64_t)z * R.L[1] + y) * R.L[0] + x) * 4 + b;
+}
+
+// ------------------------------------------------------------------ MLPNet on matrix cores
+
+template <int P>
+struct NetSize;
+template <>
+struct NetSize<kP32> {
+  static constexpr int kL0 = kMT * 10 * 64 * 16;  // 40 K-steps of 2 (80 features), four per read
+  static constexpr int kL1 = kMT * 12 * 64 * 16;  // 48 K-steps of 2
+};
+template <>
+struct NetSize<kPBF16> {
+  static constexpr int kL0 = kMT * 5 * 64 * 16;   // 5 K-steps of 16
+  static constexpr int kL1 = kMT * 6 * 64 * 16;   // 6 K-steps of 16
+};
+template <>
+struct NetSize<kPBF16X3> {
+  static constexpr int kL0 = 2 * NetSize<kPBF16>::kL0;  // hi then lo
+  static constexpr int kL1 = 2 * NetSize<kPBF16>::kL1;
+};
+// Image: layer 0, layer 1, layer 2, then c1[96], c2[96], w3[96] (floats) and 16 bytes.
+template <int P>
+constexpr int net_bytes() {
+  return NetSize<P>::kL0 + 2 * NetSize<P>::kL1 + 3 * kHid * 4 + 16;
+}
+
+struct NetSmem {
+  const uint8_t *w;
+  const float *c1, *c2, *w3;
+  float b3;
+};
+
+__device__ __forceinline__ float relu(float x) { return fmaxf(x, 0.0f); }
+
+// One hidden layer: acc_out = c + W . relu(acc_in), weights at A (hi, and lo for split BF16).
+template <int P>
+__device__ __forceinline__ void net_hidden(const uint8_t *A0, const float *c, const f32x16 (&in)[kMT],
+                                           f32x16 (&out)[kMT]) {
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 5;
+#pragma unroll
+  for (int T = 0; T < kMT; ++T)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const f32x4 b = *(const f32x4 *)(c + 32 * T + 8 * j + 4 * g);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) out[T][4 * j + i] = b[i];
+    }
+  if constexpr (P == kP32) {
+    f32x16 h[kMT];
+#pragma unroll
+    for (int T = 0; T < kMT; ++T)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) h[T][v] = relu(in[T][v]);
+    // K-step s = 16T + v: lane group g supplies its own register v of M-tile T
+    const f32x4 *A = (const f32x4 *)A0;
+#pragma unroll
+    for (int T = 0; T < kMT; ++T)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int To = 0; To < kMT; ++To) {
+          const f32x4 a = A[(To * 12 + T * 4 + q) * 64 + lane];
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            out[To] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], h[T][4 * q + i], out[To], 0, 0, 0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+  } else {
+    // K-step s = 2T + hh takes registers 8hh..8hh+7 of M-tile T
+    const i32x4 *Ahi = (const i32x4 *)A0;
+    const i32x4 *Alo = (const i32x4 *)(A0 + NetSize<kPBF16>::kL1);
+#pragma unroll
+    for (int T = 0; T < kMT; ++T)
+#pragma unroll
+      for (int hh = 0; hh < 2; ++hh) {
+        i32x4 bh, bl;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float x0 = relu(in[T][8 * hh + 2 * q]);
+          const float x1 = relu(in[T][8 * hh + 2 * q + 1]);
+          const uint32_t w = pack_bf16x2(x0, x1);
+          bh[q] = (int)w;
+          if constexpr (P == kPBF16X3) bl[q] = (int)pack_bf16x2(x0 - bf16_lo_f32(w), x1 - bf16_hi_f32(w));
+        }
+        const bf16x8 Bh = __builtin_bit_cast(bf16x8, bh);
+        const int s = 2 * T + hh;
+#pragma unroll
+        for (int To = 0; To < kMT; ++To) {
+          const bf16x8 ah = __builtin_bit_cast(bf16x8, Ahi[(To * 6 + s) * 64 + lane]);
+          out[To] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, Bh, out[To], 0, 0, 0);
+          if constexpr (P == kPBF16X3) {
+            const bf16x8 Bl = __builtin_bit_cast(bf16x8, bl);
+            const bf16x8 al = __builtin_bit_cast(bf16x8, Alo[(To * 6 + s) * 64 + lane]);
+            out[To] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, Bl, out[To], 0, 0, 0);
+            out[To] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, Bh, out[To], 0, 0, 0);
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+  }
+}
+
+// Energy of the site held by this lane (lane % 32) of a 32-site tile; get(m) returns the
+// species of slot m (0 = the site, 1 + k = neighbour k, k < 18).  Both lane groups return
+// the same value.
+template <int P, typename GetSlot>
+__device__ __forceinline__ float eval_net(const NetSmem &S, GetSlot get) {
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 5;
+  f32x16 acc[kMT];
+#pragma unroll
+  for (int T = 0; T < kMT; ++T)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[T][v] = 0.0f;
+  if constexpr (P == kP32) {
+    // K-steps 2m, 2m+1 hold slot m: lane group g supplies channel g, then channel 2 + g
+    const f32x4 *A = (const f32x4 *)S.w;
+#pragma unroll
+    for (int m = 0; m < 20; ++m) {
+      const uint32_t p = m < kSlots ? (uint32_t)get(m) : 0u;  // slot 19: the constant one
+      const float b0 = (p == (uint32_t)g) ? 1.0f : 0.0f;
+      const float b1 = (p == (uint32_t)(2 + g)) ? 1.0f : 0.0f;
+#pragma unroll
+      for (int T = 0; T < kMT; ++T) {
+        const f32x4 a = A[(T * 10 + m / 2) * 64 + lane];
+        const int o = (m & 1) * 2;
+        acc[T] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[o], b0, acc[T], 0, 0, 0);
+        acc[T] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[o + 1], b1, acc[T], 0, 0, 0);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  } else {
+    // K-step s covers slots 4s..4s+3: lane group g supplies slots 4s + 2g and 4s + 2g + 1
+    const i32x4 *Ahi = (const i32x4 *)S.w;
+    const i32x4 *Alo = (const i32x4 *)(S.w + NetSize<kPBF16>::kL0);
+#pragma unroll
+    for (int s = 0; s < 5; ++s) {
+      const int m0 = 4 * s + 2 * g;
+      const uint32_t p0 = m0 < kSlots ? (uint32_t)get(m0) : 0u;
+      const uint32_t p1 = m0 + 1 < kSlots ? (uint32_t)get(m0 + 1) : 0u;  // slot 19: the constant one
+      i32x4 bw;
+      uint32_t l0, h0, l1, h1;
+      onehot_bf16(p0, l0, h0);
+      onehot_bf16(p1, l1, h1);
+      bw[0] = (int)l0; bw[1] = (int)h0; bw[2] = (int)l1; bw[3] = (int)h1;
+      const bf16x8 b = __builtin_bit_cast(bf16x8, bw);
+#pragma unroll
+      for (int T = 0; T < kMT; ++T) {
+        const bf16x8 ah = __builtin_bit_cast(bf16x8, Ahi[(T * 5 + s) * 64 + lane]);
+        acc[T] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, b, acc[T], 0, 0, 0);
+        if constexpr (P == kPBF16X3) {
+          const bf16x8 al = __builtin_bit_cast(bf16x8, Alo[(T * 5 + s) * 64 + lane]);
+          acc[T] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, b, acc[T], 0, 0, 0);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  f32x16 acc1[kMT], acc2[kMT];
+  net_hidden<P>(S.w + NetSize<P>::kL0, S.c1, acc, acc1);
+  net_hidden<P>(S.w + NetSize<P>::kL0 + NetSize<P>::kL1, S.c2, acc1, acc2);
+  float part = 0.0f;
+#pragma unroll
+  for (int T = 0; T < kMT; ++T)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const f32x4 w = *(const f32x4 *)(S.w3 + 32 * T + 8 * j + 4 * g);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) part = fmaf(w[i], relu(acc2[T][4 * j + i]), part);
+    }
+  const float other = __shfl_xor(part, 32);
+  const float q0 = g == 0 ? part : other, q1 = g == 0 ? other : part;
+  return S.b3 + (q0 + q1);
+}
+
+template <int P>
+__device__ inline NetSmem net_smem(const uint8_t *s_w, float b3) {
+  NetSmem S;
+  S.w = s_w;
+  S.c1 = (const float *)(s_w + NetSize<P>::kL0 + 2 * NetSize<P>::kL1);
+  S.c2 = S.c1 + kHid;
+  S.w3 = S.c2 + kHid;
+  S.b3 = b3;
+  return S;
+}
+
+constexpr int kNetThreads = 512;
+
+// ------------------------------------------------------------------ per-lane evaluators
+
+// qSRO local energy (Eq. 2) over FCC shells 1-3 with the host-folded coefficients (as on
+// BCC: Vf[m][c][q] = V_m^{max,min} / z_m, Wf[m][c] = W_m^c / z_m^2, K = C + lambda sum W^2).
+template <typename T, typename GetSpecies>
+__device__ inline T qsro_site(GetSpecies sp, const T *F) {
+  const T *Vf = F, *Wf = F + 75;
+  const int c = sp(-1);
+  T cnt[3][5];
+#pragma unroll
+  for (int m = 0; m < 3; ++m)
+#pragma unroll
+    for (int q = 0; q < 5; ++q) cnt[m][q] = T(0);
+#pragma unroll
+  for (int k = 0; k < kNbr; ++k) {
+    const int m = shell_of(k) - 1, q = sp(k);
+#pragma unroll
+    for (int p = 0; p < 5; ++p) cnt[m][p] += (q == p) ? T(1) : T(0);
+  }
+  T e = F[90];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    T acc = T(0);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) acc = fma(Vf[(m * 5 + c) * 5 + q], cnt[m][q], acc);
+    T self = T(0);
+#pragma unroll
+    for (int p = 0; p < 5; ++p) self += (p == c) ? cnt[m][p] : T(0);
+    e += acc + Wf[m * 5 + c] * self * self;
+  }
+  return e;
+}
+
+// ------------------------------------------------------------------ sweep phases
+
+struct Trial {
+  int32_t site;     // replica-local trial site, -1: the link cell has no site of this colour
+  int32_t partner;
+  double theta;
+  int32_t dir;
+  int32_t same;
+};
+
+struct QEntry {     // FP64 re-decision queue entry: index into the active list
+  int32_t slot;
+  float dE_fast;
+};
+
+struct Args {
+  const Replica *reps;
+  int32_t r, colour;
+  const uint64_t *sweep;
+  uint64_t seed;
+  uint8_t *occ;            // all replicas
+  float *ecache;
+  Trial *trials;           // [n_trials of the colour]
+  int32_t *active;         // [n_trials]: trial indices of different-species trials
+  uint32_t *n_active;      // device count of active trials (reset before each colour)
+  float *e1;               // [n_trials][om_n] post-swap energies of the sweep precision
+  const int8_t *om;        // [12][kOmMax][3] zone offsets
+  int32_t om_n;            // 28 (MLPNet) or 60 (qSRO)
+  double guard;
+  uint32_t *q_count;       // device count of queued trials (reset before each colour)
+  QEntry *queue;           // [n_trials]
+  unsigned long long *e_fixed;
+  uint64_t *counters;      // [4][n_replicas]
+  int32_t n_replicas;
+  double *trace_dE, *trace_dE_fast;
+  uint8_t *trace_flags;
+};
+
+// Wave-aggregated append: one atomic per wave, slots in lane order within the wave.
+__device__ __forceinline__ uint32_t wave_append(uint32_t *count, bool want) {
+  const unsigned long long m = __ballot(want);
+  const int lane = threadIdx.x & 63;
+  const int leader = m ? __ffsll((long long)m) - 1 : 0;
+  uint32_t base = 0;
+  if (m && lane == leader) base = atomicAdd(count, (uint32_t)__popcll(m));
+  base = __shfl(base, leader);
+  return base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+}
+
+__global__ __launch_bounds__(256) void k_propose(Args a) {
+  const Replica R = a.reps[a.r];
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = t < R.n_trials;
+  Trial tr{-1, 0, 0.0, 0, 1};
+  const int64_t i = live ? fcc::trial_site(R, a.colour, t) : -1;
+  if (i >= 0) {
+    const U64x4 x = philox4x64_10((uint64_t)i, *a.sweep, (uint64_t)a.r, 0, a.seed, 0);
+    const int d = dir_of(x.v[0]);
+    const double u = (double)((x.v[1] >> 11) + 1) * 0x1.0p-53;
+    const Pos pi = pos(i, R.L[0], R.L[1]);
+    const int64_t n = at(pi, dx(d), dy(d), dz(d), R.L[0], R.L[1], R.L[2]);
+    const uint8_t *occ = a.occ + R.site0;
+    tr.site = (int32_t)i;
+    tr.partner = (int32_t)n;
+    tr.theta = isinf(R.temperature) ? (double)INFINITY : -kBoltzmannEvPerK * R.temperature * log(u);
+    tr.dir = d;
+    tr.same = occ[i] == occ[n];
+    if (tr.same) {
+      if (a.trace_flags) a.trace_flags[R.site0 + i] = kFlagSame;
+      if (a.trace_dE) a.trace_dE[R.site0 + i] = 0.0;
+      if (a.trace_dE_fast) a.trace_dE_fast[R.site0 + i] = 0.0;
+    }
+  }
+  if (live) a.trials[t] = tr;
+  const bool active = i >= 0 && !tr.same;
+  const uint32_t slot = wave_append(a.n_active, active);
+  if (active) a.active[slot] = (int32_t)t;
+  const unsigned long long vm = __ballot(i >= 0), am = __ballot(active);
+  if ((threadIdx.x & 63) == 0) {
+    const int Rn = a.n_replicas;
+    if (vm) atomicAdd((unsigned long long *)&a.counters[0 * Rn + a.r], (unsigned long long)__popcll(vm));
+    if (am) atomicAdd((unsigned long long *)&a.counters[1 * Rn + a.r], (unsigned long long)__popcll(am));
+  }
+}
+
+// Species of site s of a replica as seen with sites i and n exchanged.
+__device__ __forceinline__ uint32_t swapped(const uint8_t *occ, int64_t s, int64_t i, int64_t n, uint32_t si,
+                                            uint32_t sn) {
+  return s == i ? sn : (s == n ? si : (uint32_t)occ[s]);
+}
+
+// Post-swap MLPNet energies of the zone sites of every active trial: row = active slot x
+// zone position, 32 rows per wave tile.
+template <int P>
+__global__ __launch_bounds__(kNetThreads) void k_rows_net(Args a, const uint8_t *wpack, float b3) {
+  constexpr int kW = net_bytes<P>();
+  __shared__ __attribute__((aligned(16))) uint8_t s_w[kW];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int q = tid; q < kW / 16; q += kNetThreads) ((int4 *)s_w)[q] = ((const int4 *)wpack)[q];
+  __syncthreads();
+  const NetSmem S = net_smem<P>(s_w, b3);
+  const Replica R = a.reps[a.r];
+  const uint8_t *occ = a.occ + R.site0;
+  const int64_t rows = (int64_t)(*a.n_active) * kOmMlp;
+  const int64_t tiles = (rows + 31) / 32;
+  constexpr int kWaves = kNetThreads / 64;
+  for (int64_t tile = (int64_t)blockIdx.x * kWaves + wave; tile < tiles; tile += (int64_t)gridDim.x * kWaves) {
+    const int64_t row = tile * 32 + (lane & 31);
+    const bool valid = row < rows;
+    const int64_t slot = valid ? row / kOmMlp : 0;
+    const int k = valid ? (int)(row - slot * kOmMlp) : 0;
+    const Trial tr = a.trials[a.active[slot]];
+    const int64_t i = tr.site, n = tr.partner;
+    const uint32_t si = occ[i], sn = occ[n];
+    const int8_t *o = a.om + (tr.dir * kOmMax + k) * 3;
+    const Pos pj = pos(at(pos(i, R.L[0], R.L[1]), o[0], o[1], o[2], R.L[0], R.L[1], R.L[2]), R.L[0], R.L[1]);
+    const float E = eval_net<P>(S, [&](int m) -> uint32_t {
+      const int64_t s = m == 0 ? index(pj, R.L[0], R.L[1])
+                               : at(pj, dx(m - 1), dy(m - 1), dz(m - 1), R.L[0], R.L[1], R.L[2]);
+      return swapped(occ, s, i, n, si, sn);
+    });
+    if (valid && lane < 32) a.e1[row] = E;
+  }
+}
+
+// Post-swap qSRO energies (FP32, one row per lane).
+__global__ __launch_bounds__(256) void k_rows_qsro(Args a, const float *F) {
+  const Replica R = a.reps[a.r];
+  const uint8_t *occ = a.occ + R.site0;
+  const int64_t rows = (int64_t)(*a.n_active) * kOmQsro;
+  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < rows;
+       row += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t slot = row / kOmQsro;
+    const int k = (int)(row - slot * kOmQsro);
+    const Trial tr = a.trials[a.active[slot]];
+    const int64_t i = tr.site, n = tr.partner;
+    const uint32_t si = occ[i], sn = occ[n];
+    const int8_t *o = a.om + (tr.dir * kOmMax + k) * 3;
+    const Pos pj = pos(at(pos(i, R.L[0], R.L[1]), o[0], o[1], o[2], R.L[0], R.L[1], R.L[2]), R.L[0], R.L[1]);
+    a.e1[row] = qsro_site<float>(
+        [&](int k2) -> int {
+          const int64_t s = k2 < 0 ? index(pj, R.L[0], R.L[1]) : at(pj, dx(k2), dy(k2), dz(k2), R.L[0], R.L[1], R.L[2]);
+          return (int)swapped(occ, s, i, n, si, sn);
+        },
+        F);
+  }
+}
+
+// Zone sums against the cache (fixed order), then the Metropolis decision or the FP64 queue.
+__global__ __launch_bounds__(256) void k_decide(Args a) {
+  const Replica R = a.reps[a.r];
+  const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = slot < (int64_t)(*a.n_active);
+  bool accept = false;
+  double dEd = 0.0;
+  if (live) {
+    const Trial tr = a.trials[a.active[slot]];
+    uint8_t *occ = a.occ + R.site0;
+    float *ec = a.ecache + R.site0;
+    const Pos pi = pos(tr.site, R.L[0], R.L[1]);
+    const float *e1 = a.e1 + slot * a.om_n;
+    const int8_t *o = a.om + tr.dir * kOmMax * 3;
+    float dE = 0.0f;
+    for (int k = 0; k < a.om_n; ++k)
+      dE += e1[k] - ec[at(pi, o[3 * k], o[3 * k + 1], o[3 * k + 2], R.L[0], R.L[1], R.L[2])];
+    dEd = (double)dE;
+    if (a.trace_dE_fast) a.trace_dE_fast[R.site0 + tr.site] = dEd;
+    if (fabs(dEd - tr.theta) < a.guard) {
+      const uint32_t q = atomicAdd(a.q_count, 1u);
+      a.queue[q] = QEntry{(int32_t)slot, dE};
+    } else {
+      accept = dEd <= tr.theta;
+      if (accept) {
+        const uint8_t si = occ[tr.site];
+        occ[tr.site] = occ[tr.partner];
+        occ[tr.partner] = si;
+        for (int k = 0; k < a.om_n; ++k)
+          ec[at(pi, o[3 * k], o[3 * k + 1], o[3 * k + 2], R.L[0], R.L[1], R.L[2])] = e1[k];
+        atomicAdd(&a.e_fixed[a.r], (unsigned long long)to_fixed(dEd));
+      }
+      if (a.trace_flags) a.trace_flags[R.site0 + tr.site] = accept ? kFlagAccept : 0;
+      if (a.trace_dE) a.trace_dE[R.site0 + tr.site] = dEd;
+    }
+  }
+  const unsigned long long cm = __ballot(accept);
+  if ((threadIdx.x & 63) == 0 && cm)
+    atomicAdd((unsigned long long *)&a.counters[2 * a.n_replicas + a.r], (unsigned long long)__popcll(cm));
+}
+
+// ------------------------------------------------------------------ FP64 evaluation
+
+// FP64 MLPNet blob with every weight matrix stored [input][unit] (consecutive threads own
+// consecutive units, so their loads are contiguous): W0t[76][96], b0, W1t[96][96], b1,
+// W2t[96][96], b2, W3[96], b3.
+constexpr int kRows64 = 64;       // rows per pass of the FP64 row kernel
+constexpr int kR64Threads = 384;  // 96 units x 4 parts, 16 rows per thread
+constexpr int kR64Parts = kR64Threads / kHid;
+constexpr int kR64PerThread = kRows64 / kR64Parts;
+constexpr int kHS = kHid + 1;     // padded activation row stride
+
+// FP64 energies of nrows (<= 64) rows whose slot species are in s_sp[row][19]; the result of
+// row r goes to s_out[r].  Every thread of the block takes part (block-wide barriers).
+__device__ void net64_rows(const double *W, const uint8_t *s_sp, int nrows, double *s_h, double *s_out) {
+  const int tid = threadIdx.x;
+  const int o = tid % kHid, part = tid / kHid;
+  const double *W0 = W, *b0 = W0 + kIn * kHid, *W1 = b0 + kHid, *b1 = W1 + kHid * kHid, *W2 = b1 + kHid,
+               *b2 = W2 + kHid * kHid, *W3 = b2 + kHid, *b3 = W3 + kHid;
+  double acc[kR64PerThread];
+#pragma unroll
+  for (int j = 0; j < kR64PerThread; ++j) acc[j] = b0[o];
+  for (int m = 0; m < kSlots; ++m) {
+    const double w0 = W0[(4 * m) * kHid + o], w1 = W0[(4 * m + 1) * kHid + o], w2 = W0[(4 * m + 2) * kHid + o],
+                 w3 = W0[(4 * m + 3) * kHid + o];
+#pragma unroll
+    for (int j = 0; j < kR64PerThread; ++j) {
+      const int r = part + kR64Parts * j;
+      const int sp = r < nrows ? s_sp[r * kSlots + m] : 4;
+      const double wv = sp == 0 ? w0 : (sp == 1 ? w1 : (sp == 2 ? w2 : w3));
+      if (sp < 4) acc[j] += wv;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < kR64PerThread; ++j) s_h[(part + kR64Parts * j) * kHS + o] = acc[j] > 0.0 ? acc[j] : 0.0;
+  __syncthreads();
+  for (int layer = 0; layer < 2; ++layer) {
+    const double *Wl = layer == 0 ? W1 : W2, *bl = layer == 0 ? b1 : b2;
+#pragma unroll
+    for (int j = 0; j < kR64PerThread; ++j) acc[j] = bl[o];
+    for (int k = 0; k < kHid; ++k) {
+      const double wk = Wl[k * kHid + o];
+#pragma unroll
+      for (int j = 0; j < kR64PerThread; ++j) acc[j] = fma(wk, s_h[(part + kR64Parts * j) * kHS + k], acc[j]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kR64PerThread; ++j) s_h[(part + kR64Parts * j) * kHS + o] = acc[j] > 0.0 ? acc[j] : 0.0;
+    __syncthreads();
+  }
+  // E_r = b3 + sum_o W3[o] h3[r][o], units in order
+  if (tid < nrows) {
+    double e = b3[0];
+    for (int k = 0; k < kHid; ++k) e = fma(W3[k], s_h[tid * kHS + k], e);
+    s_out[tid] = e;
+  }
+  __syncthreads();
+}
+
+// FP64 local energies of every site of one replica (MLPNet).
+__global__ __launch_bounds__(kR64Threads) void k_site_energies_net64(const Replica *reps, int32_t r,
+                                                                     const uint8_t *occ_all, const double *W,
+                                                                     double *out) {
+  __shared__ double s_h[kRows64 * kHS];
+  __shared__ double s_out[kRows64];
+  __shared__ uint8_t s_sp[kRows64 * kSlots];
+  const Replica R = reps[r];
+  const uint8_t *occ = occ_all + R.site0;
+  const int64_t passes = (R.n_sites + kRows64 - 1) / kRows64;
+  for (int64_t pass = blockIdx.x; pass < passes; pass += gridDim.x) {
+    const int64_t j0 = pass * kRows64;
+    const int nrows = R.n_sites - j0 < kRows64 ? (int)(R.n_sites - j0) : kRows64;
+    for (int v = threadIdx.x; v < nrows * kSlots; v += kR64Threads) {
+      const int lr = v / kSlots, m = v - lr * kSlots;
+      const Pos p = pos(j0 + lr, R.L[0], R.L[1]);
+      s_sp[v] = occ[m == 0 ? j0 + lr : at(p, dx(m - 1), dy(m - 1), dz(m - 1), R.L[0], R.L[1], R.L[2])];
+    }
+    __syncthreads();
+    net64_rows(W, s_sp, nrows, s_h, s_out);
+    if ((int)threadIdx.x < nrows) out[R.site0 + j0 + threadIdx.x] = s_out[threadIdx.x];
+    __syncthreads();
+  }
+}
+
+// Local energies of every site of one replica with the matrix-core MLPNet evaluator.
+template <int P>
+__global__ __launch_bounds__(kNetThreads) void k_site_energies_net(const Replica *reps, int32_t r,
+                                                                   const uint8_t *occ_all, const uint8_t *wpack,
+                                                                   float b3, float *out) {
+  constexpr int kW = net_bytes<P>();
+  __shared__ __attribute__((aligned(16))) uint8_t s_w[kW];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int q = tid; q < kW / 16; q += kNetThreads) ((int4 *)s_w)[q] = ((const int4 *)wpack)[q];
+  __syncthreads();
+  const NetSmem S = net_smem<P>(s_w, b3);
+  const Replica R = reps[r];
+  const uint8_t *occ = occ_all + R.site0;
+  const int64_t tiles = (R.n_sites + 31) / 32;
+  constexpr int kWaves = kNetThreads / 64;
+  for (int64_t tile = (int64_t)blockIdx.x * kWaves + wave; tile < tiles; tile += (int64_t)gridDim.x * kWaves) {
+    const int64_t j = tile * 32 + (lane & 31);
+    const bool valid = j < R.n_sites;
+    const Pos p = pos(valid ? j : 0, R.L[0], R.L[1]);
+    const float E = eval_net<P>(S, [&](int m) -> uint32_t {
+      if (m == 0) return occ[valid ? j : 0];
+      return occ[at(p, dx(m - 1), dy(m - 1), dz(m - 1), R.L[0], R.L[1], R.L[2])];
+    });
+    if (valid && lane < 32) out[R.site0 + j] = E;
+  }
+}
+
+// Per-lane qSRO local energies of every site (FP32 or FP64).
+template <typename T>
+__global__ void k_site_energies_qsro(const Replica *reps, int32_t r, const uint8_t *occ_all, const T *F, T *out) {
+  const Replica R = reps[r];
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= R.n_sites) return;
+  const uint8_t *occ = occ_all + R.site0;
+  const Pos p = pos(j, R.L[0], R.L[1]);
+  out[R.site0 + j] = qsro_site<T>(
+      [&](int k) -> int { return k < 0 ? occ[j] : occ[at(p, dx(k), dy(k), dz(k), R.L[0], R.L[1], R.L[2])]; }, F);
+}
+
+// FP64 re-decision of queued trials: the zone's local energies before and after the swap
+// (MLPNet: 2 x 28 rows in one pass of the row kernel; qSRO: one row per thread), dE as the
+// difference of the two zone sums in zone order, decision and apply.  The cache keeps the
+// sweep precision's post-swap energies.
+template <int MODEL>  // 0 MLPNet, 1 qSRO
+__global__ __launch_bounds__(kR64Threads) void k_recheck(Args a, const double *W) {
+  __shared__ double s_h[kRows64 * kHS];
+  __shared__ double s_out[2 * kOmMax];
+  __shared__ uint8_t s_sp[kRows64 * kSlots];
+  __shared__ int s_accept;
+  const Replica R = a.reps[a.r];
+  uint8_t *occ = a.occ + R.site0;
+  const uint32_t nq = *a.q_count;
+  const int tid = threadIdx.x;
+  for (uint32_t q = blockIdx.x; q < nq; q += gridDim.x) {
+    const QEntry qe = a.queue[q];
+    const Trial tr = a.trials[a.active[qe.slot]];
+    const int64_t i = tr.site, n = tr.partner;
+    const uint32_t si = occ[i], sn = occ[n];
+    const Pos pi = pos(i, R.L[0], R.L[1]);
+    const int8_t *o = a.om + tr.dir * kOmMax * 3;
+    const int om_n = a.om_n;
+    if constexpr (MODEL == 0) {
+      // rows 0..27 after the swap, 28..55 before
+      for (int v = tid; v < 2 * kOmMlp * kSlots; v += kR64Threads) {
+        const int row = v / kSlots, m = v - row * kSlots;
+        const bool post = row < kOmMlp;
+        const int k = post ? row : row - kOmMlp;
+        const Pos pj = pos(at(pi, o[3 * k], o[3 * k + 1], o[3 * k + 2], R.L[0], R.L[1], R.L[2]), R.L[0], R.L[1]);
+        const int64_t s = m == 0 ? index(pj, R.L[0], R.L[1])
+                                 : at(pj, dx(m - 1), dy(m - 1), dz(m - 1), R.L[0], R.L[1], R.L[2]);
+        s_sp[v] = (uint8_t)(post ? swapped(occ, s, i, n, si, sn) : (uint32_t)occ[s]);
+      }
+      __syncthreads();
+      net64_rows(W, s_sp, 2 * kOmMlp, s_h, s_out);
+    } else {
+      if (tid < 2 * kOmQsro) {
+        const bool post = tid < kOmQsro;
+        const int k = post ? tid : tid - kOmQsro;
+        const Pos pj = pos(at(pi, o[3 * k], o[3 * k + 1], o[3 * k + 2], R.L[0], R.L[1], R.L[2]), R.L[0], R.L[1]);
+        s_out[tid] = qsro_site<double>(
+            [&](int k2) -> int {
+              const int64_t s =
+                  k2 < 0 ? index(pj, R.L[0], R.L[1]) : at(pj, dx(k2), dy(k2), dz(k2), R.L[0], R.L[1], R.L[2]);
+              return (int)(post ? swapped(occ, s, i, n, si, sn) : (uint32_t)occ[s]);
+            },
+            W);
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      double e1 = 0.0, e0 = 0.0;
+      for (int k = 0; k < om_n; ++k) e1 += s_out[k];
+      for (int k = 0; k < om_n; ++k) e0 += s_out[om_n + k];
+      const double dE = e1 - e0;
+      const bool accept = dE <= tr.theta;
+      const int Rn = a.n_replicas;
+      if (accept) {
+        occ[i] = (uint8_t)sn;
+        occ[n] = (uint8_t)si;
+        atomicAdd(&a.e_fixed[a.r], (unsigned long long)to_fixed(dE));
+        atomicAdd((unsigned long long *)&a.counters[2 * Rn + a.r], 1ull);
+      }
+      atomicAdd((unsigned long long *)&a.counters[3 * Rn + a.r], 1ull);
+      if (a.trace_flags) a.trace_flags[R.site0 + i] = kFlagFp64 | (accept ? kFlagAccept : 0);
+      if (a.trace_dE) a.trace_dE[R.site0 + i] = dE;
+      s_accept = accept;
+    }
+    __syncthreads();
+    if (tid < om_n && s_accept)
+      a.ecache[R.site0 + at(pi, o[3 * tid], o[3 * tid + 1], o[3 * tid + 2], R.L[0], R.L[1], R.L[2])] =
+          a.e1[(int64_t)qe.slot * om_n + tid];
+    __syncthreads();
+  }
+}
+
+// Pair counts per shell (1-3) and ordered species pair, and species counts, of one replica.
+__global__ void k_pair_counts(const Replica *reps, int32_t r, const uint8_t *occ_all, int32_t S,
+                              unsigned long long *cnt, unsigned long long *nsp) {
+  __shared__ unsigned int s_cnt[3 * 5 * 5 + 5];
+  for (int q = threadIdx.x; q < 3 * 25 + 5; q += blockDim.x) s_cnt[q] = 0u;
+  __syncthreads();
+  const Replica R = reps[r];
+  const uint8_t *occ = occ_all + R.site0;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < R.n_sites; j += (int64_t)gridDim.x * blockDim.x) {
+    const int p = occ[j];
+    if (p >= S) continue;  // occupancies are validated on entry; never index past the histogram
+    atomicAdd(&s_cnt[75 + p], 1u);
+    const Pos ps = pos(j, R.L[0], R.L[1]);
+    for (int k = 0; k < kNbr; ++k) {
+      const int q = occ[at(ps, dx(k), dy(k), dz(k), R.L[0], R.L[1], R.L[2])];
+      if (q < S) atomicAdd(&s_cnt[((shell_of(k) - 1) * 5 + p) * 5 + q], 1u);
+    }
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < 3 * 25 + 5; q += blockDim.x) {
+    if (!s_cnt[q]) continue;
+    if (q < 75) {
+      const int m = q / 25, p = (q / 5) % 5, qq = q % 5;
+      if (p < S && qq < S) atomicAdd(&cnt[(m * S + p) * S + qq], (unsigned long long)s_cnt[q]);
+    } else if (q - 75 < S) {
+      atomicAdd(&nsp[q - 75], (unsigned long long)s_cnt[q]);
+    }
+  }
+}
+
+}  // namespace fcc
+}  // namespace smc

@@ -1,0 +1,423 @@
+// Host side of the FCC lattice path: MLPNet weight images, zone tables, context set-up, local
+// energies and the enqueue of one sweep.  Included once, by the translation unit of the C ABI
+// (the generic kernels it launches are defined there).
+#pragma once
+#include <math.h>
+
+#include <algorithm>
+#include <array>
+#include <vector>
+
+#include "context.hpp"
+#include "fcc.hpp"
+#include "pack.hpp"
+#include "sweep_mfma.hpp"
+
+namespace smc {
+namespace fcc {
+
+constexpr int kNetParams = kHid * kIn + kHid + 2 * (kHid * kHid + kHid) + kHid + 1;  // 26,113
+
+// Hidden unit held in output register v by lane group g of M-tile T.
+inline int unit_of(int T, int v, int g) { return 32 * T + 8 * (v / 4) + 4 * g + (v % 4); }
+
+// Image of the MLPNet weights in the operand order of eval_net<P> (P: 0 FP32, 1 BF16, 2 split
+// BF16).  Layer 0 takes 80 features: the 76 inputs, the bias on feature 76, zeros.
+inline std::vector<uint8_t> pack_net(int P, const float *p) {
+  constexpr int L0[3] = {NetSize<kP32>::kL0, NetSize<kPBF16>::kL0, NetSize<kPBF16X3>::kL0};
+  constexpr int L1[3] = {NetSize<kP32>::kL1, NetSize<kPBF16>::kL1, NetSize<kPBF16X3>::kL1};
+  const float *W0 = p, *b0 = W0 + kHid * kIn, *W1 = b0 + kHid, *b1 = W1 + kHid * kHid, *W2 = b1 + kHid,
+              *b2 = W2 + kHid * kHid, *W3 = b2 + kHid;
+  std::vector<uint8_t> out((size_t)L0[P] + 2 * L1[P] + 3 * kHid * 4 + 16, 0);
+  uint8_t *B = out.data();
+  for (int layer = 0; layer < 3; ++layer) {
+    uint8_t *dst = layer == 0 ? B : B + L0[P] + (layer - 1) * L1[P];
+    const float *W = layer == 1 ? W1 : W2;
+    auto w = [&](int o, int k) -> float {
+      if (layer > 0) return W[o * kHid + k];
+      return k < kIn ? W0[o * kIn + k] : (k == kIn ? b0[o] : 0.0f);
+    };
+    if (P == 0) {
+      // K-step s covers two inputs: layer 0 feature 2s + g, later layers unit_of(s/16, s%16, g)
+      float *F = (float *)dst;
+      const int nread = layer == 0 ? 10 : 12;
+      for (int T = 0; T < kMT; ++T)
+        for (int s4 = 0; s4 < nread; ++s4)
+          for (int l = 0; l < 64; ++l)
+            for (int i = 0; i < 4; ++i) {
+              const int s = 4 * s4 + i, g = l >> 5;
+              const int k = layer == 0 ? 2 * s + g : unit_of(s / 16, s % 16, g);
+              F[((T * nread + s4) * 64 + l) * 4 + i] = w(32 * T + (l & 31), k);
+            }
+    } else {
+      // K-step s covers 16 inputs, lane group g holds eight: layer 0 features 16s + 8g + e,
+      // later layers unit_of(s/2, 8(s%2) + e, g)
+      const int nstep = layer == 0 ? 5 : 6;
+      const int n = kMT * nstep * 64 * 8;
+      uint16_t *hi = (uint16_t *)dst, *lo = hi + n;
+      for (int T = 0; T < kMT; ++T)
+        for (int s = 0; s < nstep; ++s)
+          for (int l = 0; l < 64; ++l)
+            for (int e = 0; e < 8; ++e) {
+              const int g = l >> 5;
+              const int k = layer == 0 ? 16 * s + 8 * g + e : unit_of(s / 2, 8 * (s % 2) + e, g);
+              const float x = w(32 * T + (l & 31), k);
+              const int idx = ((T * nstep + s) * 64 + l) * 8 + e;
+              const uint16_t h = f32_to_bf16_rne(x);
+              hi[idx] = h;
+              if (P == 2) lo[idx] = f32_to_bf16_rne(x - bf16_to_f32(h));
+            }
+    }
+  }
+  float *vec = (float *)(B + L0[P] + 2 * L1[P]);
+  for (int h = 0; h < kHid; ++h) {
+    vec[h] = b1[h];
+    vec[kHid + h] = b2[h];
+    vec[2 * kHid + h] = W3[h];
+  }
+  return out;
+}
+
+// FP64 MLPNet blob with every weight matrix stored [input][unit].
+inline std::vector<double> net_fp64(const float *p) {
+  std::vector<double> t(kNetParams);
+  const float *W0 = p, *b0 = W0 + kHid * kIn, *W1 = b0 + kHid, *b1 = W1 + kHid * kHid, *W2 = b1 + kHid,
+              *b2 = W2 + kHid * kHid, *W3 = b2 + kHid, *b3 = W3 + kHid;
+  double *T0 = t.data(), *c0 = T0 + kIn * kHid, *T1 = c0 + kHid, *c1 = T1 + kHid * kHid, *T2 = c1 + kHid,
+         *c2 = T2 + kHid * kHid, *T3 = c2 + kHid, *c3 = T3 + kHid;
+  for (int o = 0; o < kHid; ++o) {
+    for (int f = 0; f < kIn; ++f) T0[f * kHid + o] = W0[o * kIn + f];
+    for (int k = 0; k < kHid; ++k) {
+      T1[k * kHid + o] = W1[o * kHid + k];
+      T2[k * kHid + o] = W2[o * kHid + k];
+    }
+    c0[o] = b0[o];
+    c1[o] = b1[o];
+    c2[o] = b2[o];
+    T3[o] = W3[o];
+  }
+  c3[0] = b3[0];
+  return t;
+}
+
+// Zone of a swap with partner slot d, for every d: the origin, the partner and the
+// neighbours (first n_nbr slots) of either; sorted, duplicates removed.  Returns |Omega|.
+inline int zone_table(int n_nbr, std::vector<int8_t> &out) {
+  out.assign((size_t)kDirs * kOmMax * 3, 0);
+  int count = 0;
+  for (int d = 0; d < kDirs; ++d) {
+    using V = std::array<int, 3>;
+    const V pd = {dx(d), dy(d), dz(d)};
+    std::vector<V> v = {{0, 0, 0}, pd};
+    for (int k = 0; k < n_nbr; ++k) {
+      v.push_back({dx(k), dy(k), dz(k)});
+      v.push_back({pd[0] + dx(k), pd[1] + dy(k), pd[2] + dz(k)});
+    }
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+    if ((int)v.size() > kOmMax) return -1;
+    count = (int)v.size();
+    for (int k = 0; k < count; ++k)
+      for (int a = 0; a < 3; ++a) out[((size_t)d * kOmMax + k) * 3 + a] = (int8_t)v[k][a];
+  }
+  return count;
+}
+
+inline int ensure_pack(smc_ctx *c, int P) {
+  FccState &f = c->fcc;
+  if (f.pack_ready[P]) return SMC_OK;
+  const std::vector<uint8_t> img = pack_net(P, c->host_params.data());
+  if (!f.d_pack[P]) HIPC(c, hipMalloc(&f.d_pack[P], img.size()));
+  HIPC(c, hipMemcpyAsync(f.d_pack[P], img.data(), img.size(), hipMemcpyHostToDevice, c->stream));
+  HIPC(c, hipStreamSynchronize(c->stream));  // img is freed on return
+  f.pack_ready[P] = true;
+  return SMC_OK;
+}
+
+inline int load_params(smc_ctx *c, const float *params_dev) {
+  FccState &f = c->fcc;
+  const int64_t P = c->n_params;
+  c->host_params.resize(P);
+  HIPC(c, hipMemcpyAsync(c->host_params.data(), params_dev, sizeof(float) * P, hipMemcpyDeviceToHost, c->stream));
+  HIPC(c, hipStreamSynchronize(c->stream));
+  for (bool &r : f.pack_ready) r = false;
+  const float *p = c->host_params.data();
+  if (f.model == 0) {
+    f.b3 = p[kNetParams - 1];
+    const std::vector<double> t = net_fp64(p);
+    HIPC(c, hipMemcpyAsync(c->d_w64, t.data(), sizeof(double) * t.size(), hipMemcpyHostToDevice, c->stream));
+  } else {
+    // folded qSRO coefficients with the FCC shell sizes
+    const double z[3] = {12.0, 6.0, 24.0};
+    std::vector<double> F(kQsroPacked, 0.0);
+    std::vector<float> F32(kQsroPacked);
+    for (int m = 0; m < 3; ++m)
+      for (int cc = 0; cc < 5; ++cc) {
+        for (int q = 0; q < 5; ++q)
+          if (q != cc) F[(m * 5 + cc) * 5 + q] = (double)p[(m * 5 + std::max(cc, q)) * 5 + std::min(cc, q)] / z[m];
+        F[75 + m * 5 + cc] = (double)p[75 + m * 5 + cc] / (z[m] * z[m]);
+      }
+    double K = (double)p[91];
+    for (int q = 0; q < 15; ++q) K += (double)p[90] * (double)p[75 + q] * (double)p[75 + q];
+    F[90] = K;
+    for (int q = 0; q < kQsroPacked; ++q) F32[q] = (float)F[q];
+    HIPC(c, hipMemcpyAsync(c->d_w64, F.data(), sizeof(double) * kQsroPacked, hipMemcpyHostToDevice, c->stream));
+    HIPC(c, hipMemcpyAsync(c->d_w32, F32.data(), sizeof(float) * kQsroPacked, hipMemcpyHostToDevice, c->stream));
+  }
+  HIPC(c, hipStreamSynchronize(c->stream));
+  return SMC_OK;
+}
+
+// Blocks of the matrix-core kernels: LDS holds one weight image per block.
+inline int net_blocks(const smc_ctx *c, int P) { return (P == SMC_BF16 ? 2 : 1) * c->n_cu; }
+
+template <int P>
+void launch_site_energies_net(smc_ctx *c, float *out) {
+  for (size_t r = 0; r < c->reps.size(); ++r) {
+    const int64_t tiles = (c->reps[r].n_sites + 31) / 32;
+    const unsigned grid = (unsigned)std::min<int64_t>((tiles + 7) / 8, net_blocks(c, P));
+    hipLaunchKernelGGL((k_site_energies_net<P>), dim3(grid), dim3(kNetThreads), 0, c->stream, c->d_reps, (int32_t)r,
+                       c->occ, c->fcc.d_pack[P], c->fcc.b3, out);
+  }
+}
+
+// Local energies with the sweep-precision evaluator (float out).
+inline int site_energies_fast(smc_ctx *c, int P, float *out) {
+  if (c->fcc.model == 1) {
+    if (P != SMC_FP32) return fail(c, SMC_E_UNSUPPORTED, "qSRO on FCC runs in FP32 or FP64");
+    for (size_t r = 0; r < c->reps.size(); ++r)
+      hipLaunchKernelGGL(k_site_energies_qsro<float>, dim3(grid_for(c->reps[r].n_sites, 256)), dim3(256), 0,
+                         c->stream, c->d_reps, (int32_t)r, c->occ, c->d_w32, out);
+    HIPC(c, hipGetLastError());
+    return SMC_OK;
+  }
+  if (P != SMC_FP32 && P != SMC_BF16 && P != SMC_BF16X3)
+    return fail(c, SMC_E_UNSUPPORTED, "the FCC MLPNet runs in FP32, BF16, split BF16 or FP64");
+  int rc = ensure_pack(c, P);
+  if (rc) return rc;
+  if (P == SMC_FP32) launch_site_energies_net<kP32>(c, out);
+  else if (P == SMC_BF16) launch_site_energies_net<kPBF16>(c, out);
+  else launch_site_energies_net<kPBF16X3>(c, out);
+  HIPC(c, hipGetLastError());
+  return SMC_OK;
+}
+
+inline int site_energies64(smc_ctx *c, double *out) {
+  for (size_t r = 0; r < c->reps.size(); ++r) {
+    const int64_t n = c->reps[r].n_sites;
+    if (c->fcc.model == 0) {
+      const unsigned grid = (unsigned)std::min<int64_t>((n + kRows64 - 1) / kRows64, 4 * (int64_t)c->n_cu);
+      hipLaunchKernelGGL(k_site_energies_net64, dim3(grid), dim3(kR64Threads), 0, c->stream, c->d_reps, (int32_t)r,
+                         c->occ, c->d_w64, out);
+    } else {
+      hipLaunchKernelGGL(k_site_energies_qsro<double>, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, c->d_reps,
+                         (int32_t)r, c->occ, c->d_w64, out);
+    }
+  }
+  HIPC(c, hipGetLastError());
+  return SMC_OK;
+}
+
+// FP64 from-scratch totals per replica into d_escratch.
+inline int scratch_totals(smc_ctx *c) {
+  if (!c->d_site64) HIPC(c, hipMalloc(&c->d_site64, sizeof(double) * c->n_total));
+  int rc = site_energies64(c, c->d_site64);
+  if (rc) return rc;
+  for (size_t r = 0; r < c->reps.size(); ++r)
+    hipLaunchKernelGGL(k_sum_into, dim3(1), dim3(256), 0, c->stream, c->d_site64 + c->reps[r].site0,
+                       c->reps[r].n_sites, c->d_escratch + r, 0);
+  HIPC(c, hipGetLastError());
+  return SMC_OK;
+}
+
+inline int refresh(smc_ctx *c) {
+  int rc = scratch_totals(c);
+  if (rc) return rc;
+  if (c->cfg.precision == SMC_FP64)
+    hipLaunchKernelGGL(k_narrow, dim3(grid_for(c->n_total, 256)), dim3(256), 0, c->stream, c->d_site64, c->ecache,
+                       c->n_total);
+  else if ((rc = site_energies_fast(c, c->cfg.precision, c->ecache)))
+    return rc;
+  const int R = (int)c->reps.size();
+  HIPC(c, hipMemcpyAsync(c->d_ebase, c->d_escratch, sizeof(double) * R, hipMemcpyDeviceToDevice, c->stream));
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(R, 256)), dim3(256), 0, c->stream, (uint64_t *)c->d_efixed, (int64_t)R,
+                     (uint64_t)0);
+  HIPC(c, hipGetLastError());
+  return SMC_OK;
+}
+
+template <int P>
+void launch_rows_net(smc_ctx *c, const Args &a, int64_t n_trials) {
+  const int64_t tiles = (n_trials * kOmMlp + 31) / 32;
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((tiles + 7) / 8, net_blocks(c, P)));
+  hipLaunchKernelGGL((k_rows_net<P>), dim3(grid), dim3(kNetThreads), 0, c->stream, a, c->fcc.d_pack[P], c->fcc.b3);
+}
+
+// Enqueue one sweep on c->stream (also under graph capture): per replica and colour the
+// counter reset, proposals, zone rows, decisions and FP64 re-decisions; then the device
+// sweep counter advances.
+inline int enqueue_sweep(smc_ctx *c, const smc_stats *st, bool trace) {
+  FccState &f = c->fcc;
+  const int R = (int)c->reps.size();
+  const bool fp64 = c->cfg.precision == SMC_FP64;
+  const int P = fp64 ? SMC_FP32 : c->cfg.precision;
+  for (int r = 0; r < R; ++r) {
+    const Replica &rep = c->reps[r];
+    const int64_t nt = std::max<int64_t>(1, rep.n_trials);
+    for (int col = 0; col < rep.n_colours; ++col) {
+      Args a{};
+      a.reps = c->d_reps;
+      a.r = r;
+      a.colour = col;
+      a.sweep = c->d_sweep;
+      a.seed = c->cfg.seed;
+      a.occ = c->occ;
+      a.ecache = c->ecache;
+      a.trials = f.d_trials;
+      a.active = f.d_active;
+      a.n_active = f.d_counts;
+      a.e1 = f.d_e1;
+      a.om = f.d_om;
+      a.om_n = f.om_n;
+      a.guard = fp64 ? (double)INFINITY : c->guard;
+      a.q_count = f.d_counts + 1;
+      a.queue = f.d_queue;
+      a.e_fixed = c->d_efixed;
+      a.counters = c->d_counters;
+      a.n_replicas = R;
+      if (trace) {
+        a.trace_dE = st->trace_dE;
+        a.trace_dE_fast = st->trace_dE_fast;
+        a.trace_flags = st->trace_flags;
+      }
+      hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, c->stream, (uint64_t *)f.d_counts, (int64_t)1, (uint64_t)0);
+      hipLaunchKernelGGL(k_propose, dim3(grid_for(nt, 256)), dim3(256), 0, c->stream, a);
+      const int ev = prof_begin(c);
+      if (f.model == 1) {
+        const unsigned g = (unsigned)std::min<int64_t>(grid_for(nt * kOmQsro, 256), 8 * (int64_t)c->n_cu);
+        hipLaunchKernelGGL(k_rows_qsro, dim3(g), dim3(256), 0, c->stream, a, (const float *)c->d_w32);
+      } else if (P == SMC_FP32) {
+        launch_rows_net<kP32>(c, a, nt);
+      } else if (P == SMC_BF16) {
+        launch_rows_net<kPBF16>(c, a, nt);
+      } else {
+        launch_rows_net<kPBF16X3>(c, a, nt);
+      }
+      prof_end(c, ev, 0);
+      hipLaunchKernelGGL(k_decide, dim3(grid_for(nt, 256)), dim3(256), 0, c->stream, a);
+      const unsigned rg = (unsigned)std::min<int64_t>(4 * (int64_t)c->n_cu, nt);
+      const int ev2 = prof_begin(c);
+      if (f.model == 0)
+        hipLaunchKernelGGL(k_recheck<0>, dim3(rg), dim3(kR64Threads), 0, c->stream, a, (const double *)c->d_w64);
+      else
+        hipLaunchKernelGGL(k_recheck<1>, dim3(rg), dim3(kR64Threads), 0, c->stream, a, (const double *)c->d_w64);
+      prof_end(c, ev2, 1);
+    }
+  }
+  hipLaunchKernelGGL(k_next_sweep, dim3(1), dim3(64), 0, c->stream, c->d_sweep);
+  HIPC(c, hipGetLastError());
+  return SMC_OK;
+}
+
+inline void release(smc_ctx *c) {
+  FccState &f = c->fcc;
+  void *bufs[] = {f.d_om, f.d_trials, f.d_active, f.d_e1, f.d_queue, f.d_counts, f.d_pack[0], f.d_pack[1], f.d_pack[2]};
+  for (void *p : bufs)
+    if (p) (void)hipFree(p);
+}
+
+// A context on the FCC lattice (MLPNet or qSRO); the caller has checked the pointers.
+inline int create(const smc_config *cfg, uint8_t *occ_dev, const float *params_dev, float *ecache_dev,
+                  void *hip_stream, double guard, smc_ctx **out) {
+  int model;
+  if (cfg->feature == SMC_FEAT_MLPNET_S12) {
+    model = 0;
+    if (cfg->hidden != kHid) return SMC_E_UNSUPPORTED;
+    if (cfg->precision == SMC_FP8_E4M3) return SMC_E_UNSUPPORTED;
+  } else if (cfg->feature == SMC_FEAT_QSRO_S123) {
+    model = 1;
+    if (cfg->precision != SMC_FP32 && cfg->precision != SMC_FP64) return SMC_E_UNSUPPORTED;
+  } else {
+    return SMC_E_UNSUPPORTED;
+  }
+  int64_t total = 0;
+  for (int r = 0; r < cfg->n_replicas; ++r) {
+    for (int a = 0; a < 3; ++a)
+      if (cfg->cells[3 * r + a] < 4 || cfg->cells[3 * r + a] > 4096) return SMC_E_INVALID;
+    if (!(cfg->temperature_K[r] >= 0.0)) return SMC_E_INVALID;
+    total += 4LL * cfg->cells[3 * r] * cfg->cells[3 * r + 1] * cfg->cells[3 * r + 2];
+  }
+  if (total >= (1LL << 31)) return SMC_E_UNSUPPORTED;
+  smc_ctx *c = new (std::nothrow) smc_ctx();
+  if (!c) return SMC_E_NOMEM;
+  c->cfg = *cfg;
+  c->cells.assign(cfg->cells, cfg->cells + 3 * cfg->n_replicas);
+  c->temps.assign(cfg->temperature_K, cfg->temperature_K + cfg->n_replicas);
+  c->cfg.cells = c->cells.data();
+  c->cfg.temperature_K = c->temps.data();
+  c->stream = (hipStream_t)hip_stream;
+  c->occ = occ_dev;
+  c->ecache = ecache_dev;
+  c->guard = guard;
+  FccState &f = c->fcc;
+  f.on = true;
+  f.model = model;
+  c->hidden = model == 0 ? kHid : 0;
+  c->n_in = model == 0 ? kIn : 0;
+  c->n_params = model == 0 ? kNetParams : 92;
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0) c->n_cu = n;
+  }
+  int64_t site0 = 0;
+  for (int r = 0; r < cfg->n_replicas; ++r) {
+    c->reps.push_back(make_replica(&c->cells[3 * r], site0, c->temps[r], 4));
+    site0 += c->reps.back().n_sites;
+    f.cap = std::max(f.cap, c->reps.back().n_trials);
+    c->colours_total += c->reps.back().n_colours;
+    c->max_colours = std::max(c->max_colours, c->reps.back().n_colours);
+  }
+  c->n_total = site0;
+  std::vector<int8_t> om;
+  f.om_n = zone_table(model == 0 ? kNbrMlp : kNbr, om);
+  const int R = cfg->n_replicas;
+  auto cleanup = [&](int code) {
+    smc_destroy(c);
+    return code;
+  };
+  if (f.om_n != (model == 0 ? kOmMlp : kOmQsro)) return cleanup(SMC_E_DEVICE);
+  const int64_t nw = model == 0 ? kNetParams : kQsroPacked;
+  bool ok = hipMalloc(&c->d_reps, sizeof(Replica) * R) == hipSuccess &&
+            hipMalloc(&c->d_w32, sizeof(float) * nw) == hipSuccess &&
+            hipMalloc(&c->d_w64, sizeof(double) * nw) == hipSuccess &&
+            hipMalloc(&c->d_ebase, sizeof(double) * R) == hipSuccess &&
+            hipMalloc(&c->d_efixed, sizeof(unsigned long long) * R) == hipSuccess &&
+            hipMalloc(&c->d_escratch, sizeof(double) * R) == hipSuccess &&
+            hipMalloc(&c->d_counters, sizeof(uint64_t) * 4 * R) == hipSuccess &&
+            hipMalloc(&c->d_sweep, sizeof(uint64_t)) == hipSuccess &&
+            hipMalloc(&f.d_om, om.size()) == hipSuccess &&
+            hipMalloc(&f.d_trials, sizeof(Trial) * f.cap) == hipSuccess &&
+            hipMalloc(&f.d_active, sizeof(int32_t) * f.cap) == hipSuccess &&
+            hipMalloc(&f.d_e1, sizeof(float) * f.cap * f.om_n) == hipSuccess &&
+            hipMalloc(&f.d_queue, sizeof(QEntry) * f.cap) == hipSuccess &&
+            hipMalloc(&f.d_counts, sizeof(uint64_t)) == hipSuccess;
+  if (!ok) return cleanup(SMC_E_NOMEM);
+  const uint64_t zero = 0;
+  if (hipMemcpyAsync(c->d_sweep, &zero, sizeof(uint64_t), hipMemcpyHostToDevice, c->stream) ||
+      hipMemcpyAsync(c->d_reps, c->reps.data(), sizeof(Replica) * R, hipMemcpyHostToDevice, c->stream) ||
+      hipMemcpyAsync(f.d_om, om.data(), om.size(), hipMemcpyHostToDevice, c->stream) ||
+      hipStreamSynchronize(c->stream))
+    return cleanup(SMC_E_DEVICE);
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(4 * R, 256)), dim3(256), 0, c->stream, c->d_counters, (int64_t)4 * R,
+                     (uint64_t)0);
+  int rc = load_params(c, params_dev);
+  if (!rc) rc = refresh(c);
+  if (!rc && hipStreamSynchronize(c->stream) != hipSuccess) rc = SMC_E_DEVICE;
+  if (rc) return cleanup(rc);
+  *out = c;
+  return SMC_OK;
+}
+
+}  // namespace fcc
+}  // namespace smc

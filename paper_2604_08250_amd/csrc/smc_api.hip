@@ -11,6 +11,7 @@
 #include "smc.h"
 #include "pack.hpp"
 #include "double_lattice.hpp"
+#include "fcc_host.hpp"
 #include "sweep_mfma.hpp"
 #include "sweep_scalar.hpp"
 #include "tables.hpp"
@@ -31,32 +32,6 @@ double default_guard(int prec) {
     case SMC_FP8_E4M3: return 1e-5;
     default: return 0.0;
   }
-}
-
-// Start event of a timed launch (index of the pair), or -1 when not profiling.
-int prof_begin(smc_ctx *c) {
-  if (!c->profiling) return -1;
-  const size_t k = c->ev_used;
-  if (2 * k + 2 > c->ev_pool.size()) {
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess) return -1;
-    if (hipEventCreate(&e1) != hipSuccess) {
-      (void)hipEventDestroy(e0);
-      return -1;
-    }
-    c->ev_pool.push_back(e0);
-    c->ev_pool.push_back(e1);
-    c->ev_kind.push_back(0);
-  }
-  if (hipEventRecord(c->ev_pool[2 * k], c->stream) != hipSuccess) return -1;
-  c->ev_used++;
-  return (int)k;
-}
-
-void prof_end(smc_ctx *c, int k, int kind) {
-  if (k < 0) return;
-  c->ev_kind[k] = kind;
-  (void)hipEventRecord(c->ev_pool[2 * k + 1], c->stream);
 }
 
 template <int FEAT, int H, typename T>
@@ -104,6 +79,7 @@ void launch_site_energies_mfma(smc_ctx *c, float *out, const uint8_t *occ = null
 
 // Local energies with the evaluator of precision P (float out).
 int site_energies_fast(smc_ctx *c, int P, float *out) {
+  if (c->fcc.on) return fcc::site_energies_fast(c, P, out);
   if (!c->mfma) {
     if (P != SMC_FP32) return fail(c, SMC_E_UNSUPPORTED, "low precisions need one-hot features and 128 hidden");
     return site_energies_scalar<float>(c, c->d_w32, out);
@@ -128,6 +104,7 @@ int ensure_site64(smc_ctx *c) {
 
 // FP64 from-scratch totals per replica into d_escratch.
 int scratch_totals(smc_ctx *c) {
+  if (c->fcc.on) return fcc::scratch_totals(c);
   int rc = ensure_site64(c);
   if (!rc) rc = site_energies_scalar<double>(c, c->d_w64, c->d_site64);
   if (rc) return rc;
@@ -139,6 +116,7 @@ int scratch_totals(smc_ctx *c) {
 }
 
 int refresh(smc_ctx *c) {
+  if (c->fcc.on) return fcc::refresh(c);
   int rc = scratch_totals(c);
   if (rc) return rc;
   if (c->cfg.precision == SMC_FP64)
@@ -155,6 +133,10 @@ int refresh(smc_ctx *c) {
 }
 
 int load_params(smc_ctx *c, const float *params_dev) {
+  if (c->fcc.on) {
+    drop_graph(c);  // the captured sweep holds the output bias by value
+    return fcc::load_params(c, params_dev);
+  }
   const int64_t P = c->n_params;
   c->host_params.resize(P);
   HIPC(c, hipMemcpyAsync(c->host_params.data(), params_dev, sizeof(float) * P, hipMemcpyDeviceToHost, c->stream));
@@ -331,7 +313,8 @@ int build_graph(smc_ctx *c) {
   const bool prof = c->profiling;
   c->profiling = false;
   hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
-  int rc = e == hipSuccess ? enqueue_sweep_mfma(c, nullptr, false) : SMC_E_DEVICE;
+  int rc = e != hipSuccess ? SMC_E_DEVICE
+                           : (c->fcc.on ? fcc::enqueue_sweep(c, nullptr, false) : enqueue_sweep_mfma(c, nullptr, false));
   hipGraph_t g = nullptr;
   const hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
   c->stream = user;
@@ -443,7 +426,17 @@ int enqueue_sweep_dl(smc_ctx *c, const smc_stats *st, bool trace) {
 int run_sweep(smc_ctx *c, const smc_stats *st, bool last) {
   const int R = (int)c->reps.size();
   const bool trace = last && st;
-  if (c->mfma) {
+  if (c->fcc.on) {
+    int rc = SMC_OK;
+    const int P = c->cfg.precision == SMC_FP64 ? SMC_FP32 : c->cfg.precision;
+    if (c->fcc.model == 0 && (rc = fcc::ensure_pack(c, P))) return rc;
+    if (c->use_graph && !trace && !c->profiling) {
+      if (!c->graph_exec && (rc = build_graph(c))) return rc;
+      HIPC(c, hipGraphLaunch(c->graph_exec, c->stream));
+    } else if ((rc = fcc::enqueue_sweep(c, st, trace))) {
+      return rc;
+    }
+  } else if (c->mfma) {
     const int P = c->cfg.precision == SMC_FP64 ? SMC_FP32 : c->cfg.precision;
     int rc = ensure_pack(c, P);
     if (rc) return rc;
@@ -523,6 +516,11 @@ int smc_init(const smc_config *cfg, uint8_t *occ_dev, const float *params_dev, f
   if (!cfg || !occ_dev || !params_dev || !ecache_dev || !cfg->cells || !cfg->temperature_K)
     return SMC_E_INVALID;
   if (cfg->n_replicas < 1 || cfg->n_species < 2 || cfg->n_species > 5) return SMC_E_INVALID;
+  if (cfg->precision < SMC_FP32 || cfg->precision > SMC_FP64) return SMC_E_INVALID;
+  if (cfg->lattice == SMC_LATTICE_FCC)
+    return fcc::create(cfg, occ_dev, params_dev, ecache_dev, hip_stream,
+                       cfg->guard_eV < 0 ? default_guard(cfg->precision) : cfg->guard_eV, out);
+  if (cfg->lattice != SMC_LATTICE_BCC) return SMC_E_INVALID;
   if (cfg->feature != SMC_FEAT_COUNTS_S12 && cfg->feature != SMC_FEAT_ONEHOT_S123 &&
       cfg->feature != SMC_FEAT_QSRO_S123)
     return SMC_E_INVALID;
@@ -720,6 +718,7 @@ int smc_energy(smc_ctx *c, double *e_scratch, double *e_running) {
 
 int smc_site_energies(smc_ctx *c, int32_t precision, void *out_dev) {
   if (!c || !out_dev) return SMC_E_INVALID;
+  if (c->fcc.on && precision == SMC_FP64) return fcc::site_energies64(c, (double *)out_dev);
   if (precision == SMC_FP64) return site_energies_scalar<double>(c, c->d_w64, (double *)out_dev);
   if (precision < SMC_FP32 || precision > SMC_FP8_E4M3) return fail(c, SMC_E_INVALID, "precision");
   return site_energies_fast(c, precision, (float *)out_dev);
@@ -877,15 +876,20 @@ int smc_warren_cowley(smc_ctx *c, int32_t replica, double *alpha) {
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(256), 0, c->stream, (uint64_t *)d, (int64_t)(3 * S * S + S), (uint64_t)0);
   const int64_t n = c->reps[replica].n_sites;
   const unsigned grid = (unsigned)std::min<int64_t>(grid_for(n, 256), 4 * (int64_t)c->n_cu);
-  hipLaunchKernelGGL(k_pair_counts, dim3(grid), dim3(256), 0, c->stream, c->d_reps, replica, c->occ, S, d,
-                     d + 3 * S * S);
+  if (c->fcc.on)
+    hipLaunchKernelGGL(fcc::k_pair_counts, dim3(grid), dim3(256), 0, c->stream, c->d_reps, replica, c->occ, S, d,
+                       d + 3 * S * S);
+  else
+    hipLaunchKernelGGL(k_pair_counts, dim3(grid), dim3(256), 0, c->stream, c->d_reps, replica, c->occ, S, d,
+                       d + 3 * S * S);
   const hipError_t e1 = hipMemcpyAsync(h.data(), d, sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost,
                                        c->stream);
   const hipError_t e2 = hipStreamSynchronize(c->stream);
   (void)hipFree(d);
   if (e1 != hipSuccess || e2 != hipSuccess) return fail(c, SMC_E_DEVICE, "pair counts");
   const unsigned long long *cnt = h.data(), *nsp = h.data() + 3 * S * S;
-  const double z[3] = {8.0, 6.0, 12.0};
+  const double zb[3] = {8.0, 6.0, 12.0}, zf[3] = {12.0, 6.0, 24.0};
+  const double *z = c->fcc.on ? zf : zb;
   for (int m = 0; m < 3; ++m)
     for (int p = 0; p < S; ++p)
       for (int q = 0; q < S; ++q) {
@@ -894,6 +898,29 @@ int smc_warren_cowley(smc_ctx *c, int32_t replica, double *alpha) {
         alpha[(m * S + p) * S + q] = (cq > 0 && nsp[p] > 0) ? 1.0 - pq / cq : 0.0;
       }
   return SMC_OK;
+}
+
+int smc_lattice_shells(int32_t lattice, int32_t *off, int32_t *shell, int32_t max_slots) {
+  if (max_slots < 0 || (max_slots > 0 && (!off || !shell))) return SMC_E_INVALID;
+  if (lattice == SMC_LATTICE_BCC) {
+    for (int k = 0; k < kNbr && k < max_slots; ++k) {
+      off[3 * k] = shell_dx(k);
+      off[3 * k + 1] = shell_dy(k);
+      off[3 * k + 2] = shell_dz(k);
+      shell[k] = shell_of(k);
+    }
+    return kNbr;
+  }
+  if (lattice == SMC_LATTICE_FCC) {
+    for (int k = 0; k < fcc::kNbr && k < max_slots; ++k) {
+      off[3 * k] = fcc::dx(k);
+      off[3 * k + 1] = fcc::dy(k);
+      off[3 * k + 2] = fcc::dz(k);
+      shell[k] = fcc::shell_of(k);
+    }
+    return fcc::kNbr;
+  }
+  return SMC_E_INVALID;
 }
 
 int smc_set_strategy(smc_ctx *c, int32_t strategy) {
@@ -1077,6 +1104,7 @@ void smc_destroy(smc_ctx *c) {
     if (p) (void)hipFree(p);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   fit_release(c);
+  fcc::release(c);
   delete c;
 }
 

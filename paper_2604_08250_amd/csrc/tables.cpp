@@ -24,9 +24,9 @@ OmegaTable build_omega(int n_nbr_used) {
   return t;
 }
 
-Replica make_replica(const int32_t cells[3], int64_t site0, double temperature) {
+Replica make_replica(const int32_t cells[3], int64_t site0, double temperature, int32_t basis) {
   Replica r{};
-  int32_t colours = 2;
+  int32_t colours = basis;
   int64_t trials = 1;
   for (int a = 0; a < 3; ++a) {
     r.L[a] = cells[a];
@@ -36,7 +36,8 @@ Replica make_replica(const int32_t cells[3], int64_t site0, double temperature) 
   }
   r.n_colours = colours;
   r.site0 = site0;
-  r.n_sites = 2LL * cells[0] * cells[1] * cells[2];
+  r.basis = basis;
+  r.n_sites = (int64_t)basis * cells[0] * cells[1] * cells[2];
   r.n_trials = trials;
   r.temperature = temperature;
   return r;

@@ -26,14 +26,14 @@ OmegaTable build_omega(int n_nbr_used);
 struct Replica {
   int32_t L[3];         // cubic cells per axis
   AxisCells ax[3];      // link cells per axis
-  int32_t n_colours;    // 2 * big0 * big1 * big2
-  int32_t pad_;
+  int32_t n_colours;    // basis * big0 * big1 * big2
+  int32_t basis;        // sites per cubic cell: 2 (BCC) or 4 (FCC)
   int64_t site0;        // first site of this replica in the concatenated arrays
   int64_t n_sites;
   int64_t n_trials;     // link cells = trials per colour (some colours skip short cells)
   double temperature;   // kelvin
 };
 
-Replica make_replica(const int32_t cells[3], int64_t site0, double temperature);
+Replica make_replica(const int32_t cells[3], int64_t site0, double temperature, int32_t basis = 2);
 
 }  // namespace smc

@@ -158,3 +158,44 @@ def snapshot_rows(cells, snaps):
         for j in range(s.size):
             rows.append(oracle.features(cells, 1, s, j))
     return np.asarray(rows)
+
+
+def mlpnet_emulate(params, X, prec, H=96, n_in=76):
+    """MLPNet (Eqs. (4)-(6)) as the FCC matrix-core evaluator computes it: layer 0 takes the
+    bias as a weight column on a constant-one input, later biases start the FP32 accumulators,
+    ReLU, W3 and b3 in FP32; q() quantises weights and the activations entering layers 1 and 2
+    (bf16x3: hi*hi + hi*lo + lo*hi).  X: [rows][76] one-hot features (exact in every format)."""
+    p = np.asarray(params, dtype=np.float32)
+    o = 0
+    W0 = p[o:o + H * n_in].reshape(H, n_in); o += H * n_in
+    b0 = p[o:o + H]; o += H
+    W1 = p[o:o + H * H].reshape(H, H); o += H * H
+    b1 = p[o:o + H]; o += H
+    W2 = p[o:o + H * H].reshape(H, H); o += H * H
+    b2 = p[o:o + H]; o += H
+    W3 = p[o:o + H]; o += H
+    b3 = p[o]
+    X = np.asarray(X, dtype=np.float64)
+
+    def split(a):
+        hi = bf16(a)
+        return hi.astype(np.float64), bf16(a - hi).astype(np.float64)
+
+    def matmul(Wm, A):  # Wm [out][in] fp32, A [rows][in] fp32 activations
+        if prec == "fp32":
+            return A.astype(np.float64) @ Wm.astype(np.float64).T
+        wh, wl = split(Wm)
+        ah, al = split(A)
+        if prec == "bf16":
+            return ah @ wh.T
+        return ah @ wh.T + al @ wh.T + ah @ wl.T
+
+    W0b = np.concatenate([W0, b0[:, None]], axis=1)
+    Xb = np.concatenate([X, np.ones((X.shape[0], 1))], axis=1).astype(np.float32)
+    z1 = matmul(W0b, Xb).astype(np.float32)
+    h1 = np.maximum(z1, 0).astype(np.float32)
+    z2 = (matmul(W1, h1) + b1).astype(np.float32)
+    h2 = np.maximum(z2, 0).astype(np.float32)
+    z3 = (matmul(W2, h2) + b2).astype(np.float32)
+    h3 = np.maximum(z3, 0).astype(np.float64)
+    return h3 @ W3.astype(np.float64) + float(b3)

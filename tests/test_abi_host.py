@@ -69,6 +69,7 @@ def test_null_arguments():
     assert lib.smc_sweep(None, 1, None) == -1
     assert lib.smc_energy(None, None, None) == -1
     assert lib.smc_set_temperatures(None, None) == -1
+    assert lib.smc_lattice_shells(7, None, None, 0) == -1
     assert lib.smc_warren_cowley(None, 0, None) == -1
     assert lib.smc_set_strategy(None, 1) == -1
     assert lib.smc_get_strategy(None, None) == -1
@@ -94,3 +95,17 @@ def test_fit_entry_points_reject_null_context():
     assert lib.smc_energy_bwd(None, None, 1, 4, None, None, None) == -1
     assert lib.smc_fit_step(None, None, 1, 4, None, None, None, None, 1e-3, 1, None) == -1
     assert lib.smc_ce_energy(None, None, None, 1, 4, None) == -1
+
+
+def test_lattice_shells_equal_the_oracles():
+    """The library's neighbour slot tables (BCC and FCC) equal the oracle's, slot for slot."""
+    import numpy as np
+    import oracle
+    from oracle import fcc
+    import paper_2604_08250_amd as smc
+    off, sh = smc.smc_lattice_shells(smc.SMC_LATTICE_BCC)
+    o, s = oracle.shell_table()
+    assert np.array_equal(off, o) and np.array_equal(sh, s)
+    off, sh = smc.smc_lattice_shells(smc.SMC_LATTICE_FCC)
+    o, s = fcc.shell_table()
+    assert np.array_equal(off, o) and np.array_equal(sh, s)
