@@ -269,6 +269,77 @@ def measure_qsro(workload, steps=2, warmup=1):
     return out
 
 
+# FCC MLPNet (Eqs. (4)-(6), 76 -> 96 -> 96 -> 96 -> 1): algorithmic work of one local energy,
+# the matrix-core work each precision executes (80 padded inputs, split products), zone size.
+FCC_FLOP_PER_EVAL = 2 * (76 * 96 + 2 * 96 * 96 + 96)
+FCC_EXEC_FLOP_PER_EVAL = {"fp32": 2 * (80 * 96 + 2 * 96 * 96), "bf16": 2 * (80 * 96 + 2 * 96 * 96),
+                          "bf16x3": 2 * (2 * 80 * 96 + 3 * 2 * 96 * 96)}
+FCC_OMEGA = 28
+
+
+def measure_fcc(precisions=("bf16x3", "fp32", "bf16"), steps=2, warmup=1):
+    """The paper's physical system: FCC 200^3 cells (32,000,000 sites), five species in the
+    Fe29Co29Ni28Al7Ti7 proportions, the MLPNet shape (96-wide ReLU, random weights), T = 1000 K.
+    Timed graph sweeps, then one profiled sweep for the zone-row kernel's average launch."""
+    import torch
+
+    import synth
+    import paper_2604_08250_amd as smc
+
+    w = synth.workload("fcc")
+    n_sites = sum(w.sites)
+    occ0 = w.occupancy()
+    params = w.params()
+    stream = torch.cuda.current_stream()
+    out = {"workload": f"FCC {w.cells[0][0]}^3 cells ({n_sites} sites), Fe29Co29Ni28Al7Ti7 proportions, "
+                       f"MLPNet 76-96-96-96-1 ReLU, T = {w.temperatures[0]:g} K", "precisions": {}}
+    for prec in precisions:
+        mc = smc.SwapMC(w.cells, w.temperatures, occ0, params, n_species=w.n_species,
+                        feature=smc.SMC_FEAT_MLPNET_S12, hidden=w.hidden, precision=prec, seed=w.seed,
+                        stream=stream, lattice="fcc")
+        if warmup:
+            mc.sweep(warmup)
+        mc.counters(reset=True)
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record(stream)
+        for _ in range(steps):
+            mc.sweep(1)
+        end.record(stream)
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(end)
+        cnt = mc.counters(reset=True)
+        attempts, diff = int(cnt[0].sum()), int(cnt[1].sum())
+        assert attempts == n_sites * steps
+        mc.profile(True)
+        mc.sweep(1)
+        rows_ms, recheck_ms, launches = mc.kernel_times()
+        mc.profile(False)
+        cnt1 = mc.counters(reset=True)
+        rows = int(cnt1[1].sum()) * FCC_OMEGA
+        alg = rows * FCC_FLOP_PER_EVAL / (rows_ms / 1e3) / 1e12
+        exe = rows * FCC_EXEC_FLOP_PER_EVAL[prec] / (rows_ms / 1e3) / 1e12
+        es, er = mc.energy()
+        r = {"attempts_per_s": attempts / (ms / 1e3), "ms_per_sweep": ms / steps, "sweeps": steps,
+             "accept_ratio": int(cnt[2].sum()) / max(diff, 1), "recheck_frac": int(cnt[3].sum()) / max(diff, 1),
+             "rows_kernel": f"fcc::k_rows_net<{prec}>", "rows_kernel_avg_us": rows_ms * 1e3 / max(launches, 1),
+             "rows_kernel_share": rows_ms / max(rows_ms + recheck_ms, 1e-9),
+             "rows_per_launch": rows / max(launches, 1), "algorithmic_tflops": alg, "executed_tflops": exe,
+             "peak_tflops": PEAK_TFLOPS[prec], "roofline_frac": alg / PEAK_TFLOPS[prec],
+             "executed_frac": exe / PEAK_TFLOPS[prec], "running_minus_scratch_eV": float(er.sum() - es.sum())}
+        out["precisions"][prec] = r
+        log(f"FCC MLPNet {prec}: {r['attempts_per_s']:.3e} attempts/s, {r['ms_per_sweep']:.1f} ms per sweep, "
+            f"rows kernel {r['rows_kernel_avg_us']:.1f} us, {alg:.1f} TFLOP/s")
+        mc.close()
+        del mc
+        torch.cuda.empty_cache()
+    fp32 = out["precisions"].get("fp32", {}).get("attempts_per_s")
+    if fp32:
+        for r in out["precisions"].values():
+            r["speedup_vs_fp32"] = r["attempts_per_s"] / fp32
+    return out
+
+
 # Algorithmic work of one fit row: forward (Eqs. (4)-(6)) plus the backward products
 # dL/dh1 = W1^T dL/dz2 (2*128*128), dW1 (2*128*128), dW0 over the 108 one-hot inputs (2*128*108)
 # and the bias/output terms.
@@ -385,7 +456,8 @@ def main():
     ap.add_argument("--no-fit", action="store_true", help="skip the fit-step measurement")
     ap.add_argument("--no-double-lattice", action="store_true", help="skip the double-lattice measurement")
     ap.add_argument("--no-qsro", action="store_true", help="skip the qSRO-model measurement")
-    ap.add_argument("--only", choices=["batched", "fit", "qsro"], default=None,
+    ap.add_argument("--no-fcc", action="store_true", help="skip the FCC MLPNet measurement")
+    ap.add_argument("--only", choices=["batched", "fit", "qsro", "fcc"], default=None,
                     help="run only this measurement and print its object (for profiling)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", type=float, default=0.0,
@@ -415,6 +487,9 @@ def main():
             res = measure_batched(steps=args.steps, warmup=args.warmup)
         elif args.only == "fit":
             res = measure_fit(steps=args.steps, warmup=args.warmup)
+        elif args.only == "fcc":
+            res = measure_fcc(tuple(x for x in args.precision.split(",") if x), steps=args.steps,
+                              warmup=args.warmup)
         else:
             res = measure_qsro(args.workload, steps=args.steps, warmup=args.warmup)
         print(json.dumps({args.only: res}), flush=True)
@@ -462,6 +537,8 @@ def main():
         out["double_lattice"] = dl
     if not args.no_qsro:
         out["qsro"] = measure_qsro(args.workload)
+    if not args.no_fcc:
+        out["fcc"] = measure_fcc()
     if not args.no_batched:
         out["batched"] = measure_batched()
     if not args.no_fit:

@@ -29,6 +29,8 @@ struct FccState {
   int32_t *d_active = nullptr;       // [cap]
   float *d_e1 = nullptr;             // [cap][om_n]
   fcc::QEntry *d_queue = nullptr;    // [cap]
+  double *d_rowe = nullptr;          // [cap][56] FP64 zone energies of queued MLPNet trials
+  uint32_t *d_done = nullptr;        // [cap] blocks finished per queued trial, zero between uses
   uint32_t *d_counts = nullptr;      // active trials, queued trials (one 64-bit word)
   int64_t cap = 0;                   // largest trial count of a colour
   uint8_t *d_pack[3] = {nullptr, nullptr, nullptr};  // FP32, BF16, split BF16 weight images

@@ -330,8 +330,17 @@ struct Trial {
   int32_t partner;
   double theta;
   int32_t dir;
-  int32_t same;
+  int16_t same;
+  int16_t px, py, pz;  // doubled coordinates of the trial site (each below 2 * 4096)
+  int16_t pad_;
 };
+
+__device__ __forceinline__ Pos trial_pos(const Trial &t) { return Pos{t.px, t.py, t.pz}; }
+
+// Position of zone entry k of a trial at pi (offsets from the zone table, wrapped).
+__device__ __forceinline__ Pos zone_pos(Pos pi, const int8_t *o, const Replica &R) {
+  return Pos{wrap1(pi.x + o[0], 2 * R.L[0]), wrap1(pi.y + o[1], 2 * R.L[1]), wrap1(pi.z + o[2], 2 * R.L[2])};
+}
 
 struct QEntry {     // FP64 re-decision queue entry: index into the active list
   int32_t slot;
@@ -348,7 +357,7 @@ struct Args {
   Trial *trials;           // [n_trials of the colour]
   int32_t *active;         // [n_trials]: trial indices of different-species trials
   uint32_t *n_active;      // device count of active trials (reset before each colour)
-  float *e1;               // [n_trials][om_n] post-swap energies of the sweep precision
+  float *e1;               // [active slot][om_n] post-swap energies of the sweep precision
   const int8_t *om;        // [12][kOmMax][3] zone offsets
   int32_t om_n;            // 28 (MLPNet) or 60 (qSRO)
   double guard;
@@ -361,22 +370,48 @@ struct Args {
   uint8_t *trace_flags;
 };
 
-// Wave-aggregated append: one atomic per wave, slots in lane order within the wave.
-__device__ __forceinline__ uint32_t wave_append(uint32_t *count, bool want) {
+constexpr int kPhaseThreads = 256;  // threads of the propose and decide kernels
+constexpr int kPhaseWaves = kPhaseThreads / 64;
+
+// Block-aggregated append: one atomic per block; slots in (wave, lane) order within the block.
+// Every thread of the block must call it.
+__device__ __forceinline__ uint32_t block_append(uint32_t *count, bool want, uint32_t *s_wave) {
   const unsigned long long m = __ballot(want);
-  const int lane = threadIdx.x & 63;
-  const int leader = m ? __ffsll((long long)m) - 1 : 0;
-  uint32_t base = 0;
-  if (m && lane == leader) base = atomicAdd(count, (uint32_t)__popcll(m));
-  base = __shfl(base, leader);
-  return base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) s_wave[wave] = (uint32_t)__popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t total = 0;
+    for (int w = 0; w < kPhaseWaves; ++w) {
+      const uint32_t c = s_wave[w];
+      s_wave[w] = total;
+      total += c;
+    }
+    s_wave[kPhaseWaves] = total ? atomicAdd(count, total) : 0u;
+  }
+  __syncthreads();
+  return s_wave[kPhaseWaves] + s_wave[wave] + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
 }
 
-__global__ __launch_bounds__(256) void k_propose(Args a) {
+// Block sum of a 64-bit integer per thread (every thread must call it); valid in thread 0.
+__device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v, unsigned long long *s_part) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) s_part[wave] = v;
+  __syncthreads();
+  unsigned long long t = 0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < kPhaseWaves; ++w) t += s_part[w];
+  return t;
+}
+
+__global__ __launch_bounds__(kPhaseThreads) void k_propose(Args a) {
+  __shared__ uint32_t s_wave[kPhaseWaves + 1];
+  __shared__ unsigned long long s_part[kPhaseWaves];
   const Replica R = a.reps[a.r];
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = t < R.n_trials;
-  Trial tr{-1, 0, 0.0, 0, 1};
+  Trial tr{-1, 0, 0.0, 0, 1, 0, 0, 0, 0};
   const int64_t i = live ? fcc::trial_site(R, a.colour, t) : -1;
   if (i >= 0) {
     const U64x4 x = philox4x64_10((uint64_t)i, *a.sweep, (uint64_t)a.r, 0, a.seed, 0);
@@ -390,6 +425,9 @@ __global__ __launch_bounds__(256) void k_propose(Args a) {
     tr.theta = isinf(R.temperature) ? (double)INFINITY : -kBoltzmannEvPerK * R.temperature * log(u);
     tr.dir = d;
     tr.same = occ[i] == occ[n];
+    tr.px = (int16_t)pi.x;
+    tr.py = (int16_t)pi.y;
+    tr.pz = (int16_t)pi.z;
     if (tr.same) {
       if (a.trace_flags) a.trace_flags[R.site0 + i] = kFlagSame;
       if (a.trace_dE) a.trace_dE[R.site0 + i] = 0.0;
@@ -398,13 +436,14 @@ __global__ __launch_bounds__(256) void k_propose(Args a) {
   }
   if (live) a.trials[t] = tr;
   const bool active = i >= 0 && !tr.same;
-  const uint32_t slot = wave_append(a.n_active, active);
+  const uint32_t slot = block_append(a.n_active, active, s_wave);
   if (active) a.active[slot] = (int32_t)t;
-  const unsigned long long vm = __ballot(i >= 0), am = __ballot(active);
-  if ((threadIdx.x & 63) == 0) {
+  // attempts in the low and different-species trials in the high 32 bits
+  const unsigned long long both = block_sum_u64((i >= 0 ? 1ull : 0ull) | (active ? 1ull << 32 : 0ull), s_part);
+  if (threadIdx.x == 0 && both) {
     const int Rn = a.n_replicas;
-    if (vm) atomicAdd((unsigned long long *)&a.counters[0 * Rn + a.r], (unsigned long long)__popcll(vm));
-    if (am) atomicAdd((unsigned long long *)&a.counters[1 * Rn + a.r], (unsigned long long)__popcll(am));
+    atomicAdd((unsigned long long *)&a.counters[0 * Rn + a.r], both & 0xffffffffull);
+    atomicAdd((unsigned long long *)&a.counters[1 * Rn + a.r], both >> 32);
   }
 }
 
@@ -416,29 +455,36 @@ __device__ __forceinline__ uint32_t swapped(const uint8_t *occ, int64_t s, int64
 
 // Post-swap MLPNet energies of the zone sites of every active trial: row = active slot x
 // zone position, 32 rows per wave tile.
+// Threads of the row kernels: the BF16 image (52 KB) lets three 256-thread blocks share a
+// CU; the FP32 and split-BF16 images (103 KB) one 512-thread block.
 template <int P>
-__global__ __launch_bounds__(kNetThreads) void k_rows_net(Args a, const uint8_t *wpack, float b3) {
+constexpr int net_threads() {
+  return P == kPBF16 ? 256 : kNetThreads;
+}
+
+template <int P>
+__global__ __launch_bounds__(net_threads<P>()) void k_rows_net(Args a, const uint8_t *wpack, float b3) {
   constexpr int kW = net_bytes<P>();
+  constexpr int kThreads = net_threads<P>();
   __shared__ __attribute__((aligned(16))) uint8_t s_w[kW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int q = tid; q < kW / 16; q += kNetThreads) ((int4 *)s_w)[q] = ((const int4 *)wpack)[q];
+  for (int q = tid; q < kW / 16; q += kThreads) ((int4 *)s_w)[q] = ((const int4 *)wpack)[q];
   __syncthreads();
   const NetSmem S = net_smem<P>(s_w, b3);
   const Replica R = a.reps[a.r];
   const uint8_t *occ = a.occ + R.site0;
-  const int64_t rows = (int64_t)(*a.n_active) * kOmMlp;
-  const int64_t tiles = (rows + 31) / 32;
-  constexpr int kWaves = kNetThreads / 64;
-  for (int64_t tile = (int64_t)blockIdx.x * kWaves + wave; tile < tiles; tile += (int64_t)gridDim.x * kWaves) {
-    const int64_t row = tile * 32 + (lane & 31);
+  const int32_t rows = (int32_t)(*a.n_active) * kOmMlp;  // below 2^31: trials x 28 of one colour
+  const int32_t tiles = (rows + 31) / 32;
+  constexpr int kWaves = kThreads / 64;
+  for (int32_t tile = blockIdx.x * kWaves + wave; tile < tiles; tile += gridDim.x * kWaves) {
+    const int32_t row = tile * 32 + (lane & 31);
     const bool valid = row < rows;
-    const int64_t slot = valid ? row / kOmMlp : 0;
-    const int k = valid ? (int)(row - slot * kOmMlp) : 0;
+    const int32_t slot = valid ? row / kOmMlp : 0;
+    const int k = valid ? row - slot * kOmMlp : 0;
     const Trial tr = a.trials[a.active[slot]];
     const int64_t i = tr.site, n = tr.partner;
     const uint32_t si = occ[i], sn = occ[n];
-    const int8_t *o = a.om + (tr.dir * kOmMax + k) * 3;
-    const Pos pj = pos(at(pos(i, R.L[0], R.L[1]), o[0], o[1], o[2], R.L[0], R.L[1], R.L[2]), R.L[0], R.L[1]);
+    const Pos pj = zone_pos(trial_pos(tr), a.om + (tr.dir * kOmMax + k) * 3, R);
     const float E = eval_net<P>(S, [&](int m) -> uint32_t {
       const int64_t s = m == 0 ? index(pj, R.L[0], R.L[1])
                                : at(pj, dx(m - 1), dy(m - 1), dz(m - 1), R.L[0], R.L[1], R.L[2]);
@@ -460,8 +506,7 @@ __global__ __launch_bounds__(256) void k_rows_qsro(Args a, const float *F) {
     const Trial tr = a.trials[a.active[slot]];
     const int64_t i = tr.site, n = tr.partner;
     const uint32_t si = occ[i], sn = occ[n];
-    const int8_t *o = a.om + (tr.dir * kOmMax + k) * 3;
-    const Pos pj = pos(at(pos(i, R.L[0], R.L[1]), o[0], o[1], o[2], R.L[0], R.L[1], R.L[2]), R.L[0], R.L[1]);
+    const Pos pj = zone_pos(trial_pos(tr), a.om + (tr.dir * kOmMax + k) * 3, R);
     a.e1[row] = qsro_site<float>(
         [&](int k2) -> int {
           const int64_t s = k2 < 0 ? index(pj, R.L[0], R.L[1]) : at(pj, dx(k2), dy(k2), dz(k2), R.L[0], R.L[1], R.L[2]);
@@ -472,23 +517,35 @@ __global__ __launch_bounds__(256) void k_rows_qsro(Args a, const float *F) {
 }
 
 // Zone sums against the cache (fixed order), then the Metropolis decision or the FP64 queue.
-__global__ __launch_bounds__(256) void k_decide(Args a) {
+// The zone energies of a trial are contiguous (OM is a multiple of four): 16-byte loads, all
+// of them and the cache gathers in flight at once.
+template <int OM>
+__global__ __launch_bounds__(kPhaseThreads) void k_decide(Args a) {
+  static_assert(OM % 4 == 0, "zone size");
+  __shared__ unsigned long long s_part[kPhaseWaves];
   const Replica R = a.reps[a.r];
   const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = slot < (int64_t)(*a.n_active);
   bool accept = false;
-  double dEd = 0.0;
+  long long fixed = 0;
   if (live) {
     const Trial tr = a.trials[a.active[slot]];
     uint8_t *occ = a.occ + R.site0;
     float *ec = a.ecache + R.site0;
-    const Pos pi = pos(tr.site, R.L[0], R.L[1]);
-    const float *e1 = a.e1 + slot * a.om_n;
+    const Pos pi = trial_pos(tr);
+    const f32x4 *e1 = (const f32x4 *)(a.e1 + slot * OM);
     const int8_t *o = a.om + tr.dir * kOmMax * 3;
     float dE = 0.0f;
-    for (int k = 0; k < a.om_n; ++k)
-      dE += e1[k] - ec[at(pi, o[3 * k], o[3 * k + 1], o[3 * k + 2], R.L[0], R.L[1], R.L[2])];
-    dEd = (double)dE;
+#pragma unroll
+    for (int k4 = 0; k4 < OM / 4; ++k4) {
+      const f32x4 v = e1[k4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = 4 * k4 + q;
+        dE += v[q] - ec[at(pi, o[3 * k], o[3 * k + 1], o[3 * k + 2], R.L[0], R.L[1], R.L[2])];
+      }
+    }
+    const double dEd = (double)dE;
     if (a.trace_dE_fast) a.trace_dE_fast[R.site0 + tr.site] = dEd;
     if (fabs(dEd - tr.theta) < a.guard) {
       const uint32_t q = atomicAdd(a.q_count, 1u);
@@ -499,17 +556,30 @@ __global__ __launch_bounds__(256) void k_decide(Args a) {
         const uint8_t si = occ[tr.site];
         occ[tr.site] = occ[tr.partner];
         occ[tr.partner] = si;
-        for (int k = 0; k < a.om_n; ++k)
-          ec[at(pi, o[3 * k], o[3 * k + 1], o[3 * k + 2], R.L[0], R.L[1], R.L[2])] = e1[k];
-        atomicAdd(&a.e_fixed[a.r], (unsigned long long)to_fixed(dEd));
+#pragma unroll
+        for (int k4 = 0; k4 < OM / 4; ++k4) {
+          const f32x4 v = e1[k4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int k = 4 * k4 + q;
+            ec[at(pi, o[3 * k], o[3 * k + 1], o[3 * k + 2], R.L[0], R.L[1], R.L[2])] = v[q];
+          }
+        }
+        fixed = to_fixed(dEd);
       }
       if (a.trace_flags) a.trace_flags[R.site0 + tr.site] = accept ? kFlagAccept : 0;
       if (a.trace_dE) a.trace_dE[R.site0 + tr.site] = dEd;
     }
   }
-  const unsigned long long cm = __ballot(accept);
-  if ((threadIdx.x & 63) == 0 && cm)
-    atomicAdd((unsigned long long *)&a.counters[2 * a.n_replicas + a.r], (unsigned long long)__popcll(cm));
+  // one atomic per block for the accepted dE (2^-32 eV units, exact integer sums) and one for
+  // the accept counter
+  const unsigned long long esum = block_sum_u64((unsigned long long)fixed, s_part);
+  __syncthreads();
+  const unsigned long long nacc = block_sum_u64(accept ? 1ull : 0ull, s_part);
+  if (threadIdx.x == 0) {
+    if (esum) atomicAdd(&a.e_fixed[a.r], esum);
+    if (nacc) atomicAdd((unsigned long long *)&a.counters[2 * a.n_replicas + a.r], nacc);
+  }
 }
 
 // ------------------------------------------------------------------ FP64 evaluation
@@ -517,15 +587,17 @@ __global__ __launch_bounds__(256) void k_decide(Args a) {
 // FP64 MLPNet blob with every weight matrix stored [input][unit] (consecutive threads own
 // consecutive units, so their loads are contiguous): W0t[76][96], b0, W1t[96][96], b1,
 // W2t[96][96], b2, W3[96], b3.
-constexpr int kRows64 = 64;       // rows per pass of the FP64 row kernel
-constexpr int kR64Threads = 384;  // 96 units x 4 parts, 16 rows per thread
+constexpr int kRows64 = 64;       // rows per pass of the FP64 site-energy kernel
+constexpr int kR64Threads = 384;  // 96 units x 4 parts
 constexpr int kR64Parts = kR64Threads / kHid;
-constexpr int kR64PerThread = kRows64 / kR64Parts;
 constexpr int kHS = kHid + 1;     // padded activation row stride
 
-// FP64 energies of nrows (<= 64) rows whose slot species are in s_sp[row][19]; the result of
-// row r goes to s_out[r].  Every thread of the block takes part (block-wide barriers).
+// FP64 energies of nrows (<= 4 RPT) rows whose slot species are in s_sp[row][19]; the result
+// of row r goes to s_out[r].  Thread (unit o, part p) owns rows p + 4j, j < RPT.  Every thread
+// of the block takes part (block-wide barriers).
+template <int RPT>
 __device__ void net64_rows(const double *W, const uint8_t *s_sp, int nrows, double *s_h, double *s_out) {
+  constexpr int kR64PerThread = RPT;
   const int tid = threadIdx.x;
   const int o = tid % kHid, part = tid / kHid;
   const double *W0 = W, *b0 = W0 + kIn * kHid, *W1 = b0 + kHid, *b1 = W1 + kHid * kHid, *W2 = b1 + kHid,
@@ -533,6 +605,7 @@ __device__ void net64_rows(const double *W, const uint8_t *s_sp, int nrows, doub
   double acc[kR64PerThread];
 #pragma unroll
   for (int j = 0; j < kR64PerThread; ++j) acc[j] = b0[o];
+#pragma unroll 4
   for (int m = 0; m < kSlots; ++m) {
     const double w0 = W0[(4 * m) * kHid + o], w1 = W0[(4 * m + 1) * kHid + o], w2 = W0[(4 * m + 2) * kHid + o],
                  w3 = W0[(4 * m + 3) * kHid + o];
@@ -551,6 +624,7 @@ __device__ void net64_rows(const double *W, const uint8_t *s_sp, int nrows, doub
     const double *Wl = layer == 0 ? W1 : W2, *bl = layer == 0 ? b1 : b2;
 #pragma unroll
     for (int j = 0; j < kR64PerThread; ++j) acc[j] = bl[o];
+#pragma unroll 8
     for (int k = 0; k < kHid; ++k) {
       const double wk = Wl[k * kHid + o];
 #pragma unroll
@@ -589,7 +663,7 @@ __global__ __launch_bounds__(kR64Threads) void k_site_energies_net64(const Repli
       s_sp[v] = occ[m == 0 ? j0 + lr : at(p, dx(m - 1), dy(m - 1), dz(m - 1), R.L[0], R.L[1], R.L[2])];
     }
     __syncthreads();
-    net64_rows(W, s_sp, nrows, s_h, s_out);
+    net64_rows<kRows64 / kR64Parts>(W, s_sp, nrows, s_h, s_out);
     if ((int)threadIdx.x < nrows) out[R.site0 + j0 + threadIdx.x] = s_out[threadIdx.x];
     __syncthreads();
   }
@@ -634,15 +708,86 @@ __global__ void k_site_energies_qsro(const Replica *reps, int32_t r, const uint8
       [&](int k) -> int { return k < 0 ? occ[j] : occ[at(p, dx(k), dy(k), dz(k), R.L[0], R.L[1], R.L[2])]; }, F);
 }
 
-// FP64 re-decision of queued trials: the zone's local energies before and after the swap
-// (MLPNet: 2 x 28 rows in one pass of the row kernel; qSRO: one row per thread), dE as the
-// difference of the two zone sums in zone order, decision and apply.  The cache keeps the
-// sweep precision's post-swap energies.
-template <int MODEL>  // 0 MLPNet, 1 qSRO
-__global__ __launch_bounds__(kR64Threads) void k_recheck(Args a, const double *W) {
-  __shared__ double s_h[kRows64 * kHS];
-  __shared__ double s_out[2 * kOmMax];
-  __shared__ uint8_t s_sp[kRows64 * kSlots];
+// FP64 re-decision of queued trials (MLPNet): the zone's 28 local energies after and 28
+// before the swap, split over kRcSplit blocks of 8 rows so that a short queue still spreads
+// over the chip.  Each block writes its rows to row_e; the block that completes a trial (per
+// trial counter) sums the two zone halves in zone order, decides and applies.  No block waits
+// for another.  The cache keeps the sweep precision's post-swap energies.
+constexpr int kRcSplit = 7;
+constexpr int kRcRows = 2 * kOmMlp / kRcSplit;  // 8
+static_assert(kRcRows * kRcSplit == 2 * kOmMlp, "row split");
+
+__global__ __launch_bounds__(kR64Threads) void k_recheck_net(Args a, const double *W, double *row_e,
+                                                            uint32_t *done) {
+  __shared__ double s_h[kRcRows * kHS];
+  __shared__ double s_out[kRcRows];
+  __shared__ uint8_t s_sp[kRcRows * kSlots];
+  __shared__ int s_last, s_accept;
+  const Replica R = a.reps[a.r];
+  uint8_t *occ = a.occ + R.site0;
+  const uint32_t nq = *a.q_count;
+  const int tid = threadIdx.x;
+  for (uint32_t w = blockIdx.x; w < nq * kRcSplit; w += gridDim.x) {
+    const uint32_t q = w / kRcSplit;
+    const int r0 = (int)(w - q * kRcSplit) * kRcRows;
+    const QEntry qe = a.queue[q];
+    const Trial tr = a.trials[a.active[qe.slot]];
+    const int64_t i = tr.site, n = tr.partner;
+    const uint32_t si = occ[i], sn = occ[n];
+    const Pos pi = trial_pos(tr);
+    const int8_t *o = a.om + tr.dir * kOmMax * 3;
+    // rows 0..27 after the swap, 28..55 before
+    for (int v = tid; v < kRcRows * kSlots; v += kR64Threads) {
+      const int row = r0 + v / kSlots, m = v % kSlots;
+      const bool post = row < kOmMlp;
+      const int k = post ? row : row - kOmMlp;
+      const Pos pj = zone_pos(pi, o + 3 * k, R);
+      const int64_t s = m == 0 ? index(pj, R.L[0], R.L[1]) : at(pj, dx(m - 1), dy(m - 1), dz(m - 1), R.L[0], R.L[1], R.L[2]);
+      s_sp[v] = (uint8_t)(post ? swapped(occ, s, i, n, si, sn) : (uint32_t)occ[s]);
+    }
+    __syncthreads();
+    net64_rows<kRcRows / kR64Parts>(W, s_sp, kRcRows, s_h, s_out);
+    if (tid < kRcRows) row_e[(size_t)q * 2 * kOmMlp + r0 + tid] = s_out[tid];
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) s_last = atomicAdd(&done[q], 1u) == kRcSplit - 1;
+    __syncthreads();
+    if (s_last) {
+      __threadfence();
+      if (tid == 0) {
+        const double *re = row_e + (size_t)q * 2 * kOmMlp;
+        double e1 = 0.0, e0 = 0.0;
+        for (int k = 0; k < kOmMlp; ++k) e1 += __hip_atomic_load(re + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int k = 0; k < kOmMlp; ++k)
+          e0 += __hip_atomic_load(re + kOmMlp + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        done[q] = 0;  // ready for the next use of this queue slot
+        const double dE = e1 - e0;
+        const bool accept = dE <= tr.theta;
+        const int Rn = a.n_replicas;
+        if (accept) {
+          occ[i] = (uint8_t)sn;
+          occ[n] = (uint8_t)si;
+          atomicAdd(&a.e_fixed[a.r], (unsigned long long)to_fixed(dE));
+          atomicAdd((unsigned long long *)&a.counters[2 * Rn + a.r], 1ull);
+        }
+        atomicAdd((unsigned long long *)&a.counters[3 * Rn + a.r], 1ull);
+        if (a.trace_flags) a.trace_flags[R.site0 + i] = kFlagFp64 | (accept ? kFlagAccept : 0);
+        if (a.trace_dE) a.trace_dE[R.site0 + i] = dE;
+        s_accept = accept;
+      }
+      __syncthreads();
+      if (tid < kOmMlp && s_accept)
+        a.ecache[R.site0 + at(pi, o[3 * tid], o[3 * tid + 1], o[3 * tid + 2], R.L[0], R.L[1], R.L[2])] =
+            a.e1[(int64_t)qe.slot * kOmMlp + tid];
+    }
+    __syncthreads();
+  }
+}
+
+// FP64 re-decision of queued trials (qSRO): one row per thread, one trial per block.
+constexpr int kRcQsroThreads = 128;
+__global__ __launch_bounds__(kRcQsroThreads) void k_recheck_qsro(Args a, const double *W) {
+  __shared__ double s_out[2 * kOmQsro];
   __shared__ int s_accept;
   const Replica R = a.reps[a.r];
   uint8_t *occ = a.occ + R.site0;
@@ -653,41 +798,24 @@ __global__ __launch_bounds__(kR64Threads) void k_recheck(Args a, const double *W
     const Trial tr = a.trials[a.active[qe.slot]];
     const int64_t i = tr.site, n = tr.partner;
     const uint32_t si = occ[i], sn = occ[n];
-    const Pos pi = pos(i, R.L[0], R.L[1]);
+    const Pos pi = trial_pos(tr);
     const int8_t *o = a.om + tr.dir * kOmMax * 3;
-    const int om_n = a.om_n;
-    if constexpr (MODEL == 0) {
-      // rows 0..27 after the swap, 28..55 before
-      for (int v = tid; v < 2 * kOmMlp * kSlots; v += kR64Threads) {
-        const int row = v / kSlots, m = v - row * kSlots;
-        const bool post = row < kOmMlp;
-        const int k = post ? row : row - kOmMlp;
-        const Pos pj = pos(at(pi, o[3 * k], o[3 * k + 1], o[3 * k + 2], R.L[0], R.L[1], R.L[2]), R.L[0], R.L[1]);
-        const int64_t s = m == 0 ? index(pj, R.L[0], R.L[1])
-                                 : at(pj, dx(m - 1), dy(m - 1), dz(m - 1), R.L[0], R.L[1], R.L[2]);
-        s_sp[v] = (uint8_t)(post ? swapped(occ, s, i, n, si, sn) : (uint32_t)occ[s]);
-      }
-      __syncthreads();
-      net64_rows(W, s_sp, 2 * kOmMlp, s_h, s_out);
-    } else {
-      if (tid < 2 * kOmQsro) {
-        const bool post = tid < kOmQsro;
-        const int k = post ? tid : tid - kOmQsro;
-        const Pos pj = pos(at(pi, o[3 * k], o[3 * k + 1], o[3 * k + 2], R.L[0], R.L[1], R.L[2]), R.L[0], R.L[1]);
-        s_out[tid] = qsro_site<double>(
-            [&](int k2) -> int {
-              const int64_t s =
-                  k2 < 0 ? index(pj, R.L[0], R.L[1]) : at(pj, dx(k2), dy(k2), dz(k2), R.L[0], R.L[1], R.L[2]);
-              return (int)(post ? swapped(occ, s, i, n, si, sn) : (uint32_t)occ[s]);
-            },
-            W);
-      }
-      __syncthreads();
+    if (tid < 2 * kOmQsro) {
+      const bool post = tid < kOmQsro;
+      const int k = post ? tid : tid - kOmQsro;
+      const Pos pj = zone_pos(pi, o + 3 * k, R);
+      s_out[tid] = qsro_site<double>(
+          [&](int k2) -> int {
+            const int64_t s = k2 < 0 ? index(pj, R.L[0], R.L[1]) : at(pj, dx(k2), dy(k2), dz(k2), R.L[0], R.L[1], R.L[2]);
+            return (int)(post ? swapped(occ, s, i, n, si, sn) : (uint32_t)occ[s]);
+          },
+          W);
     }
+    __syncthreads();
     if (tid == 0) {
       double e1 = 0.0, e0 = 0.0;
-      for (int k = 0; k < om_n; ++k) e1 += s_out[k];
-      for (int k = 0; k < om_n; ++k) e0 += s_out[om_n + k];
+      for (int k = 0; k < kOmQsro; ++k) e1 += s_out[k];
+      for (int k = 0; k < kOmQsro; ++k) e0 += s_out[kOmQsro + k];
       const double dE = e1 - e0;
       const bool accept = dE <= tr.theta;
       const int Rn = a.n_replicas;
@@ -703,9 +831,9 @@ __global__ __launch_bounds__(kR64Threads) void k_recheck(Args a, const double *W
       s_accept = accept;
     }
     __syncthreads();
-    if (tid < om_n && s_accept)
+    if (tid < kOmQsro && s_accept)
       a.ecache[R.site0 + at(pi, o[3 * tid], o[3 * tid + 1], o[3 * tid + 2], R.L[0], R.L[1], R.L[2])] =
-          a.e1[(int64_t)qe.slot * om_n + tid];
+          a.e1[(int64_t)qe.slot * kOmQsro + tid];
     __syncthreads();
   }
 }

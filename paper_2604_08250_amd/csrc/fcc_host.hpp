@@ -169,7 +169,7 @@ inline int load_params(smc_ctx *c, const float *params_dev) {
 }
 
 // Blocks of the matrix-core kernels: LDS holds one weight image per block.
-inline int net_blocks(const smc_ctx *c, int P) { return (P == SMC_BF16 ? 2 : 1) * c->n_cu; }
+inline int net_blocks(const smc_ctx *c, int P) { return (P == SMC_BF16 ? 3 : 1) * c->n_cu; }
 
 template <int P>
 void launch_site_energies_net(smc_ctx *c, float *out) {
@@ -249,8 +249,11 @@ inline int refresh(smc_ctx *c) {
 template <int P>
 void launch_rows_net(smc_ctx *c, const Args &a, int64_t n_trials) {
   const int64_t tiles = (n_trials * kOmMlp + 31) / 32;
-  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((tiles + 7) / 8, net_blocks(c, P)));
-  hipLaunchKernelGGL((k_rows_net<P>), dim3(grid), dim3(kNetThreads), 0, c->stream, a, c->fcc.d_pack[P], c->fcc.b3);
+  constexpr int kWaves = net_threads<P>() / 64;
+  const unsigned grid =
+      (unsigned)std::max<int64_t>(1, std::min<int64_t>((tiles + kWaves - 1) / kWaves, net_blocks(c, P)));
+  hipLaunchKernelGGL((k_rows_net<P>), dim3(grid), dim3(net_threads<P>()), 0, c->stream, a, c->fcc.d_pack[P],
+                     c->fcc.b3);
 }
 
 // Enqueue one sweep on c->stream (also under graph capture): per replica and colour the
@@ -291,7 +294,7 @@ inline int enqueue_sweep(smc_ctx *c, const smc_stats *st, bool trace) {
         a.trace_flags = st->trace_flags;
       }
       hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, c->stream, (uint64_t *)f.d_counts, (int64_t)1, (uint64_t)0);
-      hipLaunchKernelGGL(k_propose, dim3(grid_for(nt, 256)), dim3(256), 0, c->stream, a);
+      hipLaunchKernelGGL(k_propose, dim3(grid_for(nt, kPhaseThreads)), dim3(kPhaseThreads), 0, c->stream, a);
       const int ev = prof_begin(c);
       if (f.model == 1) {
         const unsigned g = (unsigned)std::min<int64_t>(grid_for(nt * kOmQsro, 256), 8 * (int64_t)c->n_cu);
@@ -304,13 +307,22 @@ inline int enqueue_sweep(smc_ctx *c, const smc_stats *st, bool trace) {
         launch_rows_net<kPBF16X3>(c, a, nt);
       }
       prof_end(c, ev, 0);
-      hipLaunchKernelGGL(k_decide, dim3(grid_for(nt, 256)), dim3(256), 0, c->stream, a);
-      const unsigned rg = (unsigned)std::min<int64_t>(4 * (int64_t)c->n_cu, nt);
-      const int ev2 = prof_begin(c);
       if (f.model == 0)
-        hipLaunchKernelGGL(k_recheck<0>, dim3(rg), dim3(kR64Threads), 0, c->stream, a, (const double *)c->d_w64);
+        hipLaunchKernelGGL(k_decide<kOmMlp>, dim3(grid_for(nt, kPhaseThreads)), dim3(kPhaseThreads), 0, c->stream, a);
       else
-        hipLaunchKernelGGL(k_recheck<1>, dim3(rg), dim3(kR64Threads), 0, c->stream, a, (const double *)c->d_w64);
+        hipLaunchKernelGGL(k_decide<kOmQsro>, dim3(grid_for(nt, kPhaseThreads)), dim3(kPhaseThreads), 0, c->stream,
+                           a);
+      // blocks loop over the queue (usually short): a few per CU
+      const int ev2 = prof_begin(c);
+      if (f.model == 0) {
+        const unsigned rg = (unsigned)std::min<int64_t>(4 * (int64_t)c->n_cu, nt * kRcSplit);
+        hipLaunchKernelGGL(k_recheck_net, dim3(rg), dim3(kR64Threads), 0, c->stream, a, (const double *)c->d_w64,
+                           f.d_rowe, f.d_done);
+      } else {
+        const unsigned rg = (unsigned)std::min<int64_t>(2 * (int64_t)c->n_cu, nt);
+        hipLaunchKernelGGL(k_recheck_qsro, dim3(rg), dim3(kRcQsroThreads), 0, c->stream, a,
+                           (const double *)c->d_w64);
+      }
       prof_end(c, ev2, 1);
     }
   }
@@ -321,7 +333,8 @@ inline int enqueue_sweep(smc_ctx *c, const smc_stats *st, bool trace) {
 
 inline void release(smc_ctx *c) {
   FccState &f = c->fcc;
-  void *bufs[] = {f.d_om, f.d_trials, f.d_active, f.d_e1, f.d_queue, f.d_counts, f.d_pack[0], f.d_pack[1], f.d_pack[2]};
+  void *bufs[] = {f.d_om,     f.d_trials, f.d_active,  f.d_e1,      f.d_queue,  f.d_counts,
+                  f.d_rowe,   f.d_done,   f.d_pack[0], f.d_pack[1], f.d_pack[2]};
   for (void *p : bufs)
     if (p) (void)hipFree(p);
 }
@@ -401,7 +414,10 @@ inline int create(const smc_config *cfg, uint8_t *occ_dev, const float *params_d
             hipMalloc(&f.d_active, sizeof(int32_t) * f.cap) == hipSuccess &&
             hipMalloc(&f.d_e1, sizeof(float) * f.cap * f.om_n) == hipSuccess &&
             hipMalloc(&f.d_queue, sizeof(QEntry) * f.cap) == hipSuccess &&
-            hipMalloc(&f.d_counts, sizeof(uint64_t)) == hipSuccess;
+            hipMalloc(&f.d_counts, sizeof(uint64_t)) == hipSuccess &&
+            (model != 0 || (hipMalloc(&f.d_rowe, sizeof(double) * 2 * kOmMlp * f.cap) == hipSuccess &&
+                            hipMalloc(&f.d_done, sizeof(uint32_t) * f.cap) == hipSuccess &&
+                            hipMemset(f.d_done, 0, sizeof(uint32_t) * f.cap) == hipSuccess));
   if (!ok) return cleanup(SMC_E_NOMEM);
   const uint64_t zero = 0;
   if (hipMemcpyAsync(c->d_sweep, &zero, sizeof(uint64_t), hipMemcpyHostToDevice, c->stream) ||

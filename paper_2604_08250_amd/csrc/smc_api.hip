@@ -287,7 +287,9 @@ int enqueue_sweep_mfma(smc_ctx *c, const smc_stats *st, bool trace) {
       ra.trace_dE = st->trace_dE;
       ra.trace_flags = st->trace_flags;
     }
-    const int rgrid = (int)std::min<int64_t>(8 * c->n_cu, kRcSplit * std::max<int64_t>(1, c->col_trials[col]));
+    // one block per CU (the re-decision kernel's LDS admits no second); blocks loop over the
+    // queue, which is usually short, so extra blocks would only add dispatch time
+    const int rgrid = (int)std::min<int64_t>(c->n_cu, kRcSplit * std::max<int64_t>(1, c->col_trials[col]));
     const int ev2 = prof_begin(c);
     hipLaunchKernelGGL(k_recheck, dim3(rgrid), dim3(kRcThreads), 0, c->stream, ra);
     prof_end(c, ev2, 1);
@@ -411,7 +413,7 @@ int enqueue_sweep_dl(smc_ctx *c, const smc_stats *st, bool trace) {
         ra.trace_dE = st->trace_dE;
         ra.trace_flags = st->trace_flags;
       }
-      const int rgrid = (int)std::min<int64_t>(8 * c->n_cu, kRcSplit * std::max<int64_t>(1, rep.n_trials));
+      const int rgrid = (int)std::min<int64_t>(c->n_cu, kRcSplit * std::max<int64_t>(1, rep.n_trials));
       const int ev2 = prof_begin(c);
       hipLaunchKernelGGL(k_recheck, dim3(rgrid), dim3(kRcThreads), 0, c->stream, ra);
       prof_end(c, ev2, 1);
