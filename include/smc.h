@@ -189,7 +189,8 @@ int smc_profile(smc_ctx *ctx, int32_t enable);
 int smc_kernel_times(smc_ctx *ctx, double *colour_ms, double *recheck_ms, int64_t *colour_launches);
 
 /* New temperatures (host [n_replicas], >= 0 or +inf) for the following sweeps, e.g. an
- * annealing schedule (the paper's runs anneal its alloys at fixed T; Sec. IV-C).  The
+ * annealing schedule (the paper anneals its alloy from 2000 K to 1000 K in 250 K steps,
+ * Sec. V-F).  The
  * replica table is read by the kernels at run time, so captured sweeps follow the change.
  * Synchronises. */
 int smc_set_temperatures(smc_ctx *ctx, const double *temperature_K_host);
