@@ -170,37 +170,40 @@ __device__ __forceinline__ void net_hidden(const uint8_t *A0, const float *c, co
         __builtin_amdgcn_sched_barrier(0);
       }
   } else {
-    // K-step s = 2T + hh takes registers 8hh..8hh+7 of M-tile T
+    // K-step s = 2T + hh takes registers 8hh..8hh+7 of M-tile T; the B operands of step s + 1
+    // are built before the products of step s are issued
     const i32x4 *Ahi = (const i32x4 *)A0;
     const i32x4 *Alo = (const i32x4 *)(A0 + NetSize<kPBF16>::kL1);
+    auto build = [&](int T, int hh, i32x4 &bh, i32x4 &bl) {
 #pragma unroll
-    for (int T = 0; T < kMT; ++T)
-#pragma unroll
-      for (int hh = 0; hh < 2; ++hh) {
-        i32x4 bh, bl;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float x0 = relu(in[T][8 * hh + 2 * q]);
-          const float x1 = relu(in[T][8 * hh + 2 * q + 1]);
-          const uint32_t w = pack_bf16x2(x0, x1);
-          bh[q] = (int)w;
-          if constexpr (P == kPBF16X3) bl[q] = (int)pack_bf16x2(x0 - bf16_lo_f32(w), x1 - bf16_hi_f32(w));
-        }
-        const bf16x8 Bh = __builtin_bit_cast(bf16x8, bh);
-        const int s = 2 * T + hh;
-#pragma unroll
-        for (int To = 0; To < kMT; ++To) {
-          const bf16x8 ah = __builtin_bit_cast(bf16x8, Ahi[(To * 6 + s) * 64 + lane]);
-          out[To] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, Bh, out[To], 0, 0, 0);
-          if constexpr (P == kPBF16X3) {
-            const bf16x8 Bl = __builtin_bit_cast(bf16x8, bl);
-            const bf16x8 al = __builtin_bit_cast(bf16x8, Alo[(To * 6 + s) * 64 + lane]);
-            out[To] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, Bl, out[To], 0, 0, 0);
-            out[To] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, Bh, out[To], 0, 0, 0);
-          }
-        }
-        __builtin_amdgcn_sched_barrier(0);
+      for (int q = 0; q < 4; ++q) {
+        const float x0 = relu(in[T][8 * hh + 2 * q]);
+        const float x1 = relu(in[T][8 * hh + 2 * q + 1]);
+        const uint32_t w = pack_bf16x2(x0, x1);
+        bh[q] = (int)w;
+        if constexpr (P == kPBF16X3) bl[q] = (int)pack_bf16x2(x0 - bf16_lo_f32(w), x1 - bf16_hi_f32(w));
       }
+    };
+    i32x4 bh[2], bl[2];
+    build(0, 0, bh[0], bl[0]);
+#pragma unroll
+    for (int s = 0; s < 2 * kMT; ++s) {
+      const int cur = s & 1;
+      if (s + 1 < 2 * kMT) build((s + 1) >> 1, (s + 1) & 1, bh[cur ^ 1], bl[cur ^ 1]);
+      const bf16x8 Bh = __builtin_bit_cast(bf16x8, bh[cur]);
+#pragma unroll
+      for (int To = 0; To < kMT; ++To) {
+        const bf16x8 ah = __builtin_bit_cast(bf16x8, Ahi[(To * 6 + s) * 64 + lane]);
+        out[To] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, Bh, out[To], 0, 0, 0);
+        if constexpr (P == kPBF16X3) {
+          const bf16x8 Bl = __builtin_bit_cast(bf16x8, bl[cur]);
+          const bf16x8 al = __builtin_bit_cast(bf16x8, Alo[(To * 6 + s) * 64 + lane]);
+          out[To] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, Bl, out[To], 0, 0, 0);
+          out[To] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, Bh, out[To], 0, 0, 0);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
 }
 

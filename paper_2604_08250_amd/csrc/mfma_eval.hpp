@@ -223,37 +223,41 @@ __device__ __forceinline__ float eval_tile(const EvalSmem &S, GetSlot get) {
         __builtin_amdgcn_sched_barrier(0);
       }
   } else if constexpr (P == kPBF16 || P == kPBF16X3) {
-    // K-step s' = 2T + hh takes registers 8hh..8hh+7 of M-tile T.
+    // K-step s' = 2T + hh takes registers 8hh..8hh+7 of M-tile T.  The B operands of step
+    // s'+1 are built before the products of step s' are issued, so that the wave's activation
+    // work sits between its matrix products instead of waiting behind them.
     const i32x4 *Ahi = (const i32x4 *)(S.w + (P == kPBF16 ? PackSize<kPBF16>::kL0 : PackSize<kPBF16X3>::kL0));
     const i32x4 *Alo = (const i32x4 *)(S.w + PackSize<kPBF16X3>::kL0 + PackSize<kPBF16>::kL1);
+    auto build = [&](int T, int hh, i32x4 &bh, i32x4 &bl) {
 #pragma unroll
-    for (int T = 0; T < kMT; ++T)
-#pragma unroll
-      for (int hh = 0; hh < 2; ++hh) {
-        i32x4 bh, bl;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float x0 = act(acc[T][8 * hh + 2 * q], 1.0f);
-          const float x1 = act(acc[T][8 * hh + 2 * q + 1], 1.0f);
-          const uint32_t w = pack_bf16x2(x0, x1);
-          bh[q] = (int)w;
-          if constexpr (P == kPBF16X3) bl[q] = (int)pack_bf16x2(x0 - bf16_lo_f32(w), x1 - bf16_hi_f32(w));
-        }
-        const bf16x8 Bh = __builtin_bit_cast(bf16x8, bh);
-        const int s = 2 * T + hh;
-#pragma unroll
-        for (int To = 0; To < kMT; ++To) {
-          const bf16x8 ah = __builtin_bit_cast(bf16x8, Ahi[(To * 8 + s) * 64 + lane]);
-          acc1[To] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, Bh, acc1[To], 0, 0, 0);
-          if constexpr (P == kPBF16X3) {
-            const bf16x8 Bl = __builtin_bit_cast(bf16x8, bl);
-            const bf16x8 al = __builtin_bit_cast(bf16x8, Alo[(To * 8 + s) * 64 + lane]);
-            acc1[To] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, Bl, acc1[To], 0, 0, 0);
-            acc1[To] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, Bh, acc1[To], 0, 0, 0);
-          }
-        }
-        __builtin_amdgcn_sched_barrier(0);
+      for (int q = 0; q < 4; ++q) {
+        const float x0 = act(acc[T][8 * hh + 2 * q], 1.0f);
+        const float x1 = act(acc[T][8 * hh + 2 * q + 1], 1.0f);
+        const uint32_t w = pack_bf16x2(x0, x1);
+        bh[q] = (int)w;
+        if constexpr (P == kPBF16X3) bl[q] = (int)pack_bf16x2(x0 - bf16_lo_f32(w), x1 - bf16_hi_f32(w));
       }
+    };
+    i32x4 bh[2], bl[2];
+    build(0, 0, bh[0], bl[0]);
+#pragma unroll
+    for (int s = 0; s < 2 * kMT; ++s) {
+      const int cur = s & 1;
+      if (s + 1 < 2 * kMT) build((s + 1) >> 1, (s + 1) & 1, bh[cur ^ 1], bl[cur ^ 1]);
+      const bf16x8 Bh = __builtin_bit_cast(bf16x8, bh[cur]);
+#pragma unroll
+      for (int To = 0; To < kMT; ++To) {
+        const bf16x8 ah = __builtin_bit_cast(bf16x8, Ahi[(To * 8 + s) * 64 + lane]);
+        acc1[To] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, Bh, acc1[To], 0, 0, 0);
+        if constexpr (P == kPBF16X3) {
+          const bf16x8 Bl = __builtin_bit_cast(bf16x8, bl[cur]);
+          const bf16x8 al = __builtin_bit_cast(bf16x8, Alo[(To * 8 + s) * 64 + lane]);
+          acc1[To] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, Bl, acc1[To], 0, 0, 0);
+          acc1[To] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, Bh, acc1[To], 0, 0, 0);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
   } else {
     // FP8: K-step s' takes M-tiles 2s' and 2s'+1 (16 registers each) of this lane group.
     const i32x8 *A = (const i32x8 *)(S.w + PackSize<kPFP8>::kL0);
