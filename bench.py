@@ -337,6 +337,11 @@ def measure_fcc(precisions=("bf16x3", "fp32", "bf16"), steps=2, warmup=1):
     if fp32:
         for r in out["precisions"].values():
             r["speedup_vs_fp32"] = r["attempts_per_s"] / fp32
+    # the paper's single-GPU MLPNet throughputs (its Table II, FP16 tensor cores, trained MLPNet
+    # on its own FCC system): context from other hardware, not a like-for-like target -- its
+    # network and zone execute about 6.8e6 flop per attempt against ~1.1e6 here
+    out["paper_context_attempts_per_s"] = {"smc_x_a100": 1.59e7, "smc_x_h100": 2.47e7,
+                                           "smc_ai_a100": 5.35e6, "smc_ai_h100": 7.54e6}
     return out
 
 
