@@ -119,8 +119,9 @@ def test_fcc_site_energies(prec, tol):
     mc.close()
 
 
-@pytest.mark.parametrize("prec,de_tol", [("fp32", 1e-5), ("bf16x3", 2e-4), ("fp64", None)])
+@pytest.mark.parametrize("prec,de_tol", [("fp32", 1e-5), ("bf16x3", 2.5e-5), ("fp64", None)])
 def test_fcc_mlpnet_sweeps_match_oracle(prec, de_tol):
+    # de_tol: the dE error of the sweep precision stays below a quarter of its default guard
     """Two replicas (one with ragged link cells), four sweeps each."""
     need_gpu()
     cells_list = [(8, 8, 8), (5, 6, 9)]

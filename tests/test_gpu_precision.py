@@ -71,8 +71,8 @@ def test_one_hot_sweeps_bit_exact(prec):
                                    de_tol=1e-5 if prec == "fp32" else 1e-4)
         d = otr["same"] == 0
         worst = max(worst, float(np.abs(tr["dE_fast"][d] - otr["dE"][d]).max()))
-    _banner(f"{prec}: max |dE_fast - dE_fp64| = {worst:.3e}, guard {'1e-5' if prec == 'fp32' else '2e-4'}")
-    assert worst < (4e-5 if prec == "bf16x3" else 2e-6)  # guard / 5
+    _banner(f"{prec}: max |dE_fast - dE_fp64| = {worst:.3e}, guard {'1e-5' if prec == 'fp32' else '1e-4'}")
+    assert worst < (2.5e-5 if prec == "bf16x3" else 2e-6)  # guard / 4 (bf16x3), guard / 5 (fp32)
     if prec == "fp64":
         # every different-species trial was decided by the FP64 evaluator
         flags = tr["flags"]
