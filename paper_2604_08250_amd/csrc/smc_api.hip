@@ -12,6 +12,7 @@
 #include "pack.hpp"
 #include "double_lattice.hpp"
 #include "fcc_host.hpp"
+#include "recheck.hpp"
 #include "sweep_mfma.hpp"
 #include "sweep_scalar.hpp"
 #include "tables.hpp"
