@@ -13,6 +13,7 @@
 #include "double_lattice.hpp"
 #include "fcc_host.hpp"
 #include "recheck.hpp"
+#include "site64.hpp"
 #include "sweep_mfma.hpp"
 #include "sweep_scalar.hpp"
 #include "tables.hpp"
@@ -51,6 +52,20 @@ int site_energies_scalar(smc_ctx *c, const T *W, T *out) {
   else if (counts) launch_site_energies<0, 128, T>(c, W, out);
   else if (c->hidden == 64) launch_site_energies<1, 64, T>(c, W, out);
   else launch_site_energies<1, 128, T>(c, W, out);
+  HIPC(c, hipGetLastError());
+  return SMC_OK;
+}
+
+// FP64 local energies of every site: the block kernel for the one-hot 128-hidden model (same
+// arithmetic order as the per-lane kernel), the per-lane kernel otherwise.
+int site_energies64(smc_ctx *c, double *out) {
+  if (!c->mfma) return site_energies_scalar<double>(c, c->d_w64, out);
+  for (size_t r = 0; r < c->reps.size(); ++r) {
+    const int64_t passes = (c->reps[r].n_sites + kS64Rows - 1) / kS64Rows;
+    const unsigned grid = (unsigned)std::min<int64_t>(passes, 2 * (int64_t)c->n_cu);
+    hipLaunchKernelGGL(k_site_energies64_onehot, dim3(grid), dim3(kS64Threads), 0, c->stream, c->d_reps,
+                       (int32_t)r, c->occ, c->d_w64t, out);
+  }
   HIPC(c, hipGetLastError());
   return SMC_OK;
 }
@@ -108,7 +123,7 @@ int ensure_site64(smc_ctx *c) {
 int scratch_totals(smc_ctx *c) {
   if (c->fcc.on) return fcc::scratch_totals(c);
   int rc = ensure_site64(c);
-  if (!rc) rc = site_energies_scalar<double>(c, c->d_w64, c->d_site64);
+  if (!rc) rc = site_energies64(c, c->d_site64);
   if (rc) return rc;
   for (size_t r = 0; r < c->reps.size(); ++r)
     hipLaunchKernelGGL(k_sum_into, dim3(1), dim3(256), 0, c->stream, c->d_site64 + c->reps[r].site0,
@@ -723,7 +738,7 @@ int smc_energy(smc_ctx *c, double *e_scratch, double *e_running) {
 int smc_site_energies(smc_ctx *c, int32_t precision, void *out_dev) {
   if (!c || !out_dev) return SMC_E_INVALID;
   if (c->fcc.on && precision == SMC_FP64) return fcc::site_energies64(c, (double *)out_dev);
-  if (precision == SMC_FP64) return site_energies_scalar<double>(c, c->d_w64, (double *)out_dev);
+  if (precision == SMC_FP64) return site_energies64(c, (double *)out_dev);
   if (precision < SMC_FP32 || precision > SMC_FP8_E4M3) return fail(c, SMC_E_INVALID, "precision");
   return site_energies_fast(c, precision, (float *)out_dev);
 }
