@@ -337,6 +337,31 @@ def measure_fcc(precisions=("bf16x3", "fp32", "bf16"), steps=2, warmup=1):
     if fp32:
         for r in out["precisions"].values():
             r["speedup_vs_fp32"] = r["attempts_per_s"] / fp32
+    # the qSRO model (Eq. 2) over FCC shells 1-3 on the same lattice, FP32 per-lane rows
+    mc = smc.SwapMC(w.cells, w.temperatures, occ0, synth.qsro_params(w.n_species), n_species=w.n_species,
+                    feature=smc.SMC_FEAT_QSRO_S123, hidden=0, precision="fp32", seed=w.seed, stream=stream,
+                    lattice="fcc")
+    if warmup:
+        mc.sweep(warmup)
+    mc.counters(reset=True)
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(steps):
+        mc.sweep(1)
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    cnt = mc.counters(reset=True)
+    assert int(cnt[0].sum()) == n_sites * steps
+    out["qsro_fp32"] = {"attempts_per_s": n_sites * steps / (ms / 1e3), "ms_per_sweep": ms / steps,
+                        "accept_ratio": int(cnt[2].sum()) / max(int(cnt[1].sum()), 1),
+                        "paper_context_attempts_per_s": {"smc_x_a100": 2.39e7, "smc_x_h100": 3.71e7,
+                                                         "smc_ai_a100": 1.11e7, "smc_ai_h100": 1.87e7}}
+    log(f"FCC qSRO fp32: {out['qsro_fp32']['attempts_per_s']:.3e} attempts/s, {ms / steps:.1f} ms per sweep")
+    mc.close()
+    del mc
+    torch.cuda.empty_cache()
     # the paper's single-GPU MLPNet throughputs (its Table II, FP16 tensor cores, trained MLPNet
     # on its own FCC system): context from other hardware, not a like-for-like target -- its
     # network and zone execute about 6.8e6 flop per attempt against ~1.1e6 here
