@@ -301,3 +301,45 @@ def test_fcc_full_size_sampled():
     now = mc.occ.cpu().numpy()
     assert np.array_equal(np.bincount(now, minlength=5), np.bincount(occ, minlength=5))
     mc.close()
+
+
+@pytest.mark.parametrize("case", ["T0", "Tinf", "one_species", "binary"])
+def test_fcc_degenerate_cases(case):
+    """T = 0 (only dE <= 0 accepted), T = +inf (every different-species swap accepted), a lattice
+    of one species (no trial is evaluated: the active list stays empty) and a binary alloy, each
+    against the oracle for three sweeps."""
+    need_gpu()
+    import paper_2604_08250_amd as smc
+    _banner(f"fcc degenerate {case}")
+    cells = (4, 5, 6)
+    T = {"T0": 0.0, "Tinf": float("inf")}.get(case, 900.0)
+    if case == "one_species":
+        occ = np.full(4 * int(np.prod(cells)), 2, dtype=np.uint8)
+        S = 3
+    elif case == "binary":
+        occ = synth.random_occupancy(cells, 2, [0.75, 0.25], seed=12, basis=4)
+        S = 2
+    else:
+        occ = synth.random_occupancy(cells, 5, synth.HEA_COMPOSITION, seed=13, basis=4)
+        S = 5
+    p = synth.mlpnet_params(H)
+    model = fcc.MLPNet(H, p)
+    mc = smc.SwapMC([cells], [T], occ, p, n_species=S, feature=smc.SMC_FEAT_MLPNET_S12, hidden=H, precision="fp32",
+                    seed=3, lattice="fcc")
+    ref = occ.copy()
+    for t in range(3):
+        tr = trace_to_numpy(mc.sweep(1, stats=True, trace=True))
+        st, _ = _compare_sweep(cells, model, ref, T, 3, 0, t, tr, mc.occ.cpu().numpy(), 1e-5)
+        assert int(tr["attempts"][0]) == occ.size
+        if case == "one_species":
+            assert int(tr["diff_species"][0]) == 0 and int(tr["accepts"][0]) == 0
+            assert np.all(tr["flags"] == 2)
+        if case == "Tinf":
+            assert int(tr["accepts"][0]) == int(tr["diff_species"][0])
+        if case == "T0":
+            acc = (tr["flags"] & 1).astype(bool)
+            assert np.all(tr["dE"][acc] <= 0.0)
+    es, er = mc.energy()
+    assert es[0] == pytest.approx(fcc.total_energy(cells, model, ref), abs=1e-8)
+    assert np.array_equal(np.bincount(mc.occ.cpu().numpy(), minlength=S), np.bincount(occ, minlength=S))
+    mc.close()
