@@ -317,6 +317,18 @@ def measure_fcc(precisions=("bf16x3", "fp32", "bf16"), steps=2, warmup=1):
         mc.profile(False)
         cnt1 = mc.counters(reset=True)
         rows = int(cnt1[1].sum()) * FCC_OMEGA
+        # dE error against the FP64 evaluator on trials of the next sweep's first colour
+        L = w.cells[0][0]
+        rng = np.random.default_rng(2)
+        g = rng.choice((L // 4) ** 3, size=2048, replace=False)
+        gx, gy, gz = 4 * (g % (L // 4)), 4 * ((g // (L // 4)) % (L // 4)), 4 * (g // (L // 4) ** 2)
+        sites = ((gz * L + gy) * L + gx) * 4  # basis 0 at link-cell offset (0,0,0): colour 0
+        _, dE64 = mc.delta_e64(sites)
+        tr = mc.sweep(1, stats=True, trace=True)
+        fast = tr["dE_fast"].cpu().numpy()[sites]
+        dsel = (tr["flags"].cpu().numpy()[sites] & 2) == 0
+        err = fast[dsel] - dE64[dsel]
+        mc.counters(reset=True)
         alg = rows * FCC_FLOP_PER_EVAL / (rows_ms / 1e3) / 1e12
         exe = rows * FCC_EXEC_FLOP_PER_EVAL[prec] / (rows_ms / 1e3) / 1e12
         es, er = mc.energy()
@@ -326,7 +338,9 @@ def measure_fcc(precisions=("bf16x3", "fp32", "bf16"), steps=2, warmup=1):
              "rows_kernel_share": rows_ms / max(rows_ms + recheck_ms, 1e-9),
              "rows_per_launch": rows / max(launches, 1), "algorithmic_tflops": alg, "executed_tflops": exe,
              "peak_tflops": PEAK_TFLOPS[prec], "roofline_frac": alg / PEAK_TFLOPS[prec],
-             "executed_frac": exe / PEAK_TFLOPS[prec], "running_minus_scratch_eV": float(er.sum() - es.sum())}
+             "executed_frac": exe / PEAK_TFLOPS[prec], "running_minus_scratch_eV": float(er.sum() - es.sum()),
+             "dE_err_max_eV": float(np.abs(err).max()), "dE_err_rms_eV": float(np.sqrt(np.mean(err ** 2))),
+             "dE_err_trials": int(dsel.sum())}
         out["precisions"][prec] = r
         log(f"FCC MLPNet {prec}: {r['attempts_per_s']:.3e} attempts/s, {r['ms_per_sweep']:.1f} ms per sweep, "
             f"rows kernel {r['rows_kernel_avg_us']:.1f} us, {alg:.1f} TFLOP/s")

@@ -158,8 +158,8 @@ int smc_site_energies(smc_ctx *ctx, int32_t precision, void *out_dev);
  * by the same FP64 evaluator that re-decides near-threshold trials (affected-zone energies
  * after minus before, Algorithm 1's two reductions over Omega).  Nothing is changed.
  * sites_host: n replica-local site indices; partner_host (nullable) and dE_host: host
- * outputs [n].  Equal species give 0.  Needs one-hot features and 128 hidden units
- * (else SMC_E_UNSUPPORTED).  Synchronises. */
+ * outputs [n].  Equal species give 0.  On BCC it needs one-hot features and 128 hidden
+ * units (else SMC_E_UNSUPPORTED); on FCC both models are supported.  Synchronises. */
 int smc_delta_e64(smc_ctx *ctx, int32_t replica, uint64_t sweep, const int64_t *sites_host, int32_t n,
                   int64_t *partner_host, double *dE_host);
 

@@ -371,6 +371,8 @@ struct Args {
   int32_t n_replicas;
   double *trace_dE, *trace_dE_fast;
   uint8_t *trace_flags;
+  double *probe_dE;        // non-null: the re-decision kernels write dE of queue entry q to
+                           // probe_dE[q] and change nothing
 };
 
 constexpr int kPhaseThreads = 256;  // threads of the propose and decide kernels
@@ -765,17 +767,22 @@ __global__ __launch_bounds__(kR64Threads) void k_recheck_net(Args a, const doubl
           e0 += __hip_atomic_load(re + kOmMlp + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         done[q] = 0;  // ready for the next use of this queue slot
         const double dE = e1 - e0;
-        const bool accept = dE <= tr.theta;
-        const int Rn = a.n_replicas;
-        if (accept) {
-          occ[i] = (uint8_t)sn;
-          occ[n] = (uint8_t)si;
-          atomicAdd(&a.e_fixed[a.r], (unsigned long long)to_fixed(dE));
-          atomicAdd((unsigned long long *)&a.counters[2 * Rn + a.r], 1ull);
+        bool accept = false;
+        if (a.probe_dE) {
+          a.probe_dE[q] = dE;
+        } else {
+          accept = dE <= tr.theta;
+          const int Rn = a.n_replicas;
+          if (accept) {
+            occ[i] = (uint8_t)sn;
+            occ[n] = (uint8_t)si;
+            atomicAdd(&a.e_fixed[a.r], (unsigned long long)to_fixed(dE));
+            atomicAdd((unsigned long long *)&a.counters[2 * Rn + a.r], 1ull);
+          }
+          atomicAdd((unsigned long long *)&a.counters[3 * Rn + a.r], 1ull);
+          if (a.trace_flags) a.trace_flags[R.site0 + i] = kFlagFp64 | (accept ? kFlagAccept : 0);
+          if (a.trace_dE) a.trace_dE[R.site0 + i] = dE;
         }
-        atomicAdd((unsigned long long *)&a.counters[3 * Rn + a.r], 1ull);
-        if (a.trace_flags) a.trace_flags[R.site0 + i] = kFlagFp64 | (accept ? kFlagAccept : 0);
-        if (a.trace_dE) a.trace_dE[R.site0 + i] = dE;
         s_accept = accept;
       }
       __syncthreads();
@@ -820,17 +827,22 @@ __global__ __launch_bounds__(kRcQsroThreads) void k_recheck_qsro(Args a, const d
       for (int k = 0; k < kOmQsro; ++k) e1 += s_out[k];
       for (int k = 0; k < kOmQsro; ++k) e0 += s_out[kOmQsro + k];
       const double dE = e1 - e0;
-      const bool accept = dE <= tr.theta;
-      const int Rn = a.n_replicas;
-      if (accept) {
-        occ[i] = (uint8_t)sn;
-        occ[n] = (uint8_t)si;
-        atomicAdd(&a.e_fixed[a.r], (unsigned long long)to_fixed(dE));
-        atomicAdd((unsigned long long *)&a.counters[2 * Rn + a.r], 1ull);
+      bool accept = false;
+      if (a.probe_dE) {
+        a.probe_dE[q] = dE;
+      } else {
+        accept = dE <= tr.theta;
+        const int Rn = a.n_replicas;
+        if (accept) {
+          occ[i] = (uint8_t)sn;
+          occ[n] = (uint8_t)si;
+          atomicAdd(&a.e_fixed[a.r], (unsigned long long)to_fixed(dE));
+          atomicAdd((unsigned long long *)&a.counters[2 * Rn + a.r], 1ull);
+        }
+        atomicAdd((unsigned long long *)&a.counters[3 * Rn + a.r], 1ull);
+        if (a.trace_flags) a.trace_flags[R.site0 + i] = kFlagFp64 | (accept ? kFlagAccept : 0);
+        if (a.trace_dE) a.trace_dE[R.site0 + i] = dE;
       }
-      atomicAdd((unsigned long long *)&a.counters[3 * Rn + a.r], 1ull);
-      if (a.trace_flags) a.trace_flags[R.site0 + i] = kFlagFp64 | (accept ? kFlagAccept : 0);
-      if (a.trace_dE) a.trace_dE[R.site0 + i] = dE;
       s_accept = accept;
     }
     __syncthreads();

@@ -331,6 +331,78 @@ inline int enqueue_sweep(smc_ctx *c, const smc_stats *st, bool trace) {
   return SMC_OK;
 }
 
+// FP64 dE of the swaps that the given trial sites propose at `sweep` (Philox as in a sweep), on
+// the current lattice, with the re-decision kernels in probe mode (nothing changes).
+inline int delta_e64(smc_ctx *c, int32_t replica, uint64_t sweep, const int64_t *sites, int32_t n,
+                     int64_t *partner_out, double *dE_out) {
+  FccState &f = c->fcc;
+  const Replica &R = c->reps[replica];
+  std::vector<Trial> tr(n);
+  std::vector<int32_t> act(n);
+  std::vector<QEntry> qe(n);
+  for (int32_t k = 0; k < n; ++k) {
+    if (sites[k] < 0 || sites[k] >= R.n_sites) return fail(c, SMC_E_INVALID, "site out of range");
+    const U64x4 x = philox4x64_10((uint64_t)sites[k], sweep, (uint64_t)replica, 0, c->cfg.seed, 0);
+    const int d = dir_of(x.v[0]);
+    const Pos p = pos(sites[k], R.L[0], R.L[1]);
+    const int64_t nb = at(p, dx(d), dy(d), dz(d), R.L[0], R.L[1], R.L[2]);
+    tr[k] = Trial{(int32_t)sites[k], (int32_t)nb, 0.0, d, 0, (int16_t)p.x, (int16_t)p.y, (int16_t)p.z, 0};
+    act[k] = k;
+    qe[k] = QEntry{k, 0.0f};
+    if (partner_out) partner_out[k] = nb;
+  }
+  Trial *d_tr = nullptr;
+  int32_t *d_act = nullptr;
+  QEntry *d_q = nullptr;
+  uint32_t *d_n = nullptr, *d_done = nullptr;
+  double *d_out = nullptr, *d_rowe = nullptr;
+  const uint32_t nn = (uint32_t)n;
+  int rc = SMC_OK;
+  if (hipMalloc(&d_tr, sizeof(Trial) * n) || hipMalloc(&d_act, sizeof(int32_t) * n) ||
+      hipMalloc(&d_q, sizeof(QEntry) * n) || hipMalloc(&d_n, sizeof(uint32_t)) ||
+      hipMalloc(&d_out, sizeof(double) * n) || hipMalloc(&d_rowe, sizeof(double) * 2 * kOmMlp * n) ||
+      hipMalloc(&d_done, sizeof(uint32_t) * n))
+    rc = fail(c, SMC_E_NOMEM, "probe buffers");
+  if (!rc && (hipMemcpyAsync(d_tr, tr.data(), sizeof(Trial) * n, hipMemcpyHostToDevice, c->stream) ||
+              hipMemcpyAsync(d_act, act.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream) ||
+              hipMemcpyAsync(d_q, qe.data(), sizeof(QEntry) * n, hipMemcpyHostToDevice, c->stream) ||
+              hipMemcpyAsync(d_n, &nn, sizeof(uint32_t), hipMemcpyHostToDevice, c->stream) ||
+              hipMemsetAsync(d_done, 0, sizeof(uint32_t) * n, c->stream)))
+    rc = fail(c, SMC_E_DEVICE, "probe upload");
+  if (!rc) {
+    Args a{};
+    a.reps = c->d_reps;
+    a.r = replica;
+    a.occ = c->occ;
+    a.ecache = c->ecache;
+    a.trials = d_tr;
+    a.active = d_act;
+    a.e1 = f.d_e1;
+    a.om = f.d_om;
+    a.om_n = f.om_n;
+    a.q_count = d_n;
+    a.queue = d_q;
+    a.e_fixed = c->d_efixed;
+    a.counters = c->d_counters;
+    a.n_replicas = (int32_t)c->reps.size();
+    a.probe_dE = d_out;
+    if (f.model == 0)
+      hipLaunchKernelGGL(k_recheck_net, dim3((unsigned)std::min<int64_t>((int64_t)n * kRcSplit, 4 * (int64_t)c->n_cu)),
+                         dim3(kR64Threads), 0, c->stream, a, (const double *)c->d_w64, d_rowe, d_done);
+    else
+      hipLaunchKernelGGL(k_recheck_qsro, dim3((unsigned)std::min<int64_t>(n, 2 * (int64_t)c->n_cu)),
+                         dim3(kRcQsroThreads), 0, c->stream, a, (const double *)c->d_w64);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(dE_out, d_out, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream) ||
+        hipStreamSynchronize(c->stream))
+      rc = fail(c, SMC_E_DEVICE, "probe kernel");
+  }
+  void *bufs[] = {d_tr, d_act, d_q, d_n, d_out, d_rowe, d_done};
+  for (void *p : bufs)
+    if (p) (void)hipFree(p);
+  return rc;
+}
+
 inline void release(smc_ctx *c) {
   FccState &f = c->fcc;
   void *bufs[] = {f.d_om,     f.d_trials, f.d_active,  f.d_e1,      f.d_queue,  f.d_counts,

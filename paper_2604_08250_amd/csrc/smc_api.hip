@@ -746,8 +746,9 @@ int smc_site_energies(smc_ctx *c, int32_t precision, void *out_dev) {
 int smc_delta_e64(smc_ctx *c, int32_t replica, uint64_t sweep, const int64_t *sites, int32_t n,
                   int64_t *partner_out, double *dE_out) {
   if (!c || !sites || n < 0 || replica < 0 || replica >= (int32_t)c->reps.size()) return SMC_E_INVALID;
-  if (!c->mfma) return fail(c, SMC_E_UNSUPPORTED, "FP64 probe needs one-hot features and 128 hidden");
   if (n == 0) return SMC_OK;
+  if (c->fcc.on) return fcc::delta_e64(c, replica, sweep, sites, n, partner_out, dE_out);
+  if (!c->mfma) return fail(c, SMC_E_UNSUPPORTED, "FP64 probe needs one-hot features and 128 hidden");
   const Replica &R = c->reps[replica];
   std::vector<RecheckEntry> h(n);
   for (int32_t k = 0; k < n; ++k) {

@@ -343,3 +343,26 @@ def test_fcc_degenerate_cases(case):
     assert es[0] == pytest.approx(fcc.total_energy(cells, model, ref), abs=1e-8)
     assert np.array_equal(np.bincount(mc.occ.cpu().numpy(), minlength=S), np.bincount(occ, minlength=S))
     mc.close()
+
+
+@pytest.mark.parametrize("kind", ["mlpnet", "qsro"])
+def test_fcc_fp64_probe_matches_oracle(kind):
+    """smc_delta_e64 on FCC: the partner of each trial site's proposal and the FP64 dE of that
+    swap on the current lattice, against the oracle's proposal and dE; nothing changes."""
+    need_gpu()
+    _banner(f"fcc fp64 probe {kind}")
+    cells = (5, 6, 9)
+    mc, model, occ = _make([cells], [900.0], model=kind)
+    mc.sweep(2)
+    now = mc.occ.cpu().numpy().copy()
+    ec = mc.ecache.cpu().numpy().copy()
+    rng = np.random.default_rng(8)
+    sites = rng.choice(now.size, size=200, replace=False)
+    partners, d64 = mc.delta_e64(sites, sweep=5)
+    for s, p, d in zip(sites, partners, d64):
+        dir_, _ = fcc.propose(7, int(s), 5, 0)
+        assert p == fcc.neighbor(cells, int(s), dir_)
+        want = 0.0 if now[s] == now[p] else fcc.delta_e(cells, model, now, int(s), int(p))
+        assert d == pytest.approx(want, abs=1e-10)
+    assert np.array_equal(mc.occ.cpu().numpy(), now) and np.array_equal(mc.ecache.cpu().numpy(), ec)
+    mc.close()
