@@ -366,3 +366,33 @@ def test_fcc_fp64_probe_matches_oracle(kind):
         assert d == pytest.approx(want, abs=1e-10)
     assert np.array_equal(mc.occ.cpu().numpy(), now) and np.array_equal(mc.ecache.cpu().numpy(), ec)
     mc.close()
+
+
+def test_fcc_set_params_and_resume():
+    """New weights through smc_set_params (the captured sweep holds the output bias, so it must be
+    rebuilt) give the oracle's energies and sweeps; a fresh context resumed at the same sweep
+    index from the same lattice continues the same chain."""
+    need_gpu()
+    import paper_2604_08250_amd as smc
+    _banner("fcc set_params and resume")
+    cells = (6, 5, 4)
+    a, model, occ = _make([cells], [900.0], precision="fp32")
+    a.use_graph(True)
+    a.sweep(2)
+    p2 = synth.mlpnet_params(H, seed=21)
+    a.set_params(p2)
+    m2 = fcc.MLPNet(H, p2)
+    now = a.occ.cpu().numpy().copy()
+    np.testing.assert_allclose(a.site_energies("fp64").cpu().numpy(), fcc.all_site_energies(cells, m2, now),
+                               rtol=1e-12, atol=1e-12)
+    b = smc.SwapMC([cells], [900.0], now, p2, n_species=5, feature=smc.SMC_FEAT_MLPNET_S12, hidden=H,
+                   precision="fp32", seed=7, lattice="fcc")
+    b.sweep_index = a.sweep_index
+    ref = now.copy()
+    for t in range(2):
+        a.sweep(1)
+        tr = trace_to_numpy(b.sweep(1, stats=True, trace=True))
+        _compare_sweep(cells, m2, ref, 900.0, 7, 0, 2 + t, tr, b.occ.cpu().numpy(), 1e-5)
+        assert np.array_equal(a.occ.cpu().numpy(), b.occ.cpu().numpy())
+    a.close()
+    b.close()
