@@ -213,8 +213,10 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
     }
   };
 
-  // gather loads of one group into registers (the loads stay in flight until used)
-  uint8_t pf_reg[kPfReg];
+  // gather loads of one group into registers (the loads stay in flight until used); the
+  // region bytes are packed four to a register
+  constexpr int kPfReg4 = (kPfReg + 3) / 4;
+  uint32_t pf_reg[kPfReg4];
   float pf_om[kPfOm];
   auto gather_issue = [&](const TrialBuf<GROUP> &tb) {
     const int nact = tb.nact;
@@ -222,13 +224,16 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
     const uint8_t *occ = a.occ + R.site0;
     const float *ec = a.ecache + R.site0;
 #pragma unroll
+    for (int j4 = 0; j4 < kPfReg4; ++j4) pf_reg[j4] = 0u;
+#pragma unroll
     for (int j = 0; j < kPfReg; ++j) {
       const int q = tid + j * kMfmaThreads;
       if (q < nact * kReg) {
         const int t = q / kReg, p = q - t * kReg;
         int dx, dy, dz;
         unpack_off(s_roff[tb.dir[t] * kReg + p], dx, dy, dz);
-        pf_reg[j] = occ[site_at(Pos{tb.px[t], tb.py[t], tb.pz[t]}, dx, dy, dz, R.L[0], R.L[1], R.L[2])];
+        pf_reg[j >> 2] |= (uint32_t)occ[site_at(Pos{tb.px[t], tb.py[t], tb.pz[t]}, dx, dy, dz, R.L[0], R.L[1], R.L[2])]
+                          << (8 * (j & 3));
       }
     }
 #pragma unroll
@@ -250,7 +255,7 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
       if (q < nact * kReg) {
         const int t = q / kReg, p = q - t * kReg;
         const int d = tb.dir[t];
-        uint8_t v = pf_reg[j];
+        uint8_t v = (uint8_t)(pf_reg[j >> 2] >> (8 * (j & 3)));
         if (p == s_rpos[2 * d]) v = tb.sn[t];
         if (p == s_rpos[2 * d + 1]) v = tb.si[t];
         s_reg[q] = v;
