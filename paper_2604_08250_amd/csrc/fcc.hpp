@@ -58,24 +58,27 @@ __host__ __device__ constexpr int8_t dz(int k) {
 }
 __host__ __device__ constexpr int shell_of(int k) { return k < 12 ? 1 : (k < 18 ? 2 : 3); }
 
-__host__ __device__ inline Pos pos(int64_t s, int32_t lx, int32_t ly) {
-  const int32_t b = (int32_t)(s & 3);
-  const int64_t c = s >> 2;
-  const int32_t x = (int32_t)(c % lx);
-  const int64_t r = c / lx;
-  const int32_t y = (int32_t)(r % ly);
-  const int32_t z = (int32_t)(r / ly);
+// Replica-local site indices stay below 2^31 (checked when a context is made), so positions
+// and indices use 32-bit arithmetic.
+__host__ __device__ inline Pos pos(int64_t s64, int32_t lx, int32_t ly) {
+  const uint32_t s = (uint32_t)s64;
+  const int32_t b = (int32_t)(s & 3u);
+  const uint32_t c = s >> 2;
+  const int32_t x = (int32_t)(c % (uint32_t)lx);
+  const uint32_t r = c / (uint32_t)lx;
+  const int32_t y = (int32_t)(r % (uint32_t)ly);
+  const int32_t z = (int32_t)(r / (uint32_t)ly);
   // basis offsets (0,0,0), (0,1,1), (1,0,1), (1,1,0): x parity is bit 1 of b, y parity bit 0
   const int32_t bx = b >> 1, by = b & 1, bz = bx ^ by;
   return Pos{2 * x + bx, 2 * y + by, 2 * z + bz};
 }
 
-__host__ __device__ inline int64_t index(Pos p, int32_t lx, int32_t ly) {
+__host__ __device__ inline int32_t index(Pos p, int32_t lx, int32_t ly) {
   const int32_t b = ((p.x & 1) << 1) | (p.y & 1);
-  return (((int64_t)(p.z >> 1) * ly + (p.y >> 1)) * lx + (p.x >> 1)) * 4 + b;
+  return (((p.z >> 1) * ly + (p.y >> 1)) * lx + (p.x >> 1)) * 4 + b;
 }
 
-__host__ __device__ inline int64_t at(Pos p, int ddx, int ddy, int ddz, int32_t lx, int32_t ly, int32_t lz) {
+__host__ __device__ inline int32_t at(Pos p, int ddx, int ddy, int ddz, int32_t lx, int32_t ly, int32_t lz) {
   Pos q{wrap1(p.x + ddx, 2 * lx), wrap1(p.y + ddy, 2 * ly), wrap1(p.z + ddz, 2 * lz)};
   return index(q, lx, ly);
 }
@@ -132,7 +135,9 @@ struct NetSmem {
   float b3;
 };
 
-__device__ __forceinline__ float relu(float x) { return fmaxf(x, 0.0f); }
+// max(x, 0) as one median-of-three instruction (fmaxf also quiets signalling NaNs first, which
+// costs a second instruction); activations are finite.
+__device__ __forceinline__ float relu(float x) { return __builtin_amdgcn_fmed3f(x, 0.0f, 3.402823466e38f); }
 
 // One hidden layer: acc_out = c + W . relu(acc_in), weights at A (hi, and lo for split BF16).
 template <int P>
@@ -207,11 +212,66 @@ __device__ __forceinline__ void net_hidden(const uint8_t *A0, const float *c, co
   }
 }
 
-// Energy of the site held by this lane (lane % 32) of a 32-site tile; get(m) returns the
-// species of slot m (0 = the site, 1 + k = neighbour k, k < 18).  Both lane groups return
-// the same value.
-template <int P, typename GetSlot>
-__device__ __forceinline__ float eval_net(const NetSmem &S, GetSlot get) {
+// Slots a lane gathers for layer 0: all 20 for FP32 (both lane groups build the same B
+// operand), 10 for BF16 (lane group g takes slots 4s + 2g and 4s + 2g + 1 of K-step s).
+// Slot 0 is the site, 1 + k neighbour k (k < 18) and slot 19 the constant-one input.
+template <int P>
+constexpr int kGath = P == kP32 ? 20 : 10;
+template <int P>
+__device__ __forceinline__ int gath_slot(int q, int g) {
+  return P == kP32 ? q : 4 * (q >> 1) + 2 * g + (q & 1);
+}
+
+// Index offsets of slots 0..19 from a site of basis b, valid for every site whose doubled
+// coordinates lie two or more steps inside each face (no wrap): off[20 b + m].  Slot 19 has
+// offset 0.  Index arithmetic is linear in the cell coordinates, so one interior site per
+// basis gives the table.
+__device__ inline void fill_offsets(int32_t *s_off, const Replica &R) {
+  for (int v = threadIdx.x; v < 80; v += blockDim.x) {
+    const int b = v / 20, m = v - 20 * (v / 20);
+    const int bx = b >> 1, by = b & 1;
+    const Pos p{4 + bx, 4 + by, 4 + (bx ^ by)};
+    int32_t o = 0;
+    if (m >= 1 && m < kSlots)
+      o = index(Pos{p.x + dx(m - 1), p.y + dy(m - 1), p.z + dz(m - 1)}, R.L[0], R.L[1]) - index(p, R.L[0], R.L[1]);
+    s_off[v] = o;
+  }
+}
+
+// Species of this lane's gathered slots of the site at p; load(s) returns the species at
+// replica-local index s.  When every lane of the wave holds an interior site the indices come
+// from the offset table, otherwise each one is wrapped per axis.
+template <int P, typename Load>
+__device__ __forceinline__ void gather_slots(Pos p, const Replica &R, const int32_t *s_off, Load load,
+                                             uint32_t (&sp)[kGath<P>]) {
+  const int g = (threadIdx.x >> 5) & 1;
+  const int32_t lx = R.L[0], ly = R.L[1], lz = R.L[2];
+  const bool inner = (uint32_t)(p.x - 2) <= (uint32_t)(2 * lx - 5) && (uint32_t)(p.y - 2) <= (uint32_t)(2 * ly - 5) &&
+                     (uint32_t)(p.z - 2) <= (uint32_t)(2 * lz - 5);
+  const int32_t base = index(p, lx, ly);
+  if (__all(inner)) {
+    const int32_t *o = s_off + 20 * (((p.x & 1) << 1) | (p.y & 1));
+#pragma unroll
+    for (int q = 0; q < kGath<P>; ++q) {
+      const int m = gath_slot<P>(q, g);
+      const uint32_t v = load(base + o[m]);
+      sp[q] = m < kSlots ? v : 0u;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < kGath<P>; ++q) {
+      const int m = gath_slot<P>(q, g);
+      const int k = m > 0 ? m - 1 : 0;
+      const uint32_t v = load(m == 0 ? base : at(p, dx(k), dy(k), dz(k), lx, ly, lz));
+      sp[q] = m < kSlots ? v : 0u;
+    }
+  }
+}
+
+// Energy of the site held by this lane (lane % 32) of a 32-site tile from the species of its
+// gathered slots.  Both lane groups return the same value.
+template <int P>
+__device__ __forceinline__ float eval_net(const NetSmem &S, const uint32_t (&sp)[kGath<P>]) {
   const int lane = threadIdx.x & 63;
   const int g = lane >> 5;
   f32x16 acc[kMT];
@@ -224,7 +284,7 @@ __device__ __forceinline__ float eval_net(const NetSmem &S, GetSlot get) {
     const f32x4 *A = (const f32x4 *)S.w;
 #pragma unroll
     for (int m = 0; m < 20; ++m) {
-      const uint32_t p = m < kSlots ? (uint32_t)get(m) : 0u;  // slot 19: the constant one
+      const uint32_t p = sp[m];
       const float b0 = (p == (uint32_t)g) ? 1.0f : 0.0f;
       const float b1 = (p == (uint32_t)(2 + g)) ? 1.0f : 0.0f;
 #pragma unroll
@@ -242,9 +302,7 @@ __device__ __forceinline__ float eval_net(const NetSmem &S, GetSlot get) {
     const i32x4 *Alo = (const i32x4 *)(S.w + NetSize<kPBF16>::kL0);
 #pragma unroll
     for (int s = 0; s < 5; ++s) {
-      const int m0 = 4 * s + 2 * g;
-      const uint32_t p0 = m0 < kSlots ? (uint32_t)get(m0) : 0u;
-      const uint32_t p1 = m0 + 1 < kSlots ? (uint32_t)get(m0 + 1) : 0u;  // slot 19: the constant one
+      const uint32_t p0 = sp[2 * s], p1 = sp[2 * s + 1];
       i32x4 bw;
       uint32_t l0, h0, l1, h1;
       onehot_bf16(p0, l0, h0);
@@ -453,7 +511,7 @@ __global__ __launch_bounds__(kPhaseThreads) void k_propose(Args a) {
 }
 
 // Species of site s of a replica as seen with sites i and n exchanged.
-__device__ __forceinline__ uint32_t swapped(const uint8_t *occ, int64_t s, int64_t i, int64_t n, uint32_t si,
+__device__ __forceinline__ uint32_t swapped(const uint8_t *occ, int32_t s, int32_t i, int32_t n, uint32_t si,
                                             uint32_t sn) {
   return s == i ? sn : (s == n ? si : (uint32_t)occ[s]);
 }
@@ -472,11 +530,13 @@ __global__ __launch_bounds__(net_threads<P>()) void k_rows_net(Args a, const uin
   constexpr int kW = net_bytes<P>();
   constexpr int kThreads = net_threads<P>();
   __shared__ __attribute__((aligned(16))) uint8_t s_w[kW];
+  __shared__ int32_t s_off[80];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const Replica R = a.reps[a.r];
   for (int q = tid; q < kW / 16; q += kThreads) ((int4 *)s_w)[q] = ((const int4 *)wpack)[q];
+  fill_offsets(s_off, R);
   __syncthreads();
   const NetSmem S = net_smem<P>(s_w, b3);
-  const Replica R = a.reps[a.r];
   const uint8_t *occ = a.occ + R.site0;
   const int32_t rows = (int32_t)(*a.n_active) * kOmMlp;  // below 2^31: trials x 28 of one colour
   const int32_t tiles = (rows + 31) / 32;
@@ -490,11 +550,9 @@ __global__ __launch_bounds__(net_threads<P>()) void k_rows_net(Args a, const uin
     const int64_t i = tr.site, n = tr.partner;
     const uint32_t si = occ[i], sn = occ[n];
     const Pos pj = zone_pos(trial_pos(tr), a.om + (tr.dir * kOmMax + k) * 3, R);
-    const float E = eval_net<P>(S, [&](int m) -> uint32_t {
-      const int64_t s = m == 0 ? index(pj, R.L[0], R.L[1])
-                               : at(pj, dx(m - 1), dy(m - 1), dz(m - 1), R.L[0], R.L[1], R.L[2]);
-      return swapped(occ, s, i, n, si, sn);
-    });
+    uint32_t sp[kGath<P>];
+    gather_slots<P>(pj, R, s_off, [&](int32_t s) { return swapped(occ, s, (int32_t)i, (int32_t)n, si, sn); }, sp);
+    const float E = eval_net<P>(S, sp);
     if (valid && lane < 32) a.e1[row] = E;
   }
 }
@@ -514,8 +572,8 @@ __global__ __launch_bounds__(256) void k_rows_qsro(Args a, const float *F) {
     const Pos pj = zone_pos(trial_pos(tr), a.om + (tr.dir * kOmMax + k) * 3, R);
     a.e1[row] = qsro_site<float>(
         [&](int k2) -> int {
-          const int64_t s = k2 < 0 ? index(pj, R.L[0], R.L[1]) : at(pj, dx(k2), dy(k2), dz(k2), R.L[0], R.L[1], R.L[2]);
-          return (int)swapped(occ, s, i, n, si, sn);
+          const int32_t s = k2 < 0 ? index(pj, R.L[0], R.L[1]) : at(pj, dx(k2), dy(k2), dz(k2), R.L[0], R.L[1], R.L[2]);
+          return (int)swapped(occ, s, (int32_t)i, (int32_t)n, si, sn);
         },
         F);
   }
@@ -681,11 +739,13 @@ __global__ __launch_bounds__(kNetThreads) void k_site_energies_net(const Replica
                                                                    float b3, float *out) {
   constexpr int kW = net_bytes<P>();
   __shared__ __attribute__((aligned(16))) uint8_t s_w[kW];
+  __shared__ int32_t s_off[80];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const Replica R = reps[r];
   for (int q = tid; q < kW / 16; q += kNetThreads) ((int4 *)s_w)[q] = ((const int4 *)wpack)[q];
+  fill_offsets(s_off, R);
   __syncthreads();
   const NetSmem S = net_smem<P>(s_w, b3);
-  const Replica R = reps[r];
   const uint8_t *occ = occ_all + R.site0;
   const int64_t tiles = (R.n_sites + 31) / 32;
   constexpr int kWaves = kNetThreads / 64;
@@ -693,10 +753,9 @@ __global__ __launch_bounds__(kNetThreads) void k_site_energies_net(const Replica
     const int64_t j = tile * 32 + (lane & 31);
     const bool valid = j < R.n_sites;
     const Pos p = pos(valid ? j : 0, R.L[0], R.L[1]);
-    const float E = eval_net<P>(S, [&](int m) -> uint32_t {
-      if (m == 0) return occ[valid ? j : 0];
-      return occ[at(p, dx(m - 1), dy(m - 1), dz(m - 1), R.L[0], R.L[1], R.L[2])];
-    });
+    uint32_t sp[kGath<P>];
+    gather_slots<P>(p, R, s_off, [&](int32_t s) { return (uint32_t)occ[s]; }, sp);
+    const float E = eval_net<P>(S, sp);
     if (valid && lane < 32) out[R.site0 + j] = E;
   }
 }
@@ -747,8 +806,8 @@ __global__ __launch_bounds__(kR64Threads) void k_recheck_net(Args a, const doubl
       const bool post = row < kOmMlp;
       const int k = post ? row : row - kOmMlp;
       const Pos pj = zone_pos(pi, o + 3 * k, R);
-      const int64_t s = m == 0 ? index(pj, R.L[0], R.L[1]) : at(pj, dx(m - 1), dy(m - 1), dz(m - 1), R.L[0], R.L[1], R.L[2]);
-      s_sp[v] = (uint8_t)(post ? swapped(occ, s, i, n, si, sn) : (uint32_t)occ[s]);
+      const int32_t s = m == 0 ? index(pj, R.L[0], R.L[1]) : at(pj, dx(m - 1), dy(m - 1), dz(m - 1), R.L[0], R.L[1], R.L[2]);
+      s_sp[v] = (uint8_t)(post ? swapped(occ, s, (int32_t)i, (int32_t)n, si, sn) : (uint32_t)occ[s]);
     }
     __syncthreads();
     net64_rows<kRcRows / kR64Parts>(W, s_sp, kRcRows, s_h, s_out);
@@ -816,8 +875,8 @@ __global__ __launch_bounds__(kRcQsroThreads) void k_recheck_qsro(Args a, const d
       const Pos pj = zone_pos(pi, o + 3 * k, R);
       s_out[tid] = qsro_site<double>(
           [&](int k2) -> int {
-            const int64_t s = k2 < 0 ? index(pj, R.L[0], R.L[1]) : at(pj, dx(k2), dy(k2), dz(k2), R.L[0], R.L[1], R.L[2]);
-            return (int)(post ? swapped(occ, s, i, n, si, sn) : (uint32_t)occ[s]);
+            const int32_t s = k2 < 0 ? index(pj, R.L[0], R.L[1]) : at(pj, dx(k2), dy(k2), dz(k2), R.L[0], R.L[1], R.L[2]);
+            return (int)(post ? swapped(occ, s, (int32_t)i, (int32_t)n, si, sn) : (uint32_t)occ[s]);
           },
           W);
     }
