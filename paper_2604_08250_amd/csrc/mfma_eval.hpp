@@ -99,11 +99,143 @@ struct EvalSmem {
   float sh;                                // FP8 activation scale 2^kh
 };
 
+// Scheduling hint for one region: kM matrix products, each preceded by up to kD/kM LDS
+// reads and followed by up to kV/kM vector ALU instructions, so that one wave's activation
+// work issues while its own products run.
+template <int kM, int kV, int kD>
+__device__ __forceinline__ void interleave() {
+  constexpr int v = (kV + kM - 1) / kM, d = (kD + kM - 1) / kM;
+  __builtin_amdgcn_sched_group_barrier(0x100, d, 0);
+#pragma unroll
+  for (int i = 0; i < kM; ++i) {
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(0x402, v, 0);
+    __builtin_amdgcn_sched_group_barrier(0x100, d, 0);
+  }
+}
+
+// BF16 evaluation, software-pipelined over the four M-tiles of hidden units: while half of
+// the activations of layer-0 tile T are turned into the B operands of one layer-1 K-step
+// (vector ALU), the wave issues half of the layer-0 products of tile T+1 and the layer-1
+// products of the previous K-step (matrix cores); the last-layer activation of output tile
+// To - 1 runs while the final layer-1 products of tile To are in flight.  Each accumulator receives its products
+// in the same order as in the layer-by-layer evaluation, so the result is identical.  (Split
+// BF16 keeps the layer-by-layer order: the pipeline's extra live registers spill in the colour
+// kernel and cost more than the overlap gains.)
+template <typename GetSlot>
+__device__ __forceinline__ float eval_tile_bf16_pipe(const EvalSmem &S, GetSlot get) {
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 5;
+  const i32x4 *A0h = (const i32x4 *)S.w;
+  const i32x4 *A1h = (const i32x4 *)(S.w + PackSize<kPBF16>::kL0);
+
+  // layer-0 B operands: K-step s covers features 16s..16s+15; lane group g supplies slots
+  // 4s+2g and 4s+2g+1 (slot 27: the constant-one bias input)
+  bf16x8 b0[7];
+#pragma unroll
+  for (int s = 0; s < 7; ++s) {
+    const int m0 = 4 * s + 2 * g;
+    const uint32_t p0 = (uint32_t)get(m0);
+    const uint32_t p1 = (m0 + 1 < 27) ? (uint32_t)get(m0 + 1) : 0u;
+    i32x4 bw;
+    uint32_t l0, h0, l1, h1;
+    onehot_bf16(p0, l0, h0);
+    onehot_bf16(p1, l1, h1);
+    bw[0] = (int)l0; bw[1] = (int)h0; bw[2] = (int)l1; bw[3] = (int)h1;
+    b0[s] = __builtin_bit_cast(bf16x8, bw);
+  }
+  // layer-0 products of tile T over K-steps s0 <= s < s1
+  auto layer0 = [&](int T, int s0, int s1, f32x16 &a) {
+#pragma unroll
+    for (int s = s0; s < s1; ++s)
+      a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, A0h[(T * 7 + s) * 64 + lane]), b0[s], a,
+                                                  0, 0, 0);
+  };
+  // layer-1 B operands of K-step 2T + hh: registers 8hh..8hh+7 of layer-0 tile T
+  auto build = [&](const f32x16 &a, int hh, i32x4 &bh) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) bh[q] = (int)pack_bf16x2(act(a[8 * hh + 2 * q], 1.0f), act(a[8 * hh + 2 * q + 1], 1.0f));
+  };
+  f32x16 acc1[kMT];
+#pragma unroll
+  for (int T = 0; T < kMT; ++T)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const f32x4 b = *(const f32x4 *)(S.c1 + 32 * T + 8 * j + 4 * g);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc1[T][4 * j + i] = b[i];
+    }
+  // layer-1 K-step s into every output tile
+  auto layer1 = [&](int s, const i32x4 &bh) {
+    const bf16x8 Bh = __builtin_bit_cast(bf16x8, bh);
+#pragma unroll
+    for (int To = 0; To < kMT; ++To)
+      acc1[To] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, A1h[(To * 8 + s) * 64 + lane]), Bh,
+                                                         acc1[To], 0, 0, 0);
+  };
+  constexpr int kL0H = 4;      // layer-0 products in the first half of a tile
+  constexpr int kL1M = 4;      // products (and weight reads) of one layer-1 K-step
+  constexpr int kBuildV = 36;  // vector ALU of one build
+
+  // region k = 2T + hh builds the B operands of layer-1 K-step k, issues half of the layer-0
+  // products of tile T+1 and the layer-1 products of K-step k-1
+  f32x16 a0[2];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) a0[0][v] = 0.0f;
+  layer0(0, 0, 7, a0[0]);
+  __builtin_amdgcn_sched_barrier(0);
+  i32x4 bh[2];
+#pragma unroll
+  for (int k = 0; k < 2 * kMT; ++k) {
+    const int T = k >> 1, hh = k & 1;
+    build(a0[T & 1], hh, bh[k & 1]);
+    if (T + 1 < kMT) {
+      if (hh == 0) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) a0[(T + 1) & 1][v] = 0.0f;
+      }
+      layer0(T + 1, hh ? 4 : 0, hh ? 7 : 4, a0[(T + 1) & 1]);
+    }
+    if (k >= 1) layer1(k - 1, bh[(k - 1) & 1]);
+    if (k == 0) interleave<kL0H, kBuildV, kL0H>();
+    else if (T + 1 < kMT) interleave<kL0H + kL1M, kBuildV, kL0H + kL1M>();
+    else interleave<kL1M, kBuildV, kL1M>();
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  // last layer-1 K-step one output tile at a time; activation and output dot product of
+  // tile To - 1 alongside
+  const bf16x8 Bh7 = __builtin_bit_cast(bf16x8, bh[1]);
+  float part = 0.0f;
+  auto out_dot = [&](int T) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const f32x4 w = *(const f32x4 *)(S.w2 + 32 * T + 8 * j + 4 * g);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) part = fmaf(w[i], act(acc1[T][4 * j + i], 1.0f), part);
+    }
+  };
+#pragma unroll
+  for (int To = 0; To < kMT; ++To) {
+    acc1[To] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, A1h[(To * 8 + 7) * 64 + lane]), Bh7,
+                                                       acc1[To], 0, 0, 0);
+    if (To >= 1) {
+      out_dot(To - 1);
+      interleave<1, 16 * 5, 1>();
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  out_dot(kMT - 1);
+  const float other = __shfl_xor(part, 32);
+  const float p0 = g == 0 ? part : other, p1 = g == 0 ? other : part;
+  return S.b2 + (p0 + p1);
+}
+
 // Energy of the site held by this lane (lane % 32) of a 32-site tile.  get(m) returns the
 // species of feature slot m (0 = centre, 1 + k = neighbour k) of the lane's site; only the
 // slots the lane's operands need are requested.  Both lane groups return the same value.
 template <int P, typename GetSlot>
 __device__ __forceinline__ float eval_tile(const EvalSmem &S, GetSlot get) {
+  if constexpr (P == kPBF16) return eval_tile_bf16_pipe(S, get);
   const int lane = threadIdx.x & 63;
   const int g = lane >> 5;
   f32x16 acc[kMT];
@@ -245,16 +377,22 @@ __device__ __forceinline__ float eval_tile(const EvalSmem &S, GetSlot get) {
       const int cur = s & 1;
       if (s + 1 < 2 * kMT) build((s + 1) >> 1, (s + 1) & 1, bh[cur ^ 1], bl[cur ^ 1]);
       const bf16x8 Bh = __builtin_bit_cast(bf16x8, bh[cur]);
+      bf16x8 ah[kMT];
 #pragma unroll
       for (int To = 0; To < kMT; ++To) {
-        const bf16x8 ah = __builtin_bit_cast(bf16x8, Ahi[(To * 8 + s) * 64 + lane]);
-        acc1[To] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, Bh, acc1[To], 0, 0, 0);
-        if constexpr (P == kPBF16X3) {
-          const bf16x8 Bl = __builtin_bit_cast(bf16x8, bl[cur]);
+        ah[To] = __builtin_bit_cast(bf16x8, Ahi[(To * 8 + s) * 64 + lane]);
+        acc1[To] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[To], Bh, acc1[To], 0, 0, 0);
+      }
+      if constexpr (P == kPBF16X3) {
+        const bf16x8 Bl = __builtin_bit_cast(bf16x8, bl[cur]);
+#pragma unroll
+        for (int To = 0; To < kMT; ++To) {
           const bf16x8 al = __builtin_bit_cast(bf16x8, Alo[(To * 8 + s) * 64 + lane]);
-          acc1[To] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, Bl, acc1[To], 0, 0, 0);
           acc1[To] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, Bh, acc1[To], 0, 0, 0);
         }
+#pragma unroll
+        for (int To = 0; To < kMT; ++To)
+          acc1[To] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[To], Bl, acc1[To], 0, 0, 0);
       }
       __builtin_amdgcn_sched_barrier(0);
     }
