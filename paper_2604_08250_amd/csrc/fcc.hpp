@@ -222,20 +222,27 @@ __device__ __forceinline__ int gath_slot(int q, int g) {
   return P == kP32 ? q : 4 * (q >> 1) + 2 * g + (q & 1);
 }
 
-// Index offsets of slots 0..19 from a site of basis b, valid for every site whose doubled
-// coordinates lie two or more steps inside each face (no wrap): off[20 b + m].  Slot 19 has
-// offset 0.  Index arithmetic is linear in the cell coordinates, so one interior site per
-// basis gives the table.
+// Index offsets of slot m (0: the site, 1 + k: neighbour k, k < kUsed; further slots 0) from
+// a site of basis b, valid for every site whose doubled coordinates lie two or more steps
+// inside each face (no wrap): off[kStride b + m].  Index arithmetic is linear in the cell
+// coordinates, so one interior site per basis gives the table.
+template <int kStride, int kUsed>
 __device__ inline void fill_offsets(int32_t *s_off, const Replica &R) {
-  for (int v = threadIdx.x; v < 80; v += blockDim.x) {
-    const int b = v / 20, m = v - 20 * (v / 20);
+  for (int v = threadIdx.x; v < 4 * kStride; v += blockDim.x) {
+    const int b = v / kStride, m = v - kStride * (v / kStride);
     const int bx = b >> 1, by = b & 1;
     const Pos p{4 + bx, 4 + by, 4 + (bx ^ by)};
     int32_t o = 0;
-    if (m >= 1 && m < kSlots)
+    if (m >= 1 && m <= kUsed)
       o = index(Pos{p.x + dx(m - 1), p.y + dy(m - 1), p.z + dz(m - 1)}, R.L[0], R.L[1]) - index(p, R.L[0], R.L[1]);
     s_off[v] = o;
   }
+}
+
+// Interior test of the offset tables: every neighbour of shells 1-3 lies within the box.
+__device__ __forceinline__ bool interior(Pos p, const Replica &R) {
+  return (uint32_t)(p.x - 2) <= (uint32_t)(2 * R.L[0] - 5) && (uint32_t)(p.y - 2) <= (uint32_t)(2 * R.L[1] - 5) &&
+         (uint32_t)(p.z - 2) <= (uint32_t)(2 * R.L[2] - 5);
 }
 
 // Species of this lane's gathered slots of the site at p; load(s) returns the species at
@@ -246,10 +253,8 @@ __device__ __forceinline__ void gather_slots(Pos p, const Replica &R, const int3
                                              uint32_t (&sp)[kGath<P>]) {
   const int g = (threadIdx.x >> 5) & 1;
   const int32_t lx = R.L[0], ly = R.L[1], lz = R.L[2];
-  const bool inner = (uint32_t)(p.x - 2) <= (uint32_t)(2 * lx - 5) && (uint32_t)(p.y - 2) <= (uint32_t)(2 * ly - 5) &&
-                     (uint32_t)(p.z - 2) <= (uint32_t)(2 * lz - 5);
   const int32_t base = index(p, lx, ly);
-  if (__all(inner)) {
+  if (__all(interior(p, R))) {
     const int32_t *o = s_off + 20 * (((p.x & 1) << 1) | (p.y & 1));
 #pragma unroll
     for (int q = 0; q < kGath<P>; ++q) {
@@ -534,7 +539,7 @@ __global__ __launch_bounds__(net_threads<P>()) void k_rows_net(Args a, const uin
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const Replica R = a.reps[a.r];
   for (int q = tid; q < kW / 16; q += kThreads) ((int4 *)s_w)[q] = ((const int4 *)wpack)[q];
-  fill_offsets(s_off, R);
+  fill_offsets<20, kNbrMlp>(s_off, R);
   __syncthreads();
   const NetSmem S = net_smem<P>(s_w, b3);
   const uint8_t *occ = a.occ + R.site0;
@@ -559,36 +564,51 @@ __global__ __launch_bounds__(net_threads<P>()) void k_rows_net(Args a, const uin
 
 // Post-swap qSRO energies (FP32, one row per lane).
 __global__ __launch_bounds__(256) void k_rows_qsro(Args a, const float *F) {
+  __shared__ int32_t s_off[4 * 44];
   const Replica R = a.reps[a.r];
+  fill_offsets<44, kNbr>(s_off, R);
+  __syncthreads();
   const uint8_t *occ = a.occ + R.site0;
-  const int64_t rows = (int64_t)(*a.n_active) * kOmQsro;
-  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < rows;
-       row += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t slot = row / kOmQsro;
-    const int k = (int)(row - slot * kOmQsro);
+  const int32_t rows = (int32_t)(*a.n_active) * kOmQsro;  // below 2^31: trials x 60 of one colour
+  for (int32_t row = blockIdx.x * blockDim.x + threadIdx.x; row < rows; row += gridDim.x * blockDim.x) {
+    const int32_t slot = row / kOmQsro;
+    const int k = row - slot * kOmQsro;
     const Trial tr = a.trials[a.active[slot]];
-    const int64_t i = tr.site, n = tr.partner;
+    const int32_t i = (int32_t)tr.site, n = (int32_t)tr.partner;
     const uint32_t si = occ[i], sn = occ[n];
     const Pos pj = zone_pos(trial_pos(tr), a.om + (tr.dir * kOmMax + k) * 3, R);
-    a.e1[row] = qsro_site<float>(
-        [&](int k2) -> int {
-          const int32_t s = k2 < 0 ? index(pj, R.L[0], R.L[1]) : at(pj, dx(k2), dy(k2), dz(k2), R.L[0], R.L[1], R.L[2]);
-          return (int)swapped(occ, s, (int32_t)i, (int32_t)n, si, sn);
-        },
-        F);
+    const int32_t base = index(pj, R.L[0], R.L[1]);
+    float e;
+    if (interior(pj, R)) {
+      const int32_t *o = s_off + 44 * (((pj.x & 1) << 1) | (pj.y & 1));
+      e = qsro_site<float>([&](int k2) -> int { return (int)swapped(occ, base + o[k2 + 1], i, n, si, sn); }, F);
+    } else {
+      e = qsro_site<float>(
+          [&](int k2) -> int {
+            const int32_t s = k2 < 0 ? base : at(pj, dx(k2), dy(k2), dz(k2), R.L[0], R.L[1], R.L[2]);
+            return (int)swapped(occ, s, i, n, si, sn);
+          },
+          F);
+    }
+    a.e1[row] = e;
   }
 }
 
 // Zone sums against the cache (fixed order), then the Metropolis decision or the FP64 queue.
 // The zone energies of a trial are contiguous (OM is a multiple of four): 16-byte loads, all
 // of them and the cache gathers in flight at once.
+// Lanes per trial in k_decide: each sums a contiguous quarter of the zone.
+constexpr int kDecideLanes = 4;
+
 template <int OM>
 __global__ __launch_bounds__(kPhaseThreads) void k_decide(Args a) {
-  static_assert(OM % 4 == 0, "zone size");
+  static_assert(OM % kDecideLanes == 0, "zone size");
+  constexpr int kPer = OM / kDecideLanes;
   __shared__ unsigned long long s_part[kPhaseWaves];
   const Replica R = a.reps[a.r];
-  const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool live = slot < (int64_t)(*a.n_active);
+  const int sub = threadIdx.x & (kDecideLanes - 1);
+  const int32_t slot = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) / kDecideLanes);
+  const bool live = slot < (int32_t)(*a.n_active);  // the four lanes of a trial agree
   bool accept = false;
   long long fixed = 0;
   if (live) {
@@ -596,49 +616,48 @@ __global__ __launch_bounds__(kPhaseThreads) void k_decide(Args a) {
     uint8_t *occ = a.occ + R.site0;
     float *ec = a.ecache + R.site0;
     const Pos pi = trial_pos(tr);
-    const f32x4 *e1 = (const f32x4 *)(a.e1 + slot * OM);
-    const int8_t *o = a.om + tr.dir * kOmMax * 3;
-    float dE = 0.0f;
+    const float *e1 = a.e1 + (int64_t)slot * OM + sub * kPer;
+    const int8_t *o = a.om + (tr.dir * kOmMax + sub * kPer) * 3;
+    int32_t idx[kPer];
+    float part = 0.0f;
 #pragma unroll
-    for (int k4 = 0; k4 < OM / 4; ++k4) {
-      const f32x4 v = e1[k4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int k = 4 * k4 + q;
-        dE += v[q] - ec[at(pi, o[3 * k], o[3 * k + 1], o[3 * k + 2], R.L[0], R.L[1], R.L[2])];
-      }
+    for (int j = 0; j < kPer; ++j) {
+      idx[j] = at(pi, o[3 * j], o[3 * j + 1], o[3 * j + 2], R.L[0], R.L[1], R.L[2]);
+      part += e1[j] - ec[idx[j]];
     }
+    // (q0 + q1) + (q2 + q3) on every lane: float addition is commutative, so the four lanes
+    // hold the same dE and take the same decision
+    const float pair = part + __shfl_xor(part, 1);
+    const float dE = pair + __shfl_xor(pair, 2);
     const double dEd = (double)dE;
-    if (a.trace_dE_fast) a.trace_dE_fast[R.site0 + tr.site] = dEd;
+    const bool lead = sub == 0;
+    if (lead && a.trace_dE_fast) a.trace_dE_fast[R.site0 + tr.site] = dEd;
     if (fabs(dEd - tr.theta) < a.guard) {
-      const uint32_t q = atomicAdd(a.q_count, 1u);
-      a.queue[q] = QEntry{(int32_t)slot, dE};
+      if (lead) {
+        const uint32_t q = atomicAdd(a.q_count, 1u);
+        a.queue[q] = QEntry{slot, dE};
+      }
     } else {
       accept = dEd <= tr.theta;
       if (accept) {
-        const uint8_t si = occ[tr.site];
-        occ[tr.site] = occ[tr.partner];
-        occ[tr.partner] = si;
-#pragma unroll
-        for (int k4 = 0; k4 < OM / 4; ++k4) {
-          const f32x4 v = e1[k4];
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int k = 4 * k4 + q;
-            ec[at(pi, o[3 * k], o[3 * k + 1], o[3 * k + 2], R.L[0], R.L[1], R.L[2])] = v[q];
-          }
+        if (lead) {
+          const uint8_t si = occ[tr.site];
+          occ[tr.site] = occ[tr.partner];
+          occ[tr.partner] = si;
         }
-        fixed = to_fixed(dEd);
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) ec[idx[j]] = e1[j];
+        fixed = lead ? to_fixed(dEd) : 0;
       }
-      if (a.trace_flags) a.trace_flags[R.site0 + tr.site] = accept ? kFlagAccept : 0;
-      if (a.trace_dE) a.trace_dE[R.site0 + tr.site] = dEd;
+      if (lead && a.trace_flags) a.trace_flags[R.site0 + tr.site] = accept ? kFlagAccept : 0;
+      if (lead && a.trace_dE) a.trace_dE[R.site0 + tr.site] = dEd;
     }
   }
   // one atomic per block for the accepted dE (2^-32 eV units, exact integer sums) and one for
   // the accept counter
   const unsigned long long esum = block_sum_u64((unsigned long long)fixed, s_part);
   __syncthreads();
-  const unsigned long long nacc = block_sum_u64(accept ? 1ull : 0ull, s_part);
+  const unsigned long long nacc = block_sum_u64(accept && sub == 0 ? 1ull : 0ull, s_part);
   if (threadIdx.x == 0) {
     if (esum) atomicAdd(&a.e_fixed[a.r], esum);
     if (nacc) atomicAdd((unsigned long long *)&a.counters[2 * a.n_replicas + a.r], nacc);
@@ -743,7 +762,7 @@ __global__ __launch_bounds__(kNetThreads) void k_site_energies_net(const Replica
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const Replica R = reps[r];
   for (int q = tid; q < kW / 16; q += kNetThreads) ((int4 *)s_w)[q] = ((const int4 *)wpack)[q];
-  fill_offsets(s_off, R);
+  fill_offsets<20, kNbrMlp>(s_off, R);
   __syncthreads();
   const NetSmem S = net_smem<P>(s_w, b3);
   const uint8_t *occ = occ_all + R.site0;
@@ -785,6 +804,7 @@ __global__ __launch_bounds__(kR64Threads) void k_recheck_net(Args a, const doubl
                                                             uint32_t *done) {
   __shared__ double s_h[kRcRows * kHS];
   __shared__ double s_out[kRcRows];
+  __shared__ double s_re[2 * kOmMlp];
   __shared__ uint8_t s_sp[kRcRows * kSlots];
   __shared__ int s_last, s_accept;
   const Replica R = a.reps[a.r];
@@ -818,12 +838,14 @@ __global__ __launch_bounds__(kR64Threads) void k_recheck_net(Args a, const doubl
     __syncthreads();
     if (s_last) {
       __threadfence();
+      // the 56 row energies, one load per thread, then summed in row order
+      if (tid < 2 * kOmMlp)
+        s_re[tid] = __hip_atomic_load(row_e + (size_t)q * 2 * kOmMlp + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __syncthreads();
       if (tid == 0) {
-        const double *re = row_e + (size_t)q * 2 * kOmMlp;
         double e1 = 0.0, e0 = 0.0;
-        for (int k = 0; k < kOmMlp; ++k) e1 += __hip_atomic_load(re + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        for (int k = 0; k < kOmMlp; ++k)
-          e0 += __hip_atomic_load(re + kOmMlp + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int k = 0; k < kOmMlp; ++k) e1 += s_re[k];
+        for (int k = 0; k < kOmMlp; ++k) e0 += s_re[kOmMlp + k];
         done[q] = 0;  // ready for the next use of this queue slot
         const double dE = e1 - e0;
         bool accept = false;

@@ -307,11 +307,11 @@ inline int enqueue_sweep(smc_ctx *c, const smc_stats *st, bool trace) {
         launch_rows_net<kPBF16X3>(c, a, nt);
       }
       prof_end(c, ev, 0);
+      const dim3 dg(grid_for(nt * kDecideLanes, kPhaseThreads));
       if (f.model == 0)
-        hipLaunchKernelGGL(k_decide<kOmMlp>, dim3(grid_for(nt, kPhaseThreads)), dim3(kPhaseThreads), 0, c->stream, a);
+        hipLaunchKernelGGL(k_decide<kOmMlp>, dg, dim3(kPhaseThreads), 0, c->stream, a);
       else
-        hipLaunchKernelGGL(k_decide<kOmQsro>, dim3(grid_for(nt, kPhaseThreads)), dim3(kPhaseThreads), 0, c->stream,
-                           a);
+        hipLaunchKernelGGL(k_decide<kOmQsro>, dg, dim3(kPhaseThreads), 0, c->stream, a);
       // blocks loop over the queue (usually short): a few per CU
       const int ev2 = prof_begin(c);
       if (f.model == 0) {
