@@ -239,10 +239,10 @@ __device__ inline void fill_offsets(int32_t *s_off, const Replica &R) {
   }
 }
 
-// Interior test of the offset tables: every neighbour of shells 1-3 lies within the box.
+// Interior test of the offset tables: every neighbour of shells 1-3 lies within the box
+// (signed bounds, so that a short axis has no interior rather than a wrapped bound).
 __device__ __forceinline__ bool interior(Pos p, const Replica &R) {
-  return (uint32_t)(p.x - 2) <= (uint32_t)(2 * R.L[0] - 5) && (uint32_t)(p.y - 2) <= (uint32_t)(2 * R.L[1] - 5) &&
-         (uint32_t)(p.z - 2) <= (uint32_t)(2 * R.L[2] - 5);
+  return p.x >= 2 && p.x <= 2 * R.L[0] - 3 && p.y >= 2 && p.y <= 2 * R.L[1] - 3 && p.z >= 2 && p.z <= 2 * R.L[2] - 3;
 }
 
 // Species of this lane's gathered slots of the site at p; load(s) returns the species at
