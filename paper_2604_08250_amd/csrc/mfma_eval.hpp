@@ -370,12 +370,13 @@ __device__ __forceinline__ float eval_tile(const EvalSmem &S, GetSlot get) {
         if constexpr (P == kPBF16X3) bl[q] = (int)pack_bf16x2(x0 - bf16_lo_f32(w), x1 - bf16_hi_f32(w));
       }
     };
-    i32x4 bh[2], bl[2];
+    i32x4 bh[2], bl[2], bh7, bl7;
     build(0, 0, bh[0], bl[0]);
 #pragma unroll
-    for (int s = 0; s < 2 * kMT; ++s) {
+    for (int s = 0; s < 2 * kMT - 2; ++s) {
       const int cur = s & 1;
-      if (s + 1 < 2 * kMT) build((s + 1) >> 1, (s + 1) & 1, bh[cur ^ 1], bl[cur ^ 1]);
+      build((s + 1) >> 1, (s + 1) & 1, bh[cur ^ 1], bl[cur ^ 1]);
+      if (s + 3 == 2 * kMT) build(kMT - 1, 1, bh7, bl7);  // the last K-step too
       const bf16x8 Bh = __builtin_bit_cast(bf16x8, bh[cur]);
       bf16x8 ah[kMT];
 #pragma unroll
@@ -396,6 +397,42 @@ __device__ __forceinline__ float eval_tile(const EvalSmem &S, GetSlot get) {
       }
       __builtin_amdgcn_sched_barrier(0);
     }
+    // the last two K-steps one output tile at a time, with the activation and output dot
+    // product of the previous tile alongside (each accumulator keeps its product order)
+    const bf16x8 Bh6 = __builtin_bit_cast(bf16x8, bh[0]), Bl6 = __builtin_bit_cast(bf16x8, bl[0]);
+    const bf16x8 Bh7 = __builtin_bit_cast(bf16x8, bh7), Bl7 = __builtin_bit_cast(bf16x8, bl7);
+    float part = 0.0f;
+    auto out_dot = [&](int T) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const f32x4 w = *(const f32x4 *)(S.w2 + 32 * T + 8 * j + 4 * g);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) part = fmaf(w[i], act(acc1[T][4 * j + i], 1.0f), part);
+      }
+    };
+#pragma unroll
+    for (int To = 0; To < kMT; ++To) {
+#pragma unroll
+      for (int s = 2 * kMT - 2; s < 2 * kMT; ++s) {
+        const bf16x8 Bh = s == 2 * kMT - 2 ? Bh6 : Bh7;
+        const bf16x8 ah = __builtin_bit_cast(bf16x8, Ahi[(To * 8 + s) * 64 + lane]);
+        acc1[To] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, Bh, acc1[To], 0, 0, 0);
+        if constexpr (P == kPBF16X3) {
+          const bf16x8 al = __builtin_bit_cast(bf16x8, Alo[(To * 8 + s) * 64 + lane]);
+          acc1[To] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, Bh, acc1[To], 0, 0, 0);
+          acc1[To] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, s == 2 * kMT - 2 ? Bl6 : Bl7, acc1[To], 0, 0, 0);
+        }
+      }
+      if (To >= 1) {
+        out_dot(To - 1);
+        interleave<P == kPBF16X3 ? 6 : 2, 16 * 5, P == kPBF16X3 ? 4 : 2>();
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    out_dot(kMT - 1);
+    const float other = __shfl_xor(part, 32);
+    const float q0 = g == 0 ? part : other, q1 = g == 0 ? other : part;
+    return S.b2 + (q0 + q1);
   } else {
     // FP8: K-step s' takes M-tiles 2s' and 2s'+1 (16 registers each) of this lane group.
     const i32x8 *A = (const i32x8 *)(S.w + PackSize<kPFP8>::kL0);
