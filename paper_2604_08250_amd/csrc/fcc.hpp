@@ -530,8 +530,11 @@ constexpr int net_threads() {
   return P == kPBF16 ? 256 : kNetThreads;
 }
 
+// At least two waves per SIMD: the register budget is then the architectural VGPRs alone, so
+// the accumulators stay in VGPRs (with a 256-thread block the compiler otherwise places them
+// in AGPRs and copies every activation out first).
 template <int P>
-__global__ __launch_bounds__(net_threads<P>()) void k_rows_net(Args a, const uint8_t *wpack, float b3) {
+__global__ __launch_bounds__(net_threads<P>(), 2) void k_rows_net(Args a, const uint8_t *wpack, float b3) {
   constexpr int kW = net_bytes<P>();
   constexpr int kThreads = net_threads<P>();
   __shared__ __attribute__((aligned(16))) uint8_t s_w[kW];
