@@ -30,14 +30,18 @@ struct RecheckArgs {
 constexpr int kRcThreads = 1024;
 constexpr int kRows64 = 2 * kOm;              // rows 0..39 after the swap, 40..79 before
 constexpr int kRcSplit = 1;                   // blocks sharing one queued trial
-constexpr int kRcRowsB = kRows64 / kRcSplit;  // 16 rows per block
+constexpr int kRcRowsB = kRows64 / kRcSplit;  // rows per block: all 80
 constexpr int kRcParts = kRcThreads / kHid;   // 8 threads per hidden unit
-constexpr int kRcRows = kRcRowsB / kRcParts;  // 2 rows per thread
+constexpr int kRcRows = kRcRowsB / kRcParts;  // rows per thread: 10
 constexpr int kHStride = kHid + 1;            // padded row stride of the activation buffer
 
-// One block per (queued trial, block of 16 rows): FP64 local energies of its rows go to
-// row_e; the block that completes a trial (per-trial counter) reduces the 80 energies in a
-// fixed order, decides and applies.  No block ever waits for another.
+// One block per (queued trial, block of kRcRowsB rows); with kRcSplit = 1 a block holds all
+// 80 rows of its trial and reduces them from LDS.  With a split, each block writes its rows to
+// row_e and the block that completes a trial (per-trial counter) reduces the 80 energies; the
+// reduction is in a fixed order either way, then the decision and the apply.  No block ever
+// waits for another.  A split was measured several times slower: every block's device-scope
+// fence writes back the L2 that the colour kernel has just dirtied.  The layer-0 slot loop
+// stays rolled: at 1024 threads (128 VGPRs) unrolling it by three already spills.
 __global__ __launch_bounds__(kRcThreads) void k_recheck(RecheckArgs a) {
   __shared__ double s_h[kRcRowsB * kHStride];  // activations, then per-unit terms of layer 2
   __shared__ double s_part[kRcRowsB * kRcParts];
