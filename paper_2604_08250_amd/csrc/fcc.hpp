@@ -364,17 +364,19 @@ template <typename T, typename GetSpecies>
 __device__ inline T qsro_site(GetSpecies sp, const T *F) {
   const T *Vf = F, *Wf = F + 75;
   const int c = sp(-1);
+  // per-shell species counts as 6-bit fields of one integer (at most 24 neighbours per
+  // shell); species 5 and above count nowhere
+  uint32_t packed[3] = {0u, 0u, 0u};
+#pragma unroll
+  for (int k = 0; k < kNbr; ++k) {
+    const uint32_t q = (uint32_t)sp(k);
+    packed[shell_of(k) - 1] += q < 5u ? 1u << (6u * q) : 0u;
+  }
   T cnt[3][5];
 #pragma unroll
   for (int m = 0; m < 3; ++m)
 #pragma unroll
-    for (int q = 0; q < 5; ++q) cnt[m][q] = T(0);
-#pragma unroll
-  for (int k = 0; k < kNbr; ++k) {
-    const int m = shell_of(k) - 1, q = sp(k);
-#pragma unroll
-    for (int p = 0; p < 5; ++p) cnt[m][p] += (q == p) ? T(1) : T(0);
-  }
+    for (int q = 0; q < 5; ++q) cnt[m][q] = T((packed[m] >> (6 * q)) & 63u);
   T e = F[90];
 #pragma unroll
   for (int m = 0; m < 3; ++m) {
