@@ -23,12 +23,11 @@ __device__ inline float silu<float>(float z) {
   return z * __builtin_amdgcn_rcpf(1.0f + e);
 }
 
-// Species of the 27 slots of site j (replica-local index), seen with the species of the
-// sites i and n exchanged when swap is true.
-__device__ inline void gather_slots(const uint8_t *occ, int64_t j, int32_t lx, int32_t ly, int32_t lz,
-                                    int n_slots, bool swap, int64_t i, int64_t n, uint8_t si,
-                                    uint8_t sn, uint8_t *slot) {
-  const Pos p = site_pos(j, lx, ly);
+// Species of the 27 slots of site j (replica-local index) at position p, seen with the
+// species of the sites i and n exchanged when swap is true.
+__device__ inline void gather_slots_at(const uint8_t *occ, Pos p, int64_t j, int32_t lx, int32_t ly, int32_t lz,
+                                       int n_slots, bool swap, int64_t i, int64_t n, uint8_t si, uint8_t sn,
+                                       uint8_t *slot) {
   auto get = [&](int64_t s) -> uint8_t {
     if (swap) {
       if (s == i) return sn;
@@ -40,6 +39,12 @@ __device__ inline void gather_slots(const uint8_t *occ, int64_t j, int32_t lx, i
 #pragma unroll
   for (int k = 0; k < kNbr; ++k)
     if (k + 1 < n_slots) slot[k + 1] = get(site_at(p, shell_dx(k), shell_dy(k), shell_dz(k), lx, ly, lz));
+}
+
+__device__ inline void gather_slots(const uint8_t *occ, int64_t j, int32_t lx, int32_t ly, int32_t lz,
+                                    int n_slots, bool swap, int64_t i, int64_t n, uint8_t si,
+                                    uint8_t sn, uint8_t *slot) {
+  gather_slots_at(occ, site_pos(j, lx, ly), j, lx, ly, lz, n_slots, swap, i, n, si, sn, slot);
 }
 
 // E = W2 . silu(W1 . silu(W0 x + b0) + b1) + b2 with x built from the slot species.

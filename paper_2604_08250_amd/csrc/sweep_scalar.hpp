@@ -54,13 +54,27 @@ __device__ inline int64_t trial_site(const Replica &R, int32_t colour, int64_t t
   return (((int64_t)z * R.L[1] + y) * R.L[0] + x) * 2 + b;
 }
 
+// Local energy of site j at position p.
+template <int FEAT, int H, typename T>
+__device__ inline T site_energy_at(const uint8_t *occ, const Replica &R, Pos p, int64_t j, bool swap, int64_t i,
+                                   int64_t n, uint8_t si, uint8_t sn, const T *W) {
+  uint8_t slot[kSlots];
+  gather_slots_at(occ, p, j, R.L[0], R.L[1], R.L[2], FEAT == 0 ? 15 : kSlots, swap, i, n, si, sn, slot);
+  if constexpr (FEAT == 2) return qsro_scalar<T>(slot, W);
+  else return mlp_scalar<FEAT, H, T>(slot, W);
+}
+
 template <int FEAT, int H, typename T>
 __device__ inline T site_energy(const uint8_t *occ, const Replica &R, int64_t j, bool swap, int64_t i,
                                 int64_t n, uint8_t si, uint8_t sn, const T *W) {
-  uint8_t slot[kSlots];
-  gather_slots(occ, j, R.L[0], R.L[1], R.L[2], FEAT == 0 ? 15 : kSlots, swap, i, n, si, sn, slot);
-  if constexpr (FEAT == 2) return qsro_scalar<T>(slot, W);
-  else return mlp_scalar<FEAT, H, T>(slot, W);
+  return site_energy_at<FEAT, H, T>(occ, R, site_pos(j, R.L[0], R.L[1]), j, swap, i, n, si, sn, W);
+}
+
+// Zone site k of a trial at pi: its position (wrapped per axis) and replica-local index.
+__device__ inline int64_t zone_site(const Replica &R, Pos pi, const int8_t *om, int k, Pos &pj) {
+  pj = Pos{wrap1(pi.x + om[3 * k], 2 * R.L[0]), wrap1(pi.y + om[3 * k + 1], 2 * R.L[1]),
+           wrap1(pi.z + om[3 * k + 2], 2 * R.L[2])};
+  return site_index(pj, R.L[0], R.L[1]);
 }
 
 // Local energy of every site of one replica (FP32 into the cache, or FP64).
@@ -110,8 +124,9 @@ __global__ __launch_bounds__(kScalarBlock) void k_sweep_colour_scalar(SweepArgs 
       if (!exact) {
         float acc = 0.0f;
         for (int k = 0; k < a.omega_n; ++k) {
-          const int64_t j = site_at(pi, om[3 * k], om[3 * k + 1], om[3 * k + 2], R.L[0], R.L[1], R.L[2]);
-          const float e1 = site_energy<FEAT, H, float>(occ, R, j, true, i, n, si, sn, a.w32);
+          Pos pj;
+          const int64_t j = zone_site(R, pi, om, k, pj);
+          const float e1 = site_energy_at<FEAT, H, float>(occ, R, pj, j, true, i, n, si, sn, a.w32);
           s_e1[tid][k] = e1;
           acc += e1 - ec[j];
         }
@@ -122,9 +137,10 @@ __global__ __launch_bounds__(kScalarBlock) void k_sweep_colour_scalar(SweepArgs 
       if (exact) {
         double e1 = 0.0, e0 = 0.0;
         for (int k = 0; k < a.omega_n; ++k) {
-          const int64_t j = site_at(pi, om[3 * k], om[3 * k + 1], om[3 * k + 2], R.L[0], R.L[1], R.L[2]);
-          e1 += site_energy<FEAT, H, double>(occ, R, j, true, i, n, si, sn, a.w64);
-          e0 += site_energy<FEAT, H, double>(occ, R, j, false, i, n, si, sn, a.w64);
+          Pos pj;
+          const int64_t j = zone_site(R, pi, om, k, pj);
+          e1 += site_energy_at<FEAT, H, double>(occ, R, pj, j, true, i, n, si, sn, a.w64);
+          e0 += site_energy_at<FEAT, H, double>(occ, R, pj, j, false, i, n, si, sn, a.w64);
         }
         dE = e1 - e0;
         flags |= kFlagFp64;
