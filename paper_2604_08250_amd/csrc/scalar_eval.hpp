@@ -25,20 +25,28 @@ __device__ inline float silu<float>(float z) {
 
 // Species of the 27 slots of site j (replica-local index) at position p, seen with the
 // species of the sites i and n exchanged when swap is true.
+// Replica-local site indices are below 2^31 (enforced when a context is made), so the
+// neighbour indices are formed in 32-bit arithmetic.
 __device__ inline void gather_slots_at(const uint8_t *occ, Pos p, int64_t j, int32_t lx, int32_t ly, int32_t lz,
                                        int n_slots, bool swap, int64_t i, int64_t n, uint8_t si, uint8_t sn,
                                        uint8_t *slot) {
-  auto get = [&](int64_t s) -> uint8_t {
+  const int32_t i32 = (int32_t)i, n32 = (int32_t)n;  // -1 when unused (no swap)
+  auto get = [&](int32_t s) -> uint8_t {
     if (swap) {
-      if (s == i) return sn;
-      if (s == n) return si;
+      if (s == i32) return sn;
+      if (s == n32) return si;
     }
     return occ[s];
   };
-  slot[0] = get(j);
+  auto at32 = [&](int k) -> int32_t {
+    const int32_t x = wrap1(p.x + shell_dx(k), 2 * lx), y = wrap1(p.y + shell_dy(k), 2 * ly),
+                  z = wrap1(p.z + shell_dz(k), 2 * lz);
+    return (((z >> 1) * ly + (y >> 1)) * lx + (x >> 1)) * 2 + (x & 1);
+  };
+  slot[0] = get((int32_t)j);
 #pragma unroll
   for (int k = 0; k < kNbr; ++k)
-    if (k + 1 < n_slots) slot[k + 1] = get(site_at(p, shell_dx(k), shell_dy(k), shell_dz(k), lx, ly, lz));
+    if (k + 1 < n_slots) slot[k + 1] = get(at32(k));
 }
 
 __device__ inline void gather_slots(const uint8_t *occ, int64_t j, int32_t lx, int32_t ly, int32_t lz,
