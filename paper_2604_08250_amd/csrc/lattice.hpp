@@ -59,6 +59,24 @@ __host__ __device__ inline int64_t site_index(Pos p, int32_t lx, int32_t ly) {
   return (((int64_t)(p.z >> 1) * ly + (p.y >> 1)) * lx + (p.x >> 1)) * 2 + (p.x & 1);
 }
 
+// 32-bit forms for replica-local indices, which stay below 2^31 (checked when a context is
+// made).
+__host__ __device__ inline Pos site_pos32(int32_t s, int32_t lx, int32_t ly) {
+  const uint32_t u = (uint32_t)s;
+  const int32_t b = (int32_t)(u & 1u);
+  const uint32_t c = u >> 1;
+  const int32_t x = (int32_t)(c % (uint32_t)lx);
+  const uint32_t r = c / (uint32_t)lx;
+  const int32_t y = (int32_t)(r % (uint32_t)ly);
+  const int32_t z = (int32_t)(r / (uint32_t)ly);
+  return Pos{2 * x + b, 2 * y + b, 2 * z + b};
+}
+
+__host__ __device__ inline int32_t site_at32(Pos p, int dx, int dy, int dz, int32_t lx, int32_t ly, int32_t lz) {
+  const int32_t x = wrap1(p.x + dx, 2 * lx), y = wrap1(p.y + dy, 2 * ly), z = wrap1(p.z + dz, 2 * lz);
+  return (((z >> 1) * ly + (y >> 1)) * lx + (x >> 1)) * 2 + (x & 1);
+}
+
 __host__ __device__ inline int64_t site_at(Pos p, int dx, int dy, int dz, int32_t lx, int32_t ly,
                                            int32_t lz) {
   Pos q{wrap1(p.x + dx, 2 * lx), wrap1(p.y + dy, 2 * ly), wrap1(p.z + dz, 2 * lz)};

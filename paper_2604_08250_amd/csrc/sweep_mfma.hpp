@@ -181,8 +181,8 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
       d = (int)(r.v[0] >> 61);
       const double u = (double)((r.v[1] >> 11) + 1) * 0x1.0p-53;
       theta = isinf(R.temperature) ? (double)INFINITY : -kBoltzmannEvPerK * R.temperature * log(u);
-      pi = site_pos(i, R.L[0], R.L[1]);
-      n = site_at(pi, shell_dx(d), shell_dy(d), shell_dz(d), R.L[0], R.L[1], R.L[2]);
+      pi = site_pos32((int32_t)i, R.L[0], R.L[1]);
+      n = site_at32(pi, shell_dx(d), shell_dy(d), shell_dz(d), R.L[0], R.L[1], R.L[2]);
       si = occ[i];
       sn = occ[n];
       active = si != sn;
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
         const int t = q / kReg, p = q - t * kReg;
         int dx, dy, dz;
         unpack_off(s_roff[tb.dir[t] * kReg + p], dx, dy, dz);
-        pf_reg[j >> 2] |= (uint32_t)occ[site_at(Pos{tb.px[t], tb.py[t], tb.pz[t]}, dx, dy, dz, R.L[0], R.L[1], R.L[2])]
+        pf_reg[j >> 2] |= (uint32_t)occ[site_at32(Pos{tb.px[t], tb.py[t], tb.pz[t]}, dx, dy, dz, R.L[0], R.L[1], R.L[2])]
                           << (8 * (j & 3));
       }
     }
@@ -243,7 +243,7 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
         const int t = q / kOm, k = q - t * kOm;
         int dx, dy, dz;
         unpack_off(s_ooff[tb.dir[t] * kOm + k], dx, dy, dz);
-        pf_om[j] = ec[site_at(Pos{tb.px[t], tb.py[t], tb.pz[t]}, dx, dy, dz, R.L[0], R.L[1], R.L[2])];
+        pf_om[j] = ec[site_at32(Pos{tb.px[t], tb.py[t], tb.pz[t]}, dx, dy, dz, R.L[0], R.L[1], R.L[2])];
       }
     }
   };
@@ -382,7 +382,7 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
       if (!s_acc[t]) continue;
       int dx, dy, dz;
       unpack_off(s_ooff[cur.dir[t] * kOm + k], dx, dy, dz);
-      ec[site_at(Pos{cur.px[t], cur.py[t], cur.pz[t]}, dx, dy, dz, R.L[0], R.L[1], R.L[2])] = s_e[q];
+      ec[site_at32(Pos{cur.px[t], cur.py[t], cur.pz[t]}, dx, dy, dz, R.L[0], R.L[1], R.L[2])] = s_e[q];
     }
     __syncthreads();
   }
