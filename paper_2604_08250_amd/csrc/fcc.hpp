@@ -95,13 +95,15 @@ __device__ inline int64_t trial_site(const Replica &R, int32_t colour, int64_t t
   rest /= R.ax[0].big;
   const int32_t oy = rest % R.ax[1].big;
   const int32_t oz = rest / R.ax[1].big;
-  const int32_t cx = (int32_t)(t % R.ax[0].q);
-  const int64_t t1 = t / R.ax[0].q;
-  const int32_t cy = (int32_t)(t1 % R.ax[1].q);
-  const int32_t cz = (int32_t)(t1 / R.ax[1].q);
+  // link-cell and site indices stay below 2^31: 32-bit arithmetic
+  const uint32_t tu = (uint32_t)t, q0 = (uint32_t)R.ax[0].q, q1 = (uint32_t)R.ax[1].q;
+  const int32_t cx = (int32_t)(tu % q0);
+  const uint32_t t1 = tu / q0;
+  const int32_t cy = (int32_t)(t1 % q1);
+  const int32_t cz = (int32_t)(t1 / q1);
   if (ox >= axis_len(R.ax[0], cx) || oy >= axis_len(R.ax[1], cy) || oz >= axis_len(R.ax[2], cz)) return -1;
   const int32_t x = axis_start(R.ax[0], cx) + ox, y = axis_start(R.ax[1], cy) + oy, z = axis_start(R.ax[2], cz) + oz;
-  return (((int64_t)z * R.L[1] + y) * R.L[0] + x) * 4 + b;
+  return ((z * R.L[1] + y) * R.L[0] + x) * 4 + b;
 }
 
 // ------------------------------------------------------------------ MLPNet on matrix cores
