@@ -87,8 +87,8 @@ void launch_site_energies_mfma(smc_ctx *c, float *out, const uint8_t *occ = null
   for (size_t r = 0; r < c->reps.size(); ++r) {
     if (only >= 0 && (int)r != only) continue;
     const int64_t tiles = (c->reps[r].n_sites + 31) / 32;
-    const unsigned grid = (unsigned)std::min<int64_t>((tiles + 3) / 4, 4 * (int64_t)c->n_cu);
-    hipLaunchKernelGGL((k_site_energies_mfma<P>), dim3(grid), dim3(256), 0, c->stream, c->d_reps, (int32_t)r,
+    const unsigned grid = (unsigned)std::min<int64_t>((tiles + 7) / 8, (int64_t)c->n_cu);
+    hipLaunchKernelGGL((k_site_energies_mfma<P>), dim3(grid), dim3(kSeThreads), 0, c->stream, c->d_reps, (int32_t)r,
                        occ ? occ : c->occ, dp.dev, dp.host.b2, dp.host.k_scale_a0, dp.host.k_scale_a1,
                        dp.host.k_scale_h, dp.host.sh, out);
   }

@@ -395,14 +395,18 @@ __global__ void k_next_sweep(uint64_t *sweep) {
 }
 
 // Local energy of every site of one replica with the matrix-core evaluator (fills the cache).
+// Eight waves per block, like the colour kernel: two per SIMD with one block per CU.
+constexpr int kSeThreads = 512;
 template <int P>
-__global__ __launch_bounds__(256) void k_site_energies_mfma(const Replica *reps, int32_t r, const uint8_t *occ_all,
-                                                           const uint8_t *wpack, float b2, int32_t k_a0,
-                                                           int32_t k_a1, int32_t k_h, float sh, float *out) {
+__global__ __launch_bounds__(kSeThreads) void k_site_energies_mfma(const Replica *reps, int32_t r,
+                                                                  const uint8_t *occ_all, const uint8_t *wpack,
+                                                                  float b2, int32_t k_a0, int32_t k_a1, int32_t k_h,
+                                                                  float sh, float *out) {
   constexpr int kW = pack_bytes<P>();
+  constexpr int kWaves = kSeThreads / 64;
   __shared__ __attribute__((aligned(16))) uint8_t s_w[kW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int q = tid; q < kW / 16; q += 256) ((int4 *)s_w)[q] = ((const int4 *)wpack)[q];
+  for (int q = tid; q < kW / 16; q += kSeThreads) ((int4 *)s_w)[q] = ((const int4 *)wpack)[q];
   __syncthreads();
   const Replica R = reps[r];
   const uint8_t *occ = occ_all + R.site0;
@@ -417,14 +421,14 @@ __global__ __launch_bounds__(256) void k_site_energies_mfma(const Replica *reps,
   S.k_scale_h = k_h;
   S.sh = sh;
   const int64_t tiles = (R.n_sites + 31) / 32;
-  for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < tiles; tile += (int64_t)gridDim.x * 4) {
+  for (int64_t tile = (int64_t)blockIdx.x * kWaves + wave; tile < tiles; tile += (int64_t)gridDim.x * kWaves) {
     const int64_t j = tile * 32 + (lane & 31);
     const bool valid = j < R.n_sites;
-    const Pos p = site_pos(valid ? j : 0, R.L[0], R.L[1]);
+    const Pos p = site_pos32(valid ? (int32_t)j : 0, R.L[0], R.L[1]);
     const float E = eval_tile<P>(S, [&](int m) -> uint32_t {
       if (m == 0) return occ[valid ? j : 0];
       const int k = m - 1;
-      return occ[site_at(p, shell_dx(k), shell_dy(k), shell_dz(k), R.L[0], R.L[1], R.L[2])];
+      return occ[site_at32(p, shell_dx(k), shell_dy(k), shell_dz(k), R.L[0], R.L[1], R.L[2])];
     });
     if (valid && lane < 32) out[R.site0 + j] = E;
   }
