@@ -99,7 +99,9 @@ def lib():
                                 C.c_int64, C.c_int64, C.POINTER(TrialRec)]),
             "or_sweep": (C.c_int, [i32p, C.POINTER(Model), u8p, C.c_double, C.c_uint64, C.c_int64,
                                    C.c_int64, C.POINTER(Stats), C.c_void_p, C.c_int32, i64p,
-                                   C.c_int32, C.c_int32]),
+                                   C.c_int32, C.c_int32, C.POINTER(C.c_int8)]),
+            "or_proposals": (None, [i32p, C.c_uint64, C.c_int64, C.c_int64, C.c_double, i64p, C.c_int64,
+                                    i32p, i64p, f64p]),
             "or_warren_cowley": (None, [i32p, u8p, C.c_int32, f64p]),
             "or_ce_triangles": (C.c_int32, [i32p, C.c_int32]),
             "or_ce_site_energy": (C.c_double, [i32p, C.POINTER(CE), u8p, C.c_int64]),
@@ -268,6 +270,19 @@ def propose(seed, site, sweep, replica):
     return d.value, u.value
 
 
+def proposals(cells, seed, replica, sweep_index, temperature_K, sites):
+    """(partner slot, partner site, theta) of many trial sites at once."""
+    sites = np.ascontiguousarray(sites, dtype=np.int64)
+    n = sites.size
+    d = np.zeros(n, dtype=np.int32)
+    p = np.zeros(n, dtype=np.int64)
+    th = np.zeros(n, dtype=np.float64)
+    lib().or_proposals(_ptr(_dims(cells), C.c_int32), int(seed), int(replica), int(sweep_index),
+                       float(temperature_K), _ptr(sites, C.c_int64), n, _ptr(d, C.c_int32),
+                       _ptr(p, C.c_int64), _ptr(th, C.c_double))
+    return d, p, th
+
+
 def theta(temperature_K, u) -> float:
     return float(lib().or_theta(temperature_K, u))
 
@@ -283,18 +298,26 @@ def trial(cells, model: MLP, occ, temperature_K, seed, replica, sweep, site) -> 
 def sweep(cells, model: MLP, occ: np.ndarray, temperature_K: float, seed: int, replica: int,
           sweep_index: int, stats: Stats | None = None, trace: bool = False,
           order: int = ORDER_SNAPSHOT, given_order=None, nthreads: int = 1,
-          colours_limit: int = -1):
-    """Advance ``occ`` (uint8, modified in place) by one sweep; returns (stats, trace|None)."""
+          colours_limit: int = -1, force=None):
+    """Advance ``occ`` (uint8, modified in place) by one sweep; returns (stats, trace|None).
+
+    force (optional int8 [N]): 0/1 replaces the decision of the different-species trial at
+    that site, -1 keeps the Metropolis decision."""
     assert occ.dtype == np.uint8 and occ.flags.c_contiguous
     st = stats if stats is not None else Stats()
     tr = np.zeros(occ.size, dtype=TRIAL_DTYPE) if trace else None
     go = None
     if given_order is not None:
         go = np.ascontiguousarray(given_order, dtype=np.int64)
+    fo = None
+    if force is not None:
+        fo = np.ascontiguousarray(force, dtype=np.int8)
+        assert fo.size == occ.size
     rc = lib().or_sweep(_ptr(_dims(cells), C.c_int32), model.c, _ptr(occ, C.c_uint8),
                         float(temperature_K), int(seed), int(replica), int(sweep_index),
                         C.byref(st), tr.ctypes.data if tr is not None else None, order,
-                        _ptr(go, C.c_int64) if go is not None else None, nthreads, colours_limit)
+                        _ptr(go, C.c_int64) if go is not None else None, nthreads, colours_limit,
+                        _ptr(fo, C.c_int8) if fo is not None else None)
     if rc != 0:
         raise MemoryError("oracle sweep failed to allocate")
     return st, tr

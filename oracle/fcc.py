@@ -45,7 +45,8 @@ def lib():
             "or_fcc_colour_of": (C.c_int32, [i32p, C.c_int64]),
             "or_fcc_propose": (None, [C.c_uint64, C.c_int64, C.c_int64, C.c_int64, i32p, f64p]),
             "or_fcc_sweep": (C.c_int, [i32p, M, u8p, C.c_double, C.c_uint64, C.c_int64, C.c_int64,
-                                       C.POINTER(Stats), C.c_void_p, C.c_int32, i64p, C.c_int32, C.c_int32]),
+                                       C.POINTER(Stats), C.c_void_p, C.c_int32, i64p, C.c_int32, C.c_int32,
+                                       C.POINTER(C.c_int8)]),
             "or_fcc_warren_cowley": (None, [i32p, u8p, C.c_int32, f64p]),
         }
         for name, (res, args) in sig.items():
@@ -185,16 +186,21 @@ def propose(seed, site, sweep, replica):
 
 def sweep(cells, model, occ: np.ndarray, temperature_K: float, seed: int, replica: int, sweep_index: int,
           stats: Stats | None = None, trace: bool = False, order: int = ORDER_SNAPSHOT, given_order=None,
-          nthreads: int = 1, colours_limit: int = -1):
-    """Advance ``occ`` (uint8, modified in place) by one sweep; returns (stats, trace|None)."""
+          nthreads: int = 1, colours_limit: int = -1, force=None):
+    """Advance ``occ`` (uint8, modified in place) by one sweep; returns (stats, trace|None).
+    force (optional int8 [N]): 0/1 replaces the decision of the different-species trial at
+    that site, -1 keeps the Metropolis decision."""
     assert occ.dtype == np.uint8 and occ.flags.c_contiguous
     st = stats if stats is not None else Stats()
     tr = np.zeros(occ.size, dtype=TRIAL_DTYPE) if trace else None
     go = None if given_order is None else np.ascontiguousarray(given_order, dtype=np.int64)
+    fo = None if force is None else np.ascontiguousarray(force, dtype=np.int8)
+    assert fo is None or fo.size == occ.size
     rc = lib().or_fcc_sweep(_ptr(_dims(cells), C.c_int32), model.c, _ptr(occ, C.c_uint8), float(temperature_K),
                             int(seed), int(replica), int(sweep_index), C.byref(st),
                             tr.ctypes.data if tr is not None else None, order,
-                            _ptr(go, C.c_int64) if go is not None else None, nthreads, colours_limit)
+                            _ptr(go, C.c_int64) if go is not None else None, nthreads, colours_limit,
+                            _ptr(fo, C.c_int8) if fo is not None else None)
     if rc != 0:
         raise MemoryError("oracle sweep failed to allocate")
     return st, tr

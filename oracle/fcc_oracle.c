@@ -328,12 +328,19 @@ static void fcc_trial(const int32_t L[3], const or_fcc_model *m, const uint8_t *
   }
 }
 
+/* An outside decision replaces the Metropolis decision of a different-species trial
+ * (force[site] = 0 or 1; negative: none), so that tests can follow a chain decided the other
+ * way within rounding of the threshold. */
+static void fcc_force(or_trial_rec *r, const int8_t *force) {
+  if (force && force[r->site] >= 0 && !r->same) r->accept = force[r->site] ? 1 : 0;
+}
+
 /* One sweep: colours in order, every site of a colour a trial site once.  Snapshot order
  * decides all trials of a mini-step on the same lattice and then copies accepted pairs
  * back (Algorithm 1); the sequential orders test independence from the trial order. */
 int or_fcc_sweep(const int32_t L[3], const or_fcc_model *m, uint8_t *occ, double temperature_K, uint64_t seed,
                  int64_t replica, int64_t sweep, or_stats *st, or_trial_rec *trace, int32_t order,
-                 const int64_t *given_order, int32_t nthreads, int32_t colours_limit) {
+                 const int64_t *given_order, int32_t nthreads, int32_t colours_limit, const int8_t *force) {
   const int64_t N = or_fcc_n_sites(L);
   const int32_t C = or_fcc_n_colours(L);
   fcc_tables();
@@ -366,8 +373,10 @@ int or_fcc_sweep(const int32_t L[3], const or_fcc_model *m, uint8_t *occ, double
 #ifdef _OPENMP
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 0 ? nthreads : 1)
 #endif
-      for (int64_t a = b0; a < b1; ++a)
+      for (int64_t a = b0; a < b1; ++a) {
         fcc_trial(L, m, occ, temperature_K, seed, replica, sweep, sites[a], &rec[a - b0]);
+        fcc_force(&rec[a - b0], force);
+      }
       for (int64_t a = b0; a < b1; ++a) {
         const or_trial_rec *r = &rec[a - b0];
         if (r->accept) {
@@ -379,6 +388,7 @@ int or_fcc_sweep(const int32_t L[3], const or_fcc_model *m, uint8_t *occ, double
     } else {
       for (int64_t a = b0; a < b1; ++a) {
         fcc_trial(L, m, occ, temperature_K, seed, replica, sweep, sites[a], &rec[a - b0]);
+        fcc_force(&rec[a - b0], force);
         const or_trial_rec *r = &rec[a - b0];
         if (r->accept) {
           uint8_t t = occ[r->site];

@@ -382,13 +382,36 @@ void or_trial(const int32_t L[3], const or_model *m, const uint8_t *occ, double 
   }
 }
 
+/* Proposals of many trial sites at once (partner slot, partner site, threshold), the same
+ * steps as the start of or_trial. */
+void or_proposals(const int32_t L[3], uint64_t seed, int64_t replica, int64_t sweep, double temperature_K,
+                  const int64_t *sites, int64_t n, int32_t *dir, int64_t *partner, double *theta) {
+  for (int64_t a = 0; a < n; ++a) {
+    int32_t d;
+    double u;
+    or_propose(seed, sites[a], sweep, replica, &d, &u);
+    if (dir) dir[a] = d;
+    if (partner) partner[a] = or_neighbor(L, sites[a], d);
+    if (theta) theta[a] = or_theta(temperature_K, u);
+  }
+}
+
+/* A decision given from outside replaces the Metropolis decision of a different-species
+ * trial (force[site] = 0 or 1; negative: no override).  The tests use it to keep following a
+ * chain whose decision another implementation took the other way within rounding of the
+ * threshold; the trial's dE and theta stay the oracle's own. */
+static void or_force(or_trial_rec *r, const int8_t *force) {
+  if (force && force[r->site] >= 0 && !r->same) r->accept = force[r->site] ? 1 : 0;
+}
+
 /* One sweep: colours 0..C-1 in order; inside a colour every site of that colour is a
  * trial site once.  OR_ORDER_SNAPSHOT follows Algorithm 1 literally (all trials of the
  * mini-step decided on the same lattice, then accepted pairs copied back); the
  * sequential orders exist to test that the result does not depend on the order. */
 int or_sweep(const int32_t L[3], const or_model *m, uint8_t *occ, double temperature_K,
              uint64_t seed, int64_t replica, int64_t sweep, or_stats *st, or_trial_rec *trace,
-             int32_t order, const int64_t *given_order, int32_t nthreads, int32_t colours_limit) {
+             int32_t order, const int64_t *given_order, int32_t nthreads, int32_t colours_limit,
+             const int8_t *force) {
   const int64_t N = or_n_sites(L);
   const int32_t C = or_n_colours(L);
   or_tables(); /* initialise the shell table before any parallel region reads it */
@@ -425,8 +448,10 @@ int or_sweep(const int32_t L[3], const or_model *m, uint8_t *occ, double tempera
 #ifdef _OPENMP
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 0 ? nthreads : 1)
 #endif
-      for (int64_t a = b0; a < b1; ++a)
+      for (int64_t a = b0; a < b1; ++a) {
         or_trial(L, m, occ, temperature_K, seed, replica, sweep, sites[a], &rec[a - b0]);
+        or_force(&rec[a - b0], force);
+      }
       for (int64_t a = b0; a < b1; ++a) {
         const or_trial_rec *r = &rec[a - b0];
         if (r->accept) {
@@ -438,6 +463,7 @@ int or_sweep(const int32_t L[3], const or_model *m, uint8_t *occ, double tempera
     } else {
       for (int64_t a = b0; a < b1; ++a) {
         or_trial(L, m, occ, temperature_K, seed, replica, sweep, sites[a], &rec[a - b0]);
+        or_force(&rec[a - b0], force);
         const or_trial_rec *r = &rec[a - b0];
         if (r->accept) {
           uint8_t t = occ[r->site];

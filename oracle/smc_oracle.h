@@ -90,7 +90,12 @@ void or_trial(const int32_t L[3], const or_model *m, const uint8_t *occ, double 
 /* Sweeps.  trace (optional) is indexed by trial site.  colours_limit < 0 runs every colour. */
 int or_sweep(const int32_t L[3], const or_model *m, uint8_t *occ, double temperature_K,
              uint64_t seed, int64_t replica, int64_t sweep, or_stats *st, or_trial_rec *trace,
-             int32_t order, const int64_t *given_order, int32_t nthreads, int32_t colours_limit);
+             int32_t order, const int64_t *given_order, int32_t nthreads, int32_t colours_limit,
+             const int8_t *force);
+/* force (nullable, [N]): force[s] in {0, 1} replaces the decision of a different-species trial
+ * at site s; negative entries leave the Metropolis decision. */
+void or_proposals(const int32_t L[3], uint64_t seed, int64_t replica, int64_t sweep, double temperature_K,
+                  const int64_t *sites, int64_t n, int32_t *dir, int64_t *partner, double *theta);
 
 /* Observables. alpha is [3][S][S]. */
 void or_warren_cowley(const int32_t L[3], const uint8_t *occ, int32_t n_species, double *alpha);
@@ -129,7 +134,7 @@ int32_t or_fcc_colour_of(const int32_t L[3], int64_t s);
 void or_fcc_propose(uint64_t seed, int64_t site, int64_t sweep, int64_t replica, int32_t *dir, double *u);
 int or_fcc_sweep(const int32_t L[3], const or_fcc_model *m, uint8_t *occ, double temperature_K, uint64_t seed,
                  int64_t replica, int64_t sweep, or_stats *st, or_trial_rec *trace, int32_t order,
-                 const int64_t *given_order, int32_t nthreads, int32_t colours_limit);
+                 const int64_t *given_order, int32_t nthreads, int32_t colours_limit, const int8_t *force);
 void or_fcc_warren_cowley(const int32_t L[3], const uint8_t *occ, int32_t n_species, double *alpha);
 
 /* Differentiation pattern (fit_oracle.c). */

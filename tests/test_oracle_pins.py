@@ -485,3 +485,65 @@ def test_equiatomic_counts_largest_remainder():
     assert c.tolist() == [6710887, 6710887, 6710886, 6710886, 6710886]
     occ = synth.random_occupancy((8, 8, 8), 4)
     assert np.bincount(occ).tolist() == [256] * 4
+
+
+def test_batched_proposals_follow_the_philox_definition():
+    """Batched proposals against numpy's Philox4x64-10 (a library routine) and a brute-force
+    neighbour lookup: slot = r0 >> 61, theta = -kB T ln(((r1 >> 11) + 1) 2^-53)."""
+    cells = (5, 6, 7)
+    sites = np.arange(0, oracle.n_sites(cells), 7)
+    T, seed, sweep_index, replica = 900.0, 11, 3, 2
+    d, p, th = oracle.proposals(cells, seed, replica, sweep_index, T, sites)
+    off, _ = oracle.shell_table()
+    nbr = brute_neighbor_map(cells, off[:8])
+    for a, s in enumerate(sites[:200]):
+        # numpy's block for counter c is the block of c + 1 (it increments before drawing)
+        ctr = np.array([int(s), sweep_index, replica, 0], dtype=np.uint64)
+        bg = np.random.Philox(counter=_counter_minus_one(ctr), key=np.array([seed, 0], dtype=np.uint64))
+        r = bg.random_raw(4)
+        assert d[a] == int(r[0]) >> 61
+        u = ((int(r[1]) >> 11) + 1) * 2.0 ** -53
+        assert th[a] == pytest.approx(-KB * T * math.log(u), rel=1e-15, abs=1e-300)
+        assert p[a] == nbr[s, d[a]]
+
+
+def _counter_minus_one(ctr):
+    c = [int(v) for v in ctr]
+    for k in range(4):
+        if c[k] > 0:
+            c[k] -= 1
+            break
+        c[k] = 2 ** 64 - 1
+    return np.array(c, dtype=np.uint64)
+
+
+def test_forced_decisions():
+    """An imposed decision replaces the Metropolis one: imposing every trial's own decision
+    changes nothing; imposing acceptance everywhere is the T = +inf sweep; imposing rejection
+    everywhere leaves the lattice as it was; imposing one flipped decision changes exactly
+    that pair of its colour and nothing before it."""
+    cells, m, occ0 = _c1_like()
+    ref = occ0.copy()
+    _, tr = oracle.sweep(cells, m, ref, 800.0, 0, 0, 0, trace=True)
+    o = occ0.copy()
+    own = np.where(tr["same"] == 1, -1, tr["accept"]).astype(np.int8)
+    _, tr2 = oracle.sweep(cells, m, o, 800.0, 0, 0, 0, trace=True, force=own)
+    assert np.array_equal(o, ref) and np.array_equal(tr2["accept"], tr["accept"])
+    o, inf = occ0.copy(), occ0.copy()
+    oracle.sweep(cells, m, o, 800.0, 0, 0, 0, force=np.ones(o.size, dtype=np.int8))
+    oracle.sweep(cells, m, inf, float("inf"), 0, 0, 0)
+    assert np.array_equal(o, inf)
+    o = occ0.copy()
+    oracle.sweep(cells, m, o, 800.0, 0, 0, 0, force=np.zeros(o.size, dtype=np.int8))
+    assert np.array_equal(o, occ0)
+    # flip the first different-species trial of the last colour: only that pair changes
+    C = oracle.n_colours(cells)
+    last = [s for s in np.nonzero(tr["colour"] == C - 1)[0] if tr["same"][s] == 0][0]
+    f = np.full(o.size, -1, dtype=np.int8)
+    f[last] = 1 - tr["accept"][last]
+    o = occ0.copy()
+    _, tr3 = oracle.sweep(cells, m, o, 800.0, 0, 0, 0, trace=True, force=f)
+    changed = np.nonzero(o != ref)[0]
+    assert set(changed) == {last, tr["partner"][last]}
+    assert tr3["accept"][last] == 1 - tr["accept"][last]
+    assert tr3["dE"][last] == tr["dE"][last]
