@@ -45,27 +45,35 @@ def compare_sweep(cells, model, occ_oracle, temperature, seed, sweep_index, gpu_
                   check_de=True, de_tol=FP32_DE_TOL_EV, nthreads=8):
     """Advance the oracle one sweep and compare it with the GPU's trace and occupancy.
 
-    Returns the number of tolerated near-threshold disagreements; on one, the GPU's state is
-    copied into the oracle (the chains would otherwise diverge)."""
-    st, tr = oracle.sweep(cells, model, occ_oracle, temperature, seed, 0, sweep_index, trace=True,
-                          nthreads=nthreads)
+    A decision that differs from the oracle's is tolerated only where the oracle's dE lies
+    within DECISION_BAND_EV of the threshold.  The oracle's sweep is then run again from the
+    same start with the GPU's decision imposed on exactly those trials (every other trial keeps
+    the oracle's own Metropolis decision), and the whole lattice and every other decision must
+    still agree.  Returns (number of tolerated disagreements, oracle trace)."""
+    start = occ_oracle.copy()
     flags = gpu_trace["flags"]
     acc_gpu = (flags & 1).astype(bool)
     same_gpu = (flags & 2).astype(bool)
-    assert np.array_equal(same_gpu, tr["same"].astype(bool))
-    acc_or = tr["accept"].astype(bool)
-    diff = np.nonzero(acc_gpu != acc_or)[0]
+    force = np.full(occ_oracle.size, -1, dtype=np.int8)
     tolerated = 0
-    for s in diff:
-        gap = abs(tr["dE"][s] - tr["theta"][s])
-        assert gap < DECISION_BAND_EV, (
-            f"sweep {sweep_index} site {s}: gpu accept {acc_gpu[s]} oracle {acc_or[s]} "
-            f"dE_oracle {tr['dE'][s]!r} theta {tr['theta'][s]!r} dE_gpu {gpu_trace['dE'][s]!r}")
-        tolerated += 1
-    if tolerated:
-        occ_oracle[:] = gpu_occ
+    for _ in range(64):
+        occ_oracle[:] = start
+        st, tr = oracle.sweep(cells, model, occ_oracle, temperature, seed, 0, sweep_index, trace=True,
+                              nthreads=nthreads, force=force if tolerated else None)
+        assert np.array_equal(same_gpu, tr["same"].astype(bool))
+        diff = np.nonzero(acc_gpu != tr["accept"].astype(bool))[0]
+        if diff.size == 0:
+            break
+        for s in diff:
+            gap = abs(tr["dE"][s] - tr["theta"][s])
+            assert force[s] < 0 and gap < DECISION_BAND_EV, (
+                f"sweep {sweep_index} site {s}: gpu accept {acc_gpu[s]} oracle {tr['accept'][s]} "
+                f"dE_oracle {tr['dE'][s]!r} theta {tr['theta'][s]!r} dE_gpu {gpu_trace['dE'][s]!r}")
+            force[s] = 1 if acc_gpu[s] else 0
+            tolerated += 1
     else:
-        assert np.array_equal(gpu_occ, occ_oracle), f"occupancy differs after sweep {sweep_index}"
+        raise AssertionError("forced re-runs of the oracle sweep did not converge")
+    assert np.array_equal(gpu_occ, occ_oracle), f"occupancy differs after sweep {sweep_index}"
     if check_de:
         d = ~tr["same"].astype(bool)
         err = np.abs(gpu_trace["dE_fast"][d] - tr["dE"][d])

@@ -71,19 +71,32 @@ def _check_running_total(mc, d0, accepts, rechecks, per_recheck):
 
 
 def _compare_sweep(cells, model, occ_or, T, seed, replica, sweep, tr, gpu_occ, de_tol):
-    st, ref = fcc.sweep(cells, model, occ_or, T, seed, replica, sweep, trace=True, nthreads=8)
+    """One oracle sweep against the GPU's.  A decision that differs is tolerated only within
+    DECISION_BAND_EV of the threshold; the oracle sweep is then run again from the same start
+    with the GPU's decision imposed on exactly those trials, and the lattice and every other
+    decision must agree.  Returns (oracle stats of the final run, tolerated disagreements)."""
+    start = occ_or.copy()
     flags = tr["flags"]
     same = (flags & 2).astype(bool)
-    assert np.array_equal(same, ref["same"].astype(bool))
     acc_gpu = (flags & 1).astype(bool)
-    diff = np.nonzero(acc_gpu != ref["accept"].astype(bool))[0]
-    for s in diff:
-        gap = abs(ref["dE"][s] - ref["theta"][s])
-        assert gap < DECISION_BAND_EV, (sweep, s, ref["dE"][s], ref["theta"][s], tr["dE"][s])
-    if len(diff):
-        occ_or[:] = gpu_occ
+    force = np.full(occ_or.size, -1, dtype=np.int8)
+    tolerated = 0
+    for _ in range(64):
+        occ_or[:] = start
+        st, ref = fcc.sweep(cells, model, occ_or, T, seed, replica, sweep, trace=True, nthreads=8,
+                            force=force if tolerated else None)
+        assert np.array_equal(same, ref["same"].astype(bool))
+        diff = np.nonzero(acc_gpu != ref["accept"].astype(bool))[0]
+        if diff.size == 0:
+            break
+        for s in diff:
+            gap = abs(ref["dE"][s] - ref["theta"][s])
+            assert force[s] < 0 and gap < DECISION_BAND_EV, (sweep, s, ref["dE"][s], ref["theta"][s], tr["dE"][s])
+            force[s] = 1 if acc_gpu[s] else 0
+            tolerated += 1
     else:
-        assert np.array_equal(gpu_occ, occ_or), f"occupancy differs after sweep {sweep}"
+        raise AssertionError("forced re-runs of the oracle sweep did not converge")
+    assert np.array_equal(gpu_occ, occ_or), f"occupancy differs after sweep {sweep}"
     d = ~ref["same"].astype(bool)
     if de_tol is not None:
         err = np.abs(tr["dE_fast"][d] - ref["dE"][d])
@@ -91,7 +104,7 @@ def _compare_sweep(cells, model, occ_or, T, seed, replica, sweep, tr, gpu_occ, d
     fp64 = d & ((flags & 4) != 0)
     if fp64.any():
         assert np.abs(tr["dE"][fp64] - ref["dE"][fp64]).max() < 1e-9
-    return st, len(diff)
+    return st, tolerated
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", None), ("fp32", 1e-5), ("bf16x3", 2e-4), ("bf16", None)])

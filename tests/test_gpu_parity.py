@@ -81,54 +81,6 @@ def test_uneven_lattice_and_five_species():
     mc.close()
 
 
-def test_c2_full_size_sampled():
-    """64^3 cells: the oracle re-decides sampled trials of every colour on the state the
-    GPU's own decisions imply, and the replayed decisions reproduce the GPU lattice."""
-    need_gpu()
-    w, mc, model, occ = make("c2")
-    cells, T = w.cells[0], w.temperatures[0]
-    col = _colours_fast(cells)
-    rng = np.random.default_rng(0)
-    for t in range(2):
-        _banner(f"c2 sampled sweep {t}")
-        tr = trace_to_numpy(mc.sweep(1, stats=True, trace=True))
-        flags = tr["flags"]
-        assert tr["attempts"][0] == occ.size
-        for c in range(oracle.n_colours(cells)):
-            members = np.nonzero(col == c)[0]
-            for s in rng.choice(members, size=3, replace=False):
-                rec = oracle.trial(cells, model, occ, T, w.seed, 0, t, int(s))
-                assert bool(flags[s] & 2) == bool(rec["same"])
-                if not rec["same"]:
-                    assert abs(tr["dE_fast"][s] - rec["dE"]) < 1e-5
-                    if abs(rec["dE"] - rec["theta"]) >= 1e-9:
-                        assert bool(flags[s] & 1) == bool(rec["accept"])
-            acc = members[(flags[members] & 1).astype(bool)]
-            for s in acc:
-                d, _ = oracle.propose(w.seed, int(s), t, 0)
-                n = oracle.neighbor(cells, int(s), d)
-                occ[s], occ[n] = occ[n], occ[s]
-        assert np.array_equal(occ, mc.occ.cpu().numpy())
-    es, er = mc.energy()
-    assert abs(es[0] - er[0]) < 1e-6 * abs(es[0])
-    mc.close()
-
-
-def _colours_fast(cells):
-    """Colour of every site from the schedule rule (link cells of 4 for these sizes)."""
-    lx, ly, lz = cells
-    assert lx % 4 == 0 and ly % 4 == 0 and lz % 4 == 0
-    s = np.arange(2 * lx * ly * lz)
-    b = s % 2
-    c = s // 2
-    x, y, z = c % lx, (c // lx) % ly, c // (lx * ly)
-    col = (((z % 4) * 4 + (y % 4)) * 4 + (x % 4)) * 2 + b
-    # cross-check the rule with the oracle on a few sites
-    for k in range(0, len(s), len(s) // 50):
-        assert col[k] == oracle.lib().or_colour_of(oracle._ptr(oracle._dims(cells), oracle.C.c_int32), k)
-    return col
-
-
 def test_split_run_equals_long_run_and_resume():
     need_gpu()
     _banner("split/resume")
