@@ -25,7 +25,7 @@ PRECISIONS = {"fp32": SMC_FP32, "bf16": SMC_BF16, "bf16x3": SMC_BF16X3, "fp8": S
               "fp64": SMC_FP64}
 
 EXPORTS = ["smc_init", "smc_sweep", "smc_energy", "smc_site_energies", "smc_set_params",
-           "smc_refresh", "smc_counters", "smc_delta_e64", "smc_profile", "smc_kernel_times", "smc_get_sweep",
+           "smc_refresh", "smc_counters", "smc_delta_e64", "smc_delta_e64_noalloc", "smc_profile", "smc_kernel_times", "smc_get_sweep",
            "smc_set_sweep", "smc_set_temperatures", "smc_warren_cowley", "smc_set_strategy", "smc_get_strategy", "smc_use_graph", "smc_set_variant", "smc_get_variant", "smc_autotune",
            "smc_energy_fwd", "smc_energy_bwd", "smc_fit_step", "smc_ce_energy", "smc_ce_triangles", "smc_lattice_shells",
            "smc_n_sites", "smc_n_colours", "smc_destroy", "smc_last_error", "smc_status_string"]
@@ -76,6 +76,7 @@ def lib():
             "smc_counters": (C.c_int, [vp, C.POINTER(C.c_uint64), C.c_int32]),
             "smc_delta_e64": (C.c_int, [vp, C.c_int32, C.c_uint64, C.POINTER(C.c_int64), C.c_int32,
                                         C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
+            "smc_delta_e64_noalloc": (C.c_int, [vp, C.c_int32, C.c_uint64, vp, C.c_int32, vp, vp]),
             "smc_profile": (C.c_int, [vp, C.c_int32]),
             "smc_kernel_times": (C.c_int, [vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                            C.POINTER(C.c_int64)]),
@@ -178,6 +179,12 @@ def smc_delta_e64(ctx, replica, sweep, sites):
                               partner.ctypes.data_as(C.POINTER(C.c_int64)),
                               dE.ctypes.data_as(C.POINTER(C.c_double))), ctx)
     return partner, dE
+
+
+def smc_delta_e64_noalloc(ctx, replica, sweep, sites_ptr, n, partner_ptr, dE_ptr):
+    """Device pointers (ints); asynchronous, allocates nothing."""
+    check(lib().smc_delta_e64_noalloc(ctx, int(replica), int(sweep), sites_ptr or None, int(n),
+                                      partner_ptr or None, dE_ptr or None), ctx)
 
 
 def smc_profile(ctx, enable):

@@ -74,6 +74,8 @@ struct smc_ctx {
   int32_t n_in = 0, hidden = 0, n_params = 0;
   bool mfma = false;              // one-hot features with 128 hidden: matrix-core path
   int n_cu = 256;
+  int device = 0;                 // device current at smc_init
+  void *scratch = nullptr;        // device address of the probe's static work space on that device
   hipStream_t stream = nullptr;
   uint8_t *occ = nullptr;
   float *ecache = nullptr;

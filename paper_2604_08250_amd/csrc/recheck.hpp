@@ -58,6 +58,7 @@ __global__ __launch_bounds__(kRcThreads) void k_recheck(RecheckArgs a) {
     const uint32_t q = w / kRcSplit;
     const int r0 = (int)(w % kRcSplit) * kRcRowsB;
     const RecheckEntry &e = a.queue[q];
+    if (e.site < 0) continue;  // probe entry without a valid site (uniform across the block)
     const Replica R = a.reps[e.replica];
     uint8_t *occ = a.occ + R.site0;
     const Pos pi = site_pos(e.site, R.L[0], R.L[1]);

@@ -4,6 +4,7 @@
 #include <stdio.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -512,6 +513,70 @@ int run_sweep(smc_ctx *c, const smc_stats *st, bool last) {
 
 }  // namespace
 
+// ---------------------------------------------------------------- probe without allocation
+//
+// Work space of smc_delta_e64_noalloc: the probe's queue entries followed by the queue
+// length.  Each GPU the library runs on holds its own copy until the process ends.  On the
+// host this name is only a stand-in symbol, never a device address: host code uses the
+// address resolved per device by noalloc_scratch() (at context creation, with the context's
+// device current) and passes that to the kernels.
+constexpr size_t kNoAllocEntryBytes = sizeof(RecheckEntry) * SMC_NOALLOC_MAX_TRIALS;
+constexpr size_t kNoAllocBytes = kNoAllocEntryBytes + 256;
+static __device__ __align__(256) uint8_t scratch[kNoAllocBytes];
+
+namespace smc {
+
+// Device address of `scratch` on device `dev`, resolved once per device (the device must be
+// current).  SMC_E_DEVICE if the runtime cannot resolve it.
+int noalloc_scratch(int dev, void **out) {
+  static std::mutex mu;
+  static std::vector<void *> addr;
+  std::lock_guard<std::mutex> lock(mu);
+  if (dev < 0) return SMC_E_INVALID;
+  if ((int)addr.size() <= dev) addr.resize(dev + 1, nullptr);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SMC_E_DEVICE;
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return SMC_OK;
+}
+
+// Queue entries of the probe from device site indices: the proposal of each trial site (the
+// Philox block of (site, sweep, replica, 0), partner slot r0 >> 61).  A site outside the
+// replica gets no evaluation: partner -1 and dE NaN.
+__global__ void k_probe_entries(const Replica *reps, int32_t replica, uint64_t sweep, uint64_t seed,
+                                const int64_t *sites, int32_t n, RecheckEntry *entries, uint32_t *q_count,
+                                int64_t *partner_out, double *dE_out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k == 0) *q_count = (uint32_t)n;
+  if (k >= n) return;
+  const Replica R = reps[replica];
+  const int64_t s = sites[k];
+  RecheckEntry &e = entries[k];
+  e.replica = replica;
+  e.theta = 0.0;
+  e.dE_fast = 0.0f;
+  if (s < 0 || s >= R.n_sites) {
+    e.site = -1;
+    e.partner = -1;
+    e.dir = 0;
+    if (partner_out) partner_out[k] = -1;
+    dE_out[k] = (double)NAN;
+    return;
+  }
+  const U64x4 r = philox4x64_10((uint64_t)s, sweep, (uint64_t)replica, 0, seed, 0);
+  const int d = (int)(r.v[0] >> 61);
+  const Pos p = site_pos(s, R.L[0], R.L[1]);
+  e.site = s;
+  e.dir = d;
+  e.partner = site_at(p, shell_dx(d), shell_dy(d), shell_dz(d), R.L[0], R.L[1], R.L[2]);
+  if (partner_out) partner_out[k] = e.partner;
+}
+
+}  // namespace smc
+
 extern "C" {
 
 const char *smc_status_string(int s) {
@@ -527,6 +592,7 @@ const char *smc_status_string(int s) {
 }
 
 const char *smc_last_error(const smc_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
 
 int smc_init(const smc_config *cfg, uint8_t *occ_dev, const float *params_dev, float *ecache_dev,
              void *hip_stream, smc_ctx **out) {
@@ -582,6 +648,7 @@ int smc_init(const smc_config *cfg, uint8_t *occ_dev, const float *params_dev, f
     int n = 0;
     if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0) c->n_cu = n;
   }
+  c->device = dev;
   int64_t site0 = 0, max_trials = 0;
   for (int r = 0; r < cfg->n_replicas; ++r) {
     c->reps.push_back(make_replica(&c->cells[3 * r], site0, c->temps[r]));
@@ -643,6 +710,11 @@ int smc_init(const smc_config *cfg, uint8_t *occ_dev, const float *params_dev, f
       hipMemcpyAsync(c->d_omega, om.off.data(), sizeof(om.off), hipMemcpyHostToDevice, c->stream))
     return cleanup(SMC_E_DEVICE);
   if (mfma) {
+    // work space of the probe without allocation, resolved once per device
+    if (noalloc_scratch(dev, &c->scratch) != SMC_OK) {
+      smc_destroy(c);
+      return SMC_E_DEVICE;
+    }
     const RegionTables t = build_region_tables();
     if (t.reg_off.empty()) return cleanup(SMC_E_DEVICE);
     c->queue_cap = max_trials;
@@ -807,6 +879,46 @@ int smc_delta_e64(smc_ctx *c, int32_t replica, uint64_t sweep, const int64_t *si
   (void)hipFree(d_done);
   (void)hipFree(d_n);
   return rc;
+}
+
+
+int smc_delta_e64_noalloc(smc_ctx *c, int32_t replica, uint64_t sweep, const int64_t *sites_dev, int32_t n,
+                          int64_t *partner_dev, double *dE_dev) {
+  if (!c) return SMC_E_INVALID;
+  if (replica < 0 || replica >= (int32_t)c->reps.size()) return fail(c, SMC_E_INVALID, "replica out of range");
+  if (n < 0) return fail(c, SMC_E_INVALID, "n < 0");
+  if (n > SMC_NOALLOC_MAX_TRIALS)
+    return fail(c, SMC_E_INVALID, "n = " + std::to_string(n) + " exceeds the work space of " +
+                                      std::to_string(SMC_NOALLOC_MAX_TRIALS) + " trials (SMC_NOALLOC_MAX_TRIALS)");
+  if (c->fcc.on || !c->mfma)
+    return fail(c, SMC_E_UNSUPPORTED, "the probe without allocation needs BCC, one-hot features and 128 hidden");
+  if (n == 0) return SMC_OK;
+  if (!sites_dev || !dE_dev) return fail(c, SMC_E_INVALID, "null device array");
+  if (!c->scratch) return fail(c, SMC_E_DEVICE, "work-space address not resolved");
+  RecheckEntry *entries = (RecheckEntry *)c->scratch;
+  uint32_t *qn = (uint32_t *)((uint8_t *)c->scratch + kNoAllocEntryBytes);
+  hipLaunchKernelGGL(k_probe_entries, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, c->d_reps, replica, sweep,
+                     c->cfg.seed, sites_dev, n, entries, qn, partner_dev, dE_dev);
+  RecheckArgs ra{};
+  ra.reps = c->d_reps;
+  ra.occ = c->occ;
+  ra.ecache = c->ecache;
+  ra.w64 = c->d_w64t;
+  ra.reg_off = c->d_reg_off;
+  ra.om_off = c->d_om_off;
+  ra.idx = c->d_idx;
+  ra.reg_pos = c->d_reg_pos;
+  ra.q_count = qn;
+  ra.queue = entries;
+  ra.e_fixed = c->d_efixed;
+  ra.counters = c->d_counters;
+  ra.n_replicas = (int32_t)c->reps.size();
+  ra.probe_dE = dE_dev;  // probe mode: writes dE, changes nothing else
+  ra.row_e = nullptr;    // not used with one block per trial
+  ra.done = nullptr;
+  hipLaunchKernelGGL(k_recheck, dim3(std::min(kRcSplit * n, 8 * c->n_cu)), dim3(kRcThreads), 0, c->stream, ra);
+  HIPC(c, hipGetLastError());
+  return SMC_OK;
 }
 
 int smc_set_params(smc_ctx *c, const float *params_dev) {
