@@ -169,13 +169,14 @@ int smc_delta_e64(smc_ctx *ctx, int32_t replica, uint64_t sweep, const int64_t *
  * device [n]; dE_dev: double device [n].  Same proposals and the same FP64 evaluator as
  * smc_delta_e64 (bit-identical results); a site outside the replica gets partner -1 and dE NaN.
  * Asynchronous on the context's stream: no host synchronisation, no hipMalloc or hipFree.  The
- * work space is a fixed library array of SMC_NOALLOC_MAX_TRIALS queue entries (about 3.2 MB)
- * that every GPU the library runs on holds until the process ends; n above the limit gives
+ * work space is a fixed library array of SMC_NOALLOC_MAX_TRIALS queue entries and their FP64
+ * row energies (about 6.9 MB) that every GPU the library runs on holds until the process ends;
+ * n above the limit gives
  * SMC_E_INVALID, larger batches are split by the caller.  All calls on one GPU share that array
  * and it keeps the last call's contents: calls whose work can overlap on one GPU (other
  * streams, contexts or threads) race, and the caller must order them.  BCC with one-hot
  * features and 128 hidden only (else SMC_E_UNSUPPORTED). */
-#define SMC_NOALLOC_MAX_TRIALS 16384
+#define SMC_NOALLOC_MAX_TRIALS 8192
 int smc_delta_e64_noalloc(smc_ctx *ctx, int32_t replica, uint64_t sweep, const int64_t *sites_dev, int32_t n,
                           int64_t *partner_dev, double *dE_dev);
 

@@ -85,6 +85,7 @@ struct smc_ctx {
   float *d_w32 = nullptr;
   double *d_w64 = nullptr;
   double *d_w64t = nullptr;       // FP64 blob with W0, W1 stored [input][unit] (re-decision kernel)
+  float *d_w32t = nullptr;        // the same layout in FP32 (staged in LDS by the re-decision kernel)
   int8_t *d_omega = nullptr;      // per-lane path Omega offsets
   int32_t omega_n = 0;
   uint16_t *d_reg_off = nullptr, *d_om_off = nullptr;
@@ -92,7 +93,6 @@ struct smc_ctx {
   smc::DevPack packs[4];
   smc::RecheckEntry *d_queue = nullptr;
   double *d_rowe = nullptr;       // [queue_cap][80] FP64 local energies of queued trials
-  uint32_t *d_done = nullptr;     // [queue_cap] per-entry completion counters
   uint32_t *d_qcount = nullptr;   // one counter per colour index of a sweep
   int64_t queue_cap = 0;
   int32_t colours_total = 0;

@@ -108,6 +108,7 @@ __global__ __launch_bounds__(256) void k_dl_decide(DlArgs a) {
     if (fabs(dEd - tr.theta) < a.guard) {
       const uint32_t slot = atomicAdd(a.q_count, 1u);
       RecheckEntry &e = a.queue[slot];
+      e.has_reg = 0;
       e.site = i;
       e.partner = n;
       e.theta = tr.theta;

@@ -79,6 +79,16 @@ __device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
 __device__ __forceinline__ float bf16_lo_f32(uint32_t w) { return __builtin_bit_cast(float, w << 16); }
 __device__ __forceinline__ float bf16_hi_f32(uint32_t w) { return __builtin_bit_cast(float, w & 0xffff0000u); }
 
+// Two activations (folded SiLU, s = 1) split into BF16 hi and lo parts for the split-BF16
+// products: x = y * r with r = 1 / (1 + 2^y); hi = bf16(x); lo = bf16(y * r - hi) with the
+// product unrounded (one fma).
+__device__ __forceinline__ void act_split(float y0, float y1, uint32_t &hi, uint32_t &lo) {
+  const float r0 = __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(y0) + 1.0f);
+  const float r1 = __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(y1) + 1.0f);
+  hi = pack_bf16x2(y0 * r0, y1 * r1);
+  lo = pack_bf16x2(fmaf(y0, r0, -bf16_lo_f32(hi)), fmaf(y1, r1, -bf16_hi_f32(hi)));
+}
+
 // One-hot of a species id (0..3; 4 and above: no channel) as 4 BF16 values in 2 dwords.
 __device__ __forceinline__ void onehot_bf16(uint32_t p, uint32_t &lo, uint32_t &hi) {
   const uint32_t one = 0x3F80u << ((p & 1u) << 4);
@@ -363,11 +373,14 @@ __device__ __forceinline__ float eval_tile(const EvalSmem &S, GetSlot get) {
     auto build = [&](int T, int hh, i32x4 &bh, i32x4 &bl) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const float x0 = act(acc[T][8 * hh + 2 * q], 1.0f);
-        const float x1 = act(acc[T][8 * hh + 2 * q + 1], 1.0f);
-        const uint32_t w = pack_bf16x2(x0, x1);
-        bh[q] = (int)w;
-        if constexpr (P == kPBF16X3) bl[q] = (int)pack_bf16x2(x0 - bf16_lo_f32(w), x1 - bf16_hi_f32(w));
+        if constexpr (P == kPBF16X3) {
+          uint32_t h, l;
+          act_split(acc[T][8 * hh + 2 * q], acc[T][8 * hh + 2 * q + 1], h, l);
+          bh[q] = (int)h;
+          bl[q] = (int)l;
+        } else {
+          bh[q] = (int)pack_bf16x2(act(acc[T][8 * hh + 2 * q], 1.0f), act(acc[T][8 * hh + 2 * q + 1], 1.0f));
+        }
       }
     };
     i32x4 bh[2], bl[2], bh7, bl7;

@@ -1,7 +1,16 @@
 // FP64 re-decision of the near-threshold trials queued by the matrix-core colour kernel (and
-// of the double-lattice strategy): the local energies of the zone before and after the swap in
-// FP64, their difference reduced in zone order, the Metropolis decision and the apply.
+// of the double-lattice strategy, and the FP64 probes): the local energies of the zone before
+// and after the swap in FP64, their difference reduced in zone order, the Metropolis decision
+// and the apply.
+//
+// Two launches per colour.  k_recheck_rows evaluates the 80 FP64 local energies of every
+// queued trial (rows 0..39: the zone after the swap, 40..79: before), 16 rows per block, so
+// that even a short queue spreads over the whole GPU; k_recheck_decide then reduces each
+// trial's rows in zone order, decides and applies.  The kernel boundary between them orders
+// the row energies before their use, with no device-scope fence.
 #pragma once
+#include <algorithm>
+
 #include "sweep_mfma.hpp"
 
 namespace smc {
@@ -11,6 +20,7 @@ struct RecheckArgs {
   uint8_t *occ;
   float *ecache;
   const double *w64;        // FP64 blob with W0 and W1 transposed ([input][unit]) for coalescing
+  const float *w32t;        // the same layout in FP32 (the model's own values), staged in LDS
   const uint16_t *reg_off;  // [8][192]
   const uint16_t *om_off;   // [8][40]
   const uint8_t *idx;       // [8][40][28]
@@ -24,163 +34,206 @@ struct RecheckArgs {
   uint8_t *trace_flags;
   double *probe_dE;   // non-null: write dE of queue entry q to probe_dE[q] and change nothing
   double *row_e;      // [queue capacity][80] FP64 local energies
-  uint32_t *done;     // [queue capacity] blocks finished per entry, zero between uses
 };
 
-constexpr int kRcThreads = 1024;
 constexpr int kRows64 = 2 * kOm;              // rows 0..39 after the swap, 40..79 before
-constexpr int kRcSplit = 1;                   // blocks sharing one queued trial
-constexpr int kRcRowsB = kRows64 / kRcSplit;  // rows per block: all 80
-constexpr int kRcParts = kRcThreads / kHid;   // 8 threads per hidden unit
-constexpr int kRcRows = kRcRowsB / kRcParts;  // rows per thread: 10
+constexpr int kRcRowsB = 16;                  // rows per work item of k_recheck_rows
+constexpr int kRcBlocksPerTrial = kRows64 / kRcRowsB;  // 5 work items per queued trial
+constexpr int kRcThreads = 512;
 constexpr int kHStride = kHid + 1;            // padded row stride of the activation buffer
+static_assert(kRcRowsB * kRcBlocksPerTrial == kRows64, "row split");
 
-// One block per (queued trial, block of kRcRowsB rows); with kRcSplit = 1 a block holds all
-// 80 rows of its trial and reduces them from LDS.  With a split, each block writes its rows to
-// row_e and the block that completes a trial (per-trial counter) reduces the 80 energies; the
-// reduction is in a fixed order either way, then the decision and the apply.  No block ever
-// waits for another.  A split was measured several times slower: every block's device-scope
-// fence writes back the L2 that the colour kernel has just dirtied.  The layer-0 slot loop
-// stays rolled: at 1024 threads (128 VGPRs) unrolling it by three already spills.
-__global__ __launch_bounds__(kRcThreads) void k_recheck(RecheckArgs a) {
-  __shared__ double s_h[kRcRowsB * kHStride];  // activations, then per-unit terms of layer 2
-  __shared__ double s_part[kRcRowsB * kRcParts];
-  __shared__ uint8_t s_reg[kReg];
-  __shared__ uint8_t s_sp[kRcRowsB * 27];
-  __shared__ double s_e[kRows64];
-  __shared__ int s_last, s_accept;
+// Work item w: queued trial q = w / 5 and its rows r0 = 16 (w % 5) .. r0 + 15.
+// Arithmetic order of each row energy (fixed; every FP64 evaluation of a zone uses it):
+//   z0[u] = b0[u] + the W0 column of slot m's species, added for m = 0..26 (species 4: none);
+//   z1[u] = b1[u] + sum over k = 0..127 of W1[u][k] silu(z0[k]), one fma per k in order;
+//   E = b2 + sum over chunks c = 0..7 of (sum over i = 0..15 of W2[16c+i] silu(z1[16c+i])).
+// Persistent blocks, one per CU: each stages W0 and W1 in LDS once (their FP32 values, which
+// the FP64 arithmetic takes exactly) and then walks work items with no weight traffic, two at
+// a time (one per half block), so that the gathers and LDS round trips of two items overlap.
+// In a half: layer 0, thread t owns unit t % 128 of rows 8(t / 128) .. +7; layer 1, thread t
+// owns units 4(t % 32) .. +3 of rows 2(t / 32) and +1.
+constexpr int kRcHalf = kRcThreads / 2;
+__global__ __launch_bounds__(kRcThreads) void k_recheck_rows(RecheckArgs a) {
+  __shared__ __attribute__((aligned(16))) float s_w0[108 * kHid];
+  __shared__ __attribute__((aligned(16))) float s_w1[kHid * kHid];
+  __shared__ double s_h[2][kRcRowsB * kHStride];  // silu(z0), then the W2-weighted silu(z1)
+  __shared__ double s_part[2][kRcRowsB * 8];
+  __shared__ uint8_t s_reg[2][kReg];
+  __shared__ uint8_t s_sp[2][kRcRowsB * 27];
   const uint32_t n = *a.q_count;
-  const int tid = threadIdx.x;
-  const int o = tid % kHid, part = tid / kHid;  // thread owns unit o for local rows part + 8j
-  const double *W0 = a.w64, *b0 = W0 + kHid * 108, *W1 = b0 + kHid, *b1 = W1 + kHid * kHid, *W2 = b1 + kHid,
-               *b2 = W2 + kHid;
-  for (uint32_t w = blockIdx.x; w < n * kRcSplit; w += gridDim.x) {
-    const uint32_t q = w / kRcSplit;
-    const int r0 = (int)(w % kRcSplit) * kRcRowsB;
-    const RecheckEntry &e = a.queue[q];
-    if (e.site < 0) continue;  // probe entry without a valid site (uniform across the block)
-    const Replica R = a.reps[e.replica];
-    uint8_t *occ = a.occ + R.site0;
-    const Pos pi = site_pos(e.site, R.L[0], R.L[1]);
-    const int d = e.dir;
-    const uint8_t si = occ[e.site], sn = occ[e.partner];
-    const int pos_i = a.reg_pos[2 * d], pos_n = a.reg_pos[2 * d + 1];
-    if (tid < kReg) {
-      int dx, dy, dz;
-      unpack_off(a.reg_off[d * kReg + tid], dx, dy, dz);
-      s_reg[tid] = occ[site_at(pi, dx, dy, dz, R.L[0], R.L[1], R.L[2])];
+  const uint32_t items = n * kRcBlocksPerTrial;
+  if (2 * blockIdx.x >= items) return;  // no work item for this block
+  const int tid = threadIdx.x, hf = tid / kRcHalf, lt = tid % kRcHalf;
+  const double *b0 = a.w64 + kHid * 108, *b1 = b0 + kHid + kHid * kHid, *W2 = b1 + kHid, *b2 = W2 + kHid;
+  {
+    const float4 *w0 = (const float4 *)a.w32t;
+    const float4 *w1 = (const float4 *)(a.w32t + kHid * 108 + kHid);
+    for (int q = tid; q < 108 * kHid / 4; q += kRcThreads) ((float4 *)s_w0)[q] = w0[q];
+    for (int q = tid; q < kHid * kHid / 4; q += kRcThreads) ((float4 *)s_w1)[q] = w1[q];
+  }
+  double *h = s_h[hf];
+  for (uint32_t base = 2 * blockIdx.x; base < items; base += 2 * gridDim.x) {
+    // every thread reaches every barrier; a half without a valid item computes nothing
+    const uint32_t w = base + hf;
+    const uint32_t q = w / kRcBlocksPerTrial;
+    const int r0 = (int)(w - q * kRcBlocksPerTrial) * kRcRowsB;
+    const bool live = w < items && a.queue[q].site >= 0;
+    const RecheckEntry &e = a.queue[live ? q : 0];
+    int d = 0, has_reg = 0;
+    if (live) {
+      d = e.dir;
+      has_reg = e.has_reg;
+      if (has_reg) {
+        // the colour kernel queued the region with the trial (swap applied)
+        if (lt < kReg / 4) ((uint32_t *)s_reg[hf])[lt] = ((const uint32_t *)e.reg)[lt];
+      } else if (lt < kReg) {
+        const Replica R = a.reps[e.replica];
+        const Pos pi = site_pos(e.site, R.L[0], R.L[1]);
+        int dx, dy, dz;
+        unpack_off(a.reg_off[d * kReg + lt], dx, dy, dz);
+        s_reg[hf][lt] = a.occ[R.site0 + site_at(pi, dx, dy, dz, R.L[0], R.L[1], R.L[2])];
+      }
     }
     __syncthreads();
-    // slot species of this block's rows (post-swap rows see i and n exchanged)
-    for (int v = tid; v < kRcRowsB * 27; v += kRcThreads) {
-      const int lr = v / 27, m = v - lr * 27, gr = r0 + lr;
-      const bool post = gr < kOm;
-      const int p = a.idx[(d * kOm + (post ? gr : gr - kOm)) * kIdxRow + m];
-      s_sp[v] = post ? (p == pos_i ? sn : (p == pos_n ? si : s_reg[p])) : s_reg[p];
+    // slot species of this item's rows: the rows after the swap see i and n exchanged relative
+    // to the rows before (s_reg holds the lattice after the swap when has_reg, else before)
+    if (live) {
+      const int pos_i = a.reg_pos[2 * d], pos_n = a.reg_pos[2 * d + 1];
+      const uint8_t at_i = s_reg[hf][pos_i], at_n = s_reg[hf][pos_n];
+      for (int v = lt; v < kRcRowsB * 27; v += kRcHalf) {
+        const int lr = v / 27, m = v - lr * 27, gr = r0 + lr;
+        const bool post = gr < kOm;
+        const int p = a.idx[(d * kOm + (post ? gr : gr - kOm)) * kIdxRow + m];
+        const bool exch = post != (has_reg != 0);
+        s_sp[hf][v] = exch ? (p == pos_i ? at_n : (p == pos_n ? at_i : s_reg[hf][p])) : s_reg[hf][p];
+      }
     }
     __syncthreads();
-    // layer 0 + activation: the selected W0 column of each slot, added in slot order
-    {
-      double acc[kRcRows];
+    // layer 0 + activation
+    if (live) {
+      const int o = lt % kHid, rb = (lt / kHid) * 8;
+      double acc[8];
 #pragma unroll
-      for (int j = 0; j < kRcRows; ++j) acc[j] = b0[o];
-#pragma unroll 1
+      for (int j = 0; j < 8; ++j) acc[j] = b0[o];
+#pragma unroll 3
       for (int m = 0; m < 27; ++m) {
-        const double w0 = W0[(4 * m) * kHid + o], w1 = W0[(4 * m + 1) * kHid + o],
-                     w2 = W0[(4 * m + 2) * kHid + o], w3 = W0[(4 * m + 3) * kHid + o];
 #pragma unroll
-        for (int j = 0; j < kRcRows; ++j) {
-          const int sp = s_sp[(part + kRcParts * j) * 27 + m];
-          const double wv = sp == 0 ? w0 : (sp == 1 ? w1 : (sp == 2 ? w2 : w3));
-          if (sp < 4) acc[j] += wv;
+        for (int j = 0; j < 8; ++j) {
+          const int sp = s_sp[hf][(rb + j) * 27 + m];
+          if (sp < 4) acc[j] += (double)s_w0[(4 * m + sp) * kHid + o];
         }
       }
 #pragma unroll
-      for (int j = 0; j < kRcRows; ++j) s_h[(part + kRcParts * j) * kHStride + o] = silu<double>(acc[j]);
+      for (int j = 0; j < 8; ++j) h[(rb + j) * kHStride + o] = silu<double>(acc[j]);
     }
     __syncthreads();
     // layer 1 + activation, times W2
     {
-      double acc[kRcRows];
+      const int u0 = 4 * (lt % 32), ra = 2 * (lt / 32);
+      double acc[2][4];
+      if (live) {
 #pragma unroll
-      for (int j = 0; j < kRcRows; ++j) acc[j] = b1[o];
-#pragma unroll 16
-      for (int k = 0; k < kHid; ++k) {
-        const double wk = W1[k * kHid + o];
-#pragma unroll
-        for (int j = 0; j < kRcRows; ++j) acc[j] = fma(wk, s_h[(part + kRcParts * j) * kHStride + k], acc[j]);
+        for (int i = 0; i < 4; ++i) acc[0][i] = acc[1][i] = b1[u0 + i];
+#pragma unroll 4
+        for (int k = 0; k < kHid; ++k) {
+          const float4 wf = *(const float4 *)(s_w1 + k * kHid + u0);
+          const double w0 = (double)wf.x, w1 = (double)wf.y, w2 = (double)wf.z, w3 = (double)wf.w;
+          const double h0 = h[ra * kHStride + k], h1 = h[(ra + 1) * kHStride + k];
+          acc[0][0] = fma(w0, h0, acc[0][0]);
+          acc[0][1] = fma(w1, h0, acc[0][1]);
+          acc[0][2] = fma(w2, h0, acc[0][2]);
+          acc[0][3] = fma(w3, h0, acc[0][3]);
+          acc[1][0] = fma(w0, h1, acc[1][0]);
+          acc[1][1] = fma(w1, h1, acc[1][1]);
+          acc[1][2] = fma(w2, h1, acc[1][2]);
+          acc[1][3] = fma(w3, h1, acc[1][3]);
+        }
       }
       __syncthreads();
-      const double w2 = W2[o];
+      if (live) {
 #pragma unroll
-      for (int j = 0; j < kRcRows; ++j) s_h[(part + kRcParts * j) * kHStride + o] = w2 * silu<double>(acc[j]);
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) h[(ra + r) * kHStride + u0 + i] = W2[u0 + i] * silu<double>(acc[r][i]);
+      }
     }
     __syncthreads();
     // E_r = b2 + sum over units in a fixed order: 8 consecutive chunks of 16, then the chunks
-    if (tid < kRcRowsB * kRcParts) {
-      const int lr = tid / kRcParts, c = tid % kRcParts;
-      double s = 0.0;
+    if (live && lt < kRcRowsB * 8) {
+      const int lr = lt / 8, c = lt % 8;
+      double sm = 0.0;
 #pragma unroll
-      for (int i = 0; i < kHid / kRcParts; ++i) s += s_h[lr * kHStride + c * (kHid / kRcParts) + i];
-      s_part[tid] = s;
+      for (int i = 0; i < kHid / 8; ++i) sm += h[lr * kHStride + c * (kHid / 8) + i];
+      s_part[hf][lt] = sm;
     }
     __syncthreads();
-    if (tid < kRcRowsB) {
+    if (live && lt < kRcRowsB) {
       double E = b2[0];
 #pragma unroll
-      for (int c = 0; c < kRcParts; ++c) E += s_part[tid * kRcParts + c];
-      if constexpr (kRcSplit == 1) s_e[tid] = E;
-      else a.row_e[(size_t)q * kRows64 + r0 + tid] = E;
-    }
-    if constexpr (kRcSplit > 1) {
-      __threadfence();
-      __syncthreads();
-      if (tid == 0) s_last = atomicAdd(&a.done[q], 1u) == kRcSplit - 1;
-      __syncthreads();
-    } else {
-      if (tid == 0) s_last = 1;
-      __syncthreads();
-    }
-    if (s_last) {
-      if constexpr (kRcSplit > 1) __threadfence();
-      if (tid == 0) {
-        double e1 = 0.0, e0 = 0.0;
-        if constexpr (kRcSplit == 1) {
-          for (int k = 0; k < kOm; ++k) e1 += s_e[k];
-          for (int k = 0; k < kOm; ++k) e0 += s_e[kOm + k];
-        } else {
-          const double *re = a.row_e + (size_t)q * kRows64;
-          for (int k = 0; k < kOm; ++k) e1 += __hip_atomic_load(re + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          for (int k = 0; k < kOm; ++k)
-            e0 += __hip_atomic_load(re + kOm + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          a.done[q] = 0;  // ready for the next use of this queue slot
-        }
-        const double dE = e1 - e0;
-        const bool probe = a.probe_dE != nullptr;
-        const bool accept = !probe && dE <= e.theta;
-        const int Rn = a.n_replicas;
-        if (probe) a.probe_dE[q] = dE;
-        if (accept) {
-          occ[e.site] = sn;
-          occ[e.partner] = si;
-          atomicAdd(&a.e_fixed[e.replica], (unsigned long long)to_fixed(dE));
-          atomicAdd((unsigned long long *)&a.counters[2 * Rn + e.replica], 1ull);
-        }
-        if (!probe) atomicAdd((unsigned long long *)&a.counters[3 * Rn + e.replica], 1ull);
-        if (a.trace_flags) a.trace_flags[R.site0 + e.site] = kFlagFp64 | (accept ? kFlagAccept : 0);
-        if (a.trace_dE) a.trace_dE[R.site0 + e.site] = dE;
-        s_accept = accept;
-      }
-      __syncthreads();
-      if (tid < kOm && s_accept) {
-        // the cache keeps the sweep precision's energies of the zone
-        int dx, dy, dz;
-        unpack_off(a.om_off[d * kOm + tid], dx, dy, dz);
-        a.ecache[R.site0 + site_at(pi, dx, dy, dz, R.L[0], R.L[1], R.L[2])] = e.e1[tid];
-      }
+      for (int c = 0; c < 8; ++c) E += s_part[hf][lt * 8 + c];
+      a.row_e[(size_t)q * kRows64 + r0 + lt] = E;
     }
     __syncthreads();
   }
+}
+
+// One wave per queued trial: dE = (sum of the 40 rows after) - (sum of the 40 before), each
+// summed in zone order (the rows are loaded by 40 lanes at once and added in order from lane
+// registers); decide and apply (or, for a probe, only report dE).
+__global__ __launch_bounds__(256) void k_recheck_decide(RecheckArgs a) {
+  const uint32_t n = *a.q_count;
+  const int lane = threadIdx.x & 63;
+  const uint32_t waves = gridDim.x * (blockDim.x / 64);
+  for (uint32_t q = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); q < n; q += waves) {
+    const RecheckEntry &e = a.queue[q];
+    if (e.site < 0) continue;
+    const double *re = a.row_e + (size_t)q * kRows64;
+    const double v1 = lane < kOm ? re[lane] : 0.0, v0 = lane < kOm ? re[kOm + lane] : 0.0;
+    double e1 = 0.0, e0 = 0.0;
+#pragma unroll
+    for (int k = 0; k < kOm; ++k) e1 += __shfl(v1, k);
+#pragma unroll
+    for (int k = 0; k < kOm; ++k) e0 += __shfl(v0, k);
+    const double dE = e1 - e0;
+    if (a.probe_dE) {
+      if (lane == 0) a.probe_dE[q] = dE;
+      continue;
+    }
+    const Replica R = a.reps[e.replica];
+    uint8_t *occ = a.occ + R.site0;
+    const bool accept = dE <= e.theta;
+    const int Rn = a.n_replicas;
+    if (lane == 0) {
+      if (accept) {
+        const uint8_t si = occ[e.site], sn = occ[e.partner];
+        occ[e.site] = sn;
+        occ[e.partner] = si;
+        atomicAdd(&a.e_fixed[e.replica], (unsigned long long)to_fixed(dE));
+        atomicAdd((unsigned long long *)&a.counters[2 * Rn + e.replica], 1ull);
+      }
+      atomicAdd((unsigned long long *)&a.counters[3 * Rn + e.replica], 1ull);
+      if (a.trace_flags) a.trace_flags[R.site0 + e.site] = kFlagFp64 | (accept ? kFlagAccept : 0);
+      if (a.trace_dE) a.trace_dE[R.site0 + e.site] = dE;
+    }
+    if (accept && lane < kOm) {
+      // the cache keeps the sweep precision's energies of the zone
+      const Pos pi = site_pos(e.site, R.L[0], R.L[1]);
+      int dx, dy, dz;
+      unpack_off(a.om_off[e.dir * kOm + lane], dx, dy, dz);
+      a.ecache[R.site0 + site_at(pi, dx, dy, dz, R.L[0], R.L[1], R.L[2])] = e.e1[lane];
+    }
+  }
+}
+
+// Enqueue both kernels for a queue of at most max_entries trials (the length itself is read
+// on the device).
+inline void launch_recheck(const RecheckArgs &ra, int64_t max_entries, int n_cu, hipStream_t stream) {
+  const int64_t items = std::max<int64_t>(1, max_entries) * kRcBlocksPerTrial;
+  const unsigned rows_grid = (unsigned)std::min<int64_t>((items + 1) / 2, n_cu);  // one block per CU (LDS)
+  hipLaunchKernelGGL(k_recheck_rows, dim3(rows_grid), dim3(kRcThreads), 0, stream, ra);
+  const unsigned dec_grid = (unsigned)std::min<int64_t>((std::max<int64_t>(1, max_entries) + 3) / 4, 4 * (int64_t)n_cu);
+  hipLaunchKernelGGL(k_recheck_decide, dim3(dec_grid), dim3(256), 0, stream, ra);
 }
 
 }  // namespace smc

@@ -174,7 +174,9 @@ int load_params(smc_ctx *c, const float *params_dev) {
     for (int o = 0; o < H; ++o)
       for (int k = 0; k < H; ++k) t[w1 + (size_t)k * H + o] = p[w1 + (size_t)o * H + k];
     for (size_t q = w1 + (size_t)H * H; q < (size_t)P; ++q) t[q] = p[q];
+    std::vector<float> tf(t.begin(), t.end());  // exact: every entry is an FP32 parameter
     HIPC(c, hipMemcpyAsync(c->d_w64t, t.data(), sizeof(double) * P, hipMemcpyHostToDevice, c->stream));
+    HIPC(c, hipMemcpyAsync(c->d_w32t, tf.data(), sizeof(float) * P, hipMemcpyHostToDevice, c->stream));
     HIPC(c, hipStreamSynchronize(c->stream));
   }
   if (c->cfg.feature == SMC_FEAT_QSRO_S123) {
@@ -290,6 +292,7 @@ int enqueue_sweep_mfma(smc_ctx *c, const smc_stats *st, bool trace) {
     ra.occ = c->occ;
     ra.ecache = c->ecache;
     ra.w64 = c->d_w64t;
+    ra.w32t = c->d_w32t;
     ra.reg_off = c->d_reg_off;
     ra.om_off = c->d_om_off;
     ra.idx = c->d_idx;
@@ -300,16 +303,12 @@ int enqueue_sweep_mfma(smc_ctx *c, const smc_stats *st, bool trace) {
     ra.counters = c->d_counters;
     ra.n_replicas = R;
     ra.row_e = c->d_rowe;
-    ra.done = c->d_done;
     if (trace) {
       ra.trace_dE = st->trace_dE;
       ra.trace_flags = st->trace_flags;
     }
-    // one block per CU (the re-decision kernel's LDS admits no second); blocks loop over the
-    // queue, which is usually short, so extra blocks would only add dispatch time
-    const int rgrid = (int)std::min<int64_t>(c->n_cu, kRcSplit * std::max<int64_t>(1, c->col_trials[col]));
     const int ev2 = prof_begin(c);
-    hipLaunchKernelGGL(k_recheck, dim3(rgrid), dim3(kRcThreads), 0, c->stream, ra);
+    launch_recheck(ra, c->col_trials[col], c->n_cu, c->stream);
     prof_end(c, ev2, 1);
   }
   hipLaunchKernelGGL(k_next_sweep, dim3(1), dim3(64), 0, c->stream, c->d_sweep);
@@ -416,6 +415,7 @@ int enqueue_sweep_dl(smc_ctx *c, const smc_stats *st, bool trace) {
       ra.occ = c->occ;
       ra.ecache = c->ecache;
       ra.w64 = c->d_w64t;
+    ra.w32t = c->d_w32t;
       ra.reg_off = c->d_reg_off;
       ra.om_off = c->d_om_off;
       ra.idx = c->d_idx;
@@ -426,14 +426,12 @@ int enqueue_sweep_dl(smc_ctx *c, const smc_stats *st, bool trace) {
       ra.counters = c->d_counters;
       ra.n_replicas = R;
       ra.row_e = c->d_rowe;
-      ra.done = c->d_done;
       if (trace) {
         ra.trace_dE = st->trace_dE;
         ra.trace_flags = st->trace_flags;
       }
-      const int rgrid = (int)std::min<int64_t>(c->n_cu, kRcSplit * std::max<int64_t>(1, rep.n_trials));
       const int ev2 = prof_begin(c);
-      hipLaunchKernelGGL(k_recheck, dim3(rgrid), dim3(kRcThreads), 0, c->stream, ra);
+      launch_recheck(ra, rep.n_trials, c->n_cu, c->stream);
       prof_end(c, ev2, 1);
       hipLaunchKernelGGL(k_dl_sync, dim3(tg), dim3(256), 0, c->stream, a);
     }
@@ -515,13 +513,14 @@ int run_sweep(smc_ctx *c, const smc_stats *st, bool last) {
 
 // ---------------------------------------------------------------- probe without allocation
 //
-// Work space of smc_delta_e64_noalloc: the probe's queue entries followed by the queue
-// length.  Each GPU the library runs on holds its own copy until the process ends.  On the
-// host this name is only a stand-in symbol, never a device address: host code uses the
+// Work space of smc_delta_e64_noalloc: the probe's queue entries, their FP64 row energies and
+// the queue length.  Each GPU the library runs on holds its own copy until the process ends.
+// On the host this name is only a stand-in symbol, never a device address: host code uses the
 // address resolved per device by noalloc_scratch() (at context creation, with the context's
 // device current) and passes that to the kernels.
-constexpr size_t kNoAllocEntryBytes = sizeof(RecheckEntry) * SMC_NOALLOC_MAX_TRIALS;
-constexpr size_t kNoAllocBytes = kNoAllocEntryBytes + 256;
+constexpr size_t kNoAllocEntryBytes = (sizeof(RecheckEntry) * SMC_NOALLOC_MAX_TRIALS + 255) / 256 * 256;
+constexpr size_t kNoAllocRowBytes = sizeof(double) * kRows64 * SMC_NOALLOC_MAX_TRIALS;
+constexpr size_t kNoAllocBytes = kNoAllocEntryBytes + kNoAllocRowBytes + 256;
 static __device__ __align__(256) uint8_t scratch[kNoAllocBytes];
 
 namespace smc {
@@ -558,6 +557,7 @@ __global__ void k_probe_entries(const Replica *reps, int32_t replica, uint64_t s
   e.replica = replica;
   e.theta = 0.0;
   e.dE_fast = 0.0f;
+  e.has_reg = 0;
   if (s < 0 || s >= R.n_sites) {
     e.site = -1;
     e.partner = -1;
@@ -699,6 +699,7 @@ int smc_init(const smc_config *cfg, uint8_t *occ_dev, const float *params_dev, f
   INIT_HIP(hipMalloc(&c->d_w32, sizeof(float) * c->n_params));
   INIT_HIP(hipMalloc(&c->d_w64, sizeof(double) * c->n_params));
   INIT_HIP(hipMalloc(&c->d_w64t, sizeof(double) * c->n_params));
+  INIT_HIP(hipMalloc(&c->d_w32t, sizeof(float) * c->n_params));
   INIT_HIP(hipMalloc(&c->d_omega, sizeof(om.off)));
   INIT_HIP(hipMalloc(&c->d_ebase, sizeof(double) * R));
   INIT_HIP(hipMalloc(&c->d_efixed, sizeof(unsigned long long) * R));
@@ -724,8 +725,6 @@ int smc_init(const smc_config *cfg, uint8_t *occ_dev, const float *params_dev, f
     INIT_HIP(hipMalloc(&c->d_reg_pos, t.reg_pos.size()));
     INIT_HIP(hipMalloc(&c->d_queue, sizeof(RecheckEntry) * c->queue_cap));
     INIT_HIP(hipMalloc(&c->d_rowe, sizeof(double) * kRows64 * c->queue_cap));
-    INIT_HIP(hipMalloc(&c->d_done, sizeof(uint32_t) * c->queue_cap));
-    INIT_HIP(hipMemset(c->d_done, 0, sizeof(uint32_t) * c->queue_cap));
     INIT_HIP(hipMalloc(&c->d_qcount, sizeof(uint32_t) * (c->max_colours + 4)));
     INIT_HIP(hipMalloc(&c->d_seg_rep, sizeof(int32_t) * std::max<size_t>(1, seg_rep.size())));
     for (int k = 0; k < 2; ++k) {
@@ -838,16 +837,14 @@ int smc_delta_e64(smc_ctx *c, int32_t replica, uint64_t sweep, const int64_t *si
   }
   RecheckEntry *d_e = nullptr;
   double *d_out = nullptr, *d_rowe = nullptr;
-  uint32_t *d_n = nullptr, *d_done = nullptr;
+  uint32_t *d_n = nullptr;
   const uint32_t nn = (uint32_t)n;
   int rc = SMC_OK;
   if (hipMalloc(&d_e, sizeof(RecheckEntry) * n) || hipMalloc(&d_out, sizeof(double) * n) ||
-      hipMalloc(&d_n, sizeof(uint32_t)) || hipMalloc(&d_rowe, sizeof(double) * kRows64 * n) ||
-      hipMalloc(&d_done, sizeof(uint32_t) * n))
+      hipMalloc(&d_n, sizeof(uint32_t)) || hipMalloc(&d_rowe, sizeof(double) * kRows64 * n))
     rc = fail(c, SMC_E_NOMEM, "probe buffers");
   if (!rc && (hipMemcpyAsync(d_e, h.data(), sizeof(RecheckEntry) * n, hipMemcpyHostToDevice, c->stream) ||
-              hipMemcpyAsync(d_n, &nn, sizeof(uint32_t), hipMemcpyHostToDevice, c->stream) ||
-              hipMemsetAsync(d_done, 0, sizeof(uint32_t) * n, c->stream)))
+              hipMemcpyAsync(d_n, &nn, sizeof(uint32_t), hipMemcpyHostToDevice, c->stream)))
     rc = fail(c, SMC_E_DEVICE, "probe upload");
   if (!rc) {
     RecheckArgs ra{};
@@ -855,6 +852,7 @@ int smc_delta_e64(smc_ctx *c, int32_t replica, uint64_t sweep, const int64_t *si
     ra.occ = c->occ;
     ra.ecache = c->ecache;
     ra.w64 = c->d_w64t;
+    ra.w32t = c->d_w32t;
     ra.reg_off = c->d_reg_off;
     ra.om_off = c->d_om_off;
     ra.idx = c->d_idx;
@@ -866,8 +864,7 @@ int smc_delta_e64(smc_ctx *c, int32_t replica, uint64_t sweep, const int64_t *si
     ra.n_replicas = (int32_t)c->reps.size();
     ra.probe_dE = d_out;
     ra.row_e = d_rowe;
-    ra.done = d_done;
-    hipLaunchKernelGGL(k_recheck, dim3(std::min(kRcSplit * n, 8 * c->n_cu)), dim3(kRcThreads), 0, c->stream, ra);
+    launch_recheck(ra, n, c->n_cu, c->stream);
     if (hipGetLastError() != hipSuccess ||
         hipMemcpyAsync(dE_out, d_out, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream) ||
         hipStreamSynchronize(c->stream))
@@ -876,7 +873,6 @@ int smc_delta_e64(smc_ctx *c, int32_t replica, uint64_t sweep, const int64_t *si
   (void)hipFree(d_e);
   (void)hipFree(d_out);
   (void)hipFree(d_rowe);
-  (void)hipFree(d_done);
   (void)hipFree(d_n);
   return rc;
 }
@@ -896,7 +892,8 @@ int smc_delta_e64_noalloc(smc_ctx *c, int32_t replica, uint64_t sweep, const int
   if (!sites_dev || !dE_dev) return fail(c, SMC_E_INVALID, "null device array");
   if (!c->scratch) return fail(c, SMC_E_DEVICE, "work-space address not resolved");
   RecheckEntry *entries = (RecheckEntry *)c->scratch;
-  uint32_t *qn = (uint32_t *)((uint8_t *)c->scratch + kNoAllocEntryBytes);
+  double *rows = (double *)((uint8_t *)c->scratch + kNoAllocEntryBytes);
+  uint32_t *qn = (uint32_t *)((uint8_t *)c->scratch + kNoAllocEntryBytes + kNoAllocRowBytes);
   hipLaunchKernelGGL(k_probe_entries, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, c->d_reps, replica, sweep,
                      c->cfg.seed, sites_dev, n, entries, qn, partner_dev, dE_dev);
   RecheckArgs ra{};
@@ -904,6 +901,7 @@ int smc_delta_e64_noalloc(smc_ctx *c, int32_t replica, uint64_t sweep, const int
   ra.occ = c->occ;
   ra.ecache = c->ecache;
   ra.w64 = c->d_w64t;
+    ra.w32t = c->d_w32t;
   ra.reg_off = c->d_reg_off;
   ra.om_off = c->d_om_off;
   ra.idx = c->d_idx;
@@ -914,9 +912,8 @@ int smc_delta_e64_noalloc(smc_ctx *c, int32_t replica, uint64_t sweep, const int
   ra.counters = c->d_counters;
   ra.n_replicas = (int32_t)c->reps.size();
   ra.probe_dE = dE_dev;  // probe mode: writes dE, changes nothing else
-  ra.row_e = nullptr;    // not used with one block per trial
-  ra.done = nullptr;
-  hipLaunchKernelGGL(k_recheck, dim3(std::min(kRcSplit * n, 8 * c->n_cu)), dim3(kRcThreads), 0, c->stream, ra);
+  ra.row_e = rows;
+  launch_recheck(ra, n, c->n_cu, c->stream);
   HIPC(c, hipGetLastError());
   return SMC_OK;
 }
@@ -1227,8 +1224,8 @@ void smc_destroy(smc_ctx *c) {
   else (void)hipDeviceSynchronize();
   drop_graph(c);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-  void *bufs[] = {c->d_reps, c->d_w32, c->d_w64, c->d_w64t, c->d_omega, c->d_reg_off, c->d_om_off, c->d_idx,
-                  c->d_reg_pos, c->d_queue, c->d_rowe, c->d_done, c->d_qcount, c->d_ebase, c->d_efixed, c->d_escratch,
+  void *bufs[] = {c->d_reps, c->d_w32, c->d_w64, c->d_w64t, c->d_w32t, c->d_omega, c->d_reg_off, c->d_om_off, c->d_idx,
+                  c->d_reg_pos, c->d_queue, c->d_rowe, c->d_qcount, c->d_ebase, c->d_efixed, c->d_escratch,
                   c->d_counters, c->d_site64, c->packs[0].dev, c->packs[1].dev, c->packs[2].dev,
                   c->packs[3].dev, c->d_seg_rep, c->d_seg_start[0], c->d_seg_start[1], c->d_sweep,
                   c->d_sigma1, c->d_E0, c->d_E1, c->d_dltrials};

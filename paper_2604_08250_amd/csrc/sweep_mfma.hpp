@@ -38,6 +38,8 @@ struct RecheckEntry {
   int32_t replica;
   int32_t dir;
   float e1[kOm];     // new energies of the zone from the sweep precision (cache values)
+  uint8_t reg[kReg]; // species of the read region after the swap (when has_reg)
+  int32_t has_reg;   // 0: the FP64 evaluation gathers the region from the lattice itself
 };
 
 struct MfmaArgs {
@@ -344,6 +346,9 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
           e.replica = cur.rep;
           e.dir = cur.dir[lane];
           for (int k = 0; k < kOm; ++k) e.e1[k] = s_e[lane * kOm + k];
+          // the gathered region (swap applied) travels with the entry
+          for (int k = 0; k < kReg / 4; ++k) ((uint32_t *)e.reg)[k] = ((const uint32_t *)(s_reg + lane * kReg))[k];
+          e.has_reg = 1;
           if (a.trace_dE_fast) a.trace_dE_fast[R.site0 + i] = dEd;
         } else {
           accept = dEd <= theta;

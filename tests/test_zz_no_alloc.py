@@ -18,15 +18,15 @@ def test_noalloc_probe_equals_probe_on_two_calls():
     torch = need_gpu()
     import paper_2604_08250_amd as smc
     from paper_2604_08250_amd import _lib as L
-    print("[gpu-test] no-alloc probe: 16x16x32 cells, calls of 16384 then 5000 trials", flush=True)
-    cells = (16, 16, 32)
+    print("[gpu-test] no-alloc probe: 16x16x16 cells, calls of 8192 then 3000 trials", flush=True)
+    cells = (16, 16, 16)
     w, mc, model, occ = make("c2", cells=cells)
     mc.sweep(2)
     state = mc.occ.cpu().numpy()
     sweep = mc.sweep_index
-    cap = 16384  # SMC_NOALLOC_MAX_TRIALS in include/smc.h
+    cap = 8192  # SMC_NOALLOC_MAX_TRIALS in include/smc.h
     rng = np.random.default_rng(8)
-    calls = [rng.permutation(mc.n_sites)[:cap], rng.choice(mc.n_sites, size=5000, replace=False)]
+    calls = [rng.permutation(mc.n_sites)[:cap], rng.choice(mc.n_sites, size=3000, replace=False)]
     outs = []
     for sites in calls:
         s_dev = torch.as_tensor(sites, dtype=torch.int64, device="cuda")
@@ -56,7 +56,7 @@ def test_noalloc_probe_limits():
     w, mc, model, occ = make("c2", cells=(8, 8, 8))
     dummy = torch.zeros(1, dtype=torch.int64, device="cuda")
     with pytest.raises(L.SMCError):
-        L.smc_delta_e64_noalloc(mc.ctx, 0, 0, dummy.data_ptr(), 16385, 0, dummy.data_ptr())
+        L.smc_delta_e64_noalloc(mc.ctx, 0, 0, dummy.data_ptr(), 8193, 0, dummy.data_ptr())
     with pytest.raises(L.SMCError):
         L.smc_delta_e64_noalloc(mc.ctx, 1, 0, dummy.data_ptr(), 1, 0, dummy.data_ptr())
     L.smc_delta_e64_noalloc(mc.ctx, 0, 0, 0, 0, 0, 0)  # n = 0: nothing to do
