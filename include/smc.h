@@ -170,7 +170,7 @@ int smc_delta_e64(smc_ctx *ctx, int32_t replica, uint64_t sweep, const int64_t *
  * smc_delta_e64 (bit-identical results); a site outside the replica gets partner -1 and dE NaN.
  * Asynchronous on the context's stream: no host synchronisation, no hipMalloc or hipFree.  The
  * work space is a fixed library array of SMC_NOALLOC_MAX_TRIALS queue entries and their FP64
- * row energies (about 6.9 MB) that every GPU the library runs on holds until the process ends;
+ * row energies (about 8.5 MB) that every GPU the library runs on holds until the process ends;
  * n above the limit gives
  * SMC_E_INVALID, larger batches are split by the caller.  All calls on one GPU share that array
  * and it keeps the last call's contents: calls whose work can overlap on one GPU (other
