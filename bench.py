@@ -34,7 +34,8 @@ OMEGA = 40  # local energies evaluated per different-species trial (affected zon
 EXEC_FLOP_PER_EVAL = {"fp32": 2 * (112 * 128 + 128 * 128), "bf16": 2 * (112 * 128 + 128 * 128),
                       "bf16x3": 2 * (2 * 112 * 128 + 3 * 128 * 128), "fp8": 2 * (128 * 128 + 128 * 128)}
 PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0, "fp8": 5000.0}
-DTYPE = {"fp32": "f32", "bf16": "bf16", "bf16x3": "bf16", "fp8": "fp8-e4m3"}
+# split BF16: every product takes BF16 hi/lo parts of FP32 operands (three BF16 products per pair)
+DTYPE = {"fp32": "f32", "bf16": "bf16", "bf16x3": "bf16x3", "fp8": "fp8-e4m3"}
 
 
 def log(msg):
@@ -454,7 +455,76 @@ def measure_fit(steps=5, warmup=1):
     return out
 
 
-def cpu_baseline(workload, seconds=12.0):
+def _blocking(x, nblocks=10):
+    """Mean and standard error of a correlated series from the spread of nblocks block means."""
+    x = np.asarray(x, dtype=np.float64)
+    b = x[: len(x) // nblocks * nblocks].reshape(nblocks, -1, *x.shape[1:]).mean(axis=1)
+    return x.mean(axis=0), b.std(axis=0, ddof=1) / np.sqrt(nblocks)
+
+
+def measure_observables(precisions=("fp64", "fp32", "bf16x3", "bf16", "fp8"), sweeps=160, burn=60, every=2):
+    """Observable error of each precision against the FP64 mode on the 64^3 lattice (T = 800 K):
+    the same start and Philox stream, `sweeps` sweeps, and after `burn` sweeps a sample every
+    `every` sweeps of E per atom (FP64 from scratch) and the Warren-Cowley alpha of shells 1 and
+    2 (the lattice average of the pair fractions of Eq. (3)); means with blocking errors.  FP32
+    and split BF16 decide every trial as FP64 does (re-decision inside the guard band), so their
+    chains are the FP64 chain itself; BF16 and FP8 are separate chains compared statistically."""
+    import torch
+
+    import synth
+    import paper_2604_08250_amd as smc
+
+    w = synth.workload("c2")
+    occ0, params = w.occupancy(), w.params()
+    n_sites = sum(w.sites)
+    res, final = {}, {}
+    for p in precisions:
+        t0 = time.perf_counter()
+        mc = smc.SwapMC(w.cells, w.temperatures, occ0, params, n_species=w.n_species, feature=w.feature,
+                        hidden=w.hidden, precision=p, seed=w.seed)
+        E, a1, a2 = [], [], []
+        for s in range(sweeps // every):
+            mc.sweep(every)
+            if (s + 1) * every > burn:
+                es, _ = mc.energy()
+                E.append(es[0] / n_sites)
+                al = mc.warren_cowley()
+                a1.append(al[0])
+                a2.append(al[1])
+        cnt = mc.counters()
+        es, er = mc.energy()
+        final[p] = mc.occ.cpu().numpy()
+        mE, eE = _blocking(E)
+        m1, e1 = _blocking(a1)
+        m2, e2 = _blocking(a2)
+        res[p] = {"E_per_atom_eV": float(mE), "E_per_atom_err_eV": float(eE),
+                  "alpha1": np.round(m1, 5).tolist(), "alpha1_err": np.round(e1, 5).tolist(),
+                  "alpha2": np.round(m2, 5).tolist(), "alpha2_err": np.round(e2, 5).tolist(),
+                  "accept_ratio": int(cnt[2].sum()) / max(int(cnt[1].sum()), 1),
+                  "fp64_redecided_fraction": int(cnt[3].sum()) / max(int(cnt[1].sum()), 1),
+                  "running_minus_scratch_eV": float(er[0] - es[0]), "seconds": time.perf_counter() - t0}
+        mc.close()
+        del mc
+        torch.cuda.empty_cache()
+        log(f"observables {p}: E/atom {mE:.6f} +- {eE:.6f} eV, {res[p]['seconds']:.1f} s")
+    ref = res["fp64"]
+    for p, r in res.items():
+        if p == "fp64":
+            continue
+        r["chain_equals_fp64"] = bool(np.array_equal(final[p], final["fp64"]))
+        r["dE_per_atom_eV"] = r["E_per_atom_eV"] - ref["E_per_atom_eV"]
+        r["dE_per_atom_err_eV"] = float(np.hypot(r["E_per_atom_err_eV"], ref["E_per_atom_err_eV"]))
+        for k in ("alpha1", "alpha2"):
+            d = np.abs(np.asarray(r[k]) - np.asarray(ref[k]))
+            e = np.hypot(np.asarray(r[k + "_err"]), np.asarray(ref[k + "_err"]))
+            r[f"max_abs_d{k}"] = float(d.max())
+            r[f"max_abs_d{k}_over_err"] = float((d / np.maximum(e, 1e-12)).max())
+    return {"workload": f"BCC {w.cells[0][0]}^3 cells ({n_sites} sites), {w.n_species} species, "
+                        f"T = {w.temperatures[0]:g} K, {sweeps} sweeps, samples every {every} after {burn}",
+            "precisions": res}
+
+
+def cpu_baseline(workload, seconds=12.0, cores=None):
     """The FP64 oracle, unchanged, on a bounded sample: the first trials of colour 0 of
     sweep 0 of the same workload, run on all host cores through a thread pool."""
     from concurrent.futures import ThreadPoolExecutor
@@ -466,7 +536,7 @@ def cpu_baseline(workload, seconds=12.0):
     cells = w.cells[0]
     occ = w.occupancy()
     model = oracle.MLP(w.feature, w.hidden, w.params())
-    cores = len(os.sched_getaffinity(0))
+    cores = cores or len(os.sched_getaffinity(0))
     lx, ly, lz = cells
     sites = [(((4 * c) * ly + 4 * b) * lx + 4 * a) * 2 for c in range(lz // 4)
              for b in range(ly // 4) for a in range(lx // 4)]
@@ -501,7 +571,8 @@ def main():
     ap.add_argument("--no-double-lattice", action="store_true", help="skip the double-lattice measurement")
     ap.add_argument("--no-qsro", action="store_true", help="skip the qSRO-model measurement")
     ap.add_argument("--no-fcc", action="store_true", help="skip the FCC MLPNet measurement")
-    ap.add_argument("--only", choices=["batched", "fit", "qsro", "fcc"], default=None,
+    ap.add_argument("--no-observables", action="store_true", help="skip the per-precision observable chains")
+    ap.add_argument("--only", choices=["batched", "fit", "qsro", "fcc", "observables"], default=None,
                     help="run only this measurement and print its object (for profiling)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", type=float, default=0.0,
@@ -531,6 +602,8 @@ def main():
             res = measure_batched(steps=args.steps, warmup=args.warmup)
         elif args.only == "fit":
             res = measure_fit(steps=args.steps, warmup=args.warmup)
+        elif args.only == "observables":
+            res = measure_observables()
         elif args.only == "fcc":
             res = measure_fcc(tuple(x for x in args.precision.split(",") if x), steps=args.steps,
                               warmup=args.warmup)
@@ -587,8 +660,17 @@ def main():
         out["batched"] = measure_batched()
     if not args.no_fit:
         out["fit"] = measure_fit()
+    if not args.no_observables:
+        out["observables"] = measure_observables()
+    # context, not a target: the paper's record run (Table I; Sec. V-B), 4e12 atoms of its FCC
+    # alloy with the qSRO model on 2,048 Ascend 910 NPUs (4,096 dies)
+    out["paper_context"] = {"record_run_attempts_per_s": 3.77e10, "record_run_atoms": 4.0e12,
+                            "record_run_devices": "2,048 Ascend 910 NPUs (4,096 dies)",
+                            "record_run_per_die_attempts_per_s": 3.77e10 / 4096, "record_run_model": "qSRO, FCC"}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
+        one = cpu_baseline(args.workload, args.cpu_seconds / 2, cores=1)
+        out["cpu_baseline"]["one_core"] = {"value": one["value"], "unit": one["unit"], "sample": one["sample"]}
     print(json.dumps(out), flush=True)
 
 

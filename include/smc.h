@@ -144,7 +144,9 @@ int smc_init(const smc_config *cfg, uint8_t *occ_dev, const float *params_dev,
  * Asynchronous unless stats is non-NULL. */
 int smc_sweep(smc_ctx *ctx, int32_t n_sweeps, smc_stats *stats);
 
-/* FP64 energies per replica (host arrays [n_replicas], either may be NULL):
+/* FP64 energies per replica (host arrays [n_replicas], either may be NULL).  The energy of a
+ * configuration is the sum of its local energies (Algorithm 1 reduces local energies over the
+ * affected zone; Sec. III-A), so:
  * e_scratch = sum of FP64 local energies of the current occupancy;
  * e_running = initial FP64 total plus every accepted dE.  Synchronises. */
 int smc_energy(smc_ctx *ctx, double *e_scratch_host, double *e_running_host);
@@ -180,8 +182,10 @@ int smc_delta_e64(smc_ctx *ctx, int32_t replica, uint64_t sweep, const int64_t *
 int smc_delta_e64_noalloc(smc_ctx *ctx, int32_t replica, uint64_t sweep, const int64_t *sites_dev, int32_t n,
                           int64_t *partner_dev, double *dE_dev);
 
-/* Re-read params_dev (FP32 blob), re-pack the low-precision copies, refresh the energy
- * cache and reset the running energies to the FP64 total.  Asynchronous. */
+/* Replace the model (Sec. III-A: the ML energy model is decoupled from the MC core, so it can
+ * be swapped without touching the sweep): re-read params_dev (FP32 blob), re-pack the
+ * low-precision copies, refresh the energy cache and reset the running energies to the FP64
+ * total.  Asynchronous. */
 int smc_set_params(smc_ctx *ctx, const float *params_dev);
 
 /* Re-derive the energy cache and running energies after the caller rewrote occ_dev
