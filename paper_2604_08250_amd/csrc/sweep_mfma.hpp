@@ -90,8 +90,6 @@ struct TrialBuf {
 template <int P, int GROUP>
 __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) {
   constexpr int kW = pack_bytes<P>();
-  constexpr int kPfReg = (GROUP * kReg + kMfmaThreads - 1) / kMfmaThreads;  // region bytes per thread
-  constexpr int kPfOm = (GROUP * kOm + kMfmaThreads - 1) / kMfmaThreads;    // cached energies per thread
   __shared__ __attribute__((aligned(16))) uint8_t s_w[kW];
   __shared__ __attribute__((aligned(16))) uint8_t s_idx[8 * kOm * kIdxRow];
   __shared__ uint16_t s_roff[8 * kReg];
@@ -215,58 +213,61 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
     }
   };
 
-  // gather loads of one group into registers (the loads stay in flight until used); the
-  // region bytes are packed four to a register
-  constexpr int kPfReg4 = (kPfReg + 3) / 4;
-  uint32_t pf_reg[kPfReg4];
+  // gather loads of one group into registers (the loads stay in flight until used).  Sixteen
+  // threads serve one trial: thread tid reads region positions p = tid % 16 + 16k (k < 12),
+  // packed four bytes to a register, and the cached energies of zone sites tid % 16 + 16m
+  // (m < 3, below 40) of trial tid / 16, so the trial's position and partner slot are read
+  // once per thread.
+  static_assert(kMfmaThreads == 16 * GROUP || GROUP == 16, "sixteen threads per trial");
+  constexpr int kTpt = kMfmaThreads / GROUP;  // threads per trial: 16 (GROUP 32) or 32 (GROUP 16)
+  constexpr int kPfReg = kReg / kTpt;         // region bytes per thread: 12 or 6
+  constexpr int kPfOm = (kOm + kTpt - 1) / kTpt;  // cached energies per thread: 3 or 2
+  // the loaded bytes stay unpacked until gather_store, so that issuing the loads never waits
+  // for them
+  uint32_t pf_reg[kPfReg];
   float pf_om[kPfOm];
+  const int g_t = tid / kTpt, g_l = tid % kTpt;
   auto gather_issue = [&](const TrialBuf<GROUP> &tb) {
-    const int nact = tb.nact;
     const Replica &R = a.reps[tb.rep];
     const uint8_t *occ = a.occ + R.site0;
     const float *ec = a.ecache + R.site0;
+    if (g_t < tb.nact) {
+      const Pos pt{tb.px[g_t], tb.py[g_t], tb.pz[g_t]};
+      const int d = tb.dir[g_t];
 #pragma unroll
-    for (int j4 = 0; j4 < kPfReg4; ++j4) pf_reg[j4] = 0u;
-#pragma unroll
-    for (int j = 0; j < kPfReg; ++j) {
-      const int q = tid + j * kMfmaThreads;
-      if (q < nact * kReg) {
-        const int t = q / kReg, p = q - t * kReg;
+      for (int k = 0; k < kPfReg; ++k) {
         int dx, dy, dz;
-        unpack_off(s_roff[tb.dir[t] * kReg + p], dx, dy, dz);
-        pf_reg[j >> 2] |= (uint32_t)occ[site_at32(Pos{tb.px[t], tb.py[t], tb.pz[t]}, dx, dy, dz, R.L[0], R.L[1], R.L[2])]
-                          << (8 * (j & 3));
+        unpack_off(s_roff[d * kReg + g_l + kTpt * k], dx, dy, dz);
+        pf_reg[k] = occ[site_at32(pt, dx, dy, dz, R.L[0], R.L[1], R.L[2])];
       }
-    }
 #pragma unroll
-    for (int j = 0; j < kPfOm; ++j) {
-      const int q = tid + j * kMfmaThreads;
-      if (q < nact * kOm) {
-        const int t = q / kOm, k = q - t * kOm;
-        int dx, dy, dz;
-        unpack_off(s_ooff[tb.dir[t] * kOm + k], dx, dy, dz);
-        pf_om[j] = ec[site_at32(Pos{tb.px[t], tb.py[t], tb.pz[t]}, dx, dy, dz, R.L[0], R.L[1], R.L[2])];
+      for (int m = 0; m < kPfOm; ++m) {
+        const int k = g_l + kTpt * m;
+        if (k < kOm) {
+          int dx, dy, dz;
+          unpack_off(s_ooff[d * kOm + k], dx, dy, dz);
+          pf_om[m] = ec[site_at32(pt, dx, dy, dz, R.L[0], R.L[1], R.L[2])];
+        }
       }
     }
   };
   auto gather_store = [&](const TrialBuf<GROUP> &tb) {
-    const int nact = tb.nact;
+    if (g_t < tb.nact) {
+      const int d = tb.dir[g_t];
+      const int pi = s_rpos[2 * d], pn = s_rpos[2 * d + 1];
 #pragma unroll
-    for (int j = 0; j < kPfReg; ++j) {
-      const int q = tid + j * kMfmaThreads;
-      if (q < nact * kReg) {
-        const int t = q / kReg, p = q - t * kReg;
-        const int d = tb.dir[t];
-        uint8_t v = (uint8_t)(pf_reg[j >> 2] >> (8 * (j & 3)));
-        if (p == s_rpos[2 * d]) v = tb.sn[t];
-        if (p == s_rpos[2 * d + 1]) v = tb.si[t];
-        s_reg[q] = v;
+      for (int k = 0; k < kPfReg; ++k) {
+        const int p = g_l + kTpt * k;
+        uint8_t v = (uint8_t)pf_reg[k];
+        if (p == pi) v = tb.sn[g_t];
+        if (p == pn) v = tb.si[g_t];
+        s_reg[g_t * kReg + p] = v;
       }
-    }
 #pragma unroll
-    for (int j = 0; j < kPfOm; ++j) {
-      const int q = tid + j * kMfmaThreads;
-      if (q < nact * kOm) s_ec[q] = pf_om[j];
+      for (int m = 0; m < kPfOm; ++m) {
+        const int k = g_l + kTpt * m;
+        if (k < kOm) s_ec[g_t * kOm + k] = pf_om[m];
+      }
     }
   };
 
