@@ -383,14 +383,22 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
     }
     __syncthreads();
     // ------------------------------------------------------------ apply (g)
-    for (int q = tid; q < nact * kOm; q += kMfmaThreads) {
-      const int t = q / kOm, k = q - t * kOm;
-      if (!s_acc[t]) continue;
-      int dx, dy, dz;
-      unpack_off(s_ooff[cur.dir[t] * kOm + k], dx, dy, dz);
-      ec[site_at32(Pos{cur.px[t], cur.py[t], cur.pz[t]}, dx, dy, dz, R.L[0], R.L[1], R.L[2])] = s_e[q];
+    // The threads of trial g_t write its new zone energies if it was accepted.  No barrier
+    // follows: the next group's gather_store writes only s_reg and s_ec, which this phase
+    // does not read, and the next barrier orders everything after it.
+    if (g_t < nact && s_acc[g_t]) {
+      const Pos pt{cur.px[g_t], cur.py[g_t], cur.pz[g_t]};
+      const int d = cur.dir[g_t];
+#pragma unroll
+      for (int m = 0; m < kPfOm; ++m) {
+        const int k = g_l + kTpt * m;
+        if (k < kOm) {
+          int dx, dy, dz;
+          unpack_off(s_ooff[d * kOm + k], dx, dy, dz);
+          ec[site_at32(pt, dx, dy, dz, R.L[0], R.L[1], R.L[2])] = s_e[g_t * kOm + k];
+        }
+      }
     }
-    __syncthreads();
   }
   flush();
 }
