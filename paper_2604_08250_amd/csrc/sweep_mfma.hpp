@@ -4,8 +4,9 @@
 // schedule has it (replicas of uneven size are independent and share the launch).  A
 // persistent block of 512 threads keeps the packed weights and the lookup tables in LDS and
 // walks groups of GROUP link cells as a pipeline:
-//   proposal (group g+2): Philox block per trial, partner, species, threshold theta (FP64);
-//      same-species trials are finished here, the others compacted;
+//   proposal (group g+2, by the first wave to run out of tiles of group g): Philox block per
+//      trial, partner, species, threshold theta (FP64); same-species trials are finished here,
+//      the others compacted;
 //   gather (group g+1, issued before the energies of group g and consumed after them): the
 //      192 sites read by each trial (its affected zone Omega and their neighbours) and the
 //      cached energies of the 40 zone sites, into registers, then into LDS with the two
@@ -101,7 +102,7 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
   __shared__ float s_psum[GROUP * kPart];
   __shared__ TrialBuf<GROUP> s_tb[3];
   __shared__ uint8_t s_acc[GROUP];
-  __shared__ int s_tile;
+  __shared__ int s_tile, s_prop;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
@@ -287,7 +288,7 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
     TrialBuf<GROUP> &nxt2 = s_tb[(it + 2) % 3];
     // ------------------------------------------------------------ gather (g) into LDS
     gather_store(cur);
-    if (tid == 0) s_tile = 0;
+    if (tid == 0) s_tile = s_prop = 0;
     __syncthreads();
     const int nact = cur.nact;
     const Replica &R = a.reps[cur.rep];
@@ -295,8 +296,6 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
     float *ec = a.ecache + R.site0;
     // ------------------------------------------------------------ gather (g+1) in flight
     if (grp + gstep < gend) gather_issue(nxt);
-    // ------------------------------------------------------------ proposal (g+2), wave 0
-    if (wave == 0) propose(grp + 2 * gstep, nxt2);
     // ------------------------------------------------------------ energies (g)
     const int rows = nact * kOm;
     const int ntiles = (rows + 31) / 32;
@@ -313,6 +312,13 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
       const uint8_t *reg = s_reg + t * kReg;
       const float E = eval_tile<P>(S, [&](int m) -> uint32_t { return reg[irow[m]]; });
       if (valid && lane < 32) s_e[row] = E;
+    }
+    // ------------------------------------------------------------ proposal (g+2)
+    // by the first wave that runs out of tiles (the others still finish theirs)
+    {
+      int first = 0;
+      if (lane == 0) first = atomicAdd(&s_prop, 1) == 0;
+      if (__shfl(first, 0)) propose(grp + 2 * gstep, nxt2);
     }
     __syncthreads();
     // ------------------------------------------------------------ decide (g)
