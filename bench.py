@@ -178,14 +178,28 @@ def measure_batched(precision="bf16", steps=3, warmup=1):
     cnt = mc.counters(reset=True)
     attempts = int(cnt[0].sum())
     assert attempts == n_sites * steps, (attempts, n_sites, steps)
+    # per-launch time of the colour kernel (HIP events around each launch, eager sweeps)
+    prof_sweeps = 2
+    mc.profile(True)
+    mc.sweep(prof_sweeps)
+    colour_ms, recheck_ms, launches = mc.kernel_times()
+    mc.profile(False)
+    p_diff = int(mc.counters(reset=True)[1].sum())
+    alg = p_diff * OMEGA * FLOP_PER_EVAL / (colour_ms / 1e3) / 1e12
     es, er = mc.energy()
     out = {"workload": f"{len(w.cells)} replicas, cube edges {min(c[0] for c in w.cells)}..{max(c[0] for c in w.cells)}, "
                        f"{n_sites} sites, T {min(w.temperatures):.0f}..{max(w.temperatures):.0f} K",
            "precision": precision, "attempts_per_s": attempts / (ms / 1e3), "ms_per_sweep": ms / steps, "sweeps": steps,
            "graph_replay": True, "variant": int(variant), "ms_per_variant": [float(x) for x in ms_var],
            "accept_ratio": int(cnt[2].sum()) / max(int(cnt[1].sum()), 1),
-           "running_minus_scratch_eV_max": float(np.abs(er - es).max())}
-    log(f"c4: {out['attempts_per_s']:.3e} attempts/s, {out['ms_per_sweep']:.1f} ms per sweep")
+           "running_minus_scratch_eV_max": float(np.abs(er - es).max()),
+           "colour_launches_per_sweep": launches // prof_sweeps, "colour_kernel_ms_per_sweep": colour_ms / prof_sweeps,
+           "recheck_ms_per_sweep": recheck_ms / prof_sweeps,
+           "roofline": {"bound": "mfma", "achieved": alg, "peak": PEAK_TFLOPS[precision], "unit": "TFLOP/s",
+                        "frac": alg / PEAK_TFLOPS[precision], "avg_launch_us": colour_ms * 1e3 / max(launches, 1)}}
+    log(f"c4: {out['attempts_per_s']:.3e} attempts/s, {out['ms_per_sweep']:.1f} ms per sweep; colour kernel "
+        f"{out['colour_kernel_ms_per_sweep']:.1f} ms per sweep over {out['colour_launches_per_sweep']} launches, "
+        f"{alg:.1f} TFLOP/s")
     mc.close()
     del mc
     torch.cuda.empty_cache()

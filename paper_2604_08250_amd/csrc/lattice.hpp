@@ -148,4 +148,10 @@ __host__ __device__ inline int32_t axis_len(const AxisCells &a, int32_t i) {
   return i < a.nbig ? a.big : a.small;
 }
 
+// Link cells along an axis long enough to hold offset o: all of them when o fits a short
+// cell, else only the long cells, which come first.
+__host__ __device__ inline int32_t axis_cells_holding(const AxisCells &a, int32_t o) {
+  return o < a.small ? a.q : a.nbig;
+}
+
 }  // namespace smc

@@ -673,11 +673,12 @@ int smc_init(const smc_config *cfg, uint8_t *occ_dev, const float *params_dev, f
       const Replica &rp = c->reps[r];
       if (rp.n_colours <= col) continue;
       seg_rep.push_back(r);
-      g32 += (int32_t)((rp.n_trials + 31) / 32);
-      g16 += (int32_t)((rp.n_trials + 15) / 16);
+      const int64_t nt = colour_trials(rp, col);
+      g32 += (int32_t)((nt + 31) / 32);
+      g16 += (int32_t)((nt + 15) / 16);
       seg_start[0].push_back(g32);
       seg_start[1].push_back(g16);
-      c->col_trials[col] += rp.n_trials;
+      c->col_trials[col] += nt;
     }
     c->seg_groups[0][col] = g32;
     c->seg_groups[1][col] = g16;

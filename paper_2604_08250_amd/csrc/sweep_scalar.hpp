@@ -34,24 +34,23 @@ struct SweepArgs {
 // accumulator in units of 2^-32 eV, so the running total does not depend on block order.
 __device__ __forceinline__ long long to_fixed(double x) { return __double2ll_rn(x * 4294967296.0); }
 
-// Trial site of (colour, trial) inside a replica, or -1 where that link cell is too short
-// to hold the colour's offset.
+// Trial site of (colour, trial) inside a replica, or -1 past the colour's last trial.  The
+// trials of a colour run over the link cells long enough to hold its offset (the long cells
+// come first on each axis), x fastest, so no trial index of a colour is spent on a cell that
+// cannot hold it.  Link-cell indices stay below 2^31: 32-bit arithmetic.
 __device__ inline int64_t trial_site(const Replica &R, int32_t colour, int64_t t) {
-  const int32_t b = colour & 1;
-  int32_t rest = colour >> 1;
-  const int32_t ox = rest % R.ax[0].big;
-  rest /= R.ax[0].big;
-  const int32_t oy = rest % R.ax[1].big;
-  const int32_t oz = rest / R.ax[1].big;
-  const int32_t cx = (int32_t)(t % R.ax[0].q);
-  const int64_t t1 = t / R.ax[0].q;
-  const int32_t cy = (int32_t)(t1 % R.ax[1].q);
-  const int32_t cz = (int32_t)(t1 / R.ax[1].q);
-  if (ox >= axis_len(R.ax[0], cx) || oy >= axis_len(R.ax[1], cy) || oz >= axis_len(R.ax[2], cz))
-    return -1;
-  const int32_t x = axis_start(R.ax[0], cx) + ox, y = axis_start(R.ax[1], cy) + oy,
-                z = axis_start(R.ax[2], cz) + oz;
-  return (((int64_t)z * R.L[1] + y) * R.L[0] + x) * 2 + b;
+  int32_t o[3];
+  colour_offsets(R, colour, o);
+  const uint32_t nx = (uint32_t)axis_cells_holding(R.ax[0], o[0]),
+                 ny = (uint32_t)axis_cells_holding(R.ax[1], o[1]),
+                 nz = (uint32_t)axis_cells_holding(R.ax[2], o[2]);
+  const uint32_t tu = (uint32_t)t;
+  const uint32_t t1 = tu / nx, cz = t1 / ny;
+  if (t < 0 || cz >= nz) return -1;
+  const int32_t x = axis_start(R.ax[0], (int32_t)(tu - t1 * nx)) + o[0],
+                y = axis_start(R.ax[1], (int32_t)(t1 - cz * ny)) + o[1],
+                z = axis_start(R.ax[2], (int32_t)cz) + o[2];
+  return (((int64_t)z * R.L[1] + y) * R.L[0] + x) * 2 + (colour & 1);
 }
 
 // Local energy of site j at position p.

@@ -30,10 +30,27 @@ struct Replica {
   int32_t basis;        // sites per cubic cell: 2 (BCC) or 4 (FCC)
   int64_t site0;        // first site of this replica in the concatenated arrays
   int64_t n_sites;
-  int64_t n_trials;     // link cells = trials per colour (some colours skip short cells)
+  int64_t n_trials;     // link cells: the most trials a colour has (colour_trials gives each)
   double temperature;   // kelvin
 };
 
 Replica make_replica(const int32_t cells[3], int64_t site0, double temperature, int32_t basis = 2);
+
+// Offsets (ox, oy, oz) of a colour inside its link cell; the basis site is colour % basis.
+__host__ __device__ inline void colour_offsets(const Replica &R, int32_t colour, int32_t o[3]) {
+  int32_t rest = colour / R.basis;
+  o[0] = rest % R.ax[0].big;
+  rest /= R.ax[0].big;
+  o[1] = rest % R.ax[1].big;
+  o[2] = rest / R.ax[1].big;
+}
+
+// Trials of a colour: the link cells that hold its offset on every axis.
+__host__ __device__ inline int64_t colour_trials(const Replica &R, int32_t colour) {
+  int32_t o[3];
+  colour_offsets(R, colour, o);
+  return (int64_t)axis_cells_holding(R.ax[0], o[0]) * axis_cells_holding(R.ax[1], o[1]) *
+         axis_cells_holding(R.ax[2], o[2]);
+}
 
 }  // namespace smc

@@ -103,3 +103,32 @@ def test_anneal_helper_equals_manual_schedule():
     assert a.sweep_index == b.sweep_index == 6
     a.close()
     b.close()
+
+
+def test_observable_error_of_each_precision():
+    """Chains of every precision from one start and Philox stream (32^3 cells, T = 800 K, 120
+    sweeps, samples every 2 after 40): FP32 and split BF16 must be the FP64-mode chain itself;
+    plain BF16 and FP8 follow their own chains, and their E per atom and Warren-Cowley alpha of
+    shells 1-2 (Eq. (3) pair fractions averaged over the lattice) must stay within loose bounds
+    of the FP64 chain's (printed: the observable error of each precision)."""
+    need_gpu()
+    res, final = {}, {}
+    for p in ("fp64", "fp32", "bf16x3", "bf16", "fp8"):
+        w, mc, model, occ = make("c2", precision=p, cells=(32, 32, 32))
+        n = occ.size
+        E, al = [], []
+        for s in range(60):
+            mc.sweep(2)
+            if s >= 20:
+                E.append(mc.energy()[0][0] / n)
+                al.append(mc.warren_cowley()[:2])
+        final[p] = mc.occ.cpu().numpy()
+        res[p] = (np.mean(E), np.mean(al, axis=0))
+        mc.close()
+    for p in ("fp32", "bf16x3"):
+        assert np.array_equal(final[p], final["fp64"]), f"{p} chain left the FP64 chain"
+    for p, (tol_e, tol_a) in {"bf16": (1e-4, 0.02), "fp8": (1e-3, 0.05)}.items():
+        dE = res[p][0] - res["fp64"][0]
+        da = float(np.abs(res[p][1] - res["fp64"][1]).max())
+        _banner(f"{p}: E/atom {res[p][0]:.6f} vs FP64 {res['fp64'][0]:.6f} eV (diff {dE:+.2e}), max |d alpha| {da:.4f}")
+        assert abs(dE) < tol_e and da < tol_a
