@@ -47,7 +47,7 @@ struct DevPack {  // one precision's packed weights on the device
 // Buffers of the differentiation entry points (allocated on first use, grown on demand).
 struct FitState {
   uint8_t *pack = nullptr;     // BF16 forward images (layer 0, layer 1) + c1 + w2
-  uint8_t *w1t = nullptr;      // BF16 image of W1 transposed (backward through layer 1)
+  uint8_t *bwd = nullptr;      // BF16 images of the backward (layer 0, W1, W1^T in 16x16 tiles)
   float *partial = nullptr;    // [blocks][params] per-block gradient partials
   int partial_blocks = 0;
   double *row_e = nullptr;     // [rows] local energies of the last forward

@@ -6,18 +6,20 @@
 // site and its 26 shell-1..3 neighbours, and S_b sums the rows of snapshot b.
 //
 // BF16 path (matrix cores, FP32 accumulation).  Forward: the sweep's tile evaluator.
-// Backward, fused per chunk of 128 rows in a block of four waves, each wave owning 32 rows:
-//   forward again, keeping y1 = -log2(e) z1 and y2 = -log2(e) z2 in registers;
+// Backward, fused per chunk of 128 rows in a block of eight waves, each wave owning 16 rows
+// (16x16 matrix-core tiles: two waves per SIMD fit in the register file):
+//   forward again, keeping silu'(z1) from the same exponential and reciprocal as h1;
 //   gz2 = gE W2 silu'(z2);  gh1 = W1^T gz2 (matrix cores, W1^T image in LDS);
 //   gz1 = gh1 silu'(z1);
 // then the weight gradients, which sum over rows, are matrix-core products with the rows as
 // the K dimension: the per-row vectors are staged in LDS as [unit][row] BF16 tiles (the
-// transposition that puts rows into K), and each wave owns one quarter of dW1 and of dW0:
+// transposition that puts rows into K), and each wave owns one eighth of dW1 and of dW0:
 //   phase A: dW1 = sum_r gz2 (x) h1  and  db1 = sum_r gz2;
 //   phase B: dW0 = sum_r gz1 (x) x  (x built from 4-bit species codes in LDS; feature 108 is
-//            the constant one, so db0 comes out of the same product)  and  dW2 = sum_r gE h2.
-// Each block accumulates its chunks in registers and writes one partial gradient; a second
-// kernel adds the partials in block order, so the result does not depend on timing.
+//            the constant one, so db0 comes out of the same product).
+// dW2 = sum_r gE h2 is a butterfly over the lanes of each wave.  Each block accumulates its
+// chunks in registers and writes one partial gradient; a second kernel adds the partials in
+// block order, so the result does not depend on timing.
 //
 // Reference path (FP32 or FP64): one thread per (row, unit) per layer with the per-row
 // values in global scratch, and one thread per parameter summing the rows in order.
@@ -31,12 +33,18 @@
 namespace smc {
 
 constexpr int kFitF = 108;
-constexpr int kFitThreads = 256;  // backward block: four waves
+constexpr int kFitThreads = 512;  // backward block: eight waves of 16 rows
 constexpr int kFitRows = 128;     // rows per backward chunk
 constexpr int kFitFwdThreads = 512;
 constexpr int kFitW0 = PackSize<kPBF16>::kL0;
 constexpr int kFitW1 = PackSize<kPBF16>::kL1;
 constexpr int kFitPack = kFitW0 + kFitW1 + 2 * kHid * 4;  // layer 0, layer 1, c1, w2 (scaled)
+// Backward images (16x16 tiles): layer 0 as 3 K-steps of 32 and one of 16 (112 features),
+// layer 1, W1^T, then c1 and w2 as in the forward pack.
+constexpr int kBwdW0a = 8 * 3 * 64 * 8;  // BF16 elements of the 16x16x32 steps
+constexpr int kBwdW0 = 2 * (kBwdW0a + 8 * 64 * 4);
+constexpr int kBwdW1 = 2 * kHid * kHid;
+constexpr int kBwdPack = kBwdW0 + 2 * kBwdW1 + 2 * kHid * 4;
 constexpr int kOffB0 = kHid * kFitF;
 constexpr int kOffW1 = kOffB0 + kHid;
 constexpr int kOffB1 = kOffW1 + kHid * kHid;
@@ -47,6 +55,10 @@ constexpr float kFitLog2e = 1.44269504088896340736f;
 constexpr float kFitLn2 = 0.69314718055994530942f;
 
 __device__ __forceinline__ int fit_hid(int T, int v, int g) { return 32 * T + 8 * (v >> 2) + 4 * g + (v & 3); }
+// Hidden unit behind K slot (lane group g4, element j) of K-step s in a 16x16x32 product whose
+// B operand is built from the accumulators of 16-unit tiles 2s and 2s + 1: a lane holds units
+// 4 g4 .. 4 g4 + 3 of each tile for its row.
+__device__ __forceinline__ int fit_hid16(int s, int g4, int j) { return 16 * (2 * s + (j >> 2)) + 4 * g4 + (j & 3); }
 
 // ---------------------------------------------------------------------------- packing
 
@@ -57,35 +69,63 @@ __device__ __forceinline__ uint16_t fit_bf16(float x) {
   return (uint16_t)(u >> 16);
 }
 
-// BF16 images from the FP32 blob: layer 0 (-log2(e) W0, bias in feature 108), layer 1 (W1)
-// in the operand orders of the tile evaluator, c1 = -log2(e) b1, w2 = -ln(2) W2, and W1^T
-// as the A operand of the backward product (element (T, s, lane, e): W1[o][i] with
-// i = 32T + lane%32 and o the hidden unit that register 8(s%2)+e of M-tile s/2 holds).
-__global__ void k_fit_pack_bf16(const float *p, uint8_t *pack, uint8_t *w1t) {
-  const int n0 = kFitW0 / 2, n1 = kFitW1 / 2;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+// BF16 images from the FP32 blob.  Forward pack (operand orders of the sweep's tile
+// evaluator): layer 0 (-log2(e) W0, bias in feature 108), layer 1 (W1), c1 = -log2(e) b1,
+// w2 = -ln(2) W2.  Backward pack (16x16 tiles, A operands; lane l holds row l % 16 and K
+// slots 8 (l / 16) .. + 7 of a 16x16x32 step, or 4 (l / 16) .. + 3 of a 16x16x16 step):
+// layer 0 (features 32 s + 8 (l / 16) + j, then 96 + 4 (l / 16) + j), layer 1 (W1[o][i]
+// with i = fit_hid16(s, l / 16, j)), W1^T (W1[o][i] with o = fit_hid16(s, l / 16, j)), c1, w2.
+__device__ __forceinline__ float fit_w0s(const float *W0, const float *b0, int o, int f) {
+  return f < kFitF ? -kFitLog2e * W0[o * kFitF + f] : (f == kFitF ? -kFitLog2e * b0[o] : 0.0f);
+}
+
+constexpr int kFitPackThreads = kFitW0 / 2 + kFitW1 / 2 + kBwdW0 / 2 + kBwdW1 + kHid;
+
+__global__ void k_fit_pack_bf16(const float *p, uint8_t *pack, uint8_t *bwd) {
+  const int n0 = kFitW0 / 2, n1 = kFitW1 / 2, m0 = kBwdW0 / 2, m1 = kBwdW1 / 2;
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
   const float *W0 = p, *b0 = p + kOffB0, *W1 = p + kOffW1, *b1 = p + kOffB1, *W2 = p + kOffW2;
-  uint16_t *L0 = (uint16_t *)pack, *L1 = L0 + n0, *LT = (uint16_t *)w1t;
+  uint16_t *L0 = (uint16_t *)pack, *L1 = L0 + n0;
   float *c1 = (float *)(pack + kFitW0 + kFitW1), *w2 = c1 + kHid;
+  uint16_t *B0 = (uint16_t *)bwd, *B1 = B0 + m0, *BT = B1 + m1;
+  float *bc1 = (float *)(bwd + kBwdW0 + 2 * kBwdW1), *bw2 = bc1 + kHid;
   if (t < n0) {
     const int e = t & 7, l = (t >> 3) & 63, s = (t >> 9) % 7, T = (t >> 9) / 7;
-    const int o = 32 * T + (l & 31), f = 16 * s + 8 * (l >> 5) + e;
-    const float w = f < kFitF ? -kFitLog2e * W0[o * kFitF + f] : (f == kFitF ? -kFitLog2e * b0[o] : 0.0f);
-    L0[t] = fit_bf16(w);
-  } else if (t < n0 + n1) {
-    const int u = t - n0;
-    const int e = u & 7, l = (u >> 3) & 63, s = (u >> 9) & 7, To = u >> 12;
+    L0[t] = fit_bf16(fit_w0s(W0, b0, 32 * T + (l & 31), 16 * s + 8 * (l >> 5) + e));
+    return;
+  }
+  t -= n0;
+  if (t < n1) {
+    const int e = t & 7, l = (t >> 3) & 63, s = (t >> 9) & 7, To = t >> 12;
     const int o = 32 * To + (l & 31), i = fit_hid(s >> 1, 8 * (s & 1) + e, l >> 5);
-    L1[u] = fit_bf16(W1[o * kHid + i]);
-  } else if (t < n0 + 2 * n1) {
-    const int u = t - n0 - n1;
-    const int e = u & 7, l = (u >> 3) & 63, s = (u >> 9) & 7, T = u >> 12;
-    const int i = 32 * T + (l & 31), o = fit_hid(s >> 1, 8 * (s & 1) + e, l >> 5);
-    LT[u] = fit_bf16(W1[o * kHid + i]);
-  } else if (t < n0 + 2 * n1 + kHid) {
-    const int o = t - n0 - 2 * n1;
-    c1[o] = -kFitLog2e * b1[o];
-    w2[o] = -kFitLn2 * W2[o];
+    L1[t] = fit_bf16(W1[o * kHid + i]);
+    return;
+  }
+  t -= n1;
+  if (t < m0) {
+    if (t < kBwdW0a) {
+      const int j = t & 7, l = (t >> 3) & 63, s = (t >> 9) % 3, T = (t >> 9) / 3;
+      B0[t] = fit_bf16(fit_w0s(W0, b0, 16 * T + (l & 15), 32 * s + 8 * (l >> 4) + j));
+    } else {
+      const int u = t - kBwdW0a, j = u & 3, l = (u >> 2) & 63, T = u >> 8;
+      B0[t] = fit_bf16(fit_w0s(W0, b0, 16 * T + (l & 15), 96 + 4 * (l >> 4) + j));
+    }
+    return;
+  }
+  t -= m0;
+  if (t < 2 * m1) {
+    const bool tr = t >= m1;
+    const int u = tr ? t - m1 : t;
+    const int j = u & 7, l = (u >> 3) & 63, s = (u >> 9) & 3, T = u >> 11;
+    const int a = 16 * T + (l & 15), k = fit_hid16(s, l >> 4, j);
+    if (tr) BT[u] = fit_bf16(W1[k * kHid + a]);  // A[i = a][o = k]
+    else B1[u] = fit_bf16(W1[a * kHid + k]);     // A[o = a][i = k]
+    return;
+  }
+  t -= 2 * m1;
+  if (t < kHid) {
+    c1[t] = bc1[t] = -kFitLog2e * b1[t];
+    w2[t] = bw2[t] = -kFitLn2 * W2[t];
   }
 }
 
@@ -108,12 +148,30 @@ __device__ __forceinline__ void fit_gather(const uint8_t *occ, Pos p, int32_t L,
     }
 }
 
+// Species of the 7 layer-0 slots a lane feeds in the backward's 16x16 tiles: slots
+// 8 s + 2 g4 + e (s = 0..2, e = 0, 1), then slot 24 + g4 (slot 27, the constant-one input,
+// reads the site itself; the caller replaces it by species 0).
+__device__ __forceinline__ void fit_gather16(const uint8_t *occ, Pos p, int32_t L, int g4, uint32_t sp[7]) {
+#pragma unroll
+  for (int q = 0; q < 7; ++q) {
+    int dx = 0, dy = 0, dz = 0;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int m = q < 6 ? 8 * (q >> 1) + 2 * g + (q & 1) : 24 + g;
+      const int ex = (m && m < 27) ? shell_dx(m - 1) : 0, ey = (m && m < 27) ? shell_dy(m - 1) : 0,
+                ez = (m && m < 27) ? shell_dz(m - 1) : 0;
+      if (g == g4) { dx = ex; dy = ey; dz = ez; }
+    }
+    sp[q] = occ[site_at(p, dx, dy, dz, L, L, L)];
+  }
+}
+
 struct FitArgs {
   const uint8_t *snap;  // [batch][n_sites]
   int32_t L;
   int64_t n_sites, n_rows;
-  const uint8_t *pack, *w1t;
-  const float *b2;      // forward: the output bias in the FP32 blob
+  const uint8_t *pack, *bwd;  // forward and backward BF16 images
+  const float *b2;            // forward: the output bias in the FP32 blob
   const double *gE;     // backward: [batch] upstream gradient per snapshot
   float *partial;       // backward: [gridDim.x][kFitParams]
   double *row_e;        // forward: [n_rows]
@@ -200,283 +258,295 @@ __device__ __forceinline__ float fit_sum8(const uint16_t *p) {
   return s;
 }
 
-// silu'(z) from y = -log2(e) z:  sigma = 1/(1 + 2^y),  silu'(z) = sigma (1 + z (1 - sigma)).
-__device__ __forceinline__ float fit_dsilu(float y) {
-  const float sg = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(y));
-  const float z = -kFitLn2 * y;
-  return sg * fmaf(z, 1.0f - sg, 1.0f);
-}
-
-// Sum of v over the 32 lanes of this lane group: a butterfly on the 16 values of one
-// M-tile.  Afterwards the lane with bits (b4 b3 b2 b1 b0) of lane % 32 holds the sum of
-// value 8 b4 + 4 b3 + 2 b2 + b1 (lanes 2k and 2k+1 hold the same sum).
-__device__ __forceinline__ float fit_rowsum16(const float (&v)[16], int lane) {
+// Sum of v over the 16 lanes of this lane group (lane bits 0..3), as a butterfly on the 16
+// values.  Afterwards the lane with low bits (b3 b2 b1 b0) holds the sum of value
+// 8 b3 + 4 b2 + 2 b1 + b0.
+__device__ __forceinline__ float fit_lanesum16(const float (&v)[16], int lane) {
   float x[8];
-  const bool b4 = lane & 16, b3 = lane & 8, b2 = lane & 4, b1 = lane & 2;
+  const bool b3 = lane & 8, b2 = lane & 4, b1 = lane & 2, b0 = lane & 1;
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
-    const float keep = b4 ? v[i + 8] : v[i], send = b4 ? v[i] : v[i + 8];
-    x[i] = keep + __shfl_xor(send, 16);
+    const float keep = b3 ? v[i + 8] : v[i], send = b3 ? v[i] : v[i + 8];
+    x[i] = keep + __shfl_xor(send, 8);
   }
   float y[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const float keep = b3 ? x[i + 4] : x[i], send = b3 ? x[i] : x[i + 4];
-    y[i] = keep + __shfl_xor(send, 8);
+    const float keep = b2 ? x[i + 4] : x[i], send = b2 ? x[i] : x[i + 4];
+    y[i] = keep + __shfl_xor(send, 4);
   }
   float z[2];
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
-    const float keep = b2 ? y[i + 2] : y[i], send = b2 ? y[i] : y[i + 2];
-    z[i] = keep + __shfl_xor(send, 4);
+    const float keep = b1 ? y[i + 2] : y[i], send = b1 ? y[i] : y[i + 2];
+    z[i] = keep + __shfl_xor(send, 2);
   }
-  const float keep = b1 ? z[1] : z[0], send = b1 ? z[0] : z[1];
-  const float w = keep + __shfl_xor(send, 2);
-  return w + __shfl_xor(w, 1);
+  const float keep = b0 ? z[1] : z[0], send = b0 ? z[0] : z[1];
+  return keep + __shfl_xor(send, 1);
+}
+
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f32x4 fit_mfma16(const i32x4 &a, const i32x4 &b, const f32x4 &c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0,
+                                                 0, 0);
+}
+
+// B operand of a 16x16x32 step from the accumulators of 16-unit tiles 2s and 2s + 1: K slot
+// (g4, j) holds unit fit_hid16(s, g4, j) of the lane's row.
+__device__ __forceinline__ i32x4 fit_bpack(const float (&x)[8][4], int s) {
+  i32x4 r;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int T = 2 * s + (q >> 1), v = 2 * (q & 1);
+    r[q] = (int)pack_bf16x2(x[T][v], x[T][v + 1]);
+  }
+  return r;
 }
 
 __global__ __launch_bounds__(kFitThreads) void k_fit_bwd_bf16(FitArgs a) {
-  __shared__ __attribute__((aligned(16))) uint8_t s_pack[kFitPack];
-  __shared__ __attribute__((aligned(16))) uint8_t s_w1t[kFitW1];
+  __shared__ __attribute__((aligned(16))) uint8_t s_pack[kBwdPack];
   __shared__ __attribute__((aligned(16))) uint16_t s_a[kHid * kFitRows];  // h1 (scaled), then gz1
   __shared__ __attribute__((aligned(16))) uint16_t s_b[kHid * kFitRows];  // gz2
   __shared__ uint32_t s_sp[27 * (kFitRows / 8)];                          // 4-bit species [slot][row/8]
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 5, l32 = lane & 31;
-  for (int q = tid; q < kFitPack / 16; q += kFitThreads) ((int4 *)s_pack)[q] = ((const int4 *)a.pack)[q];
-  for (int q = tid; q < kFitW1 / 16; q += kFitThreads) ((int4 *)s_w1t)[q] = ((const int4 *)a.w1t)[q];
-  const i32x4 *A0 = (const i32x4 *)s_pack;
-  const i32x4 *A1 = (const i32x4 *)(s_pack + kFitW0);
-  const i32x4 *AT = (const i32x4 *)s_w1t;
-  const float *c1v = (const float *)(s_pack + kFitW0 + kFitW1), *w2v = c1v + kHid;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g4 = lane >> 4, l16 = lane & 15;  // 16x16 roles: lane group, row
+  const int g = lane >> 5, l32 = lane & 31;   // 32x32 roles in the weight-gradient products
+  for (int q = tid; q < kBwdPack / 16; q += kFitThreads) ((int4 *)s_pack)[q] = ((const int4 *)a.bwd)[q];
+  const i32x4 *A0 = (const i32x4 *)s_pack;                                  // [T][s < 3][lane]
+  const s16x4 *A0t = (const s16x4 *)(s_pack + 2 * kBwdW0a);                // [T][lane]: the K = 16 step
+  const i32x4 *A1 = (const i32x4 *)(s_pack + kBwdW0);                       // [To][s][lane]
+  const i32x4 *AT = (const i32x4 *)(s_pack + kBwdW0 + kBwdW1);              // [Ti][s][lane]
+  const float *c1v = (const float *)(s_pack + kBwdW0 + 2 * kBwdW1), *w2v = c1v + kHid;
 
-  f32x16 accW1[kMT], accW0[kMT];  // this wave's quarter of dW1 (o tile = wave) and dW0 (f tile = wave)
+  // this wave's eighth of dW1 (o tile wave / 2, i tiles 2 (wave % 2) + n) and of dW0
+  // (feature tile wave / 2, unit tiles 2 (wave % 2) + n), in 32x32 tiles
+  const int t_hi = wave >> 1, t_lo = 2 * (wave & 1);
+  f32x16 accW1[2], accW0[2];
 #pragma unroll
-  for (int T = 0; T < kMT; ++T)
+  for (int n = 0; n < 2; ++n)
 #pragma unroll
-    for (int v = 0; v < 16; ++v) accW1[T][v] = accW0[T][v] = 0.0f;
-  float db1 = 0.0f, dw2[kMT] = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int v = 0; v < 16; ++v) accW1[n][v] = accW0[n][v] = 0.0f;
+  float db1 = 0.0f, dw2[2] = {0.0f, 0.0f};
 
   const int64_t n_chunks = (a.n_rows + kFitRows - 1) / kFitRows;
-  const int rl = 32 * wave + l32;  // row within the chunk
-  // Stage one BF16 value per (unit, row): register pair q of (T, hh) holds units
-  // u = 32T + 8j + 4g + i with j = 2hh + q/2, i = 2(q%2) + e.  In fit_off the swizzle term
-  // (row chunk) ^ (u & 15) splits into a per-lane part (chunk ^ 4g) and K = 8(j%2) + i, which
-  // takes eight values; their offsets are computed once, so each write is base + constant.
-  int sbase[8];
+  const int rl = 16 * wave + l16;  // row within the chunk
+  // Staging of one BF16 value per (unit, row): the lane holds units 16 T + 4 g4 + v of its
+  // row; in fit_off the swizzle term (row chunk) ^ (u & 15) depends on v only, so the four
+  // offsets are computed once and each write is base + 2048 T.
+  int sbase[4];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const int K = 8 * (k >> 2) + (k & 3);
-    sbase[k] = 128 * (4 * g) + 8 * (((rl >> 3) ^ (4 * g) ^ K) & 15) + (rl & 7);
-  }
-  auto stage = [&](uint16_t *dst, int T, int hh, const i32x4 &p) {
+  for (int v = 0; v < 4; ++v) sbase[v] = fit_off(4 * g4 + v, rl);
+  auto stage = [&](uint16_t *dst, const i32x4 (&b)[4]) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int s = 0; s < 4; ++s)
 #pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        const int j = 2 * hh + (q >> 1), i = 2 * (q & 1) + e;
-        const int k = 4 * (j & 1) + i;  // K = 8 (j % 2) + i
-        dst[sbase[k] + kFitRows * (32 * T + 8 * j + i)] = (uint16_t)((uint32_t)p[q] >> (16 * e));
-      }
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int T = 2 * s + (q >> 1), v = 2 * (q & 1) + e;
+          dst[sbase[v] + kFitRows * 16 * T] = (uint16_t)((uint32_t)b[s][q] >> (16 * e));
+        }
   };
-  for (int64_t chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x) {
-    for (int q = tid; q < 27 * (kFitRows / 8); q += kFitThreads) s_sp[q] = 0u;
+  // species and upstream gradient of a chunk's row, loaded one chunk ahead (consumed only in
+  // the next iteration, so the loads overlap this chunk's work)
+  uint32_t spn[7];
+  double gen = 0.0;
+  bool validn = false;
+  const bool rows32 = a.n_rows <= 0x7fffffff;  // row and site indices in 32 bits
+  auto fetch = [&](int64_t chunk) {
     const int64_t row = chunk * kFitRows + rl;
-    const bool valid = row < a.n_rows;
-    const int64_t r = valid ? row : 0;
-    const int64_t b = r / a.n_sites, j = r - b * a.n_sites;
-    const float gs = valid ? (float)a.gE[b] : 0.0f;
-    uint32_t sp[14];
-    fit_gather(a.snap + b * a.n_sites, site_pos(j, a.L, a.L), a.L, g, sp);
-    __syncthreads();  // weights loaded (first chunk); s_sp cleared; previous chunk's reads done
+    validn = row < a.n_rows;
+    const int64_t r = validn ? row : 0;
+    int64_t b;
+    Pos p;
+    if (rows32) {
+      const uint32_t ns = (uint32_t)a.n_sites, b32 = (uint32_t)r / ns;
+      b = b32;
+      p = site_pos32((int32_t)((uint32_t)r - b32 * ns), a.L, a.L);
+    } else {
+      b = r / a.n_sites;
+      p = site_pos(r - b * a.n_sites, a.L, a.L);
+    }
+    gen = a.gE[b];
+    fit_gather16(a.snap + b * a.n_sites, p, a.L, g4, spn);
+  };
+  if (blockIdx.x < n_chunks) fetch(blockIdx.x);
+  for (int64_t chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x) {
+    uint32_t sp[7];
 #pragma unroll
-    for (int s = 0; s < 7; ++s)
+    for (int q = 0; q < 7; ++q) sp[q] = spn[q];
+    if (g4 == 3) sp[6] = 0u;  // slot 27: the constant-one input, species 0
+    const float gs = validn ? (float)gen : 0.0f;
+    __syncthreads();  // weights loaded (first chunk); the previous chunk's LDS reads done
+    if (chunk + gridDim.x < n_chunks) fetch(chunk + gridDim.x);
+    // species words for phase B: row 8 c + i of a slot goes to nibble 2 (i % 4) + i / 4 of
+    // word c (byte i % 4 holds rows i and i + 4).  The eight lanes of a row octet OR their
+    // nibbles together with row shifts, and the last of them writes the word (every word of
+    // every slot below 27 is written).
 #pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        const int m = 4 * s + 2 * g + e;
-        if (m < 27) atomicOr(&s_sp[m * (kFitRows / 8) + (rl >> 3)], sp[2 * s + e] << (4 * (rl & 7)));
-      }
+    for (int q = 0; q < 7; ++q) {
+      const int m = q < 6 ? 8 * (q >> 1) + 2 * g4 + (q & 1) : 24 + g4;
+      uint32_t w = sp[q] << (8 * (l16 & 3) + 4 * ((l16 >> 2) & 1));
+      w |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0x111, 0xf, 0xf, true);  // row_shr:1
+      w |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0x112, 0xf, 0xf, true);  // row_shr:2
+      w |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0x114, 0xf, 0xf, true);  // row_shr:4
+      if (m < 27 && (l16 & 7) == 7) s_sp[m * (kFitRows / 8) + (rl >> 3)] = w;
+    }
 
     // ---------------------------------------------------------------- layer 0: y1
-    f32x16 acc0[kMT];
+    f32x4 acc[8];
 #pragma unroll
-    for (int T = 0; T < kMT; ++T)
+    for (int T = 0; T < 8; ++T) acc[T] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-      for (int v = 0; v < 16; ++v) acc0[T][v] = 0.0f;
-#pragma unroll
-    for (int s = 0; s < 7; ++s) {
+    for (int s = 0; s < 3; ++s) {
       uint32_t l0, h0, l1, h1;
       onehot_bf16(sp[2 * s], l0, h0);
       onehot_bf16(sp[2 * s + 1], l1, h1);
-      i32x4 bw;
-      bw[0] = (int)l0; bw[1] = (int)h0; bw[2] = (int)l1; bw[3] = (int)h1;
-      const bf16x8 B = __builtin_bit_cast(bf16x8, bw);
+      const i32x4 B = {(int)l0, (int)h0, (int)l1, (int)h1};
 #pragma unroll
-      for (int T = 0; T < kMT; ++T)
-        acc0[T] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, A0[(T * 7 + s) * 64 + lane]), B,
-                                                          acc0[T], 0, 0, 0);
-      __builtin_amdgcn_sched_barrier(0);
+      for (int T = 0; T < 8; ++T) acc[T] = fit_mfma16(A0[(T * 3 + s) * 64 + lane], B, acc[T]);
     }
-    // ---------------------------------------------------------------- layer 1: y2 (h1 staged)
-    f32x16 acc1[kMT];
+    {
+      uint32_t l0, h0;
+      onehot_bf16(sp[6], l0, h0);
+      const s16x4 B = __builtin_bit_cast(s16x4, (uint64_t)l0 | ((uint64_t)h0 << 32));
 #pragma unroll
-    for (int T = 0; T < kMT; ++T)
-#pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        const f32x4 c = *(const f32x4 *)(c1v + 32 * T + 8 * jj + 4 * g);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) acc1[T][4 * jj + i] = c[i];
-      }
-#pragma unroll
-    for (int T = 0; T < kMT; ++T)
-#pragma unroll
-      for (int hh = 0; hh < 2; ++hh) {
-        i32x4 a1p;
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          a1p[q] = (int)pack_bf16x2(act(acc0[T][8 * hh + 2 * q], 1.0f), act(acc0[T][8 * hh + 2 * q + 1], 1.0f));
-        const bf16x8 B = __builtin_bit_cast(bf16x8, a1p);
-#pragma unroll
-        for (int To = 0; To < kMT; ++To)
-          acc1[To] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-              __builtin_bit_cast(bf16x8, A1[(To * 8 + 2 * T + hh) * 64 + lane]), B, acc1[To], 0, 0, 0);
-        stage(s_a, T, hh, a1p);
-        __builtin_amdgcn_sched_barrier(0);
-      }
-    // ---------------------------------------------------------------- dW2 += sum_r gE h2; gz2 (staged)
-    i32x4 g2p[kMT][2];
-#pragma unroll
-    for (int T = 0; T < kMT; ++T) {
-      float hg[16];
-#pragma unroll
-      for (int hh = 0; hh < 2; ++hh) {
-        const f32x4 wa = *(const f32x4 *)(w2v + 32 * T + 8 * (2 * hh) + 4 * g);
-        const f32x4 wb = *(const f32x4 *)(w2v + 32 * T + 8 * (2 * hh + 1) + 4 * g);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          float gz[2];
-#pragma unroll
-          for (int e = 0; e < 2; ++e) {
-            const int v = 8 * hh + 2 * q + e;
-            const float y = acc1[T][v];
-            const float w2s = (2 * q + e) < 4 ? wa[2 * q + e] : wb[2 * q + e - 4];  // -ln2 W2[o]
-            const float sg = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(y));
-            const float z = -kFitLn2 * y;
-            gz[e] = gs * (-kFitLog2e * w2s) * (sg * fmaf(z, 1.0f - sg, 1.0f));
-            hg[v] = gs * (z * sg);  // gE silu(z2)
-          }
-          g2p[T][hh][q] = (int)pack_bf16x2(gz[0], gz[1]);
-        }
-        stage(s_b, T, hh, g2p[T][hh]);
-      }
-      dw2[T] += fit_rowsum16(hg, lane);
+      for (int T = 0; T < 8; ++T) acc[T] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A0t[T * 64 + lane], B, acc[T], 0, 0, 0);
     }
+    // h1 = silu(z1) (times -log2(e)) and silu'(z1) from one exponential and reciprocal
+    float h[8][4], ds1[8][4];
+#pragma unroll
+    for (int T = 0; T < 8; ++T)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const float y = acc[T][v];
+        const float sg = __builtin_amdgcn_rcpf(fmaf(__builtin_amdgcn_exp2f(y), 1.0f, 1.0f));
+        h[T][v] = y * sg;
+        ds1[T][v] = sg * fmaf(-kFitLn2 * y, 1.0f - sg, 1.0f);
+      }
+    i32x4 hb[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) hb[s] = fit_bpack(h, s);
+    stage(s_a, hb);
+    // ---------------------------------------------------------------- layer 1: y2
+#pragma unroll
+    for (int T = 0; T < 8; ++T) acc[T] = *(const f32x4 *)(c1v + 16 * T + 4 * g4);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int T = 0; T < 8; ++T) acc[T] = fit_mfma16(A1[(T * 4 + s) * 64 + lane], hb[s], acc[T]);
+    // ---------------------------------------------------------------- gz2, dW2 += sum_r gE h2
+    float gz[8][4], hg[2][16];
+#pragma unroll
+    for (int T = 0; T < 8; ++T) {
+      const f32x4 w2s = *(const f32x4 *)(w2v + 16 * T + 4 * g4);  // -ln2 W2[o]
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const float y = acc[T][v];
+        const float sg = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(y));
+        const float z = -kFitLn2 * y;
+        gz[T][v] = gs * (-kFitLog2e * w2s[v]) * (sg * fmaf(z, 1.0f - sg, 1.0f));
+        hg[T >> 2][4 * (T & 3) + v] = gs * (z * sg);  // gE silu(z2)
+      }
+    }
+    dw2[0] += fit_lanesum16(hg[0], lane);
+    dw2[1] += fit_lanesum16(hg[1], lane);
+    i32x4 gb[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) gb[s] = fit_bpack(gz, s);
+    stage(s_b, gb);
     // ---------------------------------------------------------------- gh1 = W1^T gz2, gz1
-    f32x16 accg[kMT];
 #pragma unroll
-    for (int T = 0; T < kMT; ++T)
+    for (int T = 0; T < 8; ++T) acc[T] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-      for (int v = 0; v < 16; ++v) accg[T][v] = 0.0f;
+    for (int s = 0; s < 4; ++s)
 #pragma unroll
-    for (int T = 0; T < kMT; ++T)
+      for (int T = 0; T < 8; ++T) acc[T] = fit_mfma16(AT[(T * 4 + s) * 64 + lane], gb[s], acc[T]);
 #pragma unroll
-      for (int hh = 0; hh < 2; ++hh) {
-        const bf16x8 B = __builtin_bit_cast(bf16x8, g2p[T][hh]);
+    for (int T = 0; T < 8; ++T)
 #pragma unroll
-        for (int Ti = 0; Ti < kMT; ++Ti)
-          accg[Ti] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-              __builtin_bit_cast(bf16x8, AT[(Ti * 8 + 2 * T + hh) * 64 + lane]), B, accg[Ti], 0, 0, 0);
-        __builtin_amdgcn_sched_barrier(0);
-      }
-    i32x4 g1p[kMT][2];
+      for (int v = 0; v < 4; ++v) gz[T][v] = acc[T][v] * ds1[T][v];
+    i32x4 g1b[4];
 #pragma unroll
-    for (int T = 0; T < kMT; ++T)
-#pragma unroll
-      for (int hh = 0; hh < 2; ++hh)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int v = 8 * hh + 2 * q;
-          g1p[T][hh][q] = (int)pack_bf16x2(accg[T][v] * fit_dsilu(acc0[T][v]), accg[T][v + 1] * fit_dsilu(acc0[T][v + 1]));
-        }
+    for (int s = 0; s < 4; ++s) g1b[s] = fit_bpack(gz, s);
 
     // ---------------------------------------------------------------- phase A: dW1, db1
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kFitRows / 16; ++k) {
-      const bf16x8 A = fit_ld8(s_b + fit_off(32 * wave + l32, 16 * k + 8 * g));
+      const bf16x8 A = fit_ld8(s_b + fit_off(32 * t_hi + l32, 16 * k + 8 * g));
 #pragma unroll
-      for (int nt = 0; nt < kMT; ++nt)
-        accW1[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, fit_ld8(s_a + fit_off(32 * nt + l32, 16 * k + 8 * g)),
-                                                            accW1[nt], 0, 0, 0);
+      for (int n = 0; n < 2; ++n)
+        accW1[n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+            A, fit_ld8(s_a + fit_off(32 * (t_lo + n) + l32, 16 * k + 8 * g)), accW1[n], 0, 0, 0);
     }
     {
-      const int o = tid >> 1, half = tid & 1;
+      const int o = tid >> 2, part = tid & 3;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) db1 += fit_sum8(s_b + fit_off(o, 64 * half + 8 * q));
+      for (int q = 0; q < 4; ++q) db1 += fit_sum8(s_b + fit_off(o, 32 * part + 8 * q));
     }
     __syncthreads();
     // ---------------------------------------------------------------- phase B: dW0 (+db0)
-#pragma unroll
-    for (int T = 0; T < kMT; ++T)
-#pragma unroll
-      for (int hh = 0; hh < 2; ++hh) stage(s_a, T, hh, g1p[T][hh]);
+    stage(s_a, g1b);
     __syncthreads();
     {
-      const int f = 32 * wave + l32, m = f >> 2, c = f & 3;
+      // x[row][f] as BF16 one-hot values by byte permutes: with the species of four rows as
+      // bytes b, the selector (b | 4, b, ...) picks byte b of K80 = 0x80 << 8c and of
+      // K3F = 0x3F << 8c, giving 0x3F80 (one) where b == c and zero elsewhere; the byte 0x0C
+      // selects the constant zero (features past the bias; the bias slot reads species 0)
+      const int f = 32 * t_hi + l32, m = f >> 2, c = f & 3;
+      const uint32_t k80 = 0x80u << (8 * c), k3f = 0x3Fu << (8 * c);
+      auto onehot2 = [&](uint32_t sb, uint32_t sel) -> int {
+        return (int)__builtin_amdgcn_perm(k80, k3f, __builtin_amdgcn_perm(sb | 0x04040404u, sb, sel));
+      };
 #pragma unroll
       for (int k = 0; k < kFitRows / 16; ++k) {
-        const uint32_t word = m < 27 ? s_sp[m * (kFitRows / 8) + 2 * k + g] : 0u;
-        i32x4 bw;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          uint32_t d = 0;
-#pragma unroll
-          for (int e = 0; e < 2; ++e) {
-            const uint32_t nib = (word >> (4 * (2 * q + e))) & 15u;
-            const bool one = m < 27 ? nib == (uint32_t)c : (m == 27 && c == 0);
-            d |= (one ? 0x3F80u : 0u) << (16 * e);
-          }
-          bw[q] = (int)d;
-        }
+        const uint32_t word = m < 27 ? s_sp[m * (kFitRows / 8) + 2 * k + g] : (m == 27 ? 0u : 0xCCCCCCCCu);
+        const uint32_t r03 = word & 0x0F0F0F0Fu, r47 = (word >> 4) & 0x0F0F0F0Fu;
+        const i32x4 bw = {onehot2(r03, 0x01050004u), onehot2(r03, 0x03070206u), onehot2(r47, 0x01050004u),
+                          onehot2(r47, 0x03070206u)};
         const bf16x8 B = __builtin_bit_cast(bf16x8, bw);
 #pragma unroll
-        for (int mt = 0; mt < kMT; ++mt)
-          accW0[mt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fit_ld8(s_a + fit_off(32 * mt + l32, 16 * k + 8 * g)),
-                                                              B, accW0[mt], 0, 0, 0);
+        for (int n = 0; n < 2; ++n)
+          accW0[n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fit_ld8(s_a + fit_off(32 * (t_lo + n) + l32, 16 * k + 8 * g)),
+                                                             B, accW0[n], 0, 0, 0);
       }
     }
-    __syncthreads();
   }
 
   // ------------------------------------------------------------------ this block's partial
   float *P = a.partial + (int64_t)blockIdx.x * kFitParams;
 #pragma unroll
-  for (int nt = 0; nt < kMT; ++nt)
+  for (int n = 0; n < 2; ++n)
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-      const int o = fit_hid(wave, v, g), i = 32 * nt + l32;
-      P[kOffW1 + o * kHid + i] = -kFitLn2 * accW1[nt][v];  // staged h1 carried -log2(e)
+      const int o = fit_hid(t_hi, v, g), i = 32 * (t_lo + n) + l32;
+      P[kOffW1 + o * kHid + i] = -kFitLn2 * accW1[n][v];  // staged h1 carried -log2(e)
     }
 #pragma unroll
-  for (int mt = 0; mt < kMT; ++mt)
+  for (int n = 0; n < 2; ++n)
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-      const int i = fit_hid(mt, v, g), f = 32 * wave + l32;
-      if (f < kFitF) P[i * kFitF + f] = accW0[mt][v];
-      else if (f == kFitF) P[kOffB0 + i] = accW0[mt][v];
+      const int i = fit_hid(t_lo + n, v, g), f = 32 * t_hi + l32;
+      if (f < kFitF) P[i * kFitF + f] = accW0[n][v];
+      else if (f == kFitF) P[kOffB0 + i] = accW0[n][v];
     }
-  // dW2: every wave summed its own rows; even lanes of each group hold register
-  // 8 b4 + 4 b3 + 2 b2 + b1 (lane bits 4..1) of every M-tile.  The per-wave sums meet in s_b
-  // (free after the last chunk's barrier) and are added in wave order.
+  // dW2: every wave summed its own rows; lane (g4, l16) holds unit 16 (4 h + l16 / 4) +
+  // 4 g4 + l16 % 4 of half h.  The per-wave sums meet in s_b and are added in wave order.
+  __syncthreads();  // the last chunk's reads of s_b (db1) are done
   float(*s_w2)[kHid] = (float(*)[kHid])s_b;
-  if (!(l32 & 1)) {
-    const int v = 8 * ((l32 >> 4) & 1) + 4 * ((l32 >> 3) & 1) + 2 * ((l32 >> 2) & 1) + ((l32 >> 1) & 1);
 #pragma unroll
-    for (int T = 0; T < kMT; ++T) s_w2[wave][fit_hid(T, v, g)] = dw2[T];
-  }
+  for (int hf = 0; hf < 2; ++hf) s_w2[wave][16 * (4 * hf + (l16 >> 2)) + 4 * g4 + (l16 & 3)] = dw2[hf];
   __syncthreads();
-  if (tid < kHid) P[kOffW2 + tid] = (s_w2[0][tid] + s_w2[1][tid]) + (s_w2[2][tid] + s_w2[3][tid]);
-  const float d1 = db1 + __shfl_xor(db1, 1);
-  if (!(tid & 1)) P[kOffB1 + (tid >> 1)] = d1;
+  if (tid < kHid) {
+    float sum = 0.0f;
+#pragma unroll
+    for (int w = 0; w < 8; ++w) sum += s_w2[w][tid];
+    P[kOffW2 + tid] = sum;
+  }
+  const float d1 = (db1 + __shfl_xor(db1, 1)) + (__shfl_xor(db1, 2) + __shfl_xor(db1, 3));
+  if (!(tid & 3)) P[kOffB1 + (tid >> 2)] = d1;
   if (tid == 0) P[kOffB2] = 0.0f;
 }
 

@@ -78,9 +78,9 @@ int fit_buffers(smc_ctx *c, int32_t batch, int64_t rows) {
 int fit_pack(smc_ctx *c, const float *params) {
   FitState &f = c->fit;
   if (!f.pack && hipMalloc(&f.pack, kFitPack) != hipSuccess) return fail(c, SMC_E_NOMEM, "fit pack");
-  if (!f.w1t && hipMalloc(&f.w1t, kFitW1) != hipSuccess) return fail(c, SMC_E_NOMEM, "fit W1^T pack");
-  const int n = kFitW0 / 2 + kFitW1 + kHid;
-  hipLaunchKernelGGL(k_fit_pack_bf16, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, params, f.pack, f.w1t);
+  if (!f.bwd && hipMalloc(&f.bwd, kBwdPack) != hipSuccess) return fail(c, SMC_E_NOMEM, "fit backward pack");
+  hipLaunchKernelGGL(k_fit_pack_bf16, dim3(grid_for(kFitPackThreads, 256)), dim3(256), 0, c->stream, params, f.pack,
+                     f.bwd);
   HIPC(c, hipGetLastError());
   return SMC_OK;
 }
@@ -166,7 +166,7 @@ int fit_forward(smc_ctx *c, const uint8_t *snap, int32_t batch, int32_t L, const
     a.n_sites = N;
     a.n_rows = rows;
     a.pack = c->fit.pack;
-    a.w1t = c->fit.w1t;
+    a.bwd = c->fit.bwd;
     a.b2 = params + kOffB2;
     a.row_e = c->fit.row_e;
     const int64_t tiles = (rows + 31) / 32;
@@ -201,7 +201,7 @@ int fit_backward(smc_ctx *c, const uint8_t *snap, int32_t batch, int32_t L, cons
     a.n_sites = N;
     a.n_rows = rows;
     a.pack = f.pack;
-    a.w1t = f.w1t;
+    a.bwd = f.bwd;
     a.gE = gE;
     a.partial = f.partial;
     hipLaunchKernelGGL(k_fit_bwd_bf16, dim3(grid), dim3(kFitThreads), 0, c->stream, a);
@@ -239,7 +239,7 @@ namespace smc {
 
 void fit_release(smc_ctx *c) {
   FitState &f = c->fit;
-  void *bufs[] = {f.pack, f.w1t, f.partial, f.row_e, f.S, f.gs, f.loss, f.grad, f.ref, f.ce_table};
+  void *bufs[] = {f.pack, f.bwd, f.partial, f.row_e, f.S, f.gs, f.loss, f.grad, f.ref, f.ce_table};
   for (void *p : bufs)
     if (p) (void)hipFree(p);
   f = FitState{};
