@@ -283,9 +283,10 @@ int smc_energy_fwd(smc_ctx *ctx, const uint8_t *snap_dev, int32_t batch, int32_t
 int smc_energy_bwd(smc_ctx *ctx, const uint8_t *snap_dev, int32_t batch, int32_t cells_per_axis,
                    const float *params_dev, const double *grad_e_dev, float *grad_params_dev);
 
-/* One training step on a batch: S = smc_energy_fwd(...); loss = mean_b ((S_b - E_b)/N)^2
+/* One training step on a batch: S = the snapshot energies; loss = mean_b ((S_b - E_b)/N)^2
  * with labels E (label_dev, double device [batch]) and N = 2 L^3; gradient by the backward
- * pass; Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected with step >= 1, learning rate
+ * pass (on the BF16 path one pass gives both S and the per-snapshot gradients, which the loss
+ * gradient then weights; S can differ from smc_energy_fwd's in the last bits); Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected with step >= 1, learning rate
  * lr > 0) updating params_dev (FP32 masters) and the moments adam_m_dev, adam_v_dev (float
  * device [n_params], zero before step 1) in place.  loss_host (nullable): the loss before
  * the update; giving it synchronises.  Low-precision copies used by sweeps are not touched:

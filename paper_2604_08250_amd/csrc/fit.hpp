@@ -6,10 +6,15 @@
 // site and its 26 shell-1..3 neighbours, and S_b sums the rows of snapshot b.
 //
 // BF16 path (matrix cores, FP32 accumulation).  Forward: the sweep's tile evaluator.
-// Backward, fused per chunk of 128 rows in a block of eight waves, each wave owning 16 rows
+// Backward: the gradient of the energy sum of each segment of a snapshot (a range of its
+// chunks; one segment per snapshot when there are at least as many snapshots as CUs) with a
+// unit upstream gradient, and that energy sum; a second kernel weights the segment gradients
+// by the upstream gradient of their snapshot.  The loss gradient needs the snapshot energies
+// first, so this order lets one pass serve both: the fit step runs no separate forward.
+// Per chunk of 128 rows of one snapshot, in a block of eight waves, each wave owning 16 rows
 // (16x16 matrix-core tiles: two waves per SIMD fit in the register file):
 //   forward again, keeping silu'(z1) from the same exponential and reciprocal as h1;
-//   gz2 = gE W2 silu'(z2);  gh1 = W1^T gz2 (matrix cores, W1^T image in LDS);
+//   E = W2 . silu(z2) + b2;  gz2 = W2 silu'(z2);  gh1 = W1^T gz2 (matrix cores, W1^T image in LDS);
 //   gz1 = gh1 silu'(z1);
 // then the weight gradients, which sum over rows, are matrix-core products with the rows as
 // the K dimension: the per-row vectors are staged in LDS as [unit][row] BF16 tiles (the
@@ -17,9 +22,9 @@
 //   phase A: dW1 = sum_r gz2 (x) h1  and  db1 = sum_r gz2;
 //   phase B: dW0 = sum_r gz1 (x) x  (x built from 4-bit species codes in LDS; feature 108 is
 //            the constant one, so db0 comes out of the same product).
-// dW2 = sum_r gE h2 is a butterfly over the lanes of each wave.  Each block accumulates its
-// chunks in registers and writes one partial gradient; a second kernel adds the partials in
-// block order, so the result does not depend on timing.
+// dW2 = sum_r h2 is a butterfly over the lanes of each wave.  Each block accumulates the
+// chunks of a segment in registers and writes the segment's gradient and energy sum; the
+// combination adds them in segment order, so the result does not depend on timing.
 //
 // Reference path (FP32 or FP64): one thread per (row, unit) per layer with the per-row
 // values in global scratch, and one thread per parameter summing the rows in order.
@@ -74,7 +79,7 @@ __device__ __forceinline__ uint16_t fit_bf16(float x) {
 // w2 = -ln(2) W2.  Backward pack (16x16 tiles, A operands; lane l holds row l % 16 and K
 // slots 8 (l / 16) .. + 7 of a 16x16x32 step, or 4 (l / 16) .. + 3 of a 16x16x16 step):
 // layer 0 (features 32 s + 8 (l / 16) + j, then 96 + 4 (l / 16) + j), layer 1 (W1[o][i]
-// with i = fit_hid16(s, l / 16, j)), W1^T (W1[o][i] with o = fit_hid16(s, l / 16, j)), c1, w2.
+// with i = fit_hid16(s, l / 16, j)), W1^T (W1[o][i] with o = fit_hid16(s, l / 16, j)), c1, W2.
 __device__ __forceinline__ float fit_w0s(const float *W0, const float *b0, int o, int f) {
   return f < kFitF ? -kFitLog2e * W0[o * kFitF + f] : (f == kFitF ? -kFitLog2e * b0[o] : 0.0f);
 }
@@ -125,7 +130,8 @@ __global__ void k_fit_pack_bf16(const float *p, uint8_t *pack, uint8_t *bwd) {
   t -= 2 * m1;
   if (t < kHid) {
     c1[t] = bc1[t] = -kFitLog2e * b1[t];
-    w2[t] = bw2[t] = -kFitLn2 * W2[t];
+    w2[t] = -kFitLn2 * W2[t];
+    bw2[t] = W2[t];
   }
 }
 
@@ -172,9 +178,10 @@ struct FitArgs {
   int64_t n_sites, n_rows;
   const uint8_t *pack, *bwd;  // forward and backward BF16 images
   const float *b2;            // forward: the output bias in the FP32 blob
-  const double *gE;     // backward: [batch] upstream gradient per snapshot
-  float *partial;       // backward: [gridDim.x][kFitParams]
-  double *row_e;        // forward: [n_rows]
+  float *partial;       // backward: [n_seg][kFitParams] gradient of each segment's row energies
+  double *row_e;        // forward: [n_rows]; backward: [n_seg] sum of each segment's row energies
+  // backward segments: snapshot s / nps, chunks (s % nps) cps .. + cps of its chunks_snap
+  int32_t n_seg, nps, cps, chunks_snap;
 };
 
 // ---------------------------------------------------------------------------- forward
@@ -220,14 +227,17 @@ __global__ void k_fit_snap_sum(const double *row_e, int64_t n_sites, double *S) 
   if (t == 0) S[b] = s_p[0];
 }
 
-// Fit objective (one block): loss = mean_b ((S_b - E_b)/N)^2 and gs_b = dloss/dS_b.
-__global__ void k_fit_loss(const double *S, const double *label, int32_t batch, double n_sites, double *gs,
-                           double *loss) {
+// Fit objective (one block): loss = mean_b ((S_b - E_b)/N)^2 and gs_b = dloss/dS_b, with
+// S_b the sum of the nps segment sums S[nps b .. nps b + nps - 1] in order.
+__global__ void k_fit_loss(const double *S, int32_t nps, const double *label, int32_t batch, double n_sites,
+                           double *gs, double *loss) {
   __shared__ double s_p[256];
   const int t = threadIdx.x;
   double acc = 0.0;
   for (int b = t; b < batch; b += 256) {
-    const double d = S[b] - label[b];
+    double Sb = 0.0;
+    for (int k = 0; k < nps; ++k) Sb += S[(int64_t)b * nps + k];
+    const double d = Sb - label[b];
     acc += (d / n_sites) * (d / n_sites);
     gs[b] = 2.0 * d / (n_sites * n_sites * (double)batch);
   }
@@ -309,8 +319,10 @@ __global__ __launch_bounds__(kFitThreads) void k_fit_bwd_bf16(FitArgs a) {
   __shared__ __attribute__((aligned(16))) uint16_t s_a[kHid * kFitRows];  // h1 (scaled), then gz1
   __shared__ __attribute__((aligned(16))) uint16_t s_b[kHid * kFitRows];  // gz2
   __shared__ uint32_t s_sp[27 * (kFitRows / 8)];                          // 4-bit species [slot][row/8]
+  __shared__ __attribute__((aligned(16))) float s_big[kHid];               // layer-1 start of rows past the end
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g4 = lane >> 4, l16 = lane & 15;  // 16x16 roles: lane group, row
+  if (tid < kHid) s_big[tid] = 1e30f;
   const int g = lane >> 5, l32 = lane & 31;   // 32x32 roles in the weight-gradient products
   for (int q = tid; q < kBwdPack / 16; q += kFitThreads) ((int4 *)s_pack)[q] = ((const int4 *)a.bwd)[q];
   const i32x4 *A0 = (const i32x4 *)s_pack;                                  // [T][s < 3][lane]
@@ -328,8 +340,10 @@ __global__ __launch_bounds__(kFitThreads) void k_fit_bwd_bf16(FitArgs a) {
 #pragma unroll
     for (int v = 0; v < 16; ++v) accW1[n][v] = accW0[n][v] = 0.0f;
   float db1 = 0.0f, dw2[2] = {0.0f, 0.0f};
+  double es = 0.0;  // energy sum of this lane's row position over the segment's chunks
+  const float b2 = *a.b2;
+  const uint32_t N = (uint32_t)a.n_sites;
 
-  const int64_t n_chunks = (a.n_rows + kFitRows - 1) / kFitRows;
   const int rl = 16 * wave + l16;  // row within the chunk
   // Staging of one BF16 value per (unit, row): the lane holds units 16 T + 4 g4 + v of its
   // row; in fit_off the swizzle term (row chunk) ^ (u & 15) depends on v only, so the four
@@ -348,38 +362,32 @@ __global__ __launch_bounds__(kFitThreads) void k_fit_bwd_bf16(FitArgs a) {
           dst[sbase[v] + kFitRows * 16 * T] = (uint16_t)((uint32_t)b[s][q] >> (16 * e));
         }
   };
-  // species and upstream gradient of a chunk's row, loaded one chunk ahead (consumed only in
-  // the next iteration, so the loads overlap this chunk's work)
+  // the block walks (segment, chunk) items: segments blockIdx.x + k gridDim.x, each over its
+  // chunk range; the species of the next item are loaded one item ahead (consumed only in the
+  // next iteration, so the loads overlap this chunk's work)
+  auto c_begin = [&](int seg) { return (seg % a.nps) * a.cps; };
+  auto c_end = [&](int seg) { return min(a.chunks_snap, (seg % a.nps + 1) * a.cps); };
   uint32_t spn[7];
-  double gen = 0.0;
-  bool validn = false;
-  const bool rows32 = a.n_rows <= 0x7fffffff;  // row and site indices in 32 bits
-  auto fetch = [&](int64_t chunk) {
-    const int64_t row = chunk * kFitRows + rl;
-    validn = row < a.n_rows;
-    const int64_t r = validn ? row : 0;
-    int64_t b;
-    Pos p;
-    if (rows32) {
-      const uint32_t ns = (uint32_t)a.n_sites, b32 = (uint32_t)r / ns;
-      b = b32;
-      p = site_pos32((int32_t)((uint32_t)r - b32 * ns), a.L, a.L);
-    } else {
-      b = r / a.n_sites;
-      p = site_pos(r - b * a.n_sites, a.L, a.L);
-    }
-    gen = a.gE[b];
-    fit_gather16(a.snap + b * a.n_sites, p, a.L, g4, spn);
+  auto fetch = [&](int seg, int c) {
+    const uint32_t j = (uint32_t)c * kFitRows + rl;
+    const uint32_t jj = j < N ? j : 0u;
+    fit_gather16(a.snap + (int64_t)(seg / a.nps) * a.n_sites, site_pos32((int32_t)jj, a.L, a.L), a.L, g4, spn);
   };
-  if (blockIdx.x < n_chunks) fetch(blockIdx.x);
-  for (int64_t chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x) {
+  int seg = blockIdx.x, c = seg < a.n_seg ? c_begin(seg) : 0;
+  if (seg < a.n_seg) fetch(seg, c);
+  while (seg < a.n_seg) {
     uint32_t sp[7];
 #pragma unroll
     for (int q = 0; q < 7; ++q) sp[q] = spn[q];
     if (g4 == 3) sp[6] = 0u;  // slot 27: the constant-one input, species 0
-    const float gs = validn ? (float)gen : 0.0f;
+    const bool valid = (uint32_t)c * kFitRows + rl < N;
+    int nseg = seg, nc = c + 1;
+    if (nc >= c_end(seg)) {
+      nseg = seg + gridDim.x;
+      nc = nseg < a.n_seg ? c_begin(nseg) : 0;
+    }
     __syncthreads();  // weights loaded (first chunk); the previous chunk's LDS reads done
-    if (chunk + gridDim.x < n_chunks) fetch(chunk + gridDim.x);
+    if (nseg < a.n_seg) fetch(nseg, nc);
     // species words for phase B: row 8 c + i of a slot goes to nibble 2 (i % 4) + i / 4 of
     // word c (byte i % 4 holds rows i and i + 4).  The eight lanes of a row octet OR their
     // nibbles together with row shifts, and the last of them writes the word (every word of
@@ -430,28 +438,36 @@ __global__ __launch_bounds__(kFitThreads) void k_fit_bwd_bf16(FitArgs a) {
     for (int s = 0; s < 4; ++s) hb[s] = fit_bpack(h, s);
     stage(s_a, hb);
     // ---------------------------------------------------------------- layer 1: y2
+    // rows past the snapshot's last site start from a huge pre-activation: silu(z2) and
+    // silu'(z2) are then zero, so they add nothing to any gradient or energy
+    const float *c1r = valid ? c1v : s_big;
 #pragma unroll
-    for (int T = 0; T < 8; ++T) acc[T] = *(const f32x4 *)(c1v + 16 * T + 4 * g4);
+    for (int T = 0; T < 8; ++T) acc[T] = *(const f32x4 *)(c1r + 16 * T + 4 * g4);
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int T = 0; T < 8; ++T) acc[T] = fit_mfma16(A1[(T * 4 + s) * 64 + lane], hb[s], acc[T]);
-    // ---------------------------------------------------------------- gz2, dW2 += sum_r gE h2
-    float gz[8][4], hg[2][16];
+    // ---------------------------------------------------------------- E, gz2, dW2 += sum_r h2
+    float gz[8][4], hg[2][16], ep = 0.0f;
 #pragma unroll
     for (int T = 0; T < 8; ++T) {
-      const f32x4 w2s = *(const f32x4 *)(w2v + 16 * T + 4 * g4);  // -ln2 W2[o]
+      const f32x4 w2 = *(const f32x4 *)(w2v + 16 * T + 4 * g4);  // W2[o]
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const float y = acc[T][v];
         const float sg = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(y));
-        const float z = -kFitLn2 * y;
-        gz[T][v] = gs * (-kFitLog2e * w2s[v]) * (sg * fmaf(z, 1.0f - sg, 1.0f));
-        hg[T >> 2][4 * (T & 3) + v] = gs * (z * sg);  // gE silu(z2)
+        const float z = -kFitLn2 * y, zs = z * sg;  // silu(z2)
+        gz[T][v] = w2[v] * (sg * fmaf(z, 1.0f - sg, 1.0f));
+        hg[T >> 2][4 * (T & 3) + v] = zs;
+        ep = fmaf(w2[v], zs, ep);
       }
     }
     dw2[0] += fit_lanesum16(hg[0], lane);
     dw2[1] += fit_lanesum16(hg[1], lane);
+    // row energy: the four lane groups of the row hold disjoint units
+    ep += __shfl_xor(ep, 16);
+    ep += __shfl_xor(ep, 32);
+    if (valid) es += (double)(ep + b2);
     i32x4 gb[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) gb[s] = fit_bpack(gz, s);
@@ -495,8 +511,8 @@ __global__ __launch_bounds__(kFitThreads) void k_fit_bwd_bf16(FitArgs a) {
       // bytes b, the selector (b | 4, b, ...) picks byte b of K80 = 0x80 << 8c and of
       // K3F = 0x3F << 8c, giving 0x3F80 (one) where b == c and zero elsewhere; the byte 0x0C
       // selects the constant zero (features past the bias; the bias slot reads species 0)
-      const int f = 32 * t_hi + l32, m = f >> 2, c = f & 3;
-      const uint32_t k80 = 0x80u << (8 * c), k3f = 0x3Fu << (8 * c);
+      const int f = 32 * t_hi + l32, m = f >> 2, cc = f & 3;
+      const uint32_t k80 = 0x80u << (8 * cc), k3f = 0x3Fu << (8 * cc);
       auto onehot2 = [&](uint32_t sb, uint32_t sel) -> int {
         return (int)__builtin_amdgcn_perm(k80, k3f, __builtin_amdgcn_perm(sb | 0x04040404u, sb, sel));
       };
@@ -513,55 +529,86 @@ __global__ __launch_bounds__(kFitThreads) void k_fit_bwd_bf16(FitArgs a) {
                                                              B, accW0[n], 0, 0, 0);
       }
     }
-  }
-
-  // ------------------------------------------------------------------ this block's partial
-  float *P = a.partial + (int64_t)blockIdx.x * kFitParams;
+    if (nseg != seg) {
+      // ---------------------------------------------------------------- segment done: flush
+      __syncthreads();  // every wave's phase A (s_b reads) and phase B are done
+      float *P = a.partial + (int64_t)seg * kFitParams;
+      {
+        // dW1[o][i]: o = fit_hid(t_hi, v, g), i = 32 (t_lo + n) + l32
+        float *pw = P + kOffW1 + (32 * t_hi + 4 * g) * kHid + 32 * t_lo + l32;
 #pragma unroll
-  for (int n = 0; n < 2; ++n)
+        for (int n = 0; n < 2; ++n)
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int o = fit_hid(t_hi, v, g), i = 32 * (t_lo + n) + l32;
-      P[kOffW1 + o * kHid + i] = -kFitLn2 * accW1[n][v];  // staged h1 carried -log2(e)
+          for (int v = 0; v < 16; ++v) {
+            pw[(8 * (v >> 2) + (v & 3)) * kHid + 32 * n] = -kFitLn2 * accW1[n][v];  // staged h1 carried -log2(e)
+            accW1[n][v] = 0.0f;
+          }
+        // dW0[i][f] (f < 108) and db0[i] (f = 108): i = fit_hid(t_lo + n, v, g), f = 32 t_hi + l32
+        const int f = 32 * t_hi + l32;
+        float *pb = f < kFitF ? P + (32 * t_lo + 4 * g) * kFitF + f : P + kOffB0 + 32 * t_lo + 4 * g;
+        const int stride = f < kFitF ? kFitF : 1;
+        if (f <= kFitF) {
+#pragma unroll
+          for (int n = 0; n < 2; ++n)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) pb[(32 * n + 8 * (v >> 2) + (v & 3)) * stride] = accW0[n][v];
+        }
+#pragma unroll
+        for (int n = 0; n < 2; ++n)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) accW0[n][v] = 0.0f;
+      }
+      // dW2 and the energy sum meet in s_b: lane (g4, l16) holds unit 16 (4 h + l16 / 4) +
+      // 4 g4 + l16 % 4 of half h; lanes of lane group 0 hold the row sums
+      float(*s_w2)[kHid] = (float(*)[kHid])s_b;
+      double *s_e = (double *)(s_b + 8 * kHid * 2);
+#pragma unroll
+      for (int hf = 0; hf < 2; ++hf) s_w2[wave][16 * (4 * hf + (l16 >> 2)) + 4 * g4 + (l16 & 3)] = dw2[hf];
+      if (g4 == 0) s_e[rl] = es;
+      dw2[0] = dw2[1] = 0.0f;
+      es = 0.0;
+      __syncthreads();
+      if (tid < kHid) {
+        float sum = 0.0f;
+#pragma unroll
+        for (int w = 0; w < 8; ++w) sum += s_w2[w][tid];
+        P[kOffW2 + tid] = sum;
+      } else if (tid == kHid) {
+        double e = 0.0;
+        for (int r = 0; r < kFitRows; ++r) e += s_e[r];
+        a.row_e[seg] = e;
+      }
+      const float d1 = (db1 + __shfl_xor(db1, 1)) + (__shfl_xor(db1, 2) + __shfl_xor(db1, 3));
+      if (!(tid & 3)) P[kOffB1 + (tid >> 2)] = d1;
+      db1 = 0.0f;
+      if (tid == 0) P[kOffB2] = (float)(min(N, (uint32_t)c_end(seg) * kFitRows) - (uint32_t)c_begin(seg) * kFitRows);
     }
-#pragma unroll
-  for (int n = 0; n < 2; ++n)
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int i = fit_hid(t_lo + n, v, g), f = 32 * t_hi + l32;
-      if (f < kFitF) P[i * kFitF + f] = accW0[n][v];
-      else if (f == kFitF) P[kOffB0 + i] = accW0[n][v];
-    }
-  // dW2: every wave summed its own rows; lane (g4, l16) holds unit 16 (4 h + l16 / 4) +
-  // 4 g4 + l16 % 4 of half h.  The per-wave sums meet in s_b and are added in wave order.
-  __syncthreads();  // the last chunk's reads of s_b (db1) are done
-  float(*s_w2)[kHid] = (float(*)[kHid])s_b;
-#pragma unroll
-  for (int hf = 0; hf < 2; ++hf) s_w2[wave][16 * (4 * hf + (l16 >> 2)) + 4 * g4 + (l16 & 3)] = dw2[hf];
-  __syncthreads();
-  if (tid < kHid) {
-    float sum = 0.0f;
-#pragma unroll
-    for (int w = 0; w < 8; ++w) sum += s_w2[w][tid];
-    P[kOffW2 + tid] = sum;
+    seg = nseg;
+    c = nc;
   }
-  const float d1 = (db1 + __shfl_xor(db1, 1)) + (__shfl_xor(db1, 2) + __shfl_xor(db1, 3));
-  if (!(tid & 3)) P[kOffB1 + (tid >> 2)] = d1;
-  if (tid == 0) P[kOffB2] = 0.0f;
 }
 
-// grad[p] = sum of the block partials in block order; the output bias gets sum_b gE_b N.
-__global__ void k_fit_reduce(const float *partial, int32_t n_blocks, const double *gE, int32_t batch, double n_sites,
-                             float *grad) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= kFitParams) return;
+// grad[p] = sum over segments s of ge[s / nps] * partial[s][p] in segment order: wave w of the
+// block sums segments w, w + 8, ... and the eight sums are added in wave order.  The output
+// bias entry of a segment holds its row count, so that entry becomes sum_b ge_b N.
+__global__ __launch_bounds__(512) void k_fit_combine(const float *partial, int32_t n_seg, int32_t nps,
+                                                     const double *ge, float *grad) {
+  __shared__ double s_acc[8][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int p = blockIdx.x * 64 + lane;
   double acc = 0.0;
-  if (p == kOffB2) {
-    for (int b = 0; b < batch; ++b) acc += gE[b] * n_sites;
-  } else {
-    for (int k = 0; k < n_blocks; ++k) acc += (double)partial[(int64_t)k * kFitParams + p];
+  if (p < kFitParams) {
+#pragma unroll 4
+    for (int s = w; s < n_seg; s += 8) acc += ge[s / nps] * (double)partial[(int64_t)s * kFitParams + p];
   }
-  grad[p] = (float)acc;
+  s_acc[w][lane] = acc;
+  __syncthreads();
+  if (w == 0 && p < kFitParams) {
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) t += s_acc[k][lane];
+    grad[p] = (float)t;
+  }
 }
 
 // ---------------------------------------------------------------------------- Adam

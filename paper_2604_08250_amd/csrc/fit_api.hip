@@ -182,31 +182,59 @@ int fit_forward(smc_ctx *c, const uint8_t *snap, int32_t batch, int32_t L, const
   return SMC_OK;
 }
 
+// BF16 backward pass: the gradient and energy sum of every segment of every snapshot with a
+// unit upstream gradient (f.partial, f.row_e).  Segments split a snapshot's chunks only when
+// there are fewer snapshots than CUs.  The images must be packed from params already.
+int fit_segments(smc_ctx *c, const uint8_t *snap, int32_t batch, int32_t L, const float *params, int32_t *nps_out,
+                 int32_t *n_seg_out) {
+  FitState &f = c->fit;
+  const int64_t N = 2LL * L * L * L;
+  const int chunks = (int)((N + kFitRows - 1) / kFitRows);
+  int want = std::min(chunks, std::max(1, (c->n_cu + batch - 1) / batch));
+  const int cps = (chunks + want - 1) / want, nps = (chunks + cps - 1) / cps;
+  const int64_t n_seg = (int64_t)batch * nps;
+  if (n_seg > INT32_MAX) return fail(c, SMC_E_INVALID, "too many snapshot segments");
+  const int grid = (int)std::min<int64_t>(c->n_cu, n_seg);
+  size_t cap = (size_t)f.partial_blocks * kFitParams * sizeof(float);
+  int rc = grow(c, f.partial, cap, (size_t)n_seg * kFitParams * sizeof(float));
+  if (rc) return rc;
+  f.partial_blocks = (int)(cap / (kFitParams * sizeof(float)));
+  FitArgs a{};
+  a.snap = snap;
+  a.L = L;
+  a.n_sites = N;
+  a.n_rows = N * batch;
+  a.pack = f.pack;
+  a.bwd = f.bwd;
+  a.b2 = params + kOffB2;
+  a.partial = f.partial;
+  a.row_e = f.row_e;  // rows >= segments
+  a.n_seg = (int32_t)n_seg;
+  a.nps = nps;
+  a.cps = cps;
+  a.chunks_snap = chunks;
+  hipLaunchKernelGGL(k_fit_bwd_bf16, dim3(grid), dim3(kFitThreads), 0, c->stream, a);
+  HIPC(c, hipGetLastError());
+  *nps_out = nps;
+  *n_seg_out = (int32_t)n_seg;
+  return SMC_OK;
+}
+
+// grad_out = sum over segments of ge[snapshot] * segment gradient, in segment order.
+void fit_combine(smc_ctx *c, int32_t nps, int32_t n_seg, const double *ge, float *grad_out) {
+  hipLaunchKernelGGL(k_fit_combine, dim3((kFitParams + 63) / 64), dim3(512), 0, c->stream, (const float *)c->fit.partial,
+                     n_seg, nps, ge, grad_out);
+}
+
 // grad_out = sum_b gE[b] dS_b/dparams.  On the BF16 path the images must be packed from
 // params already (fit_forward or fit_pack).
 int fit_backward(smc_ctx *c, const uint8_t *snap, int32_t batch, int32_t L, const float *params, const double *gE,
                  float *grad_out) {
-  const int64_t N = 2LL * L * L * L, rows = N * batch;
   if (c->cfg.precision == SMC_BF16) {
-    FitState &f = c->fit;
-    const int64_t chunks = (rows + kFitRows - 1) / kFitRows;
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(c->n_cu, chunks));
-    size_t cap = (size_t)f.partial_blocks * kFitParams * sizeof(float);
-    int rc = grow(c, f.partial, cap, (size_t)grid * kFitParams * sizeof(float));
+    int32_t nps = 0, n_seg = 0;
+    int rc = fit_segments(c, snap, batch, L, params, &nps, &n_seg);
     if (rc) return rc;
-    f.partial_blocks = (int)(cap / (kFitParams * sizeof(float)));
-    FitArgs a{};
-    a.snap = snap;
-    a.L = L;
-    a.n_sites = N;
-    a.n_rows = rows;
-    a.pack = f.pack;
-    a.bwd = f.bwd;
-    a.gE = gE;
-    a.partial = f.partial;
-    hipLaunchKernelGGL(k_fit_bwd_bf16, dim3(grid), dim3(kFitThreads), 0, c->stream, a);
-    hipLaunchKernelGGL(k_fit_reduce, dim3(grid_for(kFitParams, 256)), dim3(256), 0, c->stream,
-                       (const float *)f.partial, grid, gE, batch, (double)N, grad_out);
+    fit_combine(c, nps, n_seg, gE, grad_out);
     HIPC(c, hipGetLastError());
     return SMC_OK;
   }
@@ -274,10 +302,21 @@ int smc_fit_step(smc_ctx *c, const uint8_t *snap, int32_t batch, int32_t L, cons
   if (step < 1 || !(lr > 0.0f)) return fail(c, SMC_E_INVALID, "step >= 1 and lr > 0");
   FitState &f = c->fit;
   if ((rc = fit_buffers(c, batch, 2LL * L * L * L * batch))) return rc;
-  if ((rc = fit_forward(c, snap, batch, L, params, f.S))) return rc;
   const double N = 2.0 * L * L * L;
-  hipLaunchKernelGGL(k_fit_loss, dim3(1), dim3(256), 0, c->stream, (const double *)f.S, labels, batch, N, f.gs, f.loss);
-  if ((rc = fit_backward(c, snap, batch, L, params, f.gs, f.grad))) return rc;
+  if (c->cfg.precision == SMC_BF16) {
+    // one pass: segment energy sums and unit-gradient segment gradients, then the loss
+    // gradient per snapshot weights the segments
+    int32_t nps = 0, n_seg = 0;
+    if ((rc = fit_pack(c, params)) || (rc = fit_segments(c, snap, batch, L, params, &nps, &n_seg))) return rc;
+    hipLaunchKernelGGL(k_fit_loss, dim3(1), dim3(256), 0, c->stream, (const double *)f.row_e, nps, labels, batch, N,
+                       f.gs, f.loss);
+    fit_combine(c, nps, n_seg, f.gs, f.grad);
+  } else {
+    if ((rc = fit_forward(c, snap, batch, L, params, f.S))) return rc;
+    hipLaunchKernelGGL(k_fit_loss, dim3(1), dim3(256), 0, c->stream, (const double *)f.S, 1, labels, batch, N, f.gs,
+                       f.loss);
+    if ((rc = fit_backward(c, snap, batch, L, params, f.gs, f.grad))) return rc;
+  }
   const double beta1 = 0.9, beta2 = 0.999;
   const float bc1 = (float)(1.0 - pow(beta1, step)), bc2s = (float)sqrt(1.0 - pow(beta2, step));
   hipLaunchKernelGGL(k_adam, dim3(grid_for(kFitParams, 256)), dim3(256), 0, c->stream, params, adam_m, adam_v,

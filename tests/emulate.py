@@ -122,10 +122,12 @@ def dsilu_from_y(y):
 
 
 def fit_grad_bf16(params, X, g_rows):
-    """Gradient sum_r g_r dE_r/dparams as the BF16 matrix-core backward defines it: the
-    forward of energies(..., "bf16"); gz2 = q(g W2 silu'(z2)); gh1 = q(W1)^T gz2;
-    gz1 = q(gh1 silu'(z1)); dW1 = sum gz2 (x) q(h1) (h1 as the forward feeds layer 1);
-    dW0, db0 = sum gz1 (x) x; db1 = sum gz2; dW2 = sum g silu(z2); db2 = sum g; q = BF16."""
+    """Gradient sum_r g_r dE_r/dparams as the BF16 matrix-core backward defines it: each row's
+    gradient is formed with a unit upstream gradient and then weighted by g_r (the kernel
+    forms per-snapshot gradients and weights them by the snapshot's upstream gradient).  The
+    forward of energies(..., "bf16"); gz2 = q(W2 silu'(z2)); gh1 = q(W1)^T gz2;
+    gz1 = q(gh1 silu'(z1)); dW1 = sum g gz2 (x) q(h1) (h1 as the forward feeds layer 1);
+    dW0, db0 = sum g gz1 (x) x; db1 = sum g gz2; dW2 = sum g silu(z2); db2 = sum g; q = BF16."""
     W0, b0, W1, b1, W2, b2 = split_params(params)
     X = np.asarray(X, dtype=np.float64)
     g = np.asarray(g_rows, dtype=np.float64)[:, None]
@@ -138,15 +140,14 @@ def fit_grad_bf16(params, X, g_rows):
     y2 = (a1.astype(f64) @ bf16(W1).T.astype(f64) + c1).astype(np.float32)
     z2 = (-LN2 * y2).astype(np.float32)
     sg2 = (np.float32(1.0) / (np.float32(1.0) + np.exp2(y2))).astype(np.float32)
-    w2 = (-L2E * (-LN2 * W2).astype(np.float32)).astype(np.float32)
-    gz2 = bf16((g * w2[None, :] * dsilu_from_y(y2)).astype(np.float32))
-    hg = (g * (z2 * sg2)).astype(np.float64)
+    gz2 = bf16((W2.astype(np.float32)[None, :] * dsilu_from_y(y2)).astype(np.float32))
+    hg = g * (z2 * sg2).astype(np.float64)
     gh1 = (gz2.astype(f64) @ bf16(W1).astype(f64)).astype(np.float32)
-    gz1 = bf16((gh1 * dsilu_from_y(y1)).astype(np.float32))
-    dW1 = -np.float64(LN2) * (gz2.astype(f64).T @ a1.astype(f64))
-    dW0 = gz1.astype(f64).T @ X
-    out = np.concatenate([dW0.ravel(), gz1.astype(f64).sum(axis=0), dW1.ravel(), gz2.astype(f64).sum(axis=0),
-                          hg.sum(axis=0), [g.sum()]])
+    gz1 = g * bf16((gh1 * dsilu_from_y(y1)).astype(np.float32)).astype(f64)
+    gz2 = g * gz2.astype(f64)
+    dW1 = -np.float64(LN2) * (gz2.T @ a1.astype(f64))
+    dW0 = gz1.T @ X
+    out = np.concatenate([dW0.ravel(), gz1.sum(axis=0), dW1.ravel(), gz2.sum(axis=0), hg.sum(axis=0), [g.sum()]])
     return out
 
 

@@ -128,16 +128,20 @@ def test_fp64_gradient_matches_central_differences_of_gpu_forward():
     mc.close()
 
 
-def test_bf16_fwd_bwd_match_emulation_and_fp64():
+@pytest.mark.parametrize("L,B", [(4, 4), (5, 3), (6, 2)])
+def test_bf16_fwd_bwd_match_emulation_and_fp64(L, B):
+    """BF16 energies and gradient against the CPU emulation of the same quantisation points
+    and against FP64.  4^3 cells: one 128-row chunk per snapshot; 5^3: a chunk that runs past
+    the snapshot's last site; 6^3 with two snapshots: each snapshot split into segments over
+    several blocks, the last chunk partial."""
     torch = need_gpu()
     import emulate
     from paper_2604_08250_amd._lib import smc_energy_bwd, smc_energy_fwd
     params = _params()
     model = oracle.MLP(1, 128, params)
-    L, B = 4, 4
     cells = (L, L, L)
     snaps = synth.snapshots(B, L, seed=42)
-    gE = np.array([0.9, -0.4, 1.7, -1.1])
+    gE = np.array([0.9, -0.4, 1.7, -1.1])[:B]
     mc = _ctx("bf16", params)
     d_snaps = torch.from_numpy(snaps).cuda()
     d_p = torch.from_numpy(params).cuda()
@@ -151,13 +155,13 @@ def test_bf16_fwd_bwd_match_emulation_and_fp64():
     N = snaps.shape[1]
     S_emu = emulate.energies(params, X, "bf16").reshape(B, N).sum(axis=1)
     S_64 = oracle.snapshot_energies(cells, model, snaps)
-    _banner(f"bf16 S - emu {np.abs(S - S_emu).max():.3e}, S - fp64 {np.abs(S - S_64).max():.3e}")
+    _banner(f"bf16 L={L} B={B}: S - emu {np.abs(S - S_emu).max():.3e}, S - fp64 {np.abs(S - S_64).max():.3e}")
     assert np.allclose(S, S_emu, rtol=0, atol=1e-4 * N)
     g_emu = emulate.fit_grad_bf16(params, X, np.repeat(gE, N))
     g_64 = oracle.energy_grad(cells, model, snaps, gE)
     r_emu = np.linalg.norm(grad - g_emu) / np.linalg.norm(g_emu)
     r_64 = np.linalg.norm(grad - g_64) / np.linalg.norm(g_64)
-    _banner(f"bf16 gradient: rel err vs emulation {r_emu:.2e}, vs fp64 {r_64:.2e}")
+    _banner(f"bf16 L={L} B={B} gradient: rel err vs emulation {r_emu:.2e}, vs fp64 {r_64:.2e}")
     # same quantisation points: differences come from FP32 accumulation order and the rare
     # BF16 rounding flip it causes
     assert r_emu < 1e-4
@@ -246,9 +250,17 @@ def test_bf16_fit_reduces_loss():
     snaps = torch.from_numpy(synth.snapshots(B, L, seed=45)).cuda()
     labels = ce_energy(mc, p_ce, snaps, L)
     p = torch.from_numpy(params).cuda()
+    # the step's loss comes from the energies its backward pass sums; they must agree with the
+    # forward kernel's
+    from paper_2604_08250_amd._lib import smc_energy_fwd
+    S = torch.empty(B, dtype=torch.float64, device="cuda")
+    smc_energy_fwd(mc.ctx, snaps.data_ptr(), B, L, p.data_ptr(), S.data_ptr())
+    N = 2 * L ** 3
+    loss_fwd = float((((S - labels) / N) ** 2).mean())
     fit = Fitter(mc, p, lr=3e-3)
     losses = [fit.step(snaps, labels, L) for _ in range(60)]
-    _banner(f"bf16 fit: loss {losses[0]:.4e} -> {losses[-1]:.4e}")
+    _banner(f"bf16 fit: loss {losses[0]:.4e} (forward kernel {loss_fwd:.4e}) -> {losses[-1]:.4e}")
+    assert losses[0] == pytest.approx(loss_fwd, rel=1e-4)
     assert np.all(np.isfinite(losses))
     assert losses[-1] < 0.25 * losses[0]
     mc.close()
