@@ -402,6 +402,7 @@ def measure_fcc(precisions=("bf16x3", "fp32", "bf16"), steps=2, warmup=1):
 # Algorithmic work of one fit row: forward (Eqs. (4)-(6)) plus the backward products
 # dL/dh1 = W1^T dL/dz2 (2*128*128), dW1 (2*128*128), dW0 over the 108 one-hot inputs (2*128*108)
 # and the bias/output terms.
+FIT_BURN_IN = 200  # sweeps of each snapshot chain before its snapshot is taken
 FIT_FLOP_PER_ROW = FLOP_PER_EVAL + 2 * 128 * 128 + 2 * 128 * 128 + 2 * 128 * 108 + 4 * 128
 
 
@@ -413,7 +414,7 @@ def measure_fit(steps=5, warmup=1):
 
     import synth
     import paper_2604_08250_amd as smc
-    from paper_2604_08250_amd.fit import Fitter, ce_energy
+    from paper_2604_08250_amd.fit import Fitter, ce_energy, sample_snapshots
     from paper_2604_08250_amd._lib import smc_energy_bwd, smc_energy_fwd
 
     w = synth.workload("c5")
@@ -421,8 +422,18 @@ def measure_fit(steps=5, warmup=1):
     params0 = w.params()
     mc = smc.SwapMC([(4, 4, 4)], [1000.0], synth.random_occupancy(4, 4), params0, n_species=4,
                     feature=w.feature, hidden=w.hidden, precision="bf16", seed=0)
-    snaps = torch.from_numpy(synth.snapshots(B, L)).cuda()
-    labels = ce_energy(mc, synth.ce_params(), snaps, L)
+    # the batch: 1,024 swap-MC chains on the CE pair part from random placements, one per
+    # temperature drawn uniformly in [300, 3000] K, after 200 burn-in sweeps
+    ce = synth.ce_params()
+    start = synth.snapshots(B, L)
+    t0 = time.perf_counter()
+    snaps = sample_snapshots(start, L, synth.snapshot_temperatures(B), ce["pair"], burn_in=FIT_BURN_IN, seed=0)
+    torch.cuda.synchronize()
+    sample_s = time.perf_counter() - t0
+    labels = ce_energy(mc, ce, snaps, L)
+    labels0 = ce_energy(mc, ce, torch.from_numpy(start).cuda(), L)
+    log(f"c5 snapshots: {B} chains x {FIT_BURN_IN} sweeps in {sample_s:.1f} s; CE energy per atom "
+        f"{float(labels0.mean()) / (2 * L ** 3):.5f} (random placements) -> {float(labels.mean()) / (2 * L ** 3):.5f} eV")
     params = torch.from_numpy(params0).cuda()
     fit = Fitter(mc, params, lr=1e-3)
     loss0 = fit.step(snaps, labels, L)
@@ -459,7 +470,12 @@ def measure_fit(steps=5, warmup=1):
            "rows_per_s": rows * steps / (ms / 1e3), "ms_per_step": ms / steps, "steps": steps,
            "fwd_ms": t["fwd"], "bwd_ms": t["bwd"],
            "algorithmic_tflops": rows * FIT_FLOP_PER_ROW / (ms / steps / 1e3) / 1e12,
-           "loss_first": loss0, "loss_after": loss1}
+           "loss_first": loss0, "loss_after": loss1,
+           "snapshots": f"{B} swap-MC chains on the CE pair part (qSRO blob), T ~ U[300, 3000] K, "
+                        f"{FIT_BURN_IN} sweeps from random placements",
+           "snapshot_sampling_s": sample_s,
+           "ce_energy_per_atom_eV": {"random_placements": float(labels0.mean()) / (2 * L ** 3),
+                                     "sampled": float(labels.mean()) / (2 * L ** 3)}}
     out["roofline_frac"] = out["algorithmic_tflops"] / PEAK_TFLOPS["bf16"]
     log(f"c5 fit: {out['ms_per_step']:.2f} ms per step (fwd {t['fwd']:.2f} ms, bwd {t['bwd']:.2f} ms), "
         f"loss {loss0:.3e} -> {loss1:.3e}")

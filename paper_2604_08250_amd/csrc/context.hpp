@@ -100,10 +100,10 @@ struct smc_ctx {
   // per colour index: the replicas that have it and their flattened group offsets, for
   // groups of 32 [0] and 16 [1] link cells
   std::vector<int32_t> seg_off;               // [max_colours + 1] into the segment lists
-  std::vector<int32_t> seg_groups[2];         // [max_colours] total groups
+  std::vector<int32_t> seg_groups[3];         // [max_colours] total groups of 32, 16 and kScalarBlock trials
   std::vector<int64_t> col_trials;            // [max_colours] link cells over all replicas
   int32_t *d_seg_rep = nullptr;               // [segments]
-  int32_t *d_seg_start[2] = {nullptr, nullptr};  // [segments + max_colours]
+  int32_t *d_seg_start[3] = {nullptr, nullptr, nullptr};  // [segments + max_colours] per group size
   uint64_t *d_sweep = nullptr;                // device sweep counter
   int variant = 0;                            // kernel variant (autotuner)
   bool use_graph = true;

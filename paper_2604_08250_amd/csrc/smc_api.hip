@@ -207,8 +207,8 @@ int load_params(smc_ctx *c, const float *params_dev) {
 }
 
 template <int FEAT, int H>
-void launch_colour_scalar(smc_ctx *c, SweepArgs a, int64_t n_trials) {
-  hipLaunchKernelGGL((k_sweep_colour_scalar<FEAT, H>), dim3(grid_for(n_trials, kScalarBlock)),
+void launch_colour_scalar(smc_ctx *c, SweepArgs a, int64_t n_blocks) {
+  hipLaunchKernelGGL((k_sweep_colour_scalar<FEAT, H>), dim3((unsigned)std::max<int64_t>(1, n_blocks)),
                      dim3(kScalarBlock), 0, c->stream, a);
 }
 
@@ -467,40 +467,42 @@ int run_sweep(smc_ctx *c, const smc_stats *st, bool last) {
       return rc;
     }
   } else {
-    for (int r = 0; r < R; ++r) {
-      const Replica &rep = c->reps[r];
-      for (int col = 0; col < rep.n_colours; ++col) {
-        SweepArgs a{};
-        a.reps = c->d_reps;
-        a.occ = c->occ;
-        a.ecache = c->ecache;
-        a.w32 = c->d_w32;
-        a.w64 = c->d_w64;
-        a.omega = c->d_omega;
-        a.omega_n = c->omega_n;
-        a.replica = r;
-        a.colour = col;
-        a.fp64_mode = c->cfg.precision == SMC_FP64;
-        a.seed = c->cfg.seed;
-        a.sweep = c->sweep;
-        a.guard = c->guard;
-        a.e_fixed = c->d_efixed;
-        a.counters = c->d_counters;
-        a.n_replicas = R;
-        if (trace) {
-          a.trace_dE = st->trace_dE;
-          a.trace_dE_fast = st->trace_dE_fast;
-          a.trace_flags = st->trace_flags;
-        }
-        const bool onehot = c->cfg.feature == SMC_FEAT_ONEHOT_S123;
-        const int ev = prof_begin(c);
-        if (c->cfg.feature == SMC_FEAT_QSRO_S123) launch_colour_scalar<2, 0>(c, a, rep.n_trials);
-        else if (!onehot && c->hidden == 64) launch_colour_scalar<0, 64>(c, a, rep.n_trials);
-        else if (!onehot) launch_colour_scalar<0, 128>(c, a, rep.n_trials);
-        else if (c->hidden == 64) launch_colour_scalar<1, 64>(c, a, rep.n_trials);
-        else launch_colour_scalar<1, 128>(c, a, rep.n_trials);
-        prof_end(c, ev, 0);
+    // per colour index, one launch over every replica that has that colour
+    for (int col = 0; col < c->max_colours; ++col) {
+      const int so = c->seg_off[col], ns = c->seg_off[col + 1] - so;
+      const int64_t nb = c->seg_groups[2][col];
+      SweepArgs a{};
+      a.reps = c->d_reps;
+      a.occ = c->occ;
+      a.ecache = c->ecache;
+      a.w32 = c->d_w32;
+      a.w64 = c->d_w64;
+      a.omega = c->d_omega;
+      a.omega_n = c->omega_n;
+      a.seg_rep = c->d_seg_rep + so;
+      a.seg_start = c->d_seg_start[2] + so + col;  // ns + 1 entries per colour
+      a.nseg = ns;
+      a.colour = col;
+      a.fp64_mode = c->cfg.precision == SMC_FP64;
+      a.seed = c->cfg.seed;
+      a.sweep = c->sweep;
+      a.guard = c->guard;
+      a.e_fixed = c->d_efixed;
+      a.counters = c->d_counters;
+      a.n_replicas = R;
+      if (trace) {
+        a.trace_dE = st->trace_dE;
+        a.trace_dE_fast = st->trace_dE_fast;
+        a.trace_flags = st->trace_flags;
       }
+      const bool onehot = c->cfg.feature == SMC_FEAT_ONEHOT_S123;
+      const int ev = prof_begin(c);
+      if (c->cfg.feature == SMC_FEAT_QSRO_S123) launch_colour_scalar<2, 0>(c, a, nb);
+      else if (!onehot && c->hidden == 64) launch_colour_scalar<0, 64>(c, a, nb);
+      else if (!onehot) launch_colour_scalar<0, 128>(c, a, nb);
+      else if (c->hidden == 64) launch_colour_scalar<1, 64>(c, a, nb);
+      else launch_colour_scalar<1, 128>(c, a, nb);
+      prof_end(c, ev, 0);
     }
     hipLaunchKernelGGL(k_next_sweep, dim3(1), dim3(64), 0, c->stream, c->d_sweep);
   }
@@ -658,17 +660,15 @@ int smc_init(const smc_config *cfg, uint8_t *occ_dev, const float *params_dev, f
   }
   c->n_total = site0;
   // batched schedule: colour index -> replicas that have it, with flattened group offsets
-  std::vector<int32_t> seg_rep, seg_start[2];
+  std::vector<int32_t> seg_rep, seg_start[3];
   for (const Replica &rp : c->reps) c->max_colours = std::max(c->max_colours, rp.n_colours);
   c->seg_off.assign(c->max_colours + 1, 0);
-  c->seg_groups[0].assign(c->max_colours, 0);
-  c->seg_groups[1].assign(c->max_colours, 0);
+  for (int k = 0; k < 3; ++k) c->seg_groups[k].assign(c->max_colours, 0);
   c->col_trials.assign(c->max_colours, 0);
   for (int col = 0; col < c->max_colours; ++col) {
     c->seg_off[col] = (int32_t)seg_rep.size();
-    int32_t g32 = 0, g16 = 0;
-    seg_start[0].push_back(0);
-    seg_start[1].push_back(0);
+    int32_t g32 = 0, g16 = 0, gs = 0;
+    for (int k = 0; k < 3; ++k) seg_start[k].push_back(0);
     for (int r = 0; r < cfg->n_replicas; ++r) {
       const Replica &rp = c->reps[r];
       if (rp.n_colours <= col) continue;
@@ -676,12 +676,15 @@ int smc_init(const smc_config *cfg, uint8_t *occ_dev, const float *params_dev, f
       const int64_t nt = colour_trials(rp, col);
       g32 += (int32_t)((nt + 31) / 32);
       g16 += (int32_t)((nt + 15) / 16);
+      gs += (int32_t)((nt + kScalarBlock - 1) / kScalarBlock);
       seg_start[0].push_back(g32);
       seg_start[1].push_back(g16);
+      seg_start[2].push_back(gs);
       c->col_trials[col] += nt;
     }
     c->seg_groups[0][col] = g32;
     c->seg_groups[1][col] = g16;
+    c->seg_groups[2][col] = gs;
     max_trials = std::max(max_trials, c->col_trials[col]);
   }
   c->seg_off[c->max_colours] = (int32_t)seg_rep.size();
@@ -711,6 +714,15 @@ int smc_init(const smc_config *cfg, uint8_t *occ_dev, const float *params_dev, f
   if (hipMemcpyAsync(c->d_reps, c->reps.data(), sizeof(Replica) * R, hipMemcpyHostToDevice, c->stream) ||
       hipMemcpyAsync(c->d_omega, om.off.data(), sizeof(om.off), hipMemcpyHostToDevice, c->stream))
     return cleanup(SMC_E_DEVICE);
+  // batched schedule tables (both sweep paths)
+  INIT_HIP(hipMalloc(&c->d_seg_rep, sizeof(int32_t) * std::max<size_t>(1, seg_rep.size())));
+  for (int k = 0; k < 3; ++k) {
+    INIT_HIP(hipMalloc(&c->d_seg_start[k], sizeof(int32_t) * seg_start[k].size()));
+    INIT_HIP(hipMemcpy(c->d_seg_start[k], seg_start[k].data(), sizeof(int32_t) * seg_start[k].size(),
+                       hipMemcpyHostToDevice));
+  }
+  if (!seg_rep.empty())
+    INIT_HIP(hipMemcpy(c->d_seg_rep, seg_rep.data(), sizeof(int32_t) * seg_rep.size(), hipMemcpyHostToDevice));
   if (mfma) {
     // work space of the probe without allocation, resolved once per device
     if (noalloc_scratch(dev, &c->scratch) != SMC_OK) {
@@ -727,14 +739,6 @@ int smc_init(const smc_config *cfg, uint8_t *occ_dev, const float *params_dev, f
     INIT_HIP(hipMalloc(&c->d_queue, sizeof(RecheckEntry) * c->queue_cap));
     INIT_HIP(hipMalloc(&c->d_rowe, sizeof(double) * kRows64 * c->queue_cap));
     INIT_HIP(hipMalloc(&c->d_qcount, sizeof(uint32_t) * (c->max_colours + 4)));
-    INIT_HIP(hipMalloc(&c->d_seg_rep, sizeof(int32_t) * std::max<size_t>(1, seg_rep.size())));
-    for (int k = 0; k < 2; ++k) {
-      INIT_HIP(hipMalloc(&c->d_seg_start[k], sizeof(int32_t) * seg_start[k].size()));
-      INIT_HIP(hipMemcpy(c->d_seg_start[k], seg_start[k].data(), sizeof(int32_t) * seg_start[k].size(),
-                         hipMemcpyHostToDevice));
-    }
-    if (!seg_rep.empty())
-      INIT_HIP(hipMemcpy(c->d_seg_rep, seg_rep.data(), sizeof(int32_t) * seg_rep.size(), hipMemcpyHostToDevice));
     if (hipMemcpy(c->d_reg_off, t.reg_off.data(), sizeof(uint16_t) * t.reg_off.size(), hipMemcpyHostToDevice) ||
         hipMemcpy(c->d_om_off, t.om_off.data(), sizeof(uint16_t) * t.om_off.size(), hipMemcpyHostToDevice) ||
         hipMemcpy(c->d_idx, t.idx.data(), t.idx.size(), hipMemcpyHostToDevice) ||
@@ -1228,7 +1232,7 @@ void smc_destroy(smc_ctx *c) {
   void *bufs[] = {c->d_reps, c->d_w32, c->d_w64, c->d_w64t, c->d_w32t, c->d_omega, c->d_reg_off, c->d_om_off, c->d_idx,
                   c->d_reg_pos, c->d_queue, c->d_rowe, c->d_qcount, c->d_ebase, c->d_efixed, c->d_escratch,
                   c->d_counters, c->d_site64, c->packs[0].dev, c->packs[1].dev, c->packs[2].dev,
-                  c->packs[3].dev, c->d_seg_rep, c->d_seg_start[0], c->d_seg_start[1], c->d_sweep,
+                  c->packs[3].dev, c->d_seg_rep, c->d_seg_start[0], c->d_seg_start[1], c->d_seg_start[2], c->d_sweep,
                   c->d_sigma1, c->d_E0, c->d_E1, c->d_dltrials};
   for (void *p : bufs)
     if (p) (void)hipFree(p);

@@ -16,8 +16,13 @@ struct SweepArgs {
   const double *w64;
   const int8_t *omega;     // [8][kOmegaMax][3]
   int32_t omega_n;
-  int32_t replica;
+  int32_t replica;          // the replica, when seg_start is null
   int32_t colour;
+  // batched: the replicas that have this colour (seg_rep[nseg]) and the first block of each
+  // (seg_start[nseg + 1], in blocks of kScalarBlock trials); block -> (replica, trial block)
+  const int32_t *seg_rep;
+  const int32_t *seg_start;
+  int32_t nseg;
   int32_t fp64_mode;       // decide every trial with FP64 energies, no cache
   uint64_t seed;
   uint64_t sweep;
@@ -88,15 +93,27 @@ __global__ void k_site_energies(const Replica *reps, int32_t r, const uint8_t *o
 
 constexpr int kScalarBlock = 64;
 
-// One colour (mini-step) of one replica; one lane per link cell.
+// One colour (mini-step) of one replica, or of every replica that has it (each block serves
+// one replica); one lane per link cell.
 template <int FEAT, int H>
 __global__ __launch_bounds__(kScalarBlock) void k_sweep_colour_scalar(SweepArgs a) {
   __shared__ float s_e1[kScalarBlock][kOmegaMax];
   __shared__ double s_de[kScalarBlock];
   __shared__ uint32_t s_cnt[3];
-  const Replica R = a.reps[a.replica];
+  int rep = a.replica, blk = (int)blockIdx.x;
+  if (a.seg_start) {
+    int lo = 0, hi = a.nseg;  // last segment whose first block is <= blockIdx.x
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (a.seg_start[mid] <= blk) lo = mid;
+      else hi = mid;
+    }
+    rep = a.seg_rep[lo];
+    blk -= a.seg_start[lo];
+  }
+  const Replica R = a.reps[rep];
   const int tid = threadIdx.x;
-  const int64_t t = (int64_t)blockIdx.x * kScalarBlock + tid;
+  const int64_t t = (int64_t)blk * kScalarBlock + tid;
   if (tid < 3) s_cnt[tid] = 0;
   __syncthreads();
   double applied = 0.0;
@@ -104,7 +121,7 @@ __global__ __launch_bounds__(kScalarBlock) void k_sweep_colour_scalar(SweepArgs 
   if (i >= 0) {
     uint8_t *occ = a.occ + R.site0;
     float *ec = a.ecache + R.site0;
-    const U64x4 r = philox4x64_10((uint64_t)i, a.sweep, (uint64_t)a.replica, 0, a.seed, 0);
+    const U64x4 r = philox4x64_10((uint64_t)i, a.sweep, (uint64_t)rep, 0, a.seed, 0);
     const int d = (int)(r.v[0] >> 61);
     const double u = (double)((r.v[1] >> 11) + 1) * 0x1.0p-53;
     const double theta = isinf(R.temperature) ? (double)INFINITY
@@ -168,12 +185,12 @@ __global__ __launch_bounds__(kScalarBlock) void k_sweep_colour_scalar(SweepArgs 
   if (tid == 0) {
     double s = 0.0;
     for (int k = 0; k < kScalarBlock; ++k) s += s_de[k];
-    atomicAdd(&a.e_fixed[a.replica], (unsigned long long)to_fixed(s));
+    atomicAdd(&a.e_fixed[rep], (unsigned long long)to_fixed(s));
     const int R_ = a.n_replicas;
-    atomicAdd((unsigned long long *)&a.counters[0 * R_ + a.replica], (unsigned long long)__popcll(valid));
-    atomicAdd((unsigned long long *)&a.counters[1 * R_ + a.replica], (unsigned long long)s_cnt[0]);
-    atomicAdd((unsigned long long *)&a.counters[2 * R_ + a.replica], (unsigned long long)s_cnt[1]);
-    atomicAdd((unsigned long long *)&a.counters[3 * R_ + a.replica], (unsigned long long)s_cnt[2]);
+    atomicAdd((unsigned long long *)&a.counters[0 * R_ + rep], (unsigned long long)__popcll(valid));
+    atomicAdd((unsigned long long *)&a.counters[1 * R_ + rep], (unsigned long long)s_cnt[0]);
+    atomicAdd((unsigned long long *)&a.counters[2 * R_ + rep], (unsigned long long)s_cnt[1]);
+    atomicAdd((unsigned long long *)&a.counters[3 * R_ + rep], (unsigned long long)s_cnt[2]);
   }
 }
 

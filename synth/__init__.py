@@ -237,6 +237,11 @@ def snapshots(n: int, cells: int = 16, n_species: int = 4, seed: int = SEED_LATT
     return out
 
 
+def snapshot_temperatures(n: int, lo: float = 300.0, hi: float = 3000.0, seed: int = SEED_LATTICE + 101) -> np.ndarray:
+    """Temperatures (K) of ``n`` snapshot chains, uniform on [lo, hi]."""
+    return np.random.default_rng(seed).uniform(lo, hi, size=n)
+
+
 def workload(name: str, **over) -> Workload:
     name = name.lower()
     if name == "c1":

@@ -158,3 +158,55 @@ def test_energy_grad_is_linear_in_upstream():
     assert np.allclose(gc, 2 * ga - 3 * gb, rtol=1e-12, atol=1e-14)
     # the output bias enters each site once: dS/db2 = N
     assert ga[-1] == pytest.approx(snaps.shape[1])
+
+
+@pytest.mark.parametrize("S", [4, 5])
+def test_ce_pair_qsro_carries_the_ce_pair_part(S):
+    """The qSRO blob built from a CE's pair terms (the driving model of the snapshot chains):
+    the oracle's qSRO energy differs from the oracle's CE pair energy by the composition term
+    sum_i sum_m (z_m / 2) pair_m(s_i, s_i) (closed form), so any species exchange changes both
+    by the same amount."""
+    from paper_2604_08250_amd.fit import BCC_SHELL_SIZES, ce_pair_qsro
+    p = synth.ce_params(n_species=S)
+    pair = p["pair"]
+    ce = oracle.CEModel(S, pair, np.zeros((0, 6)), np.zeros((0, 3)), np.zeros(0))
+    q = oracle.QSRO(ce_pair_qsro(pair))
+    cells = (4, 5, 6)
+    occ = synth.random_occupancy(cells, S, seed=71)
+    rng = np.random.default_rng(72)
+
+    def const(o):
+        return sum(BCC_SHELL_SIZES[m] / 2.0 * pair[m][o, o].sum() for m in range(3))
+
+    # blob entries are FP32: agreement to the rounding of about 40 pair terms of ~0.1 eV
+    tol = 2e-6
+    e_ce, e_q = oracle.ce_total(cells, ce, occ), oracle.total_energy(cells, q, occ)
+    assert e_ce - e_q == pytest.approx(const(occ), abs=tol * occ.size)
+    for _ in range(40):
+        i, n = rng.choice(occ.size, size=2, replace=False)
+        nxt = occ.copy()
+        nxt[i], nxt[n] = occ[n], occ[i]
+        d_ce = oracle.ce_total(cells, ce, nxt) - e_ce
+        d_q = oracle.total_energy(cells, q, nxt) - e_q
+        assert d_q == pytest.approx(d_ce, abs=tol)
+
+
+def test_ce_pair_qsro_additive_pairs_are_flat():
+    """A CE whose pair terms are additive, pair_m(p, q) = (a_m(p) + a_m(q)) / 2, has the energy
+    sum_m (z_m / 2) sum_i a_m(s_i), fixed by the composition: its qSRO blob is zero, and no
+    exchange changes the CE energy (oracle)."""
+    from paper_2604_08250_amd.fit import BCC_SHELL_SIZES, ce_pair_qsro
+    S = 4
+    a = np.random.default_rng(73).normal(0.0, 0.03, size=(3, S))
+    pair = 0.5 * (a[:, :, None] + a[:, None, :])
+    assert not np.any(ce_pair_qsro(pair))
+    ce = oracle.CEModel(S, pair, np.zeros((0, 6)), np.zeros((0, 3)), np.zeros(0))
+    cells = (4, 4, 5)
+    occ = synth.random_occupancy(cells, S, seed=74)
+    e0 = oracle.ce_total(cells, ce, occ)
+    assert e0 == pytest.approx(sum(BCC_SHELL_SIZES[m] / 2.0 * a[m][occ].sum() for m in range(3)), abs=1e-10)
+    rng = np.random.default_rng(75)
+    for _ in range(10):
+        i, n = rng.choice(occ.size, size=2, replace=False)
+        occ[i], occ[n] = occ[n], occ[i]
+        assert oracle.ce_total(cells, ce, occ) == pytest.approx(e0, abs=1e-10)

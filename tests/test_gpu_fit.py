@@ -300,3 +300,43 @@ def test_c5_full_batch_sampled():
     _banner(f"c5 sampled gradient rel err vs fp64 {r:.2e}")
     assert r < 5e-2
     mc.close()
+
+
+def test_mc_snapshots():
+    """Snapshot chains by swap MC on the CE pair part (the fit's training snapshots): the shape
+    and each chain's composition are kept; each snapshot equals the oracle's sweeps of its
+    chain with the qSRO blob that carries the CE pairs; the same seed gives the same snapshots;
+    and from one start, the chain at 300 K ends lower in CE pair energy than the one at 3000 K."""
+    torch = need_gpu()
+    from paper_2604_08250_amd.fit import ce_pair_qsro, sample_snapshots
+    L, B = 6, 4
+    N = 2 * L ** 3
+    cells = (L, L, L)
+    start = synth.snapshots(B, L, seed=50)
+    temps = synth.snapshot_temperatures(B)
+    pair = synth.ce_params()["pair"]
+    _banner("mc snapshots")
+    out = sample_snapshots(start, L, temps, pair, burn_in=3, n_per_chain=2, gap=2, seed=13)
+    assert tuple(out.shape) == (2 * B, N) and out.dtype == torch.uint8
+    got = out.cpu().numpy()
+    for k in range(2):
+        for b in range(B):
+            assert np.array_equal(np.bincount(got[k * B + b], minlength=4), np.bincount(start[b], minlength=4))
+    model = oracle.QSRO(ce_pair_qsro(pair))
+    for b in range(B):
+        ref = start[b].copy()
+        for t in range(3):
+            oracle.sweep(cells, model, ref, temps[b], 13, b, t, nthreads=8)
+        assert np.array_equal(got[b], ref), f"chain {b} after burn-in"
+        for t in range(3, 5):
+            oracle.sweep(cells, model, ref, temps[b], 13, b, t, nthreads=8)
+        assert np.array_equal(got[B + b], ref), f"chain {b} snapshot 1"
+    again = sample_snapshots(start, L, temps, pair, burn_in=3, n_per_chain=2, gap=2, seed=13).cpu().numpy()
+    assert np.array_equal(again, got)
+    # temperature: one start, 300 K against 3000 K
+    two = np.stack([start[0], start[0]])
+    cold_hot = sample_snapshots(two, L, [300.0, 3000.0], pair, burn_in=40, seed=14).cpu().numpy()
+    ce = oracle.CEModel(4, pair, np.zeros((0, 6)), np.zeros((0, 3)), np.zeros(0))
+    e = [oracle.ce_total(cells, ce, s) / N for s in cold_hot]
+    _banner(f"CE pair energy per atom after 40 sweeps: 300 K {e[0]:.5f}, 3000 K {e[1]:.5f}")
+    assert e[0] < e[1]

@@ -55,3 +55,33 @@ def test_qsro_sweeps_bit_exact(precision, cells, S):
     assert es[0] == pytest.approx(oracle.total_energy(cells, model, occ), abs=1e-9)
     assert abs(es[0] - er[0]) < 1e-6
     mc.close()
+
+
+@pytest.mark.parametrize("model_name", ["qsro", "counts"])
+def test_scalar_path_batch_matches_oracle_per_replica(model_name):
+    """Replicas of different shapes and temperatures in one context on the scalar path (one
+    launch per colour over every replica that has it, each block serving one replica): every
+    replica equals the oracle's own sweeps of that replica."""
+    need_gpu()
+    import paper_2604_08250_amd as smc
+    qsro = model_name == "qsro"
+    cells = [(4, 4, 4), (6, 5, 7), (9, 9, 9), (5, 5, 5)]
+    temps = [400.0, 900.0, 1500.0, 2500.0]
+    S = 5 if qsro else 4
+    P = synth.qsro_params(S) if qsro else synth.mlp_params(12, 64)
+    occs = [synth.random_occupancy(c, S, None, seed=300 + r) for r, c in enumerate(cells)]
+    _banner(f"scalar-path batch {model_name}: {len(cells)} replicas")
+    mc = smc.SwapMC(cells, temps, np.concatenate(occs), P, n_species=S, feature=2 if qsro else 0,
+                    hidden=0 if qsro else 64, precision="fp32", seed=11)
+    st = mc.sweep(3, stats=True)
+    sizes = np.array([o.size for o in occs], dtype=np.uint64)
+    assert np.array_equal(st["attempts"], 3 * sizes)
+    got = mc.occ.cpu().numpy()
+    model = oracle.QSRO(P) if qsro else oracle.MLP(0, 64, P)
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    for r in range(len(cells)):
+        ref = occs[r].copy()
+        for t in range(3):
+            oracle.sweep(cells[r], model, ref, temps[r], 11, r, t, nthreads=8)
+        assert np.array_equal(got[offs[r]:offs[r + 1]], ref), f"replica {r}"
+    mc.close()
