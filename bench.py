@@ -288,11 +288,12 @@ def measure_qsro(workload, steps=2, warmup=1):
 # the matrix-core work each precision executes (80 padded inputs, split products), zone size.
 FCC_FLOP_PER_EVAL = 2 * (76 * 96 + 2 * 96 * 96 + 96)
 FCC_EXEC_FLOP_PER_EVAL = {"fp32": 2 * (80 * 96 + 2 * 96 * 96), "bf16": 2 * (80 * 96 + 2 * 96 * 96),
-                          "bf16x3": 2 * (2 * 80 * 96 + 3 * 2 * 96 * 96)}
+                          "bf16x3": 2 * (2 * 80 * 96 + 3 * 2 * 96 * 96),
+                          "fp8": 2 * (128 * 96 + 2 * 128 * 96)}  # K padded to 64-wide steps
 FCC_OMEGA = 28
 
 
-def measure_fcc(precisions=("bf16x3", "fp32", "bf16"), steps=2, warmup=1):
+def measure_fcc(precisions=("bf16x3", "fp32", "bf16", "fp8"), steps=2, warmup=1):
     """The paper's physical system: FCC 200^3 cells (32,000,000 sites), five species in the
     Fe29Co29Ni28Al7Ti7 proportions, the MLPNet shape (96-wide ReLU, random weights), T = 1000 K.
     Timed graph sweeps, then one profiled sweep for the zone-row kernel's average launch."""

@@ -33,8 +33,8 @@ struct FccState {
   uint32_t *d_done = nullptr;        // [cap] blocks finished per queued trial, zero between uses
   uint32_t *d_counts = nullptr;      // active trials, queued trials (one 64-bit word)
   int64_t cap = 0;                   // largest trial count of a colour
-  uint8_t *d_pack[3] = {nullptr, nullptr, nullptr};  // FP32, BF16, split BF16 weight images
-  bool pack_ready[3] = {false, false, false};
+  uint8_t *d_pack[4] = {nullptr, nullptr, nullptr, nullptr};  // FP32, BF16, split BF16, FP8 weight images
+  bool pack_ready[4] = {false, false, false, false};
   float b3 = 0.0f;
 };
 

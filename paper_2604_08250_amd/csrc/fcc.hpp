@@ -125,26 +125,38 @@ struct NetSize<kPBF16X3> {
   static constexpr int kL0 = 2 * NetSize<kPBF16>::kL0;  // hi then lo
   static constexpr int kL1 = 2 * NetSize<kPBF16>::kL1;
 };
-// Image: layer 0, layer 1, layer 2, then c1[96], c2[96], w3[96] (floats) and 16 bytes.
+template <>
+struct NetSize<kPFP8> {
+  static constexpr int kL0 = kMT * 2 * 64 * 32;  // 2 K-steps of 64 (80 features, zero padded)
+  static constexpr int kL1 = kMT * 2 * 64 * 32;  // 2 K-steps of 64 (96 units, zero padded)
+};
+// Image: layer 0, layer 1, layer 2, then c1[96], c2[96], w3[96] (floats) and 16 bytes.  FP8
+// also holds c0[96] (after w3): its layer 0 takes the bias in the accumulator, and the 16
+// bytes hold the E8M0 scale exponents of the products.
 template <int P>
 constexpr int net_bytes() {
-  return NetSize<P>::kL0 + 2 * NetSize<P>::kL1 + 3 * kHid * 4 + 16;
+  return NetSize<P>::kL0 + 2 * NetSize<P>::kL1 + (P == kPFP8 ? 4 : 3) * kHid * 4 + 16;
 }
 
 struct NetSmem {
   const uint8_t *w;
   const float *c1, *c2, *w3;
   float b3;
+  // FP8: accumulator start of layer 0, and the biased scale exponents of the A (weight) and B
+  // (activation) operands of layers 0, 1, 2 (layer 0's B is the exact one-hot, scale 1)
+  const float *c0;
+  int sa0, sa1, sa2, sb1, sb2;
 };
 
 // max(x, 0) as one median-of-three instruction (fmaxf also quiets signalling NaNs first, which
 // costs a second instruction); activations are finite.
 __device__ __forceinline__ float relu(float x) { return __builtin_amdgcn_fmed3f(x, 0.0f, 3.402823466e38f); }
 
-// One hidden layer: acc_out = c + W . relu(acc_in), weights at A (hi, and lo for split BF16).
+// One hidden layer: acc_out = c + W . relu(acc_in), weights at A (hi, and lo for split BF16;
+// FP8: scaled products with the biased exponents sa, sb of the weight and activation operands).
 template <int P>
 __device__ __forceinline__ void net_hidden(const uint8_t *A0, const float *c, const f32x16 (&in)[kMT],
-                                           f32x16 (&out)[kMT]) {
+                                           f32x16 (&out)[kMT], int sa = 127, int sb = 127) {
   const int lane = threadIdx.x & 63;
   const int g = lane >> 5;
 #pragma unroll
@@ -155,7 +167,34 @@ __device__ __forceinline__ void net_hidden(const uint8_t *A0, const float *c, co
 #pragma unroll
       for (int i = 0; i < 4; ++i) out[T][4 * j + i] = b[i];
     }
-  if constexpr (P == kP32) {
+  if constexpr (P == kPFP8) {
+    // K-step s takes M-tiles 2s and 2s + 1 (tile 3 is zero) of this lane group: 16 registers
+    // each, relu'd and converted to E4M3 (the accumulators are already in the units of this
+    // layer's activation scale)
+    const i32x8 *A = (const i32x8 *)A0;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      i32x8 b;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int T = 2 * s + t;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          int w = 0;
+          if (T < kMT) {
+            w = __builtin_amdgcn_cvt_pk_fp8_f32(relu(in[T][4 * q]), relu(in[T][4 * q + 1]), w, false);
+            w = __builtin_amdgcn_cvt_pk_fp8_f32(relu(in[T][4 * q + 2]), relu(in[T][4 * q + 3]), w, true);
+          }
+          b[4 * t + q] = w;
+        }
+      }
+#pragma unroll
+      for (int To = 0; To < kMT; ++To)
+        out[To] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[(To * 2 + s) * 64 + lane], b, out[To], 0, 0, 0,
+                                                                  sa, 0, sb);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  } else if constexpr (P == kP32) {
     f32x16 h[kMT];
 #pragma unroll
     for (int T = 0; T < kMT; ++T)
@@ -215,13 +254,14 @@ __device__ __forceinline__ void net_hidden(const uint8_t *A0, const float *c, co
 }
 
 // Slots a lane gathers for layer 0: all 20 for FP32 (both lane groups build the same B
-// operand), 10 for BF16 (lane group g takes slots 4s + 2g and 4s + 2g + 1 of K-step s).
+// operand), 10 for BF16 (lane group g takes slots 4s + 2g and 4s + 2g + 1 of K-step s), 16 for
+// FP8 (lane group g takes slots 16s + 8g .. + 7 of K-step s; slots 20 and up are padding).
 // Slot 0 is the site, 1 + k neighbour k (k < 18) and slot 19 the constant-one input.
 template <int P>
-constexpr int kGath = P == kP32 ? 20 : 10;
+constexpr int kGath = P == kP32 ? 20 : (P == kPFP8 ? 16 : 10);
 template <int P>
 __device__ __forceinline__ int gath_slot(int q, int g) {
-  return P == kP32 ? q : 4 * (q >> 1) + 2 * g + (q & 1);
+  return P == kP32 ? q : (P == kPFP8 ? 16 * (q >> 3) + 8 * g + (q & 7) : 4 * (q >> 1) + 2 * g + (q & 1));
 }
 
 // Index offsets of slot m (0: the site, 1 + k: neighbour k, k < kUsed; further slots 0) from
@@ -261,15 +301,15 @@ __device__ __forceinline__ void gather_slots(Pos p, const Replica &R, const int3
 #pragma unroll
     for (int q = 0; q < kGath<P>; ++q) {
       const int m = gath_slot<P>(q, g);
-      const uint32_t v = load(base + o[m]);
+      const uint32_t v = load(base + o[m < kSlots ? m : 0]);
       sp[q] = m < kSlots ? v : 0u;
     }
   } else {
 #pragma unroll
     for (int q = 0; q < kGath<P>; ++q) {
       const int m = gath_slot<P>(q, g);
-      const int k = m > 0 ? m - 1 : 0;
-      const uint32_t v = load(m == 0 ? base : at(p, dx(k), dy(k), dz(k), lx, ly, lz));
+      const int k = (m > 0 && m < kSlots) ? m - 1 : 0;
+      const uint32_t v = load((m == 0 || m >= kSlots) ? base : at(p, dx(k), dy(k), dz(k), lx, ly, lz));
       sp[q] = m < kSlots ? v : 0u;
     }
   }
@@ -286,7 +326,34 @@ __device__ __forceinline__ float eval_net(const NetSmem &S, const uint32_t (&sp)
   for (int T = 0; T < kMT; ++T)
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[T][v] = 0.0f;
-  if constexpr (P == kP32) {
+  if constexpr (P == kPFP8) {
+    // the bias starts the accumulators; K-step s covers features 64s..64s+63: lane group g
+    // supplies slots 16s + 8g .. + 7 as E4M3 one-hot dwords (slot 19, the constant-one input,
+    // and the padding slots give zero)
+#pragma unroll
+    for (int T = 0; T < kMT; ++T)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const f32x4 b = *(const f32x4 *)(S.c0 + 32 * T + 8 * j + 4 * g);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[T][4 * j + i] = b[i];
+      }
+    const i32x8 *A = (const i32x8 *)S.w;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      i32x8 b;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int m = 16 * s + 8 * g + j;
+        b[j] = m < kSlots ? (int)onehot_fp8(sp[8 * s + j]) : 0;
+      }
+#pragma unroll
+      for (int T = 0; T < kMT; ++T)
+        acc[T] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[(T * 2 + s) * 64 + lane], b, acc[T], 0, 0, 0, S.sa0,
+                                                                 0, 127);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  } else if constexpr (P == kP32) {
     // K-steps 2m, 2m+1 hold slot m: lane group g supplies channel g, then channel 2 + g
     const f32x4 *A = (const f32x4 *)S.w;
 #pragma unroll
@@ -329,8 +396,8 @@ __device__ __forceinline__ float eval_net(const NetSmem &S, const uint32_t (&sp)
     }
   }
   f32x16 acc1[kMT], acc2[kMT];
-  net_hidden<P>(S.w + NetSize<P>::kL0, S.c1, acc, acc1);
-  net_hidden<P>(S.w + NetSize<P>::kL0 + NetSize<P>::kL1, S.c2, acc1, acc2);
+  net_hidden<P>(S.w + NetSize<P>::kL0, S.c1, acc, acc1, S.sa1, S.sb1);
+  net_hidden<P>(S.w + NetSize<P>::kL0 + NetSize<P>::kL1, S.c2, acc1, acc2, S.sa2, S.sb2);
   float part = 0.0f;
 #pragma unroll
   for (int T = 0; T < kMT; ++T)
@@ -353,6 +420,16 @@ __device__ inline NetSmem net_smem(const uint8_t *s_w, float b3) {
   S.c2 = S.c1 + kHid;
   S.w3 = S.c2 + kHid;
   S.b3 = b3;
+  S.c0 = S.w3 + kHid;
+  S.sa0 = S.sa1 = S.sa2 = S.sb1 = S.sb2 = 127;
+  if constexpr (P == kPFP8) {
+    const uint32_t e0 = *(const uint32_t *)(S.c0 + kHid), e1 = *(const uint32_t *)(S.c0 + kHid + 1);
+    S.sa0 = (int)(e0 & 255u);
+    S.sa1 = (int)((e0 >> 8) & 255u);
+    S.sa2 = (int)((e0 >> 16) & 255u);
+    S.sb1 = (int)(e1 & 255u);
+    S.sb2 = (int)((e1 >> 8) & 255u);
+  }
   return S;
 }
 
@@ -527,11 +604,11 @@ __device__ __forceinline__ uint32_t swapped(const uint8_t *occ, int32_t s, int32
 
 // Post-swap MLPNet energies of the zone sites of every active trial: row = active slot x
 // zone position, 32 rows per wave tile.
-// Threads of the row kernels: the BF16 image (52 KB) lets three 256-thread blocks share a
-// CU; the FP32 and split-BF16 images (103 KB) one 512-thread block.
+// Threads of the row kernels: the BF16 (52 KB) and FP8 (38 KB) images let three 256-thread
+// blocks share a CU; the FP32 and split-BF16 images (103 KB) one 512-thread block.
 template <int P>
 constexpr int net_threads() {
-  return P == kPBF16 ? 256 : kNetThreads;
+  return (P == kPBF16 || P == kPFP8) ? 256 : kNetThreads;
 }
 
 // At least two waves per SIMD: the register budget is then the architectural VGPRs alone, so

@@ -21,15 +21,86 @@ constexpr int kNetParams = kHid * kIn + kHid + 2 * (kHid * kHid + kHid) + kHid +
 // Hidden unit held in output register v by lane group g of M-tile T.
 inline int unit_of(int T, int v, int g) { return 32 * T + 8 * (v / 4) + 4 * g + (v % 4); }
 
-// Image of the MLPNet weights in the operand order of eval_net<P> (P: 0 FP32, 1 BF16, 2 split
-// BF16).  Layer 0 takes 80 features: the 76 inputs, the bias on feature 76, zeros.
-inline std::vector<uint8_t> pack_net(int P, const float *p) {
-  constexpr int L0[3] = {NetSize<kP32>::kL0, NetSize<kPBF16>::kL0, NetSize<kPBF16X3>::kL0};
-  constexpr int L1[3] = {NetSize<kP32>::kL1, NetSize<kPBF16>::kL1, NetSize<kPBF16X3>::kL1};
+// Smallest k with x <= 2^k (0 for x <= 0).
+inline int pow2_at_least(double x) { return x > 0.0 ? (int)ceil(log2(x)) : 0; }
+
+// FP8 image: E4M3 weights with a power-of-two scale per layer (k0, k1, k2: the largest |W|
+// maps to at most 448).  The activation entering layer l + 1 is relu(z_l) / 2^kh_l, with
+// kh_l from a bound of relu(z_l) that follows from the weights: z_0 <= b0 + the sum over
+// slots of the largest positive weight of the slot, z_1 <= b1 + sum_k max(W1, 0) hmax_0.
+// Layers 0 and 1 accumulate in units of the next activation scale (their bias is divided by
+// 2^kh), so relu of the accumulator converts to E4M3 as it is; layer 2 accumulates in eV.
+// The scaled products take A scale 2^(k - kh_next) or 2^k and B scale 2^(kh_in - kh_next).
+inline void pack_net_fp8(const float *p, uint8_t *B) {
+  constexpr int L0 = NetSize<kPFP8>::kL0, L1 = NetSize<kPFP8>::kL1;
   const float *W0 = p, *b0 = W0 + kHid * kIn, *W1 = b0 + kHid, *b1 = W1 + kHid * kHid, *W2 = b1 + kHid,
               *b2 = W2 + kHid * kHid, *W3 = b2 + kHid;
-  std::vector<uint8_t> out((size_t)L0[P] + 2 * L1[P] + 3 * kHid * 4 + 16, 0);
+  double a0 = 0, a1 = 0, a2 = 0;
+  for (int i = 0; i < kHid * kIn; ++i) a0 = std::max(a0, (double)fabsf(W0[i]));
+  for (int i = 0; i < kHid * kHid; ++i) {
+    a1 = std::max(a1, (double)fabsf(W1[i]));
+    a2 = std::max(a2, (double)fabsf(W2[i]));
+  }
+  const int k0 = pow2_at_least(a0 / 448.0), k1 = pow2_at_least(a1 / 448.0), k2 = pow2_at_least(a2 / 448.0);
+  double h0 = 0.0, h1 = 0.0;
+  for (int o = 0; o < kHid; ++o) {
+    double z = b0[o];
+    for (int m = 0; m < kSlots; ++m) {
+      double best = 0.0;
+      for (int c = 0; c < 4; ++c) best = std::max(best, (double)W0[o * kIn + 4 * m + c]);
+      z += best;
+    }
+    h0 = std::max(h0, z);
+  }
+  for (int o = 0; o < kHid; ++o) {
+    double z = b1[o];
+    for (int k = 0; k < kHid; ++k) z += std::max(0.0, (double)W1[o * kHid + k]) * h0;
+    h1 = std::max(h1, z);
+  }
+  const int kh0 = pow2_at_least(h0 / 448.0), kh1 = pow2_at_least(h1 / 448.0);
+  auto e8 = [](int v) { return (uint32_t)std::min(254, std::max(0, v)); };
+  const uint32_t sa0 = e8(127 + k0 - kh0), sa1 = e8(127 + k1), sa2 = e8(127 + k2), sb1 = e8(127 + kh0 - kh1),
+                 sb2 = e8(127 + kh1);
+  const float i0 = ldexpf(1.0f, -k0), i1 = ldexpf(1.0f, -k1), i2 = ldexpf(1.0f, -k2);
+  uint8_t *A0 = B, *A1 = B + L0, *A2 = B + L0 + L1;
+  for (int T = 0; T < kMT; ++T)
+    for (int s = 0; s < 2; ++s)
+      for (int l = 0; l < 64; ++l)
+        for (int e = 0; e < 32; ++e) {
+          const int o = 32 * T + (l & 31), f = 64 * s + 32 * (l >> 5) + e;
+          const size_t idx = ((size_t)(T * 2 + s) * 64 + l) * 32 + e;
+          A0[idx] = f < kIn ? f32_to_e4m3_rne(W0[o * kIn + f] * i0) : 0;
+          const int Ti = 2 * s + e / 16;
+          const int k = Ti < kMT ? unit_of(Ti, e % 16, l >> 5) : -1;
+          A1[idx] = k >= 0 ? f32_to_e4m3_rne(W1[o * kHid + k] * i1) : 0;
+          A2[idx] = k >= 0 ? f32_to_e4m3_rne(W2[o * kHid + k] * i2) : 0;
+        }
+  float *vec = (float *)(B + L0 + 2 * L1);
+  const float s0 = ldexpf(1.0f, -kh0), s1 = ldexpf(1.0f, -kh1);
+  for (int h = 0; h < kHid; ++h) {
+    vec[h] = b1[h] * s1;
+    vec[kHid + h] = b2[h];
+    vec[2 * kHid + h] = W3[h];
+    vec[3 * kHid + h] = b0[h] * s0;
+  }
+  uint32_t *ex = (uint32_t *)(vec + 4 * kHid);
+  ex[0] = sa0 | (sa1 << 8) | (sa2 << 16);
+  ex[1] = sb1 | (sb2 << 8);
+}
+
+// Image of the MLPNet weights in the operand order of eval_net<P> (P: 0 FP32, 1 BF16, 2 split
+// BF16, 3 FP8).  Layer 0 takes 80 features: the 76 inputs, the bias on feature 76, zeros.
+inline std::vector<uint8_t> pack_net(int P, const float *p) {
+  constexpr int L0[4] = {NetSize<kP32>::kL0, NetSize<kPBF16>::kL0, NetSize<kPBF16X3>::kL0, NetSize<kPFP8>::kL0};
+  constexpr int L1[4] = {NetSize<kP32>::kL1, NetSize<kPBF16>::kL1, NetSize<kPBF16X3>::kL1, NetSize<kPFP8>::kL1};
+  const float *W0 = p, *b0 = W0 + kHid * kIn, *W1 = b0 + kHid, *b1 = W1 + kHid * kHid, *W2 = b1 + kHid,
+              *b2 = W2 + kHid * kHid, *W3 = b2 + kHid;
+  std::vector<uint8_t> out((size_t)L0[P] + 2 * L1[P] + (P == 3 ? 4 : 3) * kHid * 4 + 16, 0);
   uint8_t *B = out.data();
+  if (P == 3) {
+    pack_net_fp8(p, B);
+    return out;
+  }
   for (int layer = 0; layer < 3; ++layer) {
     uint8_t *dst = layer == 0 ? B : B + L0[P] + (layer - 1) * L1[P];
     const float *W = layer == 1 ? W1 : W2;
@@ -169,7 +240,7 @@ inline int load_params(smc_ctx *c, const float *params_dev) {
 }
 
 // Blocks of the matrix-core kernels: LDS holds one weight image per block.
-inline int net_blocks(const smc_ctx *c, int P) { return (P == SMC_BF16 ? 3 : 1) * c->n_cu; }
+inline int net_blocks(const smc_ctx *c, int P) { return (P == SMC_FP8_E4M3 ? 4 : (P == SMC_BF16 ? 3 : 1)) * c->n_cu; }
 
 template <int P>
 void launch_site_energies_net(smc_ctx *c, float *out) {
@@ -191,13 +262,14 @@ inline int site_energies_fast(smc_ctx *c, int P, float *out) {
     HIPC(c, hipGetLastError());
     return SMC_OK;
   }
-  if (P != SMC_FP32 && P != SMC_BF16 && P != SMC_BF16X3)
-    return fail(c, SMC_E_UNSUPPORTED, "the FCC MLPNet runs in FP32, BF16, split BF16 or FP64");
+  if (P != SMC_FP32 && P != SMC_BF16 && P != SMC_BF16X3 && P != SMC_FP8_E4M3)
+    return fail(c, SMC_E_UNSUPPORTED, "the FCC MLPNet runs in FP32, BF16, split BF16, FP8 or FP64");
   int rc = ensure_pack(c, P);
   if (rc) return rc;
   if (P == SMC_FP32) launch_site_energies_net<kP32>(c, out);
   else if (P == SMC_BF16) launch_site_energies_net<kPBF16>(c, out);
-  else launch_site_energies_net<kPBF16X3>(c, out);
+  else if (P == SMC_BF16X3) launch_site_energies_net<kPBF16X3>(c, out);
+  else launch_site_energies_net<kPFP8>(c, out);
   HIPC(c, hipGetLastError());
   return SMC_OK;
 }
@@ -303,8 +375,10 @@ inline int enqueue_sweep(smc_ctx *c, const smc_stats *st, bool trace) {
         launch_rows_net<kP32>(c, a, nt);
       } else if (P == SMC_BF16) {
         launch_rows_net<kPBF16>(c, a, nt);
-      } else {
+      } else if (P == SMC_BF16X3) {
         launch_rows_net<kPBF16X3>(c, a, nt);
+      } else {
+        launch_rows_net<kPFP8>(c, a, nt);
       }
       prof_end(c, ev, 0);
       const dim3 dg(grid_for(nt * kDecideLanes, kPhaseThreads));
@@ -406,7 +480,7 @@ inline int delta_e64(smc_ctx *c, int32_t replica, uint64_t sweep, const int64_t 
 inline void release(smc_ctx *c) {
   FccState &f = c->fcc;
   void *bufs[] = {f.d_om,     f.d_trials, f.d_active,  f.d_e1,      f.d_queue,  f.d_counts,
-                  f.d_rowe,   f.d_done,   f.d_pack[0], f.d_pack[1], f.d_pack[2]};
+                  f.d_rowe,   f.d_done,   f.d_pack[0], f.d_pack[1], f.d_pack[2], f.d_pack[3]};
   for (void *p : bufs)
     if (p) (void)hipFree(p);
 }
@@ -418,7 +492,6 @@ inline int create(const smc_config *cfg, uint8_t *occ_dev, const float *params_d
   if (cfg->feature == SMC_FEAT_MLPNET_S12) {
     model = 0;
     if (cfg->hidden != kHid) return SMC_E_UNSUPPORTED;
-    if (cfg->precision == SMC_FP8_E4M3) return SMC_E_UNSUPPORTED;
   } else if (cfg->feature == SMC_FEAT_QSRO_S123) {
     model = 1;
     if (cfg->precision != SMC_FP32 && cfg->precision != SMC_FP64) return SMC_E_UNSUPPORTED;

@@ -49,7 +49,8 @@ static_assert(kRcRowsB * kRcBlocksPerTrial == kRows64, "row split");
 //   z1[u] = b1[u] + sum over k = 0..127 of W1[u][k] silu(z0[k]), one fma per k in order;
 //   E = b2 + sum over chunks c = 0..7 of (sum over i = 0..15 of W2[16c+i] silu(z1[16c+i])).
 // Persistent blocks, one per CU: each stages W0 and W1 in LDS once (their FP32 values, which
-// the FP64 arithmetic takes exactly) and then walks work items with no weight traffic, two at
+// the FP64 arithmetic takes exactly) with b0, b1 and W2, and then walks work items with no
+// weight traffic, two at
 // a time (one per half block), so that the gathers and LDS round trips of two items overlap.
 // In a half: layer 0, thread t owns unit t % 128 of rows 8(t / 128) .. +7; layer 1, thread t
 // owns units 4(t % 32) .. +3 of rows 2(t / 32) and +1.
@@ -61,16 +62,35 @@ __global__ __launch_bounds__(kRcThreads) void k_recheck_rows(RecheckArgs a) {
   __shared__ double s_part[2][kRcRowsB * 8];
   __shared__ uint8_t s_reg[2][kReg];
   __shared__ uint8_t s_sp[2][kRcRowsB * 27];
+  __shared__ double s_b0[kHid], s_b1[kHid], s_w2[kHid];
   const uint32_t n = *a.q_count;
   const uint32_t items = n * kRcBlocksPerTrial;
   if (2 * blockIdx.x >= items) return;  // no work item for this block
   const int tid = threadIdx.x, hf = tid / kRcHalf, lt = tid % kRcHalf;
-  const double *b0 = a.w64 + kHid * 108, *b1 = b0 + kHid + kHid * kHid, *W2 = b1 + kHid, *b2 = W2 + kHid;
+  const double *b0 = a.w64 + kHid * 108, *b1 = b0 + kHid + kHid * kHid, *W2 = b1 + kHid;
+  const double b2 = W2[kHid];
   {
+    // every load of the staging is issued before the first LDS store (one memory round trip)
+    constexpr int n0 = 108 * kHid / 4, nw = n0 + kHid * kHid / 4, per = (nw + kRcThreads - 1) / kRcThreads;
     const float4 *w0 = (const float4 *)a.w32t;
     const float4 *w1 = (const float4 *)(a.w32t + kHid * 108 + kHid);
-    for (int q = tid; q < 108 * kHid / 4; q += kRcThreads) ((float4 *)s_w0)[q] = w0[q];
-    for (int q = tid; q < kHid * kHid / 4; q += kRcThreads) ((float4 *)s_w1)[q] = w1[q];
+    float4 t[per];
+#pragma unroll
+    for (int i = 0; i < per; ++i) {
+      const int q = tid + i * kRcThreads;
+      t[i] = q < n0 ? w0[q] : (q < nw ? w1[q - n0] : make_float4(0.0f, 0.0f, 0.0f, 0.0f));
+    }
+    const int ub = tid % kHid;
+    const double bb = (tid < kHid ? b0 : (tid < 2 * kHid ? b1 : W2))[ub];  // threads past 3 kHid load W2 unused
+#pragma unroll
+    for (int i = 0; i < per; ++i) {
+      const int q = tid + i * kRcThreads;
+      if (q < n0) ((float4 *)s_w0)[q] = t[i];
+      else if (q < nw) ((float4 *)s_w1)[q - n0] = t[i];
+    }
+    if (tid < kHid) s_b0[tid] = bb;
+    else if (tid < 2 * kHid) s_b1[tid - kHid] = bb;
+    else if (tid < 3 * kHid) s_w2[tid - 2 * kHid] = bb;
   }
   double *h = s_h[hf];
   for (uint32_t base = 2 * blockIdx.x; base < items; base += 2 * gridDim.x) {
@@ -80,10 +100,22 @@ __global__ __launch_bounds__(kRcThreads) void k_recheck_rows(RecheckArgs a) {
     const int r0 = (int)(w - q * kRcBlocksPerTrial) * kRcRowsB;
     const bool live = w < items && a.queue[q].site >= 0;
     const RecheckEntry &e = a.queue[live ? q : 0];
-    int d = 0, has_reg = 0;
+    int d = 0, has_reg = 0, pos_i = 0, pos_n = 0;
+    int pslot[2] = {0, 0};  // zone-region positions of this thread's two slot-species entries
     if (live) {
       d = e.dir;
       has_reg = e.has_reg;
+      // the table loads of the slot-species build go out with the region loads
+      pos_i = a.reg_pos[2 * d];
+      pos_n = a.reg_pos[2 * d + 1];
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int v = lt + k * kRcHalf;
+        if (v < kRcRowsB * 27) {
+          const int lr = v / 27, m = v - lr * 27, gr = r0 + lr;
+          pslot[k] = a.idx[(d * kOm + (gr < kOm ? gr : gr - kOm)) * kIdxRow + m];
+        }
+      }
       if (has_reg) {
         // the colour kernel queued the region with the trial (swap applied)
         if (lt < kReg / 4) ((uint32_t *)s_reg[hf])[lt] = ((const uint32_t *)e.reg)[lt];
@@ -99,14 +131,15 @@ __global__ __launch_bounds__(kRcThreads) void k_recheck_rows(RecheckArgs a) {
     // slot species of this item's rows: the rows after the swap see i and n exchanged relative
     // to the rows before (s_reg holds the lattice after the swap when has_reg, else before)
     if (live) {
-      const int pos_i = a.reg_pos[2 * d], pos_n = a.reg_pos[2 * d + 1];
       const uint8_t at_i = s_reg[hf][pos_i], at_n = s_reg[hf][pos_n];
-      for (int v = lt; v < kRcRowsB * 27; v += kRcHalf) {
-        const int lr = v / 27, m = v - lr * 27, gr = r0 + lr;
-        const bool post = gr < kOm;
-        const int p = a.idx[(d * kOm + (post ? gr : gr - kOm)) * kIdxRow + m];
-        const bool exch = post != (has_reg != 0);
-        s_sp[hf][v] = exch ? (p == pos_i ? at_n : (p == pos_n ? at_i : s_reg[hf][p])) : s_reg[hf][p];
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int v = lt + k * kRcHalf;
+        if (v < kRcRowsB * 27) {
+          const int gr = r0 + v / 27, p = pslot[k];
+          const bool exch = (gr < kOm) != (has_reg != 0);
+          s_sp[hf][v] = exch ? (p == pos_i ? at_n : (p == pos_n ? at_i : s_reg[hf][p])) : s_reg[hf][p];
+        }
       }
     }
     __syncthreads();
@@ -115,7 +148,7 @@ __global__ __launch_bounds__(kRcThreads) void k_recheck_rows(RecheckArgs a) {
       const int o = lt % kHid, rb = (lt / kHid) * 8;
       double acc[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) acc[j] = b0[o];
+      for (int j = 0; j < 8; ++j) acc[j] = s_b0[o];
 #pragma unroll 3
       for (int m = 0; m < 27; ++m) {
 #pragma unroll
@@ -134,7 +167,7 @@ __global__ __launch_bounds__(kRcThreads) void k_recheck_rows(RecheckArgs a) {
       double acc[2][4];
       if (live) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) acc[0][i] = acc[1][i] = b1[u0 + i];
+        for (int i = 0; i < 4; ++i) acc[0][i] = acc[1][i] = s_b1[u0 + i];
 #pragma unroll 4
         for (int k = 0; k < kHid; ++k) {
           const float4 wf = *(const float4 *)(s_w1 + k * kHid + u0);
@@ -155,7 +188,7 @@ __global__ __launch_bounds__(kRcThreads) void k_recheck_rows(RecheckArgs a) {
 #pragma unroll
         for (int r = 0; r < 2; ++r)
 #pragma unroll
-          for (int i = 0; i < 4; ++i) h[(ra + r) * kHStride + u0 + i] = W2[u0 + i] * silu<double>(acc[r][i]);
+          for (int i = 0; i < 4; ++i) h[(ra + r) * kHStride + u0 + i] = s_w2[u0 + i] * silu<double>(acc[r][i]);
       }
     }
     __syncthreads();
@@ -169,7 +202,7 @@ __global__ __launch_bounds__(kRcThreads) void k_recheck_rows(RecheckArgs a) {
     }
     __syncthreads();
     if (live && lt < kRcRowsB) {
-      double E = b2[0];
+      double E = b2;
 #pragma unroll
       for (int c = 0; c < 8; ++c) E += s_part[hf][lt * 8 + c];
       a.row_e[(size_t)q * kRows64 + r0 + lt] = E;

@@ -161,11 +161,38 @@ def snapshot_rows(cells, snaps):
     return np.asarray(rows)
 
 
+def _mlpnet_fp8(W0, b0, W1, b1, W2, b2, W3, b3, X, n_slots=19):
+    """FP8 MLPNet as the FCC evaluator defines it: E4M3 weights W / 2^k per layer (the largest
+    |W| at most 448); the activation entering layer l + 1 is E4M3(relu(z_l) / 2^kh_l), with
+    kh_l from the bound hmax_0 = max_u (b0 + sum over slots of the largest positive weight),
+    hmax_1 = max_u (b1 + sum_k max(W1, 0) hmax_0); every bias starts its FP32 accumulator."""
+    p2 = _pow2_at_least
+    W0d, W1d, W2d = (W.astype(np.float64) for W in (W0, W1, W2))
+    k0, k1, k2 = (p2(float(np.abs(W).max()) / 448.0) for W in (W0, W1, W2))
+    H = W0.shape[0]
+    z = b0.astype(np.float64) + np.maximum(0.0, W0d.reshape(H, n_slots, 4).max(axis=2)).sum(axis=1)
+    h0 = max(0.0, float(z.max()))
+    z = b1.astype(np.float64) + np.maximum(0.0, W1d).sum(axis=1) * h0
+    h1 = max(0.0, float(z.max()))
+    kh0, kh1 = p2(h0 / 448.0), p2(h1 / 448.0)
+    A0 = e4m3(W0 * np.float32(2.0 ** -k0)).astype(np.float64) * 2.0 ** k0
+    A1 = e4m3(W1 * np.float32(2.0 ** -k1)).astype(np.float64) * 2.0 ** k1
+    A2 = e4m3(W2 * np.float32(2.0 ** -k2)).astype(np.float64) * 2.0 ** k2
+    # layers 0 and 1 accumulate in units of the next activation scale
+    z0 = ((b0 * np.float32(2.0 ** -kh0)).astype(np.float64) + (X @ A0.T) * 2.0 ** -kh0).astype(np.float32)
+    a1 = e4m3(np.maximum(z0, 0)).astype(np.float64)
+    z1 = ((b1 * np.float32(2.0 ** -kh1)).astype(np.float64) + (a1 @ A1.T) * 2.0 ** (kh0 - kh1)).astype(np.float32)
+    a2 = e4m3(np.maximum(z1, 0)).astype(np.float64)
+    z2 = (b2.astype(np.float64) + (a2 @ A2.T) * 2.0 ** kh1).astype(np.float32)
+    return np.maximum(z2, 0).astype(np.float64) @ W3.astype(np.float64) + float(b3)
+
+
 def mlpnet_emulate(params, X, prec, H=96, n_in=76):
     """MLPNet (Eqs. (4)-(6)) as the FCC matrix-core evaluator computes it: layer 0 takes the
     bias as a weight column on a constant-one input, later biases start the FP32 accumulators,
     ReLU, W3 and b3 in FP32; q() quantises weights and the activations entering layers 1 and 2
-    (bf16x3: hi*hi + hi*lo + lo*hi).  X: [rows][76] one-hot features (exact in every format)."""
+    (bf16x3: hi*hi + hi*lo + lo*hi; fp8: see _mlpnet_fp8).  X: [rows][76] one-hot features
+    (exact in every format)."""
     p = np.asarray(params, dtype=np.float32)
     o = 0
     W0 = p[o:o + H * n_in].reshape(H, n_in); o += H * n_in
@@ -177,6 +204,8 @@ def mlpnet_emulate(params, X, prec, H=96, n_in=76):
     W3 = p[o:o + H]; o += H
     b3 = p[o]
     X = np.asarray(X, dtype=np.float64)
+    if prec == "fp8":
+        return _mlpnet_fp8(W0, b0, W1, b1, W2, b2, W3, b3, X)
 
     def split(a):
         hi = bf16(a)

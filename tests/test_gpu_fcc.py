@@ -107,7 +107,8 @@ def _compare_sweep(cells, model, occ_or, T, seed, replica, sweep, tr, gpu_occ, d
     return st, tolerated
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", None), ("fp32", 1e-5), ("bf16x3", 2e-4), ("bf16", None)])
+@pytest.mark.parametrize("prec,tol", [("fp64", None), ("fp32", 1e-5), ("bf16x3", 2e-4), ("bf16", None),
+                                      ("fp8", None)])
 def test_fcc_site_energies(prec, tol):
     need_gpu()
     _banner(f"fcc site energies {prec}")
@@ -124,6 +125,16 @@ def test_fcc_site_energies(prec, tol):
         assert np.linalg.norm(e - emu) / np.linalg.norm(emu) < 1e-4
         assert np.abs(e - emu).max() < 1e-2
         assert np.abs(e - want).max() < 0.05
+    elif prec == "fp8":
+        X = np.stack([fcc.features(cells, occ, j) for j in range(occ.size)])
+        emu = mlpnet_emulate(synth.mlpnet_params(H), X, "fp8")
+        d_emu, d_emu64 = np.abs(e - emu), np.abs(emu - want)
+        _banner(f"fcc fp8: |gpu-emu| rms {np.sqrt((d_emu ** 2).mean()):.3e}, |emu-fp64| rms "
+                f"{np.sqrt((d_emu64 ** 2).mean()):.3e}, |gpu-fp64| max {np.abs(e - want).max():.3e}")
+        # an E4M3 activation can round the other way when FP32 sums differ in the last bit: the
+        # disagreement must stay far below the precision's own error
+        assert np.sqrt((d_emu ** 2).mean()) < 0.1 * np.sqrt((d_emu64 ** 2).mean())
+        assert np.median(d_emu) < 0.05 * np.median(d_emu64) + 1e-6
     else:
         assert np.abs(e - want).max() < tol
         X = np.stack([fcc.features(cells, occ, j) for j in range(0, occ.size, 7)])
@@ -169,13 +180,14 @@ def test_fcc_mlpnet_sweeps_match_oracle(prec, de_tol):
     mc.close()
 
 
-def test_fcc_bf16_follows_its_own_energies():
-    """BF16 decisions follow its own dE outside the guard band; the running total keeps the
-    accounting identity with the cache offset."""
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_fcc_low_precision_follows_its_own_energies(prec):
+    """BF16 and FP8 decisions follow their own dE outside the guard band; the running total
+    keeps the accounting identity with the cache offset."""
     need_gpu()
-    _banner("fcc bf16 sweeps")
+    _banner(f"fcc {prec} sweeps")
     cells = (8, 8, 8)
-    mc, model, occ = _make([cells], [1200.0], precision="bf16")
+    mc, model, occ = _make([cells], [1200.0], precision=prec)
     d0 = _cache_offset(mc)
     for t in range(3):
         tr = trace_to_numpy(mc.sweep(1, stats=True, trace=True))
@@ -190,7 +202,7 @@ def test_fcc_bf16_follows_its_own_energies():
     es, er = mc.energy()
     assert es[0] == pytest.approx(fcc.total_energy(cells, model, mc.occ.cpu().numpy()), abs=1e-8)
     c = mc.counters()
-    _check_running_total(mc, d0, c[2], c[3], 5e-2)
+    _check_running_total(mc, d0, c[2], c[3], {"bf16": 5e-2, "fp8": 0.5}[prec])
     mc.close()
 
 
@@ -226,7 +238,7 @@ def test_fcc_qsro_sweeps_match_oracle(prec):
     mc.close()
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16", "fp8"])
 def test_fcc_graph_replays_equal_per_launch(prec):
     need_gpu()
     import torch
@@ -271,9 +283,9 @@ def test_fcc_unsupported_configurations():
     import paper_2604_08250_amd as smc
     _banner("fcc unsupported")
     occ = synth.random_occupancy((4, 4, 4), 4, None, seed=1, basis=4)
-    with pytest.raises(smc.SMCError):  # FP8 is not built for the MLPNet
-        smc.SwapMC([(4, 4, 4)], [800.0], occ, synth.mlpnet_params(H), n_species=4, feature=smc.SMC_FEAT_MLPNET_S12,
-                   hidden=H, precision="fp8", lattice="fcc")
+    with pytest.raises(smc.SMCError):  # qSRO on FCC runs in FP32 or FP64
+        smc.SwapMC([(4, 4, 4)], [800.0], occ, synth.qsro_params(4), n_species=4, feature=smc.SMC_FEAT_QSRO_S123,
+                   hidden=0, precision="fp8", lattice="fcc")
     with pytest.raises(smc.SMCError):  # the MLPNet is 96 wide
         smc.SwapMC([(4, 4, 4)], [800.0], occ, synth.mlpnet_params(64), n_species=4, feature=smc.SMC_FEAT_MLPNET_S12,
                    hidden=64, lattice="fcc")
