@@ -100,7 +100,15 @@ __global__ __launch_bounds__(kScalarBlock) void k_sweep_colour_scalar(SweepArgs 
   __shared__ float s_e1[kScalarBlock][kOmegaMax];
   __shared__ double s_de[kScalarBlock];
   __shared__ uint32_t s_cnt[3];
-  int rep = a.replica, blk = (int)blockIdx.x;
+  // XCD-aware order: blocks b and b + 8k run on one XCD (round-robin dispatch), so logical
+  // block (b % 8) per + b / 8 gives each XCD one contiguous run of link-cell rows, whose read
+  // regions overlap and stay in that XCD's L2 (the tail past a multiple of 8 keeps its index)
+  int blk = (int)blockIdx.x;
+  {
+    const int nb = (int)gridDim.x, full = nb - nb % 8;
+    if (blk < full) blk = (blk % 8) * (full / 8) + blk / 8;
+  }
+  int rep = a.replica;
   if (a.seg_start) {
     int lo = 0, hi = a.nseg;  // last segment whose first block is <= blockIdx.x
     while (hi - lo > 1) {
