@@ -755,44 +755,48 @@ __global__ __launch_bounds__(kPhaseThreads) void k_decide(Args a) {
 // W2t[96][96], b2, W3[96], b3.
 constexpr int kRows64 = 64;       // rows per pass of the FP64 site-energy kernel
 constexpr int kR64Threads = 384;  // 96 units x 4 parts
+constexpr int kNetParamsDev = kHid * kIn + kHid + 2 * (kHid * kHid + kHid) + kHid + 1;  // 26,113
 constexpr int kR64Parts = kR64Threads / kHid;
 constexpr int kHS = kHid + 1;     // padded activation row stride
 
 // FP64 energies of nrows (<= 4 RPT) rows whose slot species are in s_sp[row][19]; the result
 // of row r goes to s_out[r].  Thread (unit o, part p) owns rows p + 4j, j < RPT.  Every thread
 // of the block takes part (block-wide barriers).
-template <int RPT>
-__device__ void net64_rows(const double *W, const uint8_t *s_sp, int nrows, double *s_h, double *s_out) {
+// WT: the FP64 blob itself (global memory) or its values staged in LDS as the FP32 numbers
+// they are (read back to FP64 exactly); the arithmetic is the same either way.
+template <int RPT, typename WT>
+__device__ void net64_rows(const WT *W, const uint8_t *s_sp, int nrows, double *s_h, double *s_out) {
   constexpr int kR64PerThread = RPT;
   const int tid = threadIdx.x;
   const int o = tid % kHid, part = tid / kHid;
-  const double *W0 = W, *b0 = W0 + kIn * kHid, *W1 = b0 + kHid, *b1 = W1 + kHid * kHid, *W2 = b1 + kHid,
-               *b2 = W2 + kHid * kHid, *W3 = b2 + kHid, *b3 = W3 + kHid;
+  const WT *W0 = W, *b0 = W0 + kIn * kHid, *W1 = b0 + kHid, *b1 = W1 + kHid * kHid, *W2 = b1 + kHid,
+           *b2 = W2 + kHid * kHid, *W3 = b2 + kHid, *b3 = W3 + kHid;
   double acc[kR64PerThread];
 #pragma unroll
-  for (int j = 0; j < kR64PerThread; ++j) acc[j] = b0[o];
+  for (int j = 0; j < kR64PerThread; ++j) acc[j] = (double)b0[o];
 #pragma unroll 4
   for (int m = 0; m < kSlots; ++m) {
-    const double w0 = W0[(4 * m) * kHid + o], w1 = W0[(4 * m + 1) * kHid + o], w2 = W0[(4 * m + 2) * kHid + o],
-                 w3 = W0[(4 * m + 3) * kHid + o];
+    const double w0 = (double)W0[(4 * m) * kHid + o], w1 = (double)W0[(4 * m + 1) * kHid + o],
+                 w2 = (double)W0[(4 * m + 2) * kHid + o], w3 = (double)W0[(4 * m + 3) * kHid + o];
 #pragma unroll
     for (int j = 0; j < kR64PerThread; ++j) {
+      // no branch: species 4 and rows past nrows add +0.0, which leaves the sum as it is
       const int r = part + kR64Parts * j;
-      const int sp = r < nrows ? s_sp[r * kSlots + m] : 4;
+      const int sp = s_sp[(r < nrows ? r : 0) * kSlots + m];
       const double wv = sp == 0 ? w0 : (sp == 1 ? w1 : (sp == 2 ? w2 : w3));
-      if (sp < 4) acc[j] += wv;
+      acc[j] += (r < nrows && sp < 4) ? wv : 0.0;
     }
   }
 #pragma unroll
   for (int j = 0; j < kR64PerThread; ++j) s_h[(part + kR64Parts * j) * kHS + o] = acc[j] > 0.0 ? acc[j] : 0.0;
   __syncthreads();
   for (int layer = 0; layer < 2; ++layer) {
-    const double *Wl = layer == 0 ? W1 : W2, *bl = layer == 0 ? b1 : b2;
+    const WT *Wl = layer == 0 ? W1 : W2, *bl = layer == 0 ? b1 : b2;
 #pragma unroll
-    for (int j = 0; j < kR64PerThread; ++j) acc[j] = bl[o];
+    for (int j = 0; j < kR64PerThread; ++j) acc[j] = (double)bl[o];
 #pragma unroll 8
     for (int k = 0; k < kHid; ++k) {
-      const double wk = Wl[k * kHid + o];
+      const double wk = (double)Wl[k * kHid + o];
 #pragma unroll
       for (int j = 0; j < kR64PerThread; ++j) acc[j] = fma(wk, s_h[(part + kR64Parts * j) * kHS + k], acc[j]);
     }
@@ -803,8 +807,8 @@ __device__ void net64_rows(const double *W, const uint8_t *s_sp, int nrows, doub
   }
   // E_r = b3 + sum_o W3[o] h3[r][o], units in order
   if (tid < nrows) {
-    double e = b3[0];
-    for (int k = 0; k < kHid; ++k) e = fma(W3[k], s_h[tid * kHS + k], e);
+    double e = (double)b3[0];
+    for (int k = 0; k < kHid; ++k) e = fma((double)W3[k], s_h[tid * kHS + k], e);
     s_out[tid] = e;
   }
   __syncthreads();
@@ -886,6 +890,9 @@ static_assert(kRcRows * kRcSplit == 2 * kOmMlp, "row split");
 
 __global__ __launch_bounds__(kR64Threads) void k_recheck_net(Args a, const double *W, double *row_e,
                                                             uint32_t *done) {
+  // the blob's values in LDS (FP32 numbers, exact), loaded in one batch: the queue is short,
+  // so each block's latency is the kernel's time and weight reads must not go to L2 per layer
+  __shared__ float s_w[kNetParamsDev];
   __shared__ double s_h[kRcRows * kHS];
   __shared__ double s_out[kRcRows];
   __shared__ double s_re[2 * kOmMlp];
@@ -895,6 +902,25 @@ __global__ __launch_bounds__(kR64Threads) void k_recheck_net(Args a, const doubl
   uint8_t *occ = a.occ + R.site0;
   const uint32_t nq = *a.q_count;
   const int tid = threadIdx.x;
+  if (blockIdx.x >= nq * kRcSplit) return;  // no work item for this block
+  {
+    constexpr int per = (kNetParamsDev + kR64Threads - 1) / kR64Threads;
+#pragma unroll 17
+    for (int q0 = 0; q0 < per; q0 += 17) {
+      double t[17];
+#pragma unroll
+      for (int k = 0; k < 17; ++k) {
+        const int q = tid + (q0 + k) * kR64Threads;
+        t[k] = (q0 + k < per && q < kNetParamsDev) ? W[q] : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < 17; ++k) {
+        const int q = tid + (q0 + k) * kR64Threads;
+        if (q0 + k < per && q < kNetParamsDev) s_w[q] = (float)t[k];
+      }
+    }
+  }
+  __syncthreads();
   for (uint32_t w = blockIdx.x; w < nq * kRcSplit; w += gridDim.x) {
     const uint32_t q = w / kRcSplit;
     const int r0 = (int)(w - q * kRcSplit) * kRcRows;
@@ -914,7 +940,7 @@ __global__ __launch_bounds__(kR64Threads) void k_recheck_net(Args a, const doubl
       s_sp[v] = (uint8_t)(post ? swapped(occ, s, (int32_t)i, (int32_t)n, si, sn) : (uint32_t)occ[s]);
     }
     __syncthreads();
-    net64_rows<kRcRows / kR64Parts>(W, s_sp, kRcRows, s_h, s_out);
+    net64_rows<kRcRows / kR64Parts>(s_w, s_sp, kRcRows, s_h, s_out);
     if (tid < kRcRows) row_e[(size_t)q * 2 * kOmMlp + r0 + tid] = s_out[tid];
     __threadfence();
     __syncthreads();

@@ -389,7 +389,7 @@ inline int enqueue_sweep(smc_ctx *c, const smc_stats *st, bool trace) {
       // blocks loop over the queue (usually short): a few per CU
       const int ev2 = prof_begin(c);
       if (f.model == 0) {
-        const unsigned rg = (unsigned)std::min<int64_t>(4 * (int64_t)c->n_cu, nt * kRcSplit);
+        const unsigned rg = (unsigned)std::min<int64_t>(c->n_cu, nt * kRcSplit);  // LDS: one block per CU
         hipLaunchKernelGGL(k_recheck_net, dim3(rg), dim3(kR64Threads), 0, c->stream, a, (const double *)c->d_w64,
                            f.d_rowe, f.d_done);
       } else {
@@ -461,7 +461,7 @@ inline int delta_e64(smc_ctx *c, int32_t replica, uint64_t sweep, const int64_t 
     a.n_replicas = (int32_t)c->reps.size();
     a.probe_dE = d_out;
     if (f.model == 0)
-      hipLaunchKernelGGL(k_recheck_net, dim3((unsigned)std::min<int64_t>((int64_t)n * kRcSplit, 4 * (int64_t)c->n_cu)),
+      hipLaunchKernelGGL(k_recheck_net, dim3((unsigned)std::min<int64_t>((int64_t)n * kRcSplit, c->n_cu)),
                          dim3(kR64Threads), 0, c->stream, a, (const double *)c->d_w64, d_rowe, d_done);
     else
       hipLaunchKernelGGL(k_recheck_qsro, dim3((unsigned)std::min<int64_t>(n, 2 * (int64_t)c->n_cu)),

@@ -55,13 +55,14 @@ static_assert(kRcRowsB * kRcBlocksPerTrial == kRows64, "row split");
 // In a half: layer 0, thread t owns unit t % 128 of rows 8(t / 128) .. +7; layer 1, thread t
 // owns units 4(t % 32) .. +3 of rows 2(t / 32) and +1.
 constexpr int kRcHalf = kRcThreads / 2;
+constexpr int kSpStride = 32;  // bytes per row of slot species (27 used), two 16-byte reads
 __global__ __launch_bounds__(kRcThreads) void k_recheck_rows(RecheckArgs a) {
   __shared__ __attribute__((aligned(16))) float s_w0[108 * kHid];
   __shared__ __attribute__((aligned(16))) float s_w1[kHid * kHid];
   __shared__ double s_h[2][kRcRowsB * kHStride];  // silu(z0), then the W2-weighted silu(z1)
   __shared__ double s_part[2][kRcRowsB * 8];
   __shared__ uint8_t s_reg[2][kReg];
-  __shared__ uint8_t s_sp[2][kRcRowsB * 27];
+  __shared__ __attribute__((aligned(16))) uint8_t s_sp[2][kRcRowsB * kSpStride];
   __shared__ double s_b0[kHid], s_b1[kHid], s_w2[kHid];
   const uint32_t n = *a.q_count;
   const uint32_t items = n * kRcBlocksPerTrial;
@@ -136,26 +137,42 @@ __global__ __launch_bounds__(kRcThreads) void k_recheck_rows(RecheckArgs a) {
       for (int k = 0; k < 2; ++k) {
         const int v = lt + k * kRcHalf;
         if (v < kRcRowsB * 27) {
-          const int gr = r0 + v / 27, p = pslot[k];
+          const int lr = v / 27, gr = r0 + lr, p = pslot[k];
           const bool exch = (gr < kOm) != (has_reg != 0);
-          s_sp[hf][v] = exch ? (p == pos_i ? at_n : (p == pos_n ? at_i : s_reg[hf][p])) : s_reg[hf][p];
+          s_sp[hf][lr * kSpStride + (v - lr * 27)] =
+              exch ? (p == pos_i ? at_n : (p == pos_n ? at_i : s_reg[hf][p])) : s_reg[hf][p];
         }
       }
     }
     __syncthreads();
     // layer 0 + activation
     if (live) {
+      // the species of the thread's 8 rows come in as whole words and every weight read is
+      // issued without a branch (species 4 reads channel 3 and adds +0.0, which leaves each
+      // sum as it is), so that the LDS reads pipeline instead of waiting one by one
       const int o = lt % kHid, rb = (lt / kHid) * 8;
+      uint32_t sw[8][7];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const uint4 lo = *(const uint4 *)(s_sp[hf] + (rb + j) * kSpStride);
+        const uint4 hi = *(const uint4 *)(s_sp[hf] + (rb + j) * kSpStride + 16);
+        sw[j][0] = lo.x; sw[j][1] = lo.y; sw[j][2] = lo.z; sw[j][3] = lo.w;
+        sw[j][4] = hi.x; sw[j][5] = hi.y; sw[j][6] = hi.z;
+      }
       double acc[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) acc[j] = s_b0[o];
-#pragma unroll 3
+#pragma unroll
       for (int m = 0; m < 27; ++m) {
+        float w[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-          const int sp = s_sp[hf][(rb + j) * 27 + m];
-          if (sp < 4) acc[j] += (double)s_w0[(4 * m + sp) * kHid + o];
+          const uint32_t sp = (sw[j][m >> 2] >> (8 * (m & 3))) & 255u;
+          const float x = s_w0[(4 * m + (sp < 4u ? sp : 3u)) * kHid + o];
+          w[j] = sp < 4u ? x : 0.0f;
         }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[j] += (double)w[j];
       }
 #pragma unroll
       for (int j = 0; j < 8; ++j) h[(rb + j) * kHStride + o] = silu<double>(acc[j]);

@@ -56,9 +56,10 @@ __global__ __launch_bounds__(kS64Threads) void k_site_energies64_onehot(const Re
                    w2 = W0[(4 * m + 2) * kS64Hid + o], w3 = W0[(4 * m + 3) * kS64Hid + o];
 #pragma unroll
       for (int q = 0; q < kS64PerThread; ++q) {
+        // no branch: species 4 adds +0.0, which leaves the sum as it is
         const int sp = s_sp[(part + kS64Parts * q) * kSlots + m];
         const double wv = sp == 0 ? w0 : (sp == 1 ? w1 : (sp == 2 ? w2 : w3));
-        if (sp < 4) acc[q] += wv;
+        acc[q] += sp < 4 ? wv : 0.0;
       }
     }
 #pragma unroll
