@@ -115,6 +115,7 @@ struct smc_ctx {
   double *d_escratch = nullptr;   // [R]
   uint64_t *d_counters = nullptr; // [4][R]
   double *d_site64 = nullptr;     // [N] FP64 site energies (lazy)
+  double *d_psum = nullptr;       // [kSumChunks] partial sums of the FP64 totals (lazy)
   uint64_t sweep = 0;
   double guard = 0.0;
   // per-kernel timing: event pairs recorded around launches while profiling is on

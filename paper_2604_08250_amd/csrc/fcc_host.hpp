@@ -11,6 +11,7 @@
 #include "context.hpp"
 #include "fcc.hpp"
 #include "pack.hpp"
+#include "reduce.hpp"
 #include "sweep_mfma.hpp"
 
 namespace smc {
@@ -293,11 +294,11 @@ inline int site_energies64(smc_ctx *c, double *out) {
 // FP64 from-scratch totals per replica into d_escratch.
 inline int scratch_totals(smc_ctx *c) {
   if (!c->d_site64) HIPC(c, hipMalloc(&c->d_site64, sizeof(double) * c->n_total));
+  if (!c->d_psum) HIPC(c, hipMalloc(&c->d_psum, sizeof(double) * kSumChunks));
   int rc = site_energies64(c, c->d_site64);
   if (rc) return rc;
   for (size_t r = 0; r < c->reps.size(); ++r)
-    hipLaunchKernelGGL(k_sum_into, dim3(1), dim3(256), 0, c->stream, c->d_site64 + c->reps[r].site0,
-                       c->reps[r].n_sites, c->d_escratch + r, 0);
+    sum_doubles(c->stream, c->d_site64 + c->reps[r].site0, c->reps[r].n_sites, c->d_psum, c->d_escratch + r);
   HIPC(c, hipGetLastError());
   return SMC_OK;
 }

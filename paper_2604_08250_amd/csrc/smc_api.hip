@@ -14,6 +14,7 @@
 #include "double_lattice.hpp"
 #include "fcc_host.hpp"
 #include "recheck.hpp"
+#include "reduce.hpp"
 #include "site64.hpp"
 #include "sweep_mfma.hpp"
 #include "sweep_scalar.hpp"
@@ -117,6 +118,7 @@ int site_energies_fast(smc_ctx *c, int P, float *out) {
 
 int ensure_site64(smc_ctx *c) {
   if (!c->d_site64) HIPC(c, hipMalloc(&c->d_site64, sizeof(double) * c->n_total));
+  if (!c->d_psum) HIPC(c, hipMalloc(&c->d_psum, sizeof(double) * kSumChunks));
   return SMC_OK;
 }
 
@@ -127,8 +129,7 @@ int scratch_totals(smc_ctx *c) {
   if (!rc) rc = site_energies64(c, c->d_site64);
   if (rc) return rc;
   for (size_t r = 0; r < c->reps.size(); ++r)
-    hipLaunchKernelGGL(k_sum_into, dim3(1), dim3(256), 0, c->stream, c->d_site64 + c->reps[r].site0,
-                       c->reps[r].n_sites, c->d_escratch + r, 0);
+    sum_doubles(c->stream, c->d_site64 + c->reps[r].site0, c->reps[r].n_sites, c->d_psum, c->d_escratch + r);
   HIPC(c, hipGetLastError());
   return SMC_OK;
 }
@@ -1231,7 +1232,7 @@ void smc_destroy(smc_ctx *c) {
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   void *bufs[] = {c->d_reps, c->d_w32, c->d_w64, c->d_w64t, c->d_w32t, c->d_omega, c->d_reg_off, c->d_om_off, c->d_idx,
                   c->d_reg_pos, c->d_queue, c->d_rowe, c->d_qcount, c->d_ebase, c->d_efixed, c->d_escratch,
-                  c->d_counters, c->d_site64, c->packs[0].dev, c->packs[1].dev, c->packs[2].dev,
+                  c->d_counters, c->d_site64, c->d_psum, c->packs[0].dev, c->packs[1].dev, c->packs[2].dev,
                   c->packs[3].dev, c->d_seg_rep, c->d_seg_start[0], c->d_seg_start[1], c->d_seg_start[2], c->d_sweep,
                   c->d_sigma1, c->d_E0, c->d_E1, c->d_dltrials};
   for (void *p : bufs)
