@@ -44,17 +44,19 @@ constexpr int kHStride = kHid + 1;            // padded row stride of the activa
 static_assert(kRcRowsB * kRcBlocksPerTrial == kRows64, "row split");
 
 // Work item w: queued trial q = w / 5 and its rows r0 = 16 (w % 5) .. r0 + 15.
-// Arithmetic order of each row energy (fixed; every FP64 evaluation of a zone uses it):
+// Arithmetic of each row energy (every FP64 evaluation of a zone uses it):
 //   z0[u] = b0[u] + the W0 column of slot m's species, added for m = 0..26 (species 4: none);
-//   z1[u] = b1[u] + sum over k = 0..127 of W1[u][k] silu(z0[k]), one fma per k in order;
+//   z1[u] = b1[u] + sum over k = 0..127 of W1[u][k] silu(z0[k]), on the FP64 matrix cores in
+//           32 steps of 4 inputs;
 //   E = b2 + sum over chunks c = 0..7 of (sum over i = 0..15 of W2[16c+i] silu(z1[16c+i])).
 // Persistent blocks, one per CU: each stages W0 and W1 in LDS once (their FP32 values, which
 // the FP64 arithmetic takes exactly) with b0, b1 and W2, and then walks work items with no
 // weight traffic, two at
 // a time (one per half block), so that the gathers and LDS round trips of two items overlap.
-// In a half: layer 0, thread t owns unit t % 128 of rows 8(t / 128) .. +7; layer 1, thread t
-// owns units 4(t % 32) .. +3 of rows 2(t / 32) and +1.
+// In a half: layer 0, thread t owns unit t % 128 of rows 8(t / 128) .. +7; layer 1, wave v
+// owns units 32v .. 32v + 31 of all 16 rows.
 constexpr int kRcHalf = kRcThreads / 2;
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 constexpr int kSpStride = 32;  // bytes per row of slot species (27 used), two 16-byte reads
 __global__ __launch_bounds__(kRcThreads) void k_recheck_rows(RecheckArgs a) {
   __shared__ __attribute__((aligned(16))) float s_w0[108 * kHid];
@@ -178,34 +180,36 @@ __global__ __launch_bounds__(kRcThreads) void k_recheck_rows(RecheckArgs a) {
       for (int j = 0; j < 8; ++j) h[(rb + j) * kHStride + o] = silu<double>(acc[j]);
     }
     __syncthreads();
-    // layer 1 + activation, times W2
+    // layer 1 on the FP64 matrix cores, times W2 after the activation.  Wave v of the half
+    // owns units 32v .. 32v + 31 as two 16-unit tiles; the 16 rows are the other dimension and
+    // the 128 inputs run in steps of 4 (16x16x4 FP64 products: lane l supplies the weight of
+    // unit 16T + l % 16 and input 4s + l / 16 and the activation of that input in row l % 16,
+    // and receives units 16T + l / 16 + 4j, j = 0..3, of row l % 16).
     {
-      const int u0 = 4 * (lt % 32), ra = 2 * (lt / 32);
-      double acc[2][4];
+      const int wv = lt >> 6, li = lt & 15, lk = (lt >> 4) & 3;
+      f64x4 acc[2];
       if (live) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) acc[0][i] = acc[1][i] = s_b1[u0 + i];
-#pragma unroll 4
-        for (int k = 0; k < kHid; ++k) {
-          const float4 wf = *(const float4 *)(s_w1 + k * kHid + u0);
-          const double w0 = (double)wf.x, w1 = (double)wf.y, w2 = (double)wf.z, w3 = (double)wf.w;
-          const double h0 = h[ra * kHStride + k], h1 = h[(ra + 1) * kHStride + k];
-          acc[0][0] = fma(w0, h0, acc[0][0]);
-          acc[0][1] = fma(w1, h0, acc[0][1]);
-          acc[0][2] = fma(w2, h0, acc[0][2]);
-          acc[0][3] = fma(w3, h0, acc[0][3]);
-          acc[1][0] = fma(w0, h1, acc[1][0]);
-          acc[1][1] = fma(w1, h1, acc[1][1]);
-          acc[1][2] = fma(w2, h1, acc[1][2]);
-          acc[1][3] = fma(w3, h1, acc[1][3]);
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[t][j] = s_b1[32 * wv + 16 * t + lk + 4 * j];
+#pragma unroll 8
+        for (int s = 0; s < kHid / 4; ++s) {
+          const double b = h[li * kHStride + 4 * s + lk];
+          const float *wr = s_w1 + (4 * s + lk) * kHid + 32 * wv + li;
+          acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)wr[0], b, acc[0], 0, 0, 0);
+          acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)wr[16], b, acc[1], 0, 0, 0);
         }
       }
       __syncthreads();
       if (live) {
 #pragma unroll
-        for (int r = 0; r < 2; ++r)
+        for (int t = 0; t < 2; ++t)
 #pragma unroll
-          for (int i = 0; i < 4; ++i) h[(ra + r) * kHStride + u0 + i] = s_w2[u0 + i] * silu<double>(acc[r][i]);
+          for (int j = 0; j < 4; ++j) {
+            const int u = 32 * wv + 16 * t + lk + 4 * j;
+            h[li * kHStride + u] = s_w2[u] * silu<double>(acc[t][j]);
+          }
       }
     }
     __syncthreads();

@@ -81,6 +81,33 @@ def test_uneven_lattice_and_five_species():
     mc.close()
 
 
+@pytest.mark.parametrize("n_species", [4, 5])
+def test_fp64_probe_matches_oracle(n_species):
+    """The FP64 re-decision kernel (through smc_delta_e64, which queues the given trials exactly
+    as the sweep's near-threshold queue) against the oracle's dE trial by trial: one trial (a
+    work split that leaves a half block idle), three, and 400 (several work items per block);
+    the lattice and the energy cache are left as they were."""
+    need_gpu()
+    cells = (9, 10, 13)
+    _banner(f"fp64 probe {cells} {n_species} species")
+    w, mc, model, occ = make("c2", cells=cells, n_species=n_species, hidden=128, temperature=700.0)
+    mc.sweep(2)
+    now = mc.occ.cpu().numpy().copy()
+    ec = mc.ecache.cpu().numpy().copy()
+    T = w.temperatures[0]
+    rng = np.random.default_rng(3 + n_species)
+    for n in (1, 3, 400):
+        sites = rng.choice(now.size, size=n, replace=False)
+        partners, d64 = mc.delta_e64(sites, sweep=4)
+        for s, p, d in zip(sites, partners, d64):
+            rec = oracle.trial(cells, model, now, T, w.seed, 0, 4, int(s))
+            assert p == rec["partner"]
+            want = 0.0 if rec["same"] else rec["dE"]
+            assert abs(d - want) < 1e-10, f"{n} trials, site {s}: probe {d!r} oracle {want!r}"
+    assert np.array_equal(mc.occ.cpu().numpy(), now) and np.array_equal(mc.ecache.cpu().numpy(), ec)
+    mc.close()
+
+
 def test_split_run_equals_long_run_and_resume():
     need_gpu()
     _banner("split/resume")
