@@ -53,8 +53,7 @@ static_assert(kRcRowsB * kRcBlocksPerTrial == kRows64, "row split");
 // the FP64 arithmetic takes exactly) with b0, b1 and W2, and then walks work items with no
 // weight traffic, two at
 // a time (one per half block), so that the gathers and LDS round trips of two items overlap.
-// In a half: layer 0, thread t owns unit t % 128 of rows 8(t / 128) .. +7; layer 1, wave v
-// owns units 32v .. 32v + 31 of all 16 rows.
+// In a half, wave v owns units 32v .. 32v + 31 of all 16 rows in both layers.
 constexpr int kRcHalf = kRcThreads / 2;
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 constexpr int kSpStride = 32;  // bytes per row of slot species (27 used), two 16-byte reads
@@ -68,7 +67,7 @@ __global__ __launch_bounds__(kRcThreads) void k_recheck_rows(RecheckArgs a) {
   __shared__ double s_b0[kHid], s_b1[kHid], s_w2[kHid];
   const uint32_t n = *a.q_count;
   const uint32_t items = n * kRcBlocksPerTrial;
-  if (2 * blockIdx.x >= items) return;  // no work item for this block
+  if (blockIdx.x >= items) return;  // no work item for this block
   const int tid = threadIdx.x, hf = tid / kRcHalf, lt = tid % kRcHalf;
   const double *b0 = a.w64 + kHid * 108, *b1 = b0 + kHid + kHid * kHid, *W2 = b1 + kHid;
   const double b2 = W2[kHid];
@@ -96,9 +95,12 @@ __global__ __launch_bounds__(kRcThreads) void k_recheck_rows(RecheckArgs a) {
     else if (tid < 3 * kHid) s_w2[tid - 2 * kHid] = bb;
   }
   double *h = s_h[hf];
-  for (uint32_t base = 2 * blockIdx.x; base < items; base += 2 * gridDim.x) {
+  // item w of pass p: half 0 takes blockIdx.x + 2 G p, half 1 the item G further (G blocks), so
+  // that a last pass with fewer items than halves leaves whole blocks to one half (whose waves
+  // then have the SIMDs to themselves) and a short queue spreads over every block
+  for (uint32_t base = blockIdx.x; base < items; base += 2 * gridDim.x) {
     // every thread reaches every barrier; a half without a valid item computes nothing
-    const uint32_t w = base + hf;
+    const uint32_t w = base + hf * gridDim.x;
     const uint32_t q = w / kRcBlocksPerTrial;
     const int r0 = (int)(w - q * kRcBlocksPerTrial) * kRcRowsB;
     const bool live = w < items && a.queue[q].site >= 0;
@@ -147,37 +149,36 @@ __global__ __launch_bounds__(kRcThreads) void k_recheck_rows(RecheckArgs a) {
       }
     }
     __syncthreads();
-    // layer 0 + activation
-    if (live) {
-      // the species of the thread's 8 rows come in as whole words and every weight read is
-      // issued without a branch (species 4 reads channel 3 and adds +0.0, which leaves each
-      // sum as it is), so that the LDS reads pipeline instead of waiting one by one
-      const int o = lt % kHid, rb = (lt / kHid) * 8;
-      uint32_t sw[8][7];
+    // layer 0 + activation on the FP64 matrix cores, with the same tiles as layer 1: the
+    // one-hot input of slot m is K-step m (its four channels), lane l supplies the weight of
+    // unit 16T + l % 16 for channel l / 16 and the one-hot value of that channel in row
+    // l % 16.  A row has at most one non-zero product per K-step (none for species 4) and the
+    // others are exact zeros, so every sum is the sequence b0 + the selected W0 columns in
+    // slot order, each addition rounded once.
+    {
+      const int wv = lt >> 6, li = lt & 15, lk = (lt >> 4) & 3;
+      if (live) {
+        const uint4 lo = *(const uint4 *)(s_sp[hf] + li * kSpStride);
+        const uint4 hi = *(const uint4 *)(s_sp[hf] + li * kSpStride + 16);
+        const uint32_t sw[7] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z};
+        f64x4 acc[2];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const uint4 lo = *(const uint4 *)(s_sp[hf] + (rb + j) * kSpStride);
-        const uint4 hi = *(const uint4 *)(s_sp[hf] + (rb + j) * kSpStride + 16);
-        sw[j][0] = lo.x; sw[j][1] = lo.y; sw[j][2] = lo.z; sw[j][3] = lo.w;
-        sw[j][4] = hi.x; sw[j][5] = hi.y; sw[j][6] = hi.z;
-      }
-      double acc[8];
+        for (int t = 0; t < 2; ++t)
 #pragma unroll
-      for (int j = 0; j < 8; ++j) acc[j] = s_b0[o];
+          for (int j = 0; j < 4; ++j) acc[t][j] = s_b0[32 * wv + 16 * t + lk + 4 * j];
 #pragma unroll
-      for (int m = 0; m < 27; ++m) {
-        float w[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const uint32_t sp = (sw[j][m >> 2] >> (8 * (m & 3))) & 255u;
-          const float x = s_w0[(4 * m + (sp < 4u ? sp : 3u)) * kHid + o];
-          w[j] = sp < 4u ? x : 0.0f;
+        for (int m = 0; m < 27; ++m) {
+          const uint32_t sp = (sw[m >> 2] >> (8 * (m & 3))) & 255u;
+          const double b = sp == (uint32_t)lk ? 1.0 : 0.0;
+          const float *wr = s_w0 + (4 * m + lk) * kHid + 32 * wv + li;
+          acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)wr[0], b, acc[0], 0, 0, 0);
+          acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)wr[16], b, acc[1], 0, 0, 0);
         }
 #pragma unroll
-        for (int j = 0; j < 8; ++j) acc[j] += (double)w[j];
-      }
+        for (int t = 0; t < 2; ++t)
 #pragma unroll
-      for (int j = 0; j < 8; ++j) h[(rb + j) * kHStride + o] = silu<double>(acc[j]);
+          for (int j = 0; j < 4; ++j) h[li * kHStride + 32 * wv + 16 * t + lk + 4 * j] = silu<double>(acc[t][j]);
+      }
     }
     __syncthreads();
     // layer 1 on the FP64 matrix cores, times W2 after the activation.  Wave v of the half
@@ -234,49 +235,66 @@ __global__ __launch_bounds__(kRcThreads) void k_recheck_rows(RecheckArgs a) {
 
 // One wave per queued trial: dE = (sum of the 40 rows after) - (sum of the 40 before), each
 // summed in zone order (the rows are loaded by 40 lanes at once and added in order from lane
-// registers); decide and apply (or, for a probe, only report dE).
+// registers); decide and apply (or, for a probe, only report dE).  Everything the apply needs
+// (the replica, the two species, the zone positions, the cache values) is loaded with the rows,
+// so that a trial costs two dependent memory round trips (entry, then the rest) before its
+// writes.
 __global__ __launch_bounds__(256) void k_recheck_decide(RecheckArgs a) {
   const uint32_t n = *a.q_count;
   const int lane = threadIdx.x & 63;
   const uint32_t waves = gridDim.x * (blockDim.x / 64);
   for (uint32_t q = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); q < n; q += waves) {
     const RecheckEntry &e = a.queue[q];
-    if (e.site < 0) continue;
+    const int64_t site = e.site, partner = e.partner;
+    if (site < 0) continue;
+    const int32_t rep = e.replica, dir = e.dir;
+    const double theta = e.theta;
     const double *re = a.row_e + (size_t)q * kRows64;
     const double v1 = lane < kOm ? re[lane] : 0.0, v0 = lane < kOm ? re[kOm + lane] : 0.0;
+    const bool probe = a.probe_dE != nullptr;
+    const Replica R = a.reps[rep];
+    uint8_t *occ = a.occ + R.site0;
+    int32_t cpos = 0;
+    float ce = 0.0f;
+    uint8_t si = 0, sn = 0;
+    if (!probe) {
+      if (lane < kOm) {
+        const Pos pi = site_pos(site, R.L[0], R.L[1]);
+        int dx, dy, dz;
+        unpack_off(a.om_off[dir * kOm + lane], dx, dy, dz);
+        cpos = (int32_t)site_at(pi, dx, dy, dz, R.L[0], R.L[1], R.L[2]);
+        ce = e.e1[lane];
+      }
+      if (lane == 0) {
+        si = occ[site];
+        sn = occ[partner];
+      }
+    }
     double e1 = 0.0, e0 = 0.0;
 #pragma unroll
     for (int k = 0; k < kOm; ++k) e1 += __shfl(v1, k);
 #pragma unroll
     for (int k = 0; k < kOm; ++k) e0 += __shfl(v0, k);
     const double dE = e1 - e0;
-    if (a.probe_dE) {
+    if (probe) {
       if (lane == 0) a.probe_dE[q] = dE;
       continue;
     }
-    const Replica R = a.reps[e.replica];
-    uint8_t *occ = a.occ + R.site0;
-    const bool accept = dE <= e.theta;
+    const bool accept = dE <= theta;
     const int Rn = a.n_replicas;
     if (lane == 0) {
       if (accept) {
-        const uint8_t si = occ[e.site], sn = occ[e.partner];
-        occ[e.site] = sn;
-        occ[e.partner] = si;
-        atomicAdd(&a.e_fixed[e.replica], (unsigned long long)to_fixed(dE));
-        atomicAdd((unsigned long long *)&a.counters[2 * Rn + e.replica], 1ull);
+        occ[site] = sn;
+        occ[partner] = si;
+        atomicAdd(&a.e_fixed[rep], (unsigned long long)to_fixed(dE));
+        atomicAdd((unsigned long long *)&a.counters[2 * Rn + rep], 1ull);
       }
-      atomicAdd((unsigned long long *)&a.counters[3 * Rn + e.replica], 1ull);
-      if (a.trace_flags) a.trace_flags[R.site0 + e.site] = kFlagFp64 | (accept ? kFlagAccept : 0);
-      if (a.trace_dE) a.trace_dE[R.site0 + e.site] = dE;
+      atomicAdd((unsigned long long *)&a.counters[3 * Rn + rep], 1ull);
+      if (a.trace_flags) a.trace_flags[R.site0 + site] = kFlagFp64 | (accept ? kFlagAccept : 0);
+      if (a.trace_dE) a.trace_dE[R.site0 + site] = dE;
     }
-    if (accept && lane < kOm) {
-      // the cache keeps the sweep precision's energies of the zone
-      const Pos pi = site_pos(e.site, R.L[0], R.L[1]);
-      int dx, dy, dz;
-      unpack_off(a.om_off[e.dir * kOm + lane], dx, dy, dz);
-      a.ecache[R.site0 + site_at(pi, dx, dy, dz, R.L[0], R.L[1], R.L[2])] = e.e1[lane];
-    }
+    // the cache keeps the sweep precision's energies of the zone
+    if (accept && lane < kOm) a.ecache[R.site0 + cpos] = ce;
   }
 }
 
@@ -284,7 +302,7 @@ __global__ __launch_bounds__(256) void k_recheck_decide(RecheckArgs a) {
 // on the device).
 inline void launch_recheck(const RecheckArgs &ra, int64_t max_entries, int n_cu, hipStream_t stream) {
   const int64_t items = std::max<int64_t>(1, max_entries) * kRcBlocksPerTrial;
-  const unsigned rows_grid = (unsigned)std::min<int64_t>((items + 1) / 2, n_cu);  // one block per CU (LDS)
+  const unsigned rows_grid = (unsigned)std::min<int64_t>(items, n_cu);  // one block per CU (LDS)
   hipLaunchKernelGGL(k_recheck_rows, dim3(rows_grid), dim3(kRcThreads), 0, stream, ra);
   const unsigned dec_grid = (unsigned)std::min<int64_t>((std::max<int64_t>(1, max_entries) + 3) / 4, 4 * (int64_t)n_cu);
   hipLaunchKernelGGL(k_recheck_decide, dim3(dec_grid), dim3(256), 0, stream, ra);
