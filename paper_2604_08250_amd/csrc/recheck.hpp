@@ -51,8 +51,8 @@ static_assert(kRcRowsB * kRcBlocksPerTrial == kRows64, "row split");
 //   E = b2 + sum over chunks c = 0..7 of (sum over i = 0..15 of W2[16c+i] silu(z1[16c+i])).
 // Persistent blocks, one per CU: each stages W0 and W1 in LDS once (their FP32 values, which
 // the FP64 arithmetic takes exactly) with b0, b1 and W2, and then walks work items with no
-// weight traffic, two at
-// a time (one per half block), so that the gathers and LDS round trips of two items overlap.
+// weight traffic, two at a time (one per half block), so that the LDS round trips of two items
+// overlap; each item's global loads are issued during the previous item's layers.
 // In a half, wave v owns units 32v .. 32v + 31 of all 16 rows in both layers.
 constexpr int kRcHalf = kRcThreads / 2;
 typedef double f64x4 __attribute__((ext_vector_type(4)));
@@ -71,6 +71,55 @@ __global__ __launch_bounds__(kRcThreads) void k_recheck_rows(RecheckArgs a) {
   const int tid = threadIdx.x, hf = tid / kRcHalf, lt = tid % kRcHalf;
   const double *b0 = a.w64 + kHid * 108, *b1 = b0 + kHid + kHid * kHid, *W2 = b1 + kHid;
   const double b2 = W2[kHid];
+  // The loads of an item come in two stages, each issued while the previous item is computed:
+  // the queue entry (stage 1), then the tables its direction selects (stage 2).
+  struct Item {
+    uint32_t q;
+    int r0, d, has_reg, rep, pos_i, pos_n;
+    bool in_range, live;
+    int64_t site;
+    uint32_t regw;          // word lt of the queued region (threads lt < 48)
+    int pslot[2];           // zone-region positions of this thread's two slot-species entries
+  };
+  auto stage1 = [&](uint32_t w, Item &it) {
+    it.q = w / kRcBlocksPerTrial;
+    it.r0 = (int)(w - it.q * kRcBlocksPerTrial) * kRcRowsB;
+    it.in_range = w < items;
+    it.site = -1;
+    it.d = it.has_reg = it.rep = 0;
+    it.regw = 0u;
+    if (it.in_range) {
+      const RecheckEntry &e = a.queue[it.q];
+      it.site = e.site;
+      it.d = e.dir;
+      it.has_reg = e.has_reg;
+      it.rep = e.replica;
+      if (lt < kReg / 4) it.regw = ((const uint32_t *)e.reg)[lt];
+    }
+  };
+  auto stage2 = [&](Item &it) {
+    it.live = it.in_range && it.site >= 0;
+    it.pos_i = it.pos_n = 0;
+    it.pslot[0] = it.pslot[1] = 0;
+    if (it.live) {
+      const int d = it.d;
+      it.pos_i = a.reg_pos[2 * d];
+      it.pos_n = a.reg_pos[2 * d + 1];
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int v = lt + k * kRcHalf;
+        if (v < kRcRowsB * 27) {
+          const int lr = v / 27, m = v - lr * 27, gr = it.r0 + lr;
+          it.pslot[k] = a.idx[(d * kOm + (gr < kOm ? gr : gr - kOm)) * kIdxRow + m];
+        }
+      }
+    }
+  };
+  // item w of pass p: half 0 takes blockIdx.x + 2 G p, half 1 the item G further (G blocks), so
+  // that a last pass with fewer items than halves leaves whole blocks to one half (whose waves
+  // then have the SIMDs to themselves) and a short queue spreads over every block
+  Item cur, nxt;
+  stage1(blockIdx.x + hf * gridDim.x, cur);
   {
     // every load of the staging is issued before the first LDS store (one memory round trip)
     constexpr int n0 = 108 * kHid / 4, nw = n0 + kHid * kHid / 4, per = (nw + kRcThreads - 1) / kRcThreads;
@@ -84,6 +133,7 @@ __global__ __launch_bounds__(kRcThreads) void k_recheck_rows(RecheckArgs a) {
     }
     const int ub = tid % kHid;
     const double bb = (tid < kHid ? b0 : (tid < 2 * kHid ? b1 : W2))[ub];  // threads past 3 kHid load W2 unused
+    stage2(cur);
 #pragma unroll
     for (int i = 0; i < per; ++i) {
       const int q = tid + i * kRcThreads;
@@ -95,38 +145,18 @@ __global__ __launch_bounds__(kRcThreads) void k_recheck_rows(RecheckArgs a) {
     else if (tid < 3 * kHid) s_w2[tid - 2 * kHid] = bb;
   }
   double *h = s_h[hf];
-  // item w of pass p: half 0 takes blockIdx.x + 2 G p, half 1 the item G further (G blocks), so
-  // that a last pass with fewer items than halves leaves whole blocks to one half (whose waves
-  // then have the SIMDs to themselves) and a short queue spreads over every block
   for (uint32_t base = blockIdx.x; base < items; base += 2 * gridDim.x) {
     // every thread reaches every barrier; a half without a valid item computes nothing
-    const uint32_t w = base + hf * gridDim.x;
-    const uint32_t q = w / kRcBlocksPerTrial;
-    const int r0 = (int)(w - q * kRcBlocksPerTrial) * kRcRowsB;
-    const bool live = w < items && a.queue[q].site >= 0;
-    const RecheckEntry &e = a.queue[live ? q : 0];
-    int d = 0, has_reg = 0, pos_i = 0, pos_n = 0;
-    int pslot[2] = {0, 0};  // zone-region positions of this thread's two slot-species entries
+    const bool live = cur.live;
+    const int r0 = cur.r0, d = cur.d, has_reg = cur.has_reg, pos_i = cur.pos_i, pos_n = cur.pos_n;
+    const uint32_t q = cur.q;
     if (live) {
-      d = e.dir;
-      has_reg = e.has_reg;
-      // the table loads of the slot-species build go out with the region loads
-      pos_i = a.reg_pos[2 * d];
-      pos_n = a.reg_pos[2 * d + 1];
-#pragma unroll
-      for (int k = 0; k < 2; ++k) {
-        const int v = lt + k * kRcHalf;
-        if (v < kRcRowsB * 27) {
-          const int lr = v / 27, m = v - lr * 27, gr = r0 + lr;
-          pslot[k] = a.idx[(d * kOm + (gr < kOm ? gr : gr - kOm)) * kIdxRow + m];
-        }
-      }
       if (has_reg) {
         // the colour kernel queued the region with the trial (swap applied)
-        if (lt < kReg / 4) ((uint32_t *)s_reg[hf])[lt] = ((const uint32_t *)e.reg)[lt];
+        if (lt < kReg / 4) ((uint32_t *)s_reg[hf])[lt] = cur.regw;
       } else if (lt < kReg) {
-        const Replica R = a.reps[e.replica];
-        const Pos pi = site_pos(e.site, R.L[0], R.L[1]);
+        const Replica R = a.reps[cur.rep];
+        const Pos pi = site_pos(cur.site, R.L[0], R.L[1]);
         int dx, dy, dz;
         unpack_off(a.reg_off[d * kReg + lt], dx, dy, dz);
         s_reg[hf][lt] = a.occ[R.site0 + site_at(pi, dx, dy, dz, R.L[0], R.L[1], R.L[2])];
@@ -141,7 +171,7 @@ __global__ __launch_bounds__(kRcThreads) void k_recheck_rows(RecheckArgs a) {
       for (int k = 0; k < 2; ++k) {
         const int v = lt + k * kRcHalf;
         if (v < kRcRowsB * 27) {
-          const int lr = v / 27, gr = r0 + lr, p = pslot[k];
+          const int lr = v / 27, gr = r0 + lr, p = cur.pslot[k];
           const bool exch = (gr < kOm) != (has_reg != 0);
           s_sp[hf][lr * kSpStride + (v - lr * 27)] =
               exch ? (p == pos_i ? at_n : (p == pos_n ? at_i : s_reg[hf][p])) : s_reg[hf][p];
@@ -149,6 +179,8 @@ __global__ __launch_bounds__(kRcThreads) void k_recheck_rows(RecheckArgs a) {
       }
     }
     __syncthreads();
+    // the next item's queue entry, in flight during layer 0
+    stage1(base + 2 * gridDim.x + hf * gridDim.x, nxt);
     // layer 0 + activation on the FP64 matrix cores, with the same tiles as layer 1: the
     // one-hot input of slot m is K-step m (its four channels), lane l supplies the weight of
     // unit 16T + l % 16 for channel l / 16 and the one-hot value of that channel in row
@@ -181,6 +213,8 @@ __global__ __launch_bounds__(kRcThreads) void k_recheck_rows(RecheckArgs a) {
       }
     }
     __syncthreads();
+    // the next item's tables, in flight during layer 1
+    stage2(nxt);
     // layer 1 on the FP64 matrix cores, times W2 after the activation.  Wave v of the half
     // owns units 32v .. 32v + 31 as two 16-unit tiles; the 16 rows are the other dimension and
     // the 128 inputs run in steps of 4 (16x16x4 FP64 products: lane l supplies the weight of
@@ -230,6 +264,7 @@ __global__ __launch_bounds__(kRcThreads) void k_recheck_rows(RecheckArgs a) {
       a.row_e[(size_t)q * kRows64 + r0 + lt] = E;
     }
     __syncthreads();
+    cur = nxt;
   }
 }
 
@@ -304,7 +339,7 @@ inline void launch_recheck(const RecheckArgs &ra, int64_t max_entries, int n_cu,
   const int64_t items = std::max<int64_t>(1, max_entries) * kRcBlocksPerTrial;
   const unsigned rows_grid = (unsigned)std::min<int64_t>(items, n_cu);  // one block per CU (LDS)
   hipLaunchKernelGGL(k_recheck_rows, dim3(rows_grid), dim3(kRcThreads), 0, stream, ra);
-  const unsigned dec_grid = (unsigned)std::min<int64_t>((std::max<int64_t>(1, max_entries) + 3) / 4, 4 * (int64_t)n_cu);
+  const unsigned dec_grid = (unsigned)std::min<int64_t>((std::max<int64_t>(1, max_entries) + 3) / 4, (int64_t)n_cu);
   hipLaunchKernelGGL(k_recheck_decide, dim3(dec_grid), dim3(256), 0, stream, ra);
 }
 
