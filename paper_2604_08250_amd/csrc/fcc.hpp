@@ -814,6 +814,53 @@ __device__ void net64_rows(const WT *W, const uint8_t *s_sp, int nrows, double *
   __syncthreads();
 }
 
+// FP64 energies of up to 16 rows (slot species in s_sp[row][19]) on the FP64 matrix cores, for
+// the re-decision: wave v (of 6) owns units 16v .. 16v + 15 in every layer, the rows are the
+// other dimension of the 16x16x4 products.  W: the blob's values as FP32 numbers (exact).
+// Layer 0 takes slot m as K-step m (lane l: channel l / 16 of row l % 16); a row has at most
+// one non-zero product per K-step, so its sums are b0 plus the selected W0 columns in slot
+// order, as in net64_rows.  The hidden layers sum 4 products per step; the output layer is one
+// fma per unit in order.  Rows past nrows are computed from empty slots and not written.
+typedef double f64x4_fcc __attribute__((ext_vector_type(4)));
+__device__ void net64_rows16(const float *W, const uint8_t *s_sp, int nrows, double *s_h, double *s_out) {
+  const int tid = threadIdx.x, wv = tid >> 6, li = tid & 15, lk = (tid >> 4) & 3, u0 = 16 * wv;
+  const float *W0 = W, *b0 = W0 + kIn * kHid, *W1 = b0 + kHid, *b1 = W1 + kHid * kHid, *W2 = b1 + kHid,
+              *b2 = W2 + kHid * kHid, *W3 = b2 + kHid, *b3 = W3 + kHid;
+  const bool rv = li < nrows;
+  f64x4_fcc acc;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) acc[j] = (double)b0[u0 + lk + 4 * j];
+#pragma unroll
+  for (int m = 0; m < kSlots; ++m) {
+    const uint32_t sp = rv ? s_sp[li * kSlots + m] : 4u;
+    const double b = sp == (uint32_t)lk ? 1.0 : 0.0;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)W0[(4 * m + lk) * kHid + u0 + li], b, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) s_h[li * kHS + u0 + lk + 4 * j] = acc[j] > 0.0 ? acc[j] : 0.0;
+  __syncthreads();
+  for (int layer = 0; layer < 2; ++layer) {
+    const float *Wl = layer == 0 ? W1 : W2, *bl = layer == 0 ? b1 : b2;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = (double)bl[u0 + lk + 4 * j];
+#pragma unroll 8
+    for (int st = 0; st < kHid / 4; ++st)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)Wl[(4 * st + lk) * kHid + u0 + li],
+                                                 s_h[li * kHS + 4 * st + lk], acc, 0, 0, 0);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) s_h[li * kHS + u0 + lk + 4 * j] = acc[j] > 0.0 ? acc[j] : 0.0;
+    __syncthreads();
+  }
+  // E_r = b3 + sum_o W3[o] h3[r][o], units in order
+  if (tid < nrows) {
+    double e = (double)b3[0];
+    for (int k = 0; k < kHid; ++k) e = fma((double)W3[k], s_h[tid * kHS + k], e);
+    s_out[tid] = e;
+  }
+  __syncthreads();
+}
+
 // FP64 local energies of every site of one replica (MLPNet).
 __global__ __launch_bounds__(kR64Threads) void k_site_energies_net64(const Replica *reps, int32_t r,
                                                                      const uint8_t *occ_all, const double *W,
@@ -880,21 +927,23 @@ __global__ void k_site_energies_qsro(const Replica *reps, int32_t r, const uint8
 }
 
 // FP64 re-decision of queued trials (MLPNet): the zone's 28 local energies after and 28
-// before the swap, split over kRcSplit blocks of 8 rows so that a short queue still spreads
-// over the chip.  Each block writes its rows to row_e; the block that completes a trial (per
+// before the swap, split over kRcSplit blocks of 14 rows (one 16-row matrix-product tile) so
+// that a short queue still spreads over the chip.  Each block writes its rows to row_e; the block that completes a trial (per
 // trial counter) sums the two zone halves in zone order, decides and applies.  No block waits
 // for another.  The cache keeps the sweep precision's post-swap energies.
-constexpr int kRcSplit = 7;
-constexpr int kRcRows = 2 * kOmMlp / kRcSplit;  // 8
+constexpr int kRcSplit = 4;
+constexpr int kRcRows = 2 * kOmMlp / kRcSplit;  // 14
+static_assert(kRcRows <= 16 && (kR64Threads / 64) * 16 == kHid, "one 16-row tile; one 16-unit tile per wave");
 static_assert(kRcRows * kRcSplit == 2 * kOmMlp, "row split");
 
-__global__ __launch_bounds__(kR64Threads) void k_recheck_net(Args a, const double *W, double *row_e,
+__global__ __launch_bounds__(kR64Threads) void k_recheck_net(Args a, const float *W32, double *row_e,
                                                             uint32_t *done) {
-  // the blob's values in LDS (FP32 numbers, exact), loaded in one batch: the queue is short,
-  // so each block's latency is the kernel's time and weight reads must not go to L2 per layer
-  __shared__ float s_w[kNetParamsDev];
-  __shared__ double s_h[kRcRows * kHS];
-  __shared__ double s_out[kRcRows];
+  // the blob's values in LDS (FP32 numbers, exact: W32 is the FP64 blob rounded to FP32, which
+  // changes nothing), loaded in one batch of 16-byte loads: the queue is short, so each block's
+  // latency is the kernel's time and weight reads must not go to L2 per layer
+  __shared__ __attribute__((aligned(16))) float s_w[kNetParamsDev];
+  __shared__ double s_h[16 * kHS];
+  __shared__ double s_out[16];
   __shared__ double s_re[2 * kOmMlp];
   __shared__ uint8_t s_sp[kRcRows * kSlots];
   __shared__ int s_last, s_accept;
@@ -904,21 +953,21 @@ __global__ __launch_bounds__(kR64Threads) void k_recheck_net(Args a, const doubl
   const int tid = threadIdx.x;
   if (blockIdx.x >= nq * kRcSplit) return;  // no work item for this block
   {
-    constexpr int per = (kNetParamsDev + kR64Threads - 1) / kR64Threads;
-#pragma unroll 17
-    for (int q0 = 0; q0 < per; q0 += 17) {
-      double t[17];
+    constexpr int n4 = kNetParamsDev / 4, per = (n4 + kR64Threads - 1) / kR64Threads;
+    const float4 *w4 = (const float4 *)W32;
+    float4 t[per];
 #pragma unroll
-      for (int k = 0; k < 17; ++k) {
-        const int q = tid + (q0 + k) * kR64Threads;
-        t[k] = (q0 + k < per && q < kNetParamsDev) ? W[q] : 0.0;
-      }
-#pragma unroll
-      for (int k = 0; k < 17; ++k) {
-        const int q = tid + (q0 + k) * kR64Threads;
-        if (q0 + k < per && q < kNetParamsDev) s_w[q] = (float)t[k];
-      }
+    for (int k = 0; k < per; ++k) {
+      const int q = tid + k * kR64Threads;
+      t[k] = q < n4 ? w4[q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
+    const float tail = tid < kNetParamsDev - 4 * n4 ? W32[4 * n4 + tid] : 0.0f;
+#pragma unroll
+    for (int k = 0; k < per; ++k) {
+      const int q = tid + k * kR64Threads;
+      if (q < n4) ((float4 *)s_w)[q] = t[k];
+    }
+    if (tid < kNetParamsDev - 4 * n4) s_w[4 * n4 + tid] = tail;
   }
   __syncthreads();
   for (uint32_t w = blockIdx.x; w < nq * kRcSplit; w += gridDim.x) {
@@ -940,7 +989,7 @@ __global__ __launch_bounds__(kR64Threads) void k_recheck_net(Args a, const doubl
       s_sp[v] = (uint8_t)(post ? swapped(occ, s, (int32_t)i, (int32_t)n, si, sn) : (uint32_t)occ[s]);
     }
     __syncthreads();
-    net64_rows<kRcRows / kR64Parts>(s_w, s_sp, kRcRows, s_h, s_out);
+    net64_rows16(s_w, s_sp, kRcRows, s_h, s_out);
     if (tid < kRcRows) row_e[(size_t)q * 2 * kOmMlp + r0 + tid] = s_out[tid];
     __threadfence();
     __syncthreads();

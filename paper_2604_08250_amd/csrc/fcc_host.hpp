@@ -217,7 +217,9 @@ inline int load_params(smc_ctx *c, const float *params_dev) {
   if (f.model == 0) {
     f.b3 = p[kNetParams - 1];
     const std::vector<double> t = net_fp64(p);
+    const std::vector<float> t32(t.begin(), t.end());  // exact: every entry is an FP32 parameter
     HIPC(c, hipMemcpyAsync(c->d_w64, t.data(), sizeof(double) * t.size(), hipMemcpyHostToDevice, c->stream));
+    HIPC(c, hipMemcpyAsync(c->d_w32, t32.data(), sizeof(float) * t32.size(), hipMemcpyHostToDevice, c->stream));
   } else {
     // folded qSRO coefficients with the FCC shell sizes
     const double z[3] = {12.0, 6.0, 24.0};
@@ -391,7 +393,7 @@ inline int enqueue_sweep(smc_ctx *c, const smc_stats *st, bool trace) {
       const int ev2 = prof_begin(c);
       if (f.model == 0) {
         const unsigned rg = (unsigned)std::min<int64_t>(c->n_cu, nt * kRcSplit);  // LDS: one block per CU
-        hipLaunchKernelGGL(k_recheck_net, dim3(rg), dim3(kR64Threads), 0, c->stream, a, (const double *)c->d_w64,
+        hipLaunchKernelGGL(k_recheck_net, dim3(rg), dim3(kR64Threads), 0, c->stream, a, (const float *)c->d_w32,
                            f.d_rowe, f.d_done);
       } else {
         const unsigned rg = (unsigned)std::min<int64_t>(2 * (int64_t)c->n_cu, nt);
@@ -463,7 +465,7 @@ inline int delta_e64(smc_ctx *c, int32_t replica, uint64_t sweep, const int64_t 
     a.probe_dE = d_out;
     if (f.model == 0)
       hipLaunchKernelGGL(k_recheck_net, dim3((unsigned)std::min<int64_t>((int64_t)n * kRcSplit, c->n_cu)),
-                         dim3(kR64Threads), 0, c->stream, a, (const double *)c->d_w64, d_rowe, d_done);
+                         dim3(kR64Threads), 0, c->stream, a, (const float *)c->d_w32, d_rowe, d_done);
     else
       hipLaunchKernelGGL(k_recheck_qsro, dim3((unsigned)std::min<int64_t>(n, 2 * (int64_t)c->n_cu)),
                          dim3(kRcQsroThreads), 0, c->stream, a, (const double *)c->d_w64);
