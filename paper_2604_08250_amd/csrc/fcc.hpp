@@ -750,76 +750,19 @@ __global__ __launch_bounds__(kPhaseThreads) void k_decide(Args a) {
 
 // ------------------------------------------------------------------ FP64 evaluation
 
-// FP64 MLPNet blob with every weight matrix stored [input][unit] (consecutive threads own
-// consecutive units, so their loads are contiguous): W0t[76][96], b0, W1t[96][96], b1,
-// W2t[96][96], b2, W3[96], b3.
-constexpr int kRows64 = 64;       // rows per pass of the FP64 site-energy kernel
-constexpr int kR64Threads = 384;  // 96 units x 4 parts
+// FP64 MLPNet blob with every weight matrix stored [input][unit]: W0t[76][96], b0, W1t[96][96],
+// b1, W2t[96][96], b2, W3[96], b3.  The FP64 kernels read its values from an FP32 copy (every
+// entry is an FP32 parameter) staged in LDS.
+constexpr int kR64Threads = 384;  // six waves: one 16-unit tile of the 96 units each
 constexpr int kNetParamsDev = kHid * kIn + kHid + 2 * (kHid * kHid + kHid) + kHid + 1;  // 26,113
-constexpr int kR64Parts = kR64Threads / kHid;
 constexpr int kHS = kHid + 1;     // padded activation row stride
 
-// FP64 energies of nrows (<= 4 RPT) rows whose slot species are in s_sp[row][19]; the result
-// of row r goes to s_out[r].  Thread (unit o, part p) owns rows p + 4j, j < RPT.  Every thread
-// of the block takes part (block-wide barriers).
-// WT: the FP64 blob itself (global memory) or its values staged in LDS as the FP32 numbers
-// they are (read back to FP64 exactly); the arithmetic is the same either way.
-template <int RPT, typename WT>
-__device__ void net64_rows(const WT *W, const uint8_t *s_sp, int nrows, double *s_h, double *s_out) {
-  constexpr int kR64PerThread = RPT;
-  const int tid = threadIdx.x;
-  const int o = tid % kHid, part = tid / kHid;
-  const WT *W0 = W, *b0 = W0 + kIn * kHid, *W1 = b0 + kHid, *b1 = W1 + kHid * kHid, *W2 = b1 + kHid,
-           *b2 = W2 + kHid * kHid, *W3 = b2 + kHid, *b3 = W3 + kHid;
-  double acc[kR64PerThread];
-#pragma unroll
-  for (int j = 0; j < kR64PerThread; ++j) acc[j] = (double)b0[o];
-#pragma unroll 4
-  for (int m = 0; m < kSlots; ++m) {
-    const double w0 = (double)W0[(4 * m) * kHid + o], w1 = (double)W0[(4 * m + 1) * kHid + o],
-                 w2 = (double)W0[(4 * m + 2) * kHid + o], w3 = (double)W0[(4 * m + 3) * kHid + o];
-#pragma unroll
-    for (int j = 0; j < kR64PerThread; ++j) {
-      // no branch: species 4 and rows past nrows add +0.0, which leaves the sum as it is
-      const int r = part + kR64Parts * j;
-      const int sp = s_sp[(r < nrows ? r : 0) * kSlots + m];
-      const double wv = sp == 0 ? w0 : (sp == 1 ? w1 : (sp == 2 ? w2 : w3));
-      acc[j] += (r < nrows && sp < 4) ? wv : 0.0;
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < kR64PerThread; ++j) s_h[(part + kR64Parts * j) * kHS + o] = acc[j] > 0.0 ? acc[j] : 0.0;
-  __syncthreads();
-  for (int layer = 0; layer < 2; ++layer) {
-    const WT *Wl = layer == 0 ? W1 : W2, *bl = layer == 0 ? b1 : b2;
-#pragma unroll
-    for (int j = 0; j < kR64PerThread; ++j) acc[j] = (double)bl[o];
-#pragma unroll 8
-    for (int k = 0; k < kHid; ++k) {
-      const double wk = (double)Wl[k * kHid + o];
-#pragma unroll
-      for (int j = 0; j < kR64PerThread; ++j) acc[j] = fma(wk, s_h[(part + kR64Parts * j) * kHS + k], acc[j]);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < kR64PerThread; ++j) s_h[(part + kR64Parts * j) * kHS + o] = acc[j] > 0.0 ? acc[j] : 0.0;
-    __syncthreads();
-  }
-  // E_r = b3 + sum_o W3[o] h3[r][o], units in order
-  if (tid < nrows) {
-    double e = (double)b3[0];
-    for (int k = 0; k < kHid; ++k) e = fma((double)W3[k], s_h[tid * kHS + k], e);
-    s_out[tid] = e;
-  }
-  __syncthreads();
-}
-
 // FP64 energies of up to 16 rows (slot species in s_sp[row][19]) on the FP64 matrix cores, for
-// the re-decision: wave v (of 6) owns units 16v .. 16v + 15 in every layer, the rows are the
-// other dimension of the 16x16x4 products.  W: the blob's values as FP32 numbers (exact).
-// Layer 0 takes slot m as K-step m (lane l: channel l / 16 of row l % 16); a row has at most
-// one non-zero product per K-step, so its sums are b0 plus the selected W0 columns in slot
-// order, as in net64_rows.  The hidden layers sum 4 products per step; the output layer is one
+// the re-decision and the FP64 site energies: wave v (of 6) owns units 16v .. 16v + 15 in every
+// layer, the rows are the other dimension of the 16x16x4 products.  W: the blob's values as FP32
+// numbers (exact).  Layer 0 takes slot m as K-step m (lane l: channel l / 16 of row l % 16); a
+// row has at most one non-zero product per K-step, so its sums are b0 plus the selected W0
+// columns in slot order.  The hidden layers sum 4 products per step; the output layer is one
 // fma per unit in order.  Rows past nrows are computed from empty slots and not written.
 typedef double f64x4_fcc __attribute__((ext_vector_type(4)));
 __device__ void net64_rows16(const float *W, const uint8_t *s_sp, int nrows, double *s_h, double *s_out) {
@@ -861,28 +804,63 @@ __device__ void net64_rows16(const float *W, const uint8_t *s_sp, int nrows, dou
   __syncthreads();
 }
 
-// FP64 local energies of every site of one replica (MLPNet).
+// The network's values as FP32 numbers (exact: the FP64 blob rounded to FP32 changes nothing) into
+// LDS, in one batch of 16-byte loads (every thread of the block).
+__device__ __forceinline__ void net64_stage(float *s_w, const float *W32) {
+  constexpr int n4 = kNetParamsDev / 4, per = (n4 + kR64Threads - 1) / kR64Threads;
+  const int tid = threadIdx.x;
+  const float4 *w4 = (const float4 *)W32;
+  float4 t[per];
+#pragma unroll
+  for (int k = 0; k < per; ++k) {
+    const int q = tid + k * kR64Threads;
+    t[k] = q < n4 ? w4[q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  }
+  const float tail = tid < kNetParamsDev - 4 * n4 ? W32[4 * n4 + tid] : 0.0f;
+#pragma unroll
+  for (int k = 0; k < per; ++k) {
+    const int q = tid + k * kR64Threads;
+    if (q < n4) ((float4 *)s_w)[q] = t[k];
+  }
+  if (tid < kNetParamsDev - 4 * n4) s_w[4 * n4 + tid] = tail;
+}
+
+// FP64 local energies of every site of one replica (MLPNet) with the re-decision's row evaluator
+// (net64_rows16), 16 sites per pass and one block per CU (the weights in LDS); each thread loads
+// its slot species of the next pass while the current one is evaluated.
+constexpr int kS64NetRows = 16;
 __global__ __launch_bounds__(kR64Threads) void k_site_energies_net64(const Replica *reps, int32_t r,
-                                                                     const uint8_t *occ_all, const double *W,
+                                                                     const uint8_t *occ_all, const float *W32,
                                                                      double *out) {
-  __shared__ double s_h[kRows64 * kHS];
-  __shared__ double s_out[kRows64];
-  __shared__ uint8_t s_sp[kRows64 * kSlots];
+  __shared__ __attribute__((aligned(16))) float s_w[kNetParamsDev];
+  __shared__ double s_h[kS64NetRows * kHS];
+  __shared__ double s_out[kS64NetRows];
+  __shared__ uint8_t s_sp[kS64NetRows * kSlots];
+  static_assert(kS64NetRows * kSlots <= kR64Threads, "one slot species per thread");
   const Replica R = reps[r];
   const uint8_t *occ = occ_all + R.site0;
-  const int64_t passes = (R.n_sites + kRows64 - 1) / kRows64;
+  const int64_t passes = (R.n_sites + kS64NetRows - 1) / kS64NetRows;
+  if ((int64_t)blockIdx.x >= passes) return;
+  const int tid = threadIdx.x;
+  auto fetch = [&](int64_t pass) -> uint8_t {
+    if (tid >= kS64NetRows * kSlots || pass >= passes) return 4;
+    const int lr = tid / kSlots, m = tid - lr * kSlots;
+    const int64_t j = pass * kS64NetRows + lr;
+    if (j >= R.n_sites) return 4;
+    if (m == 0) return occ[j];
+    const Pos p = pos(j, R.L[0], R.L[1]);
+    return occ[at(p, dx(m - 1), dy(m - 1), dz(m - 1), R.L[0], R.L[1], R.L[2])];
+  };
+  uint8_t cur = fetch(blockIdx.x);
+  net64_stage(s_w, W32);
   for (int64_t pass = blockIdx.x; pass < passes; pass += gridDim.x) {
-    const int64_t j0 = pass * kRows64;
-    const int nrows = R.n_sites - j0 < kRows64 ? (int)(R.n_sites - j0) : kRows64;
-    for (int v = threadIdx.x; v < nrows * kSlots; v += kR64Threads) {
-      const int lr = v / kSlots, m = v - lr * kSlots;
-      const Pos p = pos(j0 + lr, R.L[0], R.L[1]);
-      s_sp[v] = occ[m == 0 ? j0 + lr : at(p, dx(m - 1), dy(m - 1), dz(m - 1), R.L[0], R.L[1], R.L[2])];
-    }
+    const int64_t j0 = pass * kS64NetRows;
+    const int nrows = R.n_sites - j0 < kS64NetRows ? (int)(R.n_sites - j0) : kS64NetRows;
+    if (tid < kS64NetRows * kSlots) s_sp[tid] = cur;
     __syncthreads();
-    net64_rows<kRows64 / kR64Parts>(W, s_sp, nrows, s_h, s_out);
-    if ((int)threadIdx.x < nrows) out[R.site0 + j0 + threadIdx.x] = s_out[threadIdx.x];
-    __syncthreads();
+    cur = fetch(pass + gridDim.x);
+    net64_rows16(s_w, s_sp, nrows, s_h, s_out);
+    if (tid < nrows) out[R.site0 + j0 + tid] = s_out[tid];
   }
 }
 
@@ -952,23 +930,7 @@ __global__ __launch_bounds__(kR64Threads) void k_recheck_net(Args a, const float
   const uint32_t nq = *a.q_count;
   const int tid = threadIdx.x;
   if (blockIdx.x >= nq * kRcSplit) return;  // no work item for this block
-  {
-    constexpr int n4 = kNetParamsDev / 4, per = (n4 + kR64Threads - 1) / kR64Threads;
-    const float4 *w4 = (const float4 *)W32;
-    float4 t[per];
-#pragma unroll
-    for (int k = 0; k < per; ++k) {
-      const int q = tid + k * kR64Threads;
-      t[k] = q < n4 ? w4[q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    }
-    const float tail = tid < kNetParamsDev - 4 * n4 ? W32[4 * n4 + tid] : 0.0f;
-#pragma unroll
-    for (int k = 0; k < per; ++k) {
-      const int q = tid + k * kR64Threads;
-      if (q < n4) ((float4 *)s_w)[q] = t[k];
-    }
-    if (tid < kNetParamsDev - 4 * n4) s_w[4 * n4 + tid] = tail;
-  }
+  net64_stage(s_w, W32);
   __syncthreads();
   for (uint32_t w = blockIdx.x; w < nq * kRcSplit; w += gridDim.x) {
     const uint32_t q = w / kRcSplit;

@@ -281,9 +281,9 @@ inline int site_energies64(smc_ctx *c, double *out) {
   for (size_t r = 0; r < c->reps.size(); ++r) {
     const int64_t n = c->reps[r].n_sites;
     if (c->fcc.model == 0) {
-      const unsigned grid = (unsigned)std::min<int64_t>((n + kRows64 - 1) / kRows64, 4 * (int64_t)c->n_cu);
+      const unsigned grid = (unsigned)std::min<int64_t>((n + kS64NetRows - 1) / kS64NetRows, c->n_cu);  // LDS: one per CU
       hipLaunchKernelGGL(k_site_energies_net64, dim3(grid), dim3(kR64Threads), 0, c->stream, c->d_reps, (int32_t)r,
-                         c->occ, c->d_w64, out);
+                         c->occ, (const float *)c->d_w32, out);
     } else {
       hipLaunchKernelGGL(k_site_energies_qsro<double>, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, c->d_reps,
                          (int32_t)r, c->occ, c->d_w64, out);

@@ -11,6 +11,7 @@
 #pragma once
 #include <algorithm>
 
+#include "rows64.hpp"
 #include "sweep_mfma.hpp"
 
 namespace smc {
@@ -37,40 +38,26 @@ struct RecheckArgs {
 };
 
 constexpr int kRows64 = 2 * kOm;              // rows 0..39 after the swap, 40..79 before
-constexpr int kRcRowsB = 16;                  // rows per work item of k_recheck_rows
+constexpr int kRcRowsB = kR64Rows;            // rows per work item of k_recheck_rows
 constexpr int kRcBlocksPerTrial = kRows64 / kRcRowsB;  // 5 work items per queued trial
-constexpr int kRcThreads = 512;
-constexpr int kHStride = kHid + 1;            // padded row stride of the activation buffer
+constexpr int kRcThreads = kR64Threads;
 static_assert(kRcRowsB * kRcBlocksPerTrial == kRows64, "row split");
 
-// Work item w: queued trial q = w / 5 and its rows r0 = 16 (w % 5) .. r0 + 15.
-// Arithmetic of each row energy (every FP64 evaluation of a zone uses it):
-//   z0[u] = b0[u] + the W0 column of slot m's species, added for m = 0..26 (species 4: none);
-//   z1[u] = b1[u] + sum over k = 0..127 of W1[u][k] silu(z0[k]), on the FP64 matrix cores in
-//           32 steps of 4 inputs;
-//   E = b2 + sum over chunks c = 0..7 of (sum over i = 0..15 of W2[16c+i] silu(z1[16c+i])).
-// Persistent blocks, one per CU: each stages W0 and W1 in LDS once (their FP32 values, which
-// the FP64 arithmetic takes exactly) with b0, b1 and W2, and then walks work items with no
-// weight traffic, two at a time (one per half block), so that the LDS round trips of two items
-// overlap; each item's global loads are issued during the previous item's layers.
-// In a half, wave v owns units 32v .. 32v + 31 of all 16 rows in both layers.
-constexpr int kRcHalf = kRcThreads / 2;
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-constexpr int kSpStride = 32;  // bytes per row of slot species (27 used), two 16-byte reads
+// Work item w: queued trial q = w / 5 and its rows r0 = 16 (w % 5) .. r0 + 15, evaluated by
+// rows64_half (the arithmetic every FP64 evaluation of a zone uses).  Persistent blocks, one per
+// CU: each stages W0 and W1 in LDS once and then walks work items with no weight traffic, two at
+// a time (one per half block), so that the LDS round trips of two items overlap; each item's
+// global loads are issued during the previous item's layers.
+constexpr int kRcHalf = kR64Half;
 __global__ __launch_bounds__(kRcThreads) void k_recheck_rows(RecheckArgs a) {
-  __shared__ __attribute__((aligned(16))) float s_w0[108 * kHid];
-  __shared__ __attribute__((aligned(16))) float s_w1[kHid * kHid];
-  __shared__ double s_h[2][kRcRowsB * kHStride];  // silu(z0), then the W2-weighted silu(z1)
-  __shared__ double s_part[2][kRcRowsB * 8];
+  __shared__ __attribute__((aligned(16))) Rows64W s_wt;
+  __shared__ __attribute__((aligned(16))) Rows64Half s_half[2];
   __shared__ uint8_t s_reg[2][kReg];
-  __shared__ __attribute__((aligned(16))) uint8_t s_sp[2][kRcRowsB * kSpStride];
-  __shared__ double s_b0[kHid], s_b1[kHid], s_w2[kHid];
   const uint32_t n = *a.q_count;
   const uint32_t items = n * kRcBlocksPerTrial;
   if (blockIdx.x >= items) return;  // no work item for this block
   const int tid = threadIdx.x, hf = tid / kRcHalf, lt = tid % kRcHalf;
-  const double *b0 = a.w64 + kHid * 108, *b1 = b0 + kHid + kHid * kHid, *W2 = b1 + kHid;
-  const double b2 = W2[kHid];
+  const double b2 = a.w64[kR64Hid * 108 + kR64Hid + kR64Hid * kR64Hid + 2 * kR64Hid];
   // The loads of an item come in two stages, each issued while the previous item is computed:
   // the queue entry (stage 1), then the tables its direction selects (stage 2).
   struct Item {
@@ -120,31 +107,7 @@ __global__ __launch_bounds__(kRcThreads) void k_recheck_rows(RecheckArgs a) {
   // then have the SIMDs to themselves) and a short queue spreads over every block
   Item cur, nxt;
   stage1(blockIdx.x + hf * gridDim.x, cur);
-  {
-    // every load of the staging is issued before the first LDS store (one memory round trip)
-    constexpr int n0 = 108 * kHid / 4, nw = n0 + kHid * kHid / 4, per = (nw + kRcThreads - 1) / kRcThreads;
-    const float4 *w0 = (const float4 *)a.w32t;
-    const float4 *w1 = (const float4 *)(a.w32t + kHid * 108 + kHid);
-    float4 t[per];
-#pragma unroll
-    for (int i = 0; i < per; ++i) {
-      const int q = tid + i * kRcThreads;
-      t[i] = q < n0 ? w0[q] : (q < nw ? w1[q - n0] : make_float4(0.0f, 0.0f, 0.0f, 0.0f));
-    }
-    const int ub = tid % kHid;
-    const double bb = (tid < kHid ? b0 : (tid < 2 * kHid ? b1 : W2))[ub];  // threads past 3 kHid load W2 unused
-    stage2(cur);
-#pragma unroll
-    for (int i = 0; i < per; ++i) {
-      const int q = tid + i * kRcThreads;
-      if (q < n0) ((float4 *)s_w0)[q] = t[i];
-      else if (q < nw) ((float4 *)s_w1)[q - n0] = t[i];
-    }
-    if (tid < kHid) s_b0[tid] = bb;
-    else if (tid < 2 * kHid) s_b1[tid - kHid] = bb;
-    else if (tid < 3 * kHid) s_w2[tid - 2 * kHid] = bb;
-  }
-  double *h = s_h[hf];
+  rows64_stage(s_wt, a.w32t, a.w64, [&] { stage2(cur); });
   for (uint32_t base = blockIdx.x; base < items; base += 2 * gridDim.x) {
     // every thread reaches every barrier; a half without a valid item computes nothing
     const bool live = cur.live;
@@ -173,96 +136,16 @@ __global__ __launch_bounds__(kRcThreads) void k_recheck_rows(RecheckArgs a) {
         if (v < kRcRowsB * 27) {
           const int lr = v / 27, gr = r0 + lr, p = cur.pslot[k];
           const bool exch = (gr < kOm) != (has_reg != 0);
-          s_sp[hf][lr * kSpStride + (v - lr * 27)] =
+          s_half[hf].sp[lr * kR64SpStride + (v - lr * 27)] =
               exch ? (p == pos_i ? at_n : (p == pos_n ? at_i : s_reg[hf][p])) : s_reg[hf][p];
         }
       }
     }
     __syncthreads();
-    // the next item's queue entry, in flight during layer 0
+    // the next item's queue entry in flight during layer 0, its tables during layer 1
     stage1(base + 2 * gridDim.x + hf * gridDim.x, nxt);
-    // layer 0 + activation on the FP64 matrix cores, with the same tiles as layer 1: the
-    // one-hot input of slot m is K-step m (its four channels), lane l supplies the weight of
-    // unit 16T + l % 16 for channel l / 16 and the one-hot value of that channel in row
-    // l % 16.  A row has at most one non-zero product per K-step (none for species 4) and the
-    // others are exact zeros, so every sum is the sequence b0 + the selected W0 columns in
-    // slot order, each addition rounded once.
-    {
-      const int wv = lt >> 6, li = lt & 15, lk = (lt >> 4) & 3;
-      if (live) {
-        const uint4 lo = *(const uint4 *)(s_sp[hf] + li * kSpStride);
-        const uint4 hi = *(const uint4 *)(s_sp[hf] + li * kSpStride + 16);
-        const uint32_t sw[7] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z};
-        f64x4 acc[2];
-#pragma unroll
-        for (int t = 0; t < 2; ++t)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[t][j] = s_b0[32 * wv + 16 * t + lk + 4 * j];
-#pragma unroll
-        for (int m = 0; m < 27; ++m) {
-          const uint32_t sp = (sw[m >> 2] >> (8 * (m & 3))) & 255u;
-          const double b = sp == (uint32_t)lk ? 1.0 : 0.0;
-          const float *wr = s_w0 + (4 * m + lk) * kHid + 32 * wv + li;
-          acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)wr[0], b, acc[0], 0, 0, 0);
-          acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)wr[16], b, acc[1], 0, 0, 0);
-        }
-#pragma unroll
-        for (int t = 0; t < 2; ++t)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) h[li * kHStride + 32 * wv + 16 * t + lk + 4 * j] = silu<double>(acc[t][j]);
-      }
-    }
-    __syncthreads();
-    // the next item's tables, in flight during layer 1
-    stage2(nxt);
-    // layer 1 on the FP64 matrix cores, times W2 after the activation.  Wave v of the half
-    // owns units 32v .. 32v + 31 as two 16-unit tiles; the 16 rows are the other dimension and
-    // the 128 inputs run in steps of 4 (16x16x4 FP64 products: lane l supplies the weight of
-    // unit 16T + l % 16 and input 4s + l / 16 and the activation of that input in row l % 16,
-    // and receives units 16T + l / 16 + 4j, j = 0..3, of row l % 16).
-    {
-      const int wv = lt >> 6, li = lt & 15, lk = (lt >> 4) & 3;
-      f64x4 acc[2];
-      if (live) {
-#pragma unroll
-        for (int t = 0; t < 2; ++t)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[t][j] = s_b1[32 * wv + 16 * t + lk + 4 * j];
-#pragma unroll 8
-        for (int s = 0; s < kHid / 4; ++s) {
-          const double b = h[li * kHStride + 4 * s + lk];
-          const float *wr = s_w1 + (4 * s + lk) * kHid + 32 * wv + li;
-          acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)wr[0], b, acc[0], 0, 0, 0);
-          acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)wr[16], b, acc[1], 0, 0, 0);
-        }
-      }
-      __syncthreads();
-      if (live) {
-#pragma unroll
-        for (int t = 0; t < 2; ++t)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int u = 32 * wv + 16 * t + lk + 4 * j;
-            h[li * kHStride + u] = s_w2[u] * silu<double>(acc[t][j]);
-          }
-      }
-    }
-    __syncthreads();
-    // E_r = b2 + sum over units in a fixed order: 8 consecutive chunks of 16, then the chunks
-    if (live && lt < kRcRowsB * 8) {
-      const int lr = lt / 8, c = lt % 8;
-      double sm = 0.0;
-#pragma unroll
-      for (int i = 0; i < kHid / 8; ++i) sm += h[lr * kHStride + c * (kHid / 8) + i];
-      s_part[hf][lt] = sm;
-    }
-    __syncthreads();
-    if (live && lt < kRcRowsB) {
-      double E = b2;
-#pragma unroll
-      for (int c = 0; c < 8; ++c) E += s_part[hf][lt * 8 + c];
-      a.row_e[(size_t)q * kRows64 + r0 + lt] = E;
-    }
+    const double E = rows64_half(s_wt, b2, live, lt, s_half[hf], [&] { stage2(nxt); });
+    if (live && lt < kRcRowsB) a.row_e[(size_t)q * kRows64 + r0 + lt] = E;
     __syncthreads();
     cur = nxt;
   }

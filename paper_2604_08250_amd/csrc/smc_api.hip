@@ -58,15 +58,15 @@ int site_energies_scalar(smc_ctx *c, const T *W, T *out) {
   return SMC_OK;
 }
 
-// FP64 local energies of every site: the block kernel for the one-hot 128-hidden model (same
-// arithmetic order as the per-lane kernel), the per-lane kernel otherwise.
+// FP64 local energies of every site: the matrix-core kernel for the one-hot 128-hidden model
+// (the re-decision's row arithmetic), the per-lane kernel otherwise.
 int site_energies64(smc_ctx *c, double *out) {
   if (!c->mfma) return site_energies_scalar<double>(c, c->d_w64, out);
   for (size_t r = 0; r < c->reps.size(); ++r) {
-    const int64_t passes = (c->reps[r].n_sites + kS64Rows - 1) / kS64Rows;
-    const unsigned grid = (unsigned)std::min<int64_t>(passes, 2 * (int64_t)c->n_cu);
+    const int64_t items = (c->reps[r].n_sites + kS64Rows - 1) / kS64Rows;
+    const unsigned grid = (unsigned)std::min<int64_t>(items, c->n_cu);  // one block per CU (LDS)
     hipLaunchKernelGGL(k_site_energies64_onehot, dim3(grid), dim3(kS64Threads), 0, c->stream, c->d_reps,
-                       (int32_t)r, c->occ, c->d_w64t, out);
+                       (int32_t)r, c->occ, c->d_w32t, c->d_w64t, out);
   }
   HIPC(c, hipGetLastError());
   return SMC_OK;
