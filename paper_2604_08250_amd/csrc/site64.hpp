@@ -2,7 +2,8 @@
 // matrix cores with the re-decision's row evaluator (rows64_half), so that a site's FP64 energy
 // here and in a re-decided zone is the same number.  Persistent blocks of 512 threads, one per
 // CU: the weights are staged in LDS once, then each half block takes 16 consecutive sites at a
-// time (half 1 G items after half 0, G blocks), gathers their 27 slot species and evaluates them.
+// time (half 1 G items after half 0, G blocks), gathers their 27 slot species and evaluates them;
+// each thread loads its species of the next item while the current one is evaluated.
 #pragma once
 #include "rows64.hpp"
 #include "tables.hpp"
@@ -25,37 +26,49 @@ __global__ __launch_bounds__(kS64Threads) void k_site_energies64_onehot(const Re
   if ((int64_t)blockIdx.x >= items) return;  // no work item for this block
   const int tid = threadIdx.x, hf = tid / kR64Half, lt = tid % kR64Half;
   const double b2 = w64t[kR64Hid * 108 + kR64Hid + kR64Hid * kR64Hid + 2 * kR64Hid];
+  // the two slot species of this thread for item w (16 rows x 27 slots over the half's 256
+  // threads); rows past the end get species 4 (no channel) and are not written
+  auto fetch = [&](int64_t w, uint8_t (&sp)[2]) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int v = lt + k * kR64Half;
+      sp[k] = 4;
+      if (w < items && v < kS64Rows * kSlots) {
+        const int lr = v / kSlots, m = v - lr * kSlots;
+        const int64_t j = w * kS64Rows + lr;
+        if (j < R.n_sites) {
+          if (m == 0) {
+            sp[k] = occ[j];
+          } else {
+            const Pos p = site_pos32((int32_t)j, R.L[0], R.L[1]);
+            sp[k] = occ[site_at32(p, shell_dx(m - 1), shell_dy(m - 1), shell_dz(m - 1), R.L[0], R.L[1], R.L[2])];
+          }
+        }
+      }
+    }
+  };
+  uint8_t cur[2], nxt[2];
+  fetch(blockIdx.x + hf * (int64_t)gridDim.x, cur);
   rows64_stage(s_wt, w32t, w64t, [] {});
   for (int64_t base = blockIdx.x; base < items; base += 2 * (int64_t)gridDim.x) {
     const int64_t w = base + hf * (int64_t)gridDim.x;
     const bool live = w < items;
     const int64_t j0 = w * kS64Rows;
-    if (live) {
-      // 16 rows x 27 slots over the half's 256 threads; rows past the end get species 4 (no
-      // channel) and are not written
 #pragma unroll
-      for (int k = 0; k < 2; ++k) {
-        const int v = lt + k * kR64Half;
-        if (v < kS64Rows * kSlots) {
-          const int lr = v / kSlots, m = v - lr * kSlots;
-          const int64_t j = j0 + lr;
-          uint8_t sp = 4;
-          if (j < R.n_sites) {
-            if (m == 0) {
-              sp = occ[j];
-            } else {
-              const Pos p = site_pos32((int32_t)j, R.L[0], R.L[1]);
-              sp = occ[site_at32(p, shell_dx(m - 1), shell_dy(m - 1), shell_dz(m - 1), R.L[0], R.L[1], R.L[2])];
-            }
-          }
-          s_half[hf].sp[lr * kR64SpStride + m] = sp;
-        }
+    for (int k = 0; k < 2; ++k) {
+      const int v = lt + k * kR64Half;
+      if (live && v < kS64Rows * kSlots) {
+        const int lr = v / kSlots;
+        s_half[hf].sp[lr * kR64SpStride + (v - lr * kSlots)] = cur[k];
       }
     }
     __syncthreads();
+    fetch(w + 2 * (int64_t)gridDim.x, nxt);  // in flight during the evaluation
     const double E = rows64_half(s_wt, b2, live, lt, s_half[hf], [] {});
     if (live && lt < kS64Rows && j0 + lt < R.n_sites) out[R.site0 + j0 + lt] = E;
     __syncthreads();
+    cur[0] = nxt[0];
+    cur[1] = nxt[1];
   }
 }
 
