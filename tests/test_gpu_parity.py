@@ -86,7 +86,8 @@ def test_fp64_probe_matches_oracle(n_species):
     """The FP64 re-decision kernel (through smc_delta_e64, which queues the given trials exactly
     as the sweep's near-threshold queue) against the oracle's dE trial by trial: one trial (a
     work split that leaves a half block idle), three, and 400 (several work items per block);
-    the lattice and the energy cache are left as they were."""
+    the lattice and the energy cache are left as they were.  The FP64 site energies, which use
+    the same row evaluator, match the oracle on this ragged site count."""
     need_gpu()
     cells = (9, 10, 13)
     _banner(f"fp64 probe {cells} {n_species} species")
@@ -94,6 +95,11 @@ def test_fp64_probe_matches_oracle(n_species):
     mc.sweep(2)
     now = mc.occ.cpu().numpy().copy()
     ec = mc.ecache.cpu().numpy().copy()
+    # FP64 site energies from the same row evaluator, over a site count that is not a multiple
+    # of its 16-row items
+    assert now.size % 16 != 0
+    e64 = mc.site_energies("fp64").cpu().numpy()
+    assert np.max(np.abs(e64 - oracle.all_site_energies(cells, model, now))) < 1e-12
     T = w.temperatures[0]
     rng = np.random.default_rng(3 + n_species)
     for n in (1, 3, 400):
