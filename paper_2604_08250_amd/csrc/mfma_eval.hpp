@@ -89,11 +89,14 @@ __device__ __forceinline__ void act_split(float y0, float y1, uint32_t &hi, uint
   lo = pack_bf16x2(fmaf(y0, r0, -bf16_lo_f32(hi)), fmaf(y1, r1, -bf16_hi_f32(hi)));
 }
 
-// One-hot of a species id (0..3; 4 and above: no channel) as 4 BF16 values in 2 dwords.
+// One-hot of a species id (0..3; 4 and above: no channel) as 4 BF16 values in 2 dwords: BF16 1.0
+// shifted to channel p by two 64-bit shifts of 8p bits each (p = 4 shifts it out entirely, where
+// a single shift by 64 would not; larger ids count as 4).
 __device__ __forceinline__ void onehot_bf16(uint32_t p, uint32_t &lo, uint32_t &hi) {
-  const uint32_t one = 0x3F80u << ((p & 1u) << 4);
-  lo = p < 2u ? one : 0u;
-  hi = (p - 2u) < 2u ? one : 0u;
+  const uint32_t sh = (p < 4u ? p : 4u) << 3;
+  const uint64_t v = ((uint64_t)0x3F80u << sh) << sh;
+  lo = (uint32_t)v;
+  hi = (uint32_t)(v >> 32);
 }
 
 // One-hot of a species id as 4 FP8 E4M3 bytes in one dword (1.0 = 0x38).
