@@ -73,6 +73,7 @@ struct smc_ctx {
   int64_t n_total = 0;
   int32_t n_in = 0, hidden = 0, n_params = 0;
   bool mfma = false;              // one-hot features with 128 hidden: matrix-core path
+  bool qsro_tiled = false;        // BCC qSRO in FP32: the same colour kernel, qSRO evaluation
   int n_cu = 256;
   int device = 0;                 // device current at smc_init
   void *scratch = nullptr;        // device address of the probe's static work space on that device

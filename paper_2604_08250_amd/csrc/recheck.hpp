@@ -216,12 +216,69 @@ __global__ __launch_bounds__(256) void k_recheck_decide(RecheckArgs a) {
   }
 }
 
+// FP64 rows of the qSRO model (Eq. 2) for the queue of the matrix-core path: one block per
+// queued trial (grid-stride), the region in LDS, one row per thread (rows 0..39 after the swap,
+// 40..79 before), each counted and evaluated by the per-lane evaluator in FP64.  Its decisions
+// are k_recheck_decide's, as for the MLP.
+constexpr int kRqThreads = 128;
+__global__ __launch_bounds__(kRqThreads) void k_recheck_rows_qsro(RecheckArgs a, const double *F) {
+  __shared__ uint8_t s_reg[kReg];
+  const uint32_t n = *a.q_count;
+  const int tid = threadIdx.x;
+  for (uint32_t q = blockIdx.x; q < n; q += gridDim.x) {
+    const RecheckEntry &e = a.queue[q];
+    const bool live = e.site >= 0;  // uniform over the block
+    const int d = e.dir, has_reg = e.has_reg;
+    if (live) {
+      if (has_reg) {
+        // the colour kernel queued the region with the trial (swap applied)
+        if (tid < kReg / 4) ((uint32_t *)s_reg)[tid] = ((const uint32_t *)e.reg)[tid];
+      } else {
+        const Replica R = a.reps[e.replica];
+        const Pos pi = site_pos(e.site, R.L[0], R.L[1]);
+        for (int v = tid; v < kReg; v += kRqThreads) {
+          int dx, dy, dz;
+          unpack_off(a.reg_off[d * kReg + v], dx, dy, dz);
+          s_reg[v] = a.occ[R.site0 + site_at(pi, dx, dy, dz, R.L[0], R.L[1], R.L[2])];
+        }
+      }
+    }
+    __syncthreads();
+    if (live && tid < kRows64) {
+      // the rows after the swap see i and n exchanged relative to the rows before (s_reg holds
+      // the lattice after the swap when has_reg, else before)
+      const int pos_i = a.reg_pos[2 * d], pos_n = a.reg_pos[2 * d + 1];
+      const uint8_t at_i = s_reg[pos_i], at_n = s_reg[pos_n];
+      const bool exch = (tid < kOm) != (has_reg != 0);
+      const uint8_t *irow = a.idx + (d * kOm + (tid < kOm ? tid : tid - kOm)) * kIdxRow;
+      uint8_t slot[kSlots];
+#pragma unroll
+      for (int m = 0; m < kSlots; ++m) {
+        const int p = irow[m];
+        slot[m] = exch ? (p == pos_i ? at_n : (p == pos_n ? at_i : s_reg[p])) : s_reg[p];
+      }
+      a.row_e[(size_t)q * kRows64 + tid] = qsro_scalar<double>(slot, F);
+    }
+    __syncthreads();
+  }
+}
+
 // Enqueue both kernels for a queue of at most max_entries trials (the length itself is read
 // on the device).
 inline void launch_recheck(const RecheckArgs &ra, int64_t max_entries, int n_cu, hipStream_t stream) {
   const int64_t items = std::max<int64_t>(1, max_entries) * kRcBlocksPerTrial;
   const unsigned rows_grid = (unsigned)std::min<int64_t>(items, n_cu);  // one block per CU (LDS)
   hipLaunchKernelGGL(k_recheck_rows, dim3(rows_grid), dim3(kRcThreads), 0, stream, ra);
+  const unsigned dec_grid = (unsigned)std::min<int64_t>((std::max<int64_t>(1, max_entries) + 3) / 4, (int64_t)n_cu);
+  hipLaunchKernelGGL(k_recheck_decide, dim3(dec_grid), dim3(256), 0, stream, ra);
+}
+
+// The same for the qSRO model: FP64 qSRO rows (F: the folded FP64 coefficients), then the
+// decisions.
+inline void launch_recheck_qsro(const RecheckArgs &ra, const double *F, int64_t max_entries, int n_cu,
+                                hipStream_t stream) {
+  const unsigned rows_grid = (unsigned)std::min<int64_t>(std::max<int64_t>(1, max_entries), 4 * (int64_t)n_cu);
+  hipLaunchKernelGGL(k_recheck_rows_qsro, dim3(rows_grid), dim3(kRqThreads), 0, stream, ra, F);
   const unsigned dec_grid = (unsigned)std::min<int64_t>((std::max<int64_t>(1, max_entries) + 3) / 4, (int64_t)n_cu);
   hipLaunchKernelGGL(k_recheck_decide, dim3(dec_grid), dim3(256), 0, stream, ra);
 }

@@ -220,7 +220,9 @@ constexpr int kVariantXcd[kNumVariants] = {1, 0, 1, 0};
 
 template <int P, int GROUP>
 void launch_colour_mfma_g(smc_ctx *c, const MfmaArgs &a, int n_groups) {
-  int G = std::min(n_groups, c->n_cu);
+  // the qSRO evaluation holds no weights in LDS (34 KB per block) and 125 VGPRs: two blocks
+  // per CU (measured 1.31e9 against 0.95e9 attempts/s with one, 1.27e9 with four)
+  int G = std::min(n_groups, (P == kPQsro ? 2 : 1) * c->n_cu);
   if (G >= 8) G -= G % 8;
   hipLaunchKernelGGL((k_sweep_colour_mfma<P, GROUP>), dim3(std::max(G, 1)), dim3(kMfmaThreads), 0, c->stream, a);
 }
@@ -238,8 +240,9 @@ void launch_colour_mfma(smc_ctx *c, const MfmaArgs &a, int n_groups, int group) 
 int enqueue_sweep_mfma(smc_ctx *c, const smc_stats *st, bool trace) {
   const int R = (int)c->reps.size();
   const bool fp64 = c->cfg.precision == SMC_FP64;
-  const int P = fp64 ? SMC_FP32 : c->cfg.precision;
-  const DevPack &dp = c->packs[P];
+  const bool qsro = c->qsro_tiled;
+  const int P = qsro ? kPQsro : (fp64 ? SMC_FP32 : c->cfg.precision);
+  const DevPack &dp = c->packs[qsro ? 0 : P];  // unused for qSRO
   const int group = kVariantGroup[c->variant];
   const int gi = group == 16 ? 1 : 0;
   const int64_t qwords = (c->max_colours + 1) / 2;
@@ -251,7 +254,7 @@ int enqueue_sweep_mfma(smc_ctx *c, const smc_stats *st, bool trace) {
     a.reps = c->d_reps;
     a.occ = c->occ;
     a.ecache = c->ecache;
-    a.wpack = dp.dev;
+    a.wpack = qsro ? (const uint8_t *)c->d_w32 : dp.dev;  // qSRO: the folded FP32 coefficients
     a.reg_off = c->d_reg_off;
     a.om_off = c->d_om_off;
     a.idx = c->d_idx;
@@ -285,6 +288,7 @@ int enqueue_sweep_mfma(smc_ctx *c, const smc_stats *st, bool trace) {
       case SMC_FP32: launch_colour_mfma<kP32>(c, a, n_groups, group); break;
       case SMC_BF16: launch_colour_mfma<kPBF16>(c, a, n_groups, group); break;
       case SMC_BF16X3: launch_colour_mfma<kPBF16X3>(c, a, n_groups, group); break;
+      case kPQsro: launch_colour_mfma<kPQsro>(c, a, n_groups, group); break;
       default: launch_colour_mfma<kPFP8>(c, a, n_groups, group); break;
     }
     prof_end(c, ev, 0);
@@ -309,7 +313,10 @@ int enqueue_sweep_mfma(smc_ctx *c, const smc_stats *st, bool trace) {
       ra.trace_flags = st->trace_flags;
     }
     const int ev2 = prof_begin(c);
-    launch_recheck(ra, c->col_trials[col], c->n_cu, c->stream);
+    if (qsro)
+      launch_recheck_qsro(ra, c->d_w64, c->col_trials[col], c->n_cu, c->stream);
+    else
+      launch_recheck(ra, c->col_trials[col], c->n_cu, c->stream);
     prof_end(c, ev2, 1);
   }
   hipLaunchKernelGGL(k_next_sweep, dim3(1), dim3(64), 0, c->stream, c->d_sweep);
@@ -455,10 +462,9 @@ int run_sweep(smc_ctx *c, const smc_stats *st, bool last) {
     } else if ((rc = fcc::enqueue_sweep(c, st, trace))) {
       return rc;
     }
-  } else if (c->mfma) {
-    const int P = c->cfg.precision == SMC_FP64 ? SMC_FP32 : c->cfg.precision;
-    int rc = ensure_pack(c, P);
-    if (rc) return rc;
+  } else if (c->mfma || c->qsro_tiled) {
+    int rc = SMC_OK;
+    if (c->mfma && (rc = ensure_pack(c, c->cfg.precision == SMC_FP64 ? SMC_FP32 : c->cfg.precision))) return rc;
     if (c->strategy == SMC_STRATEGY_DOUBLE_LATTICE) {
       if ((rc = enqueue_sweep_dl(c, st, trace))) return rc;
     } else if (c->use_graph && !trace && !c->profiling) {
@@ -637,6 +643,7 @@ int smc_init(const smc_config *cfg, uint8_t *occ_dev, const float *params_dev, f
   c->occ = occ_dev;
   c->ecache = ecache_dev;
   c->mfma = mfma;
+  c->qsro_tiled = qsro && cfg->precision == SMC_FP32;
   c->n_in = cfg->feature == SMC_FEAT_COUNTS_S12 ? 12 : 108;
   c->hidden = cfg->hidden;
   c->n_params = c->hidden * c->n_in + c->hidden + c->hidden * c->hidden + c->hidden + c->hidden + 1;
@@ -730,6 +737,8 @@ int smc_init(const smc_config *cfg, uint8_t *occ_dev, const float *params_dev, f
       smc_destroy(c);
       return SMC_E_DEVICE;
     }
+  }
+  if (mfma || c->qsro_tiled) {
     const RegionTables t = build_region_tables();
     if (t.reg_off.empty()) return cleanup(SMC_E_DEVICE);
     c->queue_cap = max_trials;
@@ -1093,7 +1102,7 @@ int smc_use_graph(smc_ctx *c, int32_t enable) {
 
 int smc_autotune(smc_ctx *c, const char *cache_path, int32_t *chosen, float *ms_per_variant) {
   if (!c) return SMC_E_INVALID;
-  if (!c->mfma) {
+  if (!c->mfma && !c->qsro_tiled) {
     if (chosen) *chosen = c->variant;
     return SMC_OK;  // the per-lane path has a single variant
   }

@@ -12,7 +12,9 @@
 //      cached energies of the 40 zone sites, into registers, then into LDS with the two
 //      swapped species exchanged;
 //   energy (group g): the post-swap local energies of every zone site, 32 sites per
-//      matrix-core tile (mfma_eval.hpp), tiles claimed dynamically by the eight waves;
+//      matrix-core tile (mfma_eval.hpp), tiles claimed dynamically by the eight waves; for the
+//      qSRO model (Eq. 2, P = kPQsro) 64 sites per wave tile, one per lane, each counting its
+//      neighbours' species from the staged region (the per-lane evaluator's arithmetic);
 //   decide (group g): dE = sum over the zone of (new - cached) in a fixed order; trials with
 //      |dE - theta| inside the guard band go to a queue re-decided in FP64, the others are
 //      accepted iff dE <= theta;
@@ -30,6 +32,15 @@ constexpr int kReg = 192;
 constexpr int kOm = 40;
 constexpr int kIdxRow = 28;
 constexpr int kPart = 8;  // dE partial sums per trial
+constexpr int kPQsro = 4; // the qSRO model's evaluation in place of the MLP's precisions
+
+// Bytes of the evaluator's parameters in LDS: the packed MLP weights of a precision, or the
+// folded qSRO coefficients (kQsroPacked floats, padded to 16 bytes).
+template <int P>
+constexpr int smem_weight_bytes() {
+  if constexpr (P == kPQsro) return (kQsroPacked * 4 + 15) / 16 * 16;
+  else return pack_bytes<P>();
+}
 
 struct RecheckEntry {
   int64_t site;      // replica-local trial site
@@ -90,7 +101,7 @@ struct TrialBuf {
 
 template <int P, int GROUP>
 __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) {
-  constexpr int kW = pack_bytes<P>();
+  constexpr int kW = smem_weight_bytes<P>();
   __shared__ __attribute__((aligned(16))) uint8_t s_w[kW];
   __shared__ __attribute__((aligned(16))) uint8_t s_idx[8 * kOm * kIdxRow];
   __shared__ uint16_t s_roff[8 * kReg];
@@ -106,21 +117,27 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
-  for (int q = tid; q < kW / 16; q += kMfmaThreads) ((int4 *)s_w)[q] = ((const int4 *)a.wpack)[q];
+  if constexpr (P == kPQsro) {
+    for (int q = tid; q < kQsroPacked; q += kMfmaThreads) ((float *)s_w)[q] = ((const float *)a.wpack)[q];
+  } else {
+    for (int q = tid; q < kW / 16; q += kMfmaThreads) ((int4 *)s_w)[q] = ((const int4 *)a.wpack)[q];
+  }
   for (int q = tid; q < 8 * kOm * kIdxRow / 4; q += kMfmaThreads) ((int *)s_idx)[q] = ((const int *)a.idx)[q];
   for (int q = tid; q < 8 * kReg; q += kMfmaThreads) s_roff[q] = a.reg_off[q];
   for (int q = tid; q < 8 * kOm; q += kMfmaThreads) s_ooff[q] = a.om_off[q];
   if (tid < 16) s_rpos[tid] = a.reg_pos[tid];
-  EvalSmem S;
-  S.w = s_w;
-  S.c0 = (const float *)(s_w + PackSize<P>::kL0 + PackSize<P>::kL1);
-  S.c1 = S.c0 + kHid;
-  S.w2 = S.c1 + kHid;
-  S.b2 = a.b2;
-  S.k_scale_a0 = a.k_a0;
-  S.k_scale_a1 = a.k_a1;
-  S.k_scale_h = a.k_h;
-  S.sh = a.sh;
+  EvalSmem S{};
+  if constexpr (P != kPQsro) {
+    S.w = s_w;
+    S.c0 = (const float *)(s_w + PackSize<P>::kL0 + PackSize<P>::kL1);
+    S.c1 = S.c0 + kHid;
+    S.w2 = S.c1 + kHid;
+    S.b2 = a.b2;
+    S.k_scale_a0 = a.k_a0;
+    S.k_scale_a1 = a.k_a1;
+    S.k_scale_h = a.k_h;
+    S.sh = a.sh;
+  }
   const uint64_t sweep = *a.sweep;
 
   // Flattened groups of all participating replicas.  XCD-aware order: blocks b and b+8k
@@ -298,20 +315,29 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
     if (grp + gstep < gend) gather_issue(nxt);
     // ------------------------------------------------------------ energies (g)
     const int rows = nact * kOm;
-    const int ntiles = (rows + 31) / 32;
+    constexpr int kTileRows = P == kPQsro ? 64 : 32;
+    const int ntiles = (rows + kTileRows - 1) / kTileRows;
     for (;;) {
       int tile = 0;
       if (lane == 0) tile = atomicAdd(&s_tile, 1);
       tile = __shfl(tile, 0);
       if (tile >= ntiles) break;
-      const int row = tile * 32 + (lane & 31);
+      const int row = tile * kTileRows + (lane & (kTileRows - 1));
       const bool valid = row < rows;
       const int t = valid ? row / kOm : 0;
       const int k = valid ? row - t * kOm : 0;
       const uint8_t *irow = s_idx + (cur.dir[t] * kOm + k) * kIdxRow;
       const uint8_t *reg = s_reg + t * kReg;
-      const float E = eval_tile<P>(S, [&](int m) -> uint32_t { return reg[irow[m]]; });
-      if (valid && lane < 32) s_e[row] = E;
+      if constexpr (P == kPQsro) {
+        uint8_t slot[kSlots];
+#pragma unroll
+        for (int m = 0; m < kSlots; ++m) slot[m] = reg[irow[m]];
+        const float E = qsro_scalar<float>(slot, (const float *)s_w);
+        if (valid) s_e[row] = E;
+      } else {
+        const float E = eval_tile<P>(S, [&](int m) -> uint32_t { return reg[irow[m]]; });
+        if (valid && lane < 32) s_e[row] = E;
+      }
     }
     // ------------------------------------------------------------ proposal (g+2)
     // by the first wave that runs out of tiles (the others still finish theirs)

@@ -1,8 +1,11 @@
-"""The qSRO model (Eq. 2) through the C ABI on the per-lane path, against the oracle.
+"""The qSRO model (Eq. 2) through the C ABI, against the oracle: FP32 sweeps run in the tiled
+colour kernel (regions staged in LDS, per-lane qSRO evaluation, FP64 re-decision of the queue),
+FP64 sweeps on the per-lane path.
 
 Bar: site energies within 1e-12 (FP64) and 1e-6 eV (FP32) of the oracle; sweeps bit-exact with
 the oracle under the same Philox stream, decisions equal except within 1e-9 eV of the
-threshold (FP32 dE within 1e-6 eV), FP64 running totals equal the from-scratch total."""
+threshold (FP32 dE within 1e-6 eV); running totals equal the from-scratch total up to the
+random walk of the per-trial dE error."""
 import numpy as np
 import pytest
 
@@ -46,21 +49,29 @@ def test_qsro_sweeps_bit_exact(precision, cells, S):
     mc, model, occ = _make(cells, S, precision, T=T)
     _banner(f"qSRO {precision} {cells} S={S}")
     counts0 = np.bincount(occ, minlength=S)
+    accepts = 0
+    max_err = 0.0
     for t in range(8):
         tr = trace_to_numpy(mc.sweep(1, stats=True, trace=True))
         gocc = mc.occ.cpu().numpy()
         assert np.array_equal(np.bincount(gocc, minlength=S), counts0)
-        compare_sweep(cells, model, occ, T, 7, t, tr, gocc, de_tol=1e-6)
+        _, otr = compare_sweep(cells, model, occ, T, 7, t, tr, gocc, de_tol=1e-6)
+        accepts += int(tr["accepts"][0])
+        d = otr["same"] == 0
+        max_err = max(max_err, float(np.abs(tr["dE"][d] - otr["dE"][d]).max(initial=0.0)))
     es, er = mc.energy()
     assert es[0] == pytest.approx(oracle.total_energy(cells, model, occ), abs=1e-9)
-    assert abs(es[0] - er[0]) < 1e-6
+    # the running total adds each accepted swap's deciding dE, so it drifts from the from-scratch
+    # total like a random walk of the per-trial dE error (exactly equal in FP64)
+    assert abs(es[0] - er[0]) <= 10.0 * max_err * np.sqrt(max(accepts, 1)) + 1e-9 * abs(es[0])
     mc.close()
 
 
 @pytest.mark.parametrize("model_name", ["qsro", "counts"])
-def test_scalar_path_batch_matches_oracle_per_replica(model_name):
-    """Replicas of different shapes and temperatures in one context on the scalar path (one
-    launch per colour over every replica that has it, each block serving one replica): every
+def test_batch_matches_oracle_per_replica(model_name):
+    """Replicas of different shapes and temperatures in one context, one launch per colour over
+    every replica that has it (qSRO: the tiled colour kernel, groups of link cells mapped to
+    their replica; counts model: the per-lane path, each block serving one replica): every
     replica equals the oracle's own sweeps of that replica."""
     need_gpu()
     import paper_2604_08250_amd as smc
@@ -70,7 +81,7 @@ def test_scalar_path_batch_matches_oracle_per_replica(model_name):
     S = 5 if qsro else 4
     P = synth.qsro_params(S) if qsro else synth.mlp_params(12, 64)
     occs = [synth.random_occupancy(c, S, None, seed=300 + r) for r, c in enumerate(cells)]
-    _banner(f"scalar-path batch {model_name}: {len(cells)} replicas")
+    _banner(f"batch {model_name}: {len(cells)} replicas")
     mc = smc.SwapMC(cells, temps, np.concatenate(occs), P, n_species=S, feature=2 if qsro else 0,
                     hidden=0 if qsro else 64, precision="fp32", seed=11)
     st = mc.sweep(3, stats=True)
