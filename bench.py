@@ -246,8 +246,9 @@ def measure_double_lattice(workload, precision, steps=1, warmup=0):
 
 
 def measure_qsro(workload, steps=2, warmup=1):
-    """The qSRO model (Eq. 2) on the headline lattice: per-lane evaluator (neighbour counts
-    and a quadratic per site, no matrix products), FP32 with the FP64 re-decision band."""
+    """The qSRO model (Eq. 2) on the headline lattice in FP32 with the FP64 re-decision band:
+    the tiled colour kernel (each trial's region staged in LDS) evaluating neighbour counts and
+    a quadratic per zone site, one site per lane, no matrix products."""
     import torch
 
     import synth
