@@ -31,7 +31,7 @@ struct FccState {
   fcc::QEntry *d_queue = nullptr;    // [cap]
   double *d_rowe = nullptr;          // [cap][56] FP64 zone energies of queued MLPNet trials
   uint32_t *d_done = nullptr;        // [cap] blocks finished per queued trial, zero between uses
-  uint32_t *d_counts = nullptr;      // active trials, queued trials (one 64-bit word)
+  uint32_t *d_counts = nullptr;      // [replica colours] active trials, queued trials (one 64-bit word each)
   int64_t cap = 0;                   // largest trial count of a colour
   uint8_t *d_pack[4] = {nullptr, nullptr, nullptr, nullptr};  // FP32, BF16, split BF16, FP8 weight images
   bool pack_ready[4] = {false, false, false, false};

@@ -339,10 +339,15 @@ inline int enqueue_sweep(smc_ctx *c, const smc_stats *st, bool trace) {
   const int R = (int)c->reps.size();
   const bool fp64 = c->cfg.precision == SMC_FP64;
   const int P = fp64 ? SMC_FP32 : c->cfg.precision;
+  // one pair of counters (active, queued) per replica colour, all cleared here, so that no
+  // colour waits on a clearing launch of its own
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(c->colours_total, 256)), dim3(256), 0, c->stream,
+                     (uint64_t *)f.d_counts, (int64_t)c->colours_total, (uint64_t)0);
+  int slot = 0;
   for (int r = 0; r < R; ++r) {
     const Replica &rep = c->reps[r];
     const int64_t nt = std::max<int64_t>(1, rep.n_trials);
-    for (int col = 0; col < rep.n_colours; ++col) {
+    for (int col = 0; col < rep.n_colours; ++col, ++slot) {
       Args a{};
       a.reps = c->d_reps;
       a.r = r;
@@ -353,12 +358,12 @@ inline int enqueue_sweep(smc_ctx *c, const smc_stats *st, bool trace) {
       a.ecache = c->ecache;
       a.trials = f.d_trials;
       a.active = f.d_active;
-      a.n_active = f.d_counts;
+      a.n_active = f.d_counts + 2 * slot;
       a.e1 = f.d_e1;
       a.om = f.d_om;
       a.om_n = f.om_n;
       a.guard = fp64 ? (double)INFINITY : c->guard;
-      a.q_count = f.d_counts + 1;
+      a.q_count = f.d_counts + 2 * slot + 1;
       a.queue = f.d_queue;
       a.e_fixed = c->d_efixed;
       a.counters = c->d_counters;
@@ -368,7 +373,6 @@ inline int enqueue_sweep(smc_ctx *c, const smc_stats *st, bool trace) {
         a.trace_dE_fast = st->trace_dE_fast;
         a.trace_flags = st->trace_flags;
       }
-      hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, c->stream, (uint64_t *)f.d_counts, (int64_t)1, (uint64_t)0);
       hipLaunchKernelGGL(k_propose, dim3(grid_for(nt, kPhaseThreads)), dim3(kPhaseThreads), 0, c->stream, a);
       const int ev = prof_begin(c);
       if (f.model == 1) {
@@ -562,7 +566,7 @@ inline int create(const smc_config *cfg, uint8_t *occ_dev, const float *params_d
             hipMalloc(&f.d_active, sizeof(int32_t) * f.cap) == hipSuccess &&
             hipMalloc(&f.d_e1, sizeof(float) * f.cap * f.om_n) == hipSuccess &&
             hipMalloc(&f.d_queue, sizeof(QEntry) * f.cap) == hipSuccess &&
-            hipMalloc(&f.d_counts, sizeof(uint64_t)) == hipSuccess &&
+            hipMalloc(&f.d_counts, sizeof(uint64_t) * c->colours_total) == hipSuccess &&
             (model != 0 || (hipMalloc(&f.d_rowe, sizeof(double) * 2 * kOmMlp * f.cap) == hipSuccess &&
                             hipMalloc(&f.d_done, sizeof(uint32_t) * f.cap) == hipSuccess &&
                             hipMemset(f.d_done, 0, sizeof(uint32_t) * f.cap) == hipSuccess));
