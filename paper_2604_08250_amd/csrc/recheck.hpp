@@ -4,10 +4,11 @@
 // and the apply.
 //
 // Two launches per colour.  k_recheck_rows evaluates the 80 FP64 local energies of every
-// queued trial (rows 0..39: the zone after the swap, 40..79: before), 16 rows per block, so
-// that even a short queue spreads over the whole GPU; k_recheck_decide then reduces each
-// trial's rows in zone order, decides and applies.  The kernel boundary between them orders
-// the row energies before their use, with no device-scope fence.
+// queued trial (rows 0..39: the zone after the swap, 40..79: before) on the FP64 matrix cores,
+// 16 rows per half block, so that even a short queue spreads over the whole GPU (for the qSRO
+// model, k_recheck_rows_qsro: one row per thread); k_recheck_decide then reduces each trial's
+// rows in zone order, decides and applies.  The kernel boundary between them orders the row
+// energies before their use, with no device-scope fence.
 #pragma once
 #include <algorithm>
 
