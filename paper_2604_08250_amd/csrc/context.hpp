@@ -32,6 +32,9 @@ struct FccState {
   double *d_rowe = nullptr;          // [cap][56] FP64 zone energies of queued MLPNet trials
   uint32_t *d_done = nullptr;        // [cap] blocks finished per queued trial, zero between uses
   uint32_t *d_counts = nullptr;      // [replica colours] active trials, queued trials (one 64-bit word each)
+  uint16_t *d_rq_off = nullptr;      // qSRO: [12][304] read-region offsets per partner slot
+  uint16_t *d_rq_idx = nullptr;      // qSRO: [12][60][43] region position of each zone row's slots
+  uint16_t *d_rq_pos = nullptr;      // qSRO: [12][2] region positions of the trial site and partner
   int64_t cap = 0;                   // largest trial count of a colour
   uint8_t *d_pack[4] = {nullptr, nullptr, nullptr, nullptr};  // FP32, BF16, split BF16, FP8 weight images
   bool pack_ready[4] = {false, false, false, false};

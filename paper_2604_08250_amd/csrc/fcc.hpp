@@ -33,6 +33,7 @@ constexpr int kDirs = 12;       // nearest neighbours = swap partners
 constexpr int kOmMlp = 28;      // |Omega| with shells 1-2
 constexpr int kOmQsro = 60;     // |Omega| with shells 1-3
 constexpr int kOmMax = 60;
+constexpr int kRegQ = 304;      // read region of a qSRO trial: the zone and its shells 1-3
 constexpr int kHid = 96;
 constexpr int kMT = 3;          // M-tiles of 32 hidden units
 constexpr int kIn = 76;         // 19 slots x 4 channels
@@ -646,35 +647,70 @@ __global__ __launch_bounds__(net_threads<P>(), 2) void k_rows_net(Args a, const 
   }
 }
 
-// Post-swap qSRO energies (FP32, one row per lane).
-__global__ __launch_bounds__(256) void k_rows_qsro(Args a, const float *F) {
-  __shared__ int32_t s_off[4 * 44];
+// Post-swap qSRO energies (FP32): a block stages the read regions of kRqTrials active trials in
+// LDS (304 sites each, the swapped pair exchanged, one byte load per site instead of one per
+// zone row and slot), then evaluates their 60 zone rows from LDS, one row per thread, with the
+// per-lane arithmetic.  The region tables (offsets per partner slot, and the region position of
+// every zone row's slot) stay in LDS for the whole launch.
+constexpr int kRqTrials = 16;
+constexpr int kRqThreads = 1024;  // 960 rows per pass, one per thread (measured: 256 threads 3.8e8,
+                                  // 512 threads 4.8e8, 1024 threads 5.3e8 attempts/s on 200^3)
+__global__ __launch_bounds__(kRqThreads) void k_rows_qsro(Args a, const float *F, const uint16_t *roff,
+                                                          const uint16_t *ridx, const uint16_t *rpos) {
+  __shared__ __attribute__((aligned(16))) uint16_t s_idx[kDirs * kOmQsro * (kNbr + 1)];
+  __shared__ uint16_t s_roff[kDirs * kRegQ];
+  __shared__ uint16_t s_rpos[2 * kDirs];
+  __shared__ uint8_t s_reg[kRqTrials * kRegQ];
+  __shared__ float s_F[kQsroPacked];
+  __shared__ int32_t s_site[kRqTrials], s_part[kRqTrials];
+  __shared__ int16_t s_px[kRqTrials], s_py[kRqTrials], s_pz[kRqTrials];
+  __shared__ uint8_t s_dir[kRqTrials];
   const Replica R = a.reps[a.r];
-  fill_offsets<44, kNbr>(s_off, R);
-  __syncthreads();
   const uint8_t *occ = a.occ + R.site0;
-  const int32_t rows = (int32_t)(*a.n_active) * kOmQsro;  // below 2^31: trials x 60 of one colour
-  for (int32_t row = blockIdx.x * blockDim.x + threadIdx.x; row < rows; row += gridDim.x * blockDim.x) {
-    const int32_t slot = row / kOmQsro;
-    const int k = row - slot * kOmQsro;
-    const Trial tr = a.trials[a.active[slot]];
-    const int32_t i = (int32_t)tr.site, n = (int32_t)tr.partner;
-    const uint32_t si = occ[i], sn = occ[n];
-    const Pos pj = zone_pos(trial_pos(tr), a.om + (tr.dir * kOmMax + k) * 3, R);
-    const int32_t base = index(pj, R.L[0], R.L[1]);
-    float e;
-    if (interior(pj, R)) {
-      const int32_t *o = s_off + 44 * (((pj.x & 1) << 1) | (pj.y & 1));
-      e = qsro_site<float>([&](int k2) -> int { return (int)swapped(occ, base + o[k2 + 1], i, n, si, sn); }, F);
-    } else {
-      e = qsro_site<float>(
-          [&](int k2) -> int {
-            const int32_t s = k2 < 0 ? base : at(pj, dx(k2), dy(k2), dz(k2), R.L[0], R.L[1], R.L[2]);
-            return (int)swapped(occ, s, i, n, si, sn);
-          },
-          F);
+  const int tid = threadIdx.x;
+  const int32_t ntr = (int32_t)(*a.n_active);
+  if ((int32_t)blockIdx.x * kRqTrials >= ntr) return;  // no trial for this block
+  static_assert((kDirs * kOmQsro * (kNbr + 1)) % 2 == 0, "idx table in 4-byte words");
+  for (int q = tid; q < kDirs * kOmQsro * (kNbr + 1) / 2; q += kRqThreads)
+    ((uint32_t *)s_idx)[q] = ((const uint32_t *)ridx)[q];
+  for (int q = tid; q < kDirs * kRegQ; q += kRqThreads) s_roff[q] = roff[q];
+  if (tid < 2 * kDirs) s_rpos[tid] = rpos[tid];
+  for (int q = tid; q < kQsroPacked; q += kRqThreads) s_F[q] = F[q];
+  for (int32_t b0 = (int32_t)blockIdx.x * kRqTrials; b0 < ntr; b0 += (int32_t)gridDim.x * kRqTrials) {
+    if (tid < kRqTrials && b0 + tid < ntr) {
+      const Trial tr = a.trials[a.active[b0 + tid]];
+      s_site[tid] = tr.site;
+      s_part[tid] = tr.partner;
+      s_px[tid] = tr.px;
+      s_py[tid] = tr.py;
+      s_pz[tid] = tr.pz;
+      s_dir[tid] = (uint8_t)tr.dir;
     }
-    a.e1[row] = e;
+    __syncthreads();
+    // regions: the trial site holds the partner's species and the partner the site's
+    for (int v = tid; v < kRqTrials * kRegQ; v += kRqThreads) {
+      const int tt = v / kRegQ, p = v - tt * kRegQ;
+      if (b0 + tt < ntr) {
+        const int d = s_dir[tt];
+        const uint32_t o = s_roff[d * kRegQ + p];
+        const Pos pi{s_px[tt], s_py[tt], s_pz[tt]};
+        int32_t s = at(pi, (int)(o & 15u) - 8, (int)((o >> 4) & 15u) - 8, (int)((o >> 8) & 15u) - 8, R.L[0], R.L[1],
+                       R.L[2]);
+        if (p == s_rpos[2 * d]) s = s_part[tt];
+        else if (p == s_rpos[2 * d + 1]) s = s_site[tt];
+        s_reg[v] = occ[s];
+      }
+    }
+    __syncthreads();
+    for (int r = tid; r < kRqTrials * kOmQsro; r += kRqThreads) {
+      const int tt = r / kOmQsro, k = r - tt * kOmQsro;
+      if (b0 + tt < ntr) {
+        const uint16_t *ir = s_idx + (s_dir[tt] * kOmQsro + k) * (kNbr + 1);
+        const uint8_t *reg = s_reg + tt * kRegQ;
+        a.e1[(int64_t)(b0 + tt) * kOmQsro + k] = qsro_site<float>([&](int k2) -> int { return reg[ir[k2 + 1]]; }, s_F);
+      }
+    }
+    __syncthreads();
   }
 }
 

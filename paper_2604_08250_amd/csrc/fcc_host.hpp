@@ -195,6 +195,42 @@ inline int zone_table(int n_nbr, std::vector<int8_t> &out) {
   return count;
 }
 
+// Read region of a qSRO trial with partner slot d: every zone site and its 42 neighbours, in the
+// order first met walking the zone (om, the table above) and each site's slots (centre, then
+// neighbours 0..41).  off: [12][kRegQ] offsets packed as (dx + 8) | (dy + 8) << 4 | (dz + 8) << 8;
+// idx: [12][60][43] region position of zone row k's slot m; pos: [12][2] positions of the trial
+// site (offset 0) and the partner (offset of slot d).  Returns false if a region size differs
+// from kRegQ.
+inline bool qsro_region_tables(const std::vector<int8_t> &om, std::vector<uint16_t> &off, std::vector<uint16_t> &idx,
+                               std::vector<uint16_t> &pos) {
+  off.assign((size_t)kDirs * kRegQ, 0);
+  idx.assign((size_t)kDirs * kOmQsro * (kNbr + 1), 0);
+  pos.assign((size_t)kDirs * 2, 0);
+  for (int d = 0; d < kDirs; ++d) {
+    std::vector<std::array<int, 3>> reg;
+    auto find = [&](const std::array<int, 3> &v) -> int {
+      for (size_t q = 0; q < reg.size(); ++q)
+        if (reg[q] == v) return (int)q;
+      reg.push_back(v);
+      return (int)reg.size() - 1;
+    };
+    for (int k = 0; k < kOmQsro; ++k) {
+      const int8_t *o = &om[((size_t)d * kOmMax + k) * 3];
+      for (int m = 0; m <= kNbr; ++m) {
+        const std::array<int, 3> v = {o[0] + (m ? dx(m - 1) : 0), o[1] + (m ? dy(m - 1) : 0), o[2] + (m ? dz(m - 1) : 0)};
+        idx[((size_t)d * kOmQsro + k) * (kNbr + 1) + m] = (uint16_t)find(v);
+      }
+    }
+    if ((int)reg.size() != kRegQ) return false;
+    for (int q = 0; q < kRegQ; ++q)
+      off[(size_t)d * kRegQ + q] = (uint16_t)((reg[q][0] + 8) | ((reg[q][1] + 8) << 4) | ((reg[q][2] + 8) << 8));
+    pos[2 * d] = (uint16_t)find({0, 0, 0});
+    pos[2 * d + 1] = (uint16_t)find({dx(d), dy(d), dz(d)});
+    if ((int)reg.size() != kRegQ) return false;  // both are zone sites, already present
+  }
+  return true;
+}
+
 inline int ensure_pack(smc_ctx *c, int P) {
   FccState &f = c->fcc;
   if (f.pack_ready[P]) return SMC_OK;
@@ -376,8 +412,10 @@ inline int enqueue_sweep(smc_ctx *c, const smc_stats *st, bool trace) {
       hipLaunchKernelGGL(k_propose, dim3(grid_for(nt, kPhaseThreads)), dim3(kPhaseThreads), 0, c->stream, a);
       const int ev = prof_begin(c);
       if (f.model == 1) {
-        const unsigned g = (unsigned)std::min<int64_t>(grid_for(nt * kOmQsro, 256), 8 * (int64_t)c->n_cu);
-        hipLaunchKernelGGL(k_rows_qsro, dim3(g), dim3(256), 0, c->stream, a, (const float *)c->d_w32);
+        // 75 KB of LDS per block: at most two blocks per CU
+        const unsigned g = (unsigned)std::min<int64_t>((nt + kRqTrials - 1) / kRqTrials, 2 * (int64_t)c->n_cu);
+        hipLaunchKernelGGL(k_rows_qsro, dim3(g), dim3(kRqThreads), 0, c->stream, a, (const float *)c->d_w32, f.d_rq_off,
+                           f.d_rq_idx, f.d_rq_pos);
       } else if (P == SMC_FP32) {
         launch_rows_net<kP32>(c, a, nt);
       } else if (P == SMC_BF16) {
@@ -487,7 +525,8 @@ inline int delta_e64(smc_ctx *c, int32_t replica, uint64_t sweep, const int64_t 
 inline void release(smc_ctx *c) {
   FccState &f = c->fcc;
   void *bufs[] = {f.d_om,     f.d_trials, f.d_active,  f.d_e1,      f.d_queue,  f.d_counts,
-                  f.d_rowe,   f.d_done,   f.d_pack[0], f.d_pack[1], f.d_pack[2], f.d_pack[3]};
+                  f.d_rowe,   f.d_done,   f.d_pack[0], f.d_pack[1], f.d_pack[2], f.d_pack[3],
+                  f.d_rq_off, f.d_rq_idx, f.d_rq_pos};
   for (void *p : bufs)
     if (p) (void)hipFree(p);
 }
@@ -577,6 +616,18 @@ inline int create(const smc_config *cfg, uint8_t *occ_dev, const float *params_d
       hipMemcpyAsync(f.d_om, om.data(), om.size(), hipMemcpyHostToDevice, c->stream) ||
       hipStreamSynchronize(c->stream))
     return cleanup(SMC_E_DEVICE);
+  if (model == 1) {
+    std::vector<uint16_t> roff, ridx, rpos;
+    if (!qsro_region_tables(om, roff, ridx, rpos)) return cleanup(SMC_E_DEVICE);
+    if (hipMalloc(&f.d_rq_off, sizeof(uint16_t) * roff.size()) != hipSuccess ||
+        hipMalloc(&f.d_rq_idx, sizeof(uint16_t) * ridx.size()) != hipSuccess ||
+        hipMalloc(&f.d_rq_pos, sizeof(uint16_t) * rpos.size()) != hipSuccess)
+      return cleanup(SMC_E_NOMEM);
+    if (hipMemcpy(f.d_rq_off, roff.data(), sizeof(uint16_t) * roff.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(f.d_rq_idx, ridx.data(), sizeof(uint16_t) * ridx.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(f.d_rq_pos, rpos.data(), sizeof(uint16_t) * rpos.size(), hipMemcpyHostToDevice) != hipSuccess)
+      return cleanup(SMC_E_DEVICE);
+  }
   hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(4 * R, 256)), dim3(256), 0, c->stream, c->d_counters, (int64_t)4 * R,
                      (uint64_t)0);
   int rc = load_params(c, params_dev);
