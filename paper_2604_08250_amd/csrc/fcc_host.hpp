@@ -195,16 +195,16 @@ inline int zone_table(int n_nbr, std::vector<int8_t> &out) {
   return count;
 }
 
-// Read region of a qSRO trial with partner slot d: every zone site and its 42 neighbours, in the
-// order first met walking the zone (om, the table above) and each site's slots (centre, then
-// neighbours 0..41).  off: [12][kRegQ] offsets packed as (dx + 8) | (dy + 8) << 4 | (dz + 8) << 8;
-// idx: [12][60][43] region position of zone row k's slot m; pos: [12][2] positions of the trial
-// site (offset 0) and the partner (offset of slot d).  Returns false if a region size differs
-// from kRegQ.
-inline bool qsro_region_tables(const std::vector<int8_t> &om, std::vector<uint16_t> &off, std::vector<uint16_t> &idx,
-                               std::vector<uint16_t> &pos) {
-  off.assign((size_t)kDirs * kRegQ, 0);
-  idx.assign((size_t)kDirs * kOmQsro * (kNbr + 1), 0);
+// Read region of a trial with partner slot d: every zone site and its first n_nbr neighbours, in
+// the order first met walking the zone (om, the table above: n_om sites) and each site's slots
+// (centre, then neighbours 0..n_nbr-1).  off: [12][n_reg] offsets packed as (dx + 8) |
+// (dy + 8) << 4 | (dz + 8) << 8; idx: [12][n_om][n_nbr + 1] region position of zone row k's
+// slot m; pos: [12][2] positions of the trial site (offset 0) and the partner (offset of slot
+// d).  Returns false if a region size differs from n_reg.
+inline bool region_tables(const std::vector<int8_t> &om, int n_om, int n_nbr, int n_reg, std::vector<uint16_t> &off,
+                          std::vector<uint16_t> &idx, std::vector<uint16_t> &pos) {
+  off.assign((size_t)kDirs * n_reg, 0);
+  idx.assign((size_t)kDirs * n_om * (n_nbr + 1), 0);
   pos.assign((size_t)kDirs * 2, 0);
   for (int d = 0; d < kDirs; ++d) {
     std::vector<std::array<int, 3>> reg;
@@ -214,19 +214,18 @@ inline bool qsro_region_tables(const std::vector<int8_t> &om, std::vector<uint16
       reg.push_back(v);
       return (int)reg.size() - 1;
     };
-    for (int k = 0; k < kOmQsro; ++k) {
+    for (int k = 0; k < n_om; ++k) {
       const int8_t *o = &om[((size_t)d * kOmMax + k) * 3];
-      for (int m = 0; m <= kNbr; ++m) {
+      for (int m = 0; m <= n_nbr; ++m) {
         const std::array<int, 3> v = {o[0] + (m ? dx(m - 1) : 0), o[1] + (m ? dy(m - 1) : 0), o[2] + (m ? dz(m - 1) : 0)};
-        idx[((size_t)d * kOmQsro + k) * (kNbr + 1) + m] = (uint16_t)find(v);
+        idx[((size_t)d * n_om + k) * (n_nbr + 1) + m] = (uint16_t)find(v);
       }
     }
-    if ((int)reg.size() != kRegQ) return false;
-    for (int q = 0; q < kRegQ; ++q)
-      off[(size_t)d * kRegQ + q] = (uint16_t)((reg[q][0] + 8) | ((reg[q][1] + 8) << 4) | ((reg[q][2] + 8) << 8));
-    pos[2 * d] = (uint16_t)find({0, 0, 0});
+    pos[2 * d] = (uint16_t)find({0, 0, 0});            // zone sites: already present
     pos[2 * d + 1] = (uint16_t)find({dx(d), dy(d), dz(d)});
-    if ((int)reg.size() != kRegQ) return false;  // both are zone sites, already present
+    if ((int)reg.size() != n_reg) return false;
+    for (int q = 0; q < n_reg; ++q)
+      off[(size_t)d * n_reg + q] = (uint16_t)((reg[q][0] + 8) | ((reg[q][1] + 8) << 4) | ((reg[q][2] + 8) << 8));
   }
   return true;
 }
@@ -618,7 +617,7 @@ inline int create(const smc_config *cfg, uint8_t *occ_dev, const float *params_d
     return cleanup(SMC_E_DEVICE);
   if (model == 1) {
     std::vector<uint16_t> roff, ridx, rpos;
-    if (!qsro_region_tables(om, roff, ridx, rpos)) return cleanup(SMC_E_DEVICE);
+    if (!region_tables(om, kOmQsro, kNbr, kRegQ, roff, ridx, rpos)) return cleanup(SMC_E_DEVICE);
     if (hipMalloc(&f.d_rq_off, sizeof(uint16_t) * roff.size()) != hipSuccess ||
         hipMalloc(&f.d_rq_idx, sizeof(uint16_t) * ridx.size()) != hipSuccess ||
         hipMalloc(&f.d_rq_pos, sizeof(uint16_t) * rpos.size()) != hipSuccess)
