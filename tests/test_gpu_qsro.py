@@ -96,3 +96,33 @@ def test_batch_matches_oracle_per_replica(model_name):
             oracle.sweep(cells[r], model, ref, temps[r], 11, r, t, nthreads=8)
         assert np.array_equal(got[offs[r]:offs[r + 1]], ref), f"replica {r}"
     mc.close()
+
+
+def test_qsro_graph_replay_equals_per_launch():
+    """FP32 qSRO sweeps run in the captured colour-kernel path: replays of the captured sweep
+    over uneven replicas, with eager work between them, equal the per-launch sweeps after every
+    replay (occupancy, energy cache, counters, running energies)."""
+    need_gpu()
+    import paper_2604_08250_amd as smc
+    cells = [(8, 8, 8), (9, 10, 13), (12, 12, 12)]
+    temps = [600.0, 1200.0, 2500.0]
+    P = synth.qsro_params(5)
+    occ = np.concatenate([synth.random_occupancy(c, 5, None, seed=40 + r) for r, c in enumerate(cells)])
+    _banner("qSRO graph vs per-launch")
+    runs = []
+    for graph in (True, False):
+        mc = smc.SwapMC(cells, temps, occ, P, n_species=5, feature=2, hidden=0, precision="fp32", seed=13)
+        mc.use_graph(graph)
+        runs.append(mc)
+    g, e = runs
+    for t in range(5):
+        g.sweep(1)
+        e.sweep(1)
+        _ = g.site_energies("fp64")  # eager work between replays
+        sg, se = g.energy(), e.energy()
+        assert np.array_equal(g.occ.cpu().numpy(), e.occ.cpu().numpy()), f"sweep {t}: occupancy"
+        assert np.array_equal(g.ecache.cpu().numpy(), e.ecache.cpu().numpy()), f"sweep {t}: energy cache"
+        assert np.array_equal(g.counters(), e.counters()), f"sweep {t}: counters"
+        assert np.array_equal(sg[1], se[1]), f"sweep {t}: running energies"
+    g.close()
+    e.close()
