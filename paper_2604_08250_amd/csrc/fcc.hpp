@@ -940,27 +940,23 @@ __global__ void k_site_energies_qsro(const Replica *reps, int32_t r, const uint8
       [&](int k) -> int { return k < 0 ? occ[j] : occ[at(p, dx(k), dy(k), dz(k), R.L[0], R.L[1], R.L[2])]; }, F);
 }
 
-// FP64 re-decision of queued trials (MLPNet): the zone's 28 local energies after and 28
-// before the swap, split over kRcSplit blocks of 14 rows (one 16-row matrix-product tile) so
-// that a short queue still spreads over the chip.  Each block writes its rows to row_e; the block that completes a trial (per
-// trial counter) sums the two zone halves in zone order, decides and applies.  No block waits
-// for another.  The cache keeps the sweep precision's post-swap energies.
+// FP64 re-decision of queued trials (MLPNet), first launch: the zone's 28 local energies after
+// and 28 before the swap, split over kRcSplit work items of 14 rows (one 16-row matrix-product
+// tile) so that a short queue still spreads over the chip; each writes its rows to row_e.
+// k_recheck_net_decide sums, decides and applies.
 constexpr int kRcSplit = 4;
 constexpr int kRcRows = 2 * kOmMlp / kRcSplit;  // 14
 static_assert(kRcRows <= 16 && (kR64Threads / 64) * 16 == kHid, "one 16-row tile; one 16-unit tile per wave");
 static_assert(kRcRows * kRcSplit == 2 * kOmMlp, "row split");
 
-__global__ __launch_bounds__(kR64Threads) void k_recheck_net(Args a, const float *W32, double *row_e,
-                                                            uint32_t *done) {
+__global__ __launch_bounds__(kR64Threads) void k_recheck_net(Args a, const float *W32, double *row_e) {
   // the blob's values in LDS (FP32 numbers, exact: W32 is the FP64 blob rounded to FP32, which
   // changes nothing), loaded in one batch of 16-byte loads: the queue is short, so each block's
   // latency is the kernel's time and weight reads must not go to L2 per layer
   __shared__ __attribute__((aligned(16))) float s_w[kNetParamsDev];
   __shared__ double s_h[16 * kHS];
   __shared__ double s_out[16];
-  __shared__ double s_re[2 * kOmMlp];
   __shared__ uint8_t s_sp[kRcRows * kSlots];
-  __shared__ int s_last, s_accept;
   const Replica R = a.reps[a.r];
   uint8_t *occ = a.occ + R.site0;
   const uint32_t nq = *a.q_count;
@@ -989,46 +985,57 @@ __global__ __launch_bounds__(kR64Threads) void k_recheck_net(Args a, const float
     __syncthreads();
     net64_rows16(s_w, s_sp, kRcRows, s_h, s_out);
     if (tid < kRcRows) row_e[(size_t)q * 2 * kOmMlp + r0 + tid] = s_out[tid];
-    __threadfence();
     __syncthreads();
-    if (tid == 0) s_last = atomicAdd(&done[q], 1u) == kRcSplit - 1;
-    __syncthreads();
-    if (s_last) {
-      __threadfence();
-      // the 56 row energies, one load per thread, then summed in row order
-      if (tid < 2 * kOmMlp)
-        s_re[tid] = __hip_atomic_load(row_e + (size_t)q * 2 * kOmMlp + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __syncthreads();
-      if (tid == 0) {
-        double e1 = 0.0, e0 = 0.0;
-        for (int k = 0; k < kOmMlp; ++k) e1 += s_re[k];
-        for (int k = 0; k < kOmMlp; ++k) e0 += s_re[kOmMlp + k];
-        done[q] = 0;  // ready for the next use of this queue slot
-        const double dE = e1 - e0;
-        bool accept = false;
-        if (a.probe_dE) {
-          a.probe_dE[q] = dE;
-        } else {
-          accept = dE <= tr.theta;
-          const int Rn = a.n_replicas;
-          if (accept) {
-            occ[i] = (uint8_t)sn;
-            occ[n] = (uint8_t)si;
-            atomicAdd(&a.e_fixed[a.r], (unsigned long long)to_fixed(dE));
-            atomicAdd((unsigned long long *)&a.counters[2 * Rn + a.r], 1ull);
-          }
-          atomicAdd((unsigned long long *)&a.counters[3 * Rn + a.r], 1ull);
-          if (a.trace_flags) a.trace_flags[R.site0 + i] = kFlagFp64 | (accept ? kFlagAccept : 0);
-          if (a.trace_dE) a.trace_dE[R.site0 + i] = dE;
-        }
-        s_accept = accept;
-      }
-      __syncthreads();
-      if (tid < kOmMlp && s_accept)
-        a.ecache[R.site0 + at(pi, o[3 * tid], o[3 * tid + 1], o[3 * tid + 2], R.L[0], R.L[1], R.L[2])] =
-            a.e1[(int64_t)qe.slot * kOmMlp + tid];
+  }
+}
+
+// Decision of the queued MLPNet trials after k_recheck_net (the kernel boundary orders the rows),
+// one wave per trial: the 56 row energies loaded by 56 lanes and summed in row order (rows
+// 0..27 after the swap, 28..55 before), the Metropolis decision and the apply (or, for a probe,
+// dE only).
+__global__ __launch_bounds__(256) void k_recheck_net_decide(Args a, const double *row_e) {
+  const Replica R = a.reps[a.r];
+  uint8_t *occ = a.occ + R.site0;
+  const uint32_t nq = *a.q_count;
+  const int lane = threadIdx.x & 63;
+  const uint32_t waves = gridDim.x * (blockDim.x / 64);
+  for (uint32_t q = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); q < nq; q += waves) {
+    const QEntry qe = a.queue[q];
+    const Trial tr = a.trials[a.active[qe.slot]];
+    const double *re = row_e + (size_t)q * 2 * kOmMlp;
+    const double v1 = lane < kOmMlp ? re[lane] : 0.0, v0 = lane < kOmMlp ? re[kOmMlp + lane] : 0.0;
+    double e1 = 0.0, e0 = 0.0;
+#pragma unroll
+    for (int k = 0; k < kOmMlp; ++k) e1 += __shfl(v1, k);
+#pragma unroll
+    for (int k = 0; k < kOmMlp; ++k) e0 += __shfl(v0, k);
+    const double dE = e1 - e0;
+    if (a.probe_dE) {
+      if (lane == 0) a.probe_dE[q] = dE;
+      continue;
     }
-    __syncthreads();
+    const bool accept = dE <= tr.theta;
+    const int Rn = a.n_replicas;
+    if (lane == 0) {
+      const int64_t i = tr.site, n = tr.partner;
+      if (accept) {
+        const uint8_t si = occ[i], sn = occ[n];
+        occ[i] = sn;
+        occ[n] = si;
+        atomicAdd(&a.e_fixed[a.r], (unsigned long long)to_fixed(dE));
+        atomicAdd((unsigned long long *)&a.counters[2 * Rn + a.r], 1ull);
+      }
+      atomicAdd((unsigned long long *)&a.counters[3 * Rn + a.r], 1ull);
+      if (a.trace_flags) a.trace_flags[R.site0 + i] = kFlagFp64 | (accept ? kFlagAccept : 0);
+      if (a.trace_dE) a.trace_dE[R.site0 + i] = dE;
+    }
+    if (accept && lane < kOmMlp) {
+      // the cache keeps the sweep precision's post-swap energies
+      const Pos pi = trial_pos(tr);
+      const int8_t *o = a.om + tr.dir * kOmMax * 3;
+      a.ecache[R.site0 + at(pi, o[3 * lane], o[3 * lane + 1], o[3 * lane + 2], R.L[0], R.L[1], R.L[2])] =
+          a.e1[(int64_t)qe.slot * kOmMlp + lane];
+    }
   }
 }
 

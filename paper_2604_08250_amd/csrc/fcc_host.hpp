@@ -278,6 +278,12 @@ inline int load_params(smc_ctx *c, const float *params_dev) {
 }
 
 // Blocks of the matrix-core kernels: LDS holds one weight image per block.
+// k_recheck_net_decide: one wave per queued trial (at most n of them), four waves per block, at
+// most one block per CU (the waves loop over the queue)
+inline unsigned net_decide_grid(const smc_ctx *c, int64_t n) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 3) / 4, c->n_cu));
+}
+
 inline int net_blocks(const smc_ctx *c, int P) { return (P == SMC_FP8_E4M3 ? 4 : (P == SMC_BF16 ? 3 : 1)) * c->n_cu; }
 
 template <int P>
@@ -435,7 +441,9 @@ inline int enqueue_sweep(smc_ctx *c, const smc_stats *st, bool trace) {
       if (f.model == 0) {
         const unsigned rg = (unsigned)std::min<int64_t>(c->n_cu, nt * kRcSplit);  // LDS: one block per CU
         hipLaunchKernelGGL(k_recheck_net, dim3(rg), dim3(kR64Threads), 0, c->stream, a, (const float *)c->d_w32,
-                           f.d_rowe, f.d_done);
+                           f.d_rowe);
+        hipLaunchKernelGGL(k_recheck_net_decide, dim3(net_decide_grid(c, nt)), dim3(256), 0, c->stream, a,
+                           (const double *)f.d_rowe);
       } else {
         const unsigned rg = (unsigned)std::min<int64_t>(2 * (int64_t)c->n_cu, nt);
         hipLaunchKernelGGL(k_recheck_qsro, dim3(rg), dim3(kRcQsroThreads), 0, c->stream, a,
@@ -472,20 +480,18 @@ inline int delta_e64(smc_ctx *c, int32_t replica, uint64_t sweep, const int64_t 
   Trial *d_tr = nullptr;
   int32_t *d_act = nullptr;
   QEntry *d_q = nullptr;
-  uint32_t *d_n = nullptr, *d_done = nullptr;
+  uint32_t *d_n = nullptr;
   double *d_out = nullptr, *d_rowe = nullptr;
   const uint32_t nn = (uint32_t)n;
   int rc = SMC_OK;
   if (hipMalloc(&d_tr, sizeof(Trial) * n) || hipMalloc(&d_act, sizeof(int32_t) * n) ||
       hipMalloc(&d_q, sizeof(QEntry) * n) || hipMalloc(&d_n, sizeof(uint32_t)) ||
-      hipMalloc(&d_out, sizeof(double) * n) || hipMalloc(&d_rowe, sizeof(double) * 2 * kOmMlp * n) ||
-      hipMalloc(&d_done, sizeof(uint32_t) * n))
+      hipMalloc(&d_out, sizeof(double) * n) || hipMalloc(&d_rowe, sizeof(double) * 2 * kOmMlp * n))
     rc = fail(c, SMC_E_NOMEM, "probe buffers");
   if (!rc && (hipMemcpyAsync(d_tr, tr.data(), sizeof(Trial) * n, hipMemcpyHostToDevice, c->stream) ||
               hipMemcpyAsync(d_act, act.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream) ||
               hipMemcpyAsync(d_q, qe.data(), sizeof(QEntry) * n, hipMemcpyHostToDevice, c->stream) ||
-              hipMemcpyAsync(d_n, &nn, sizeof(uint32_t), hipMemcpyHostToDevice, c->stream) ||
-              hipMemsetAsync(d_done, 0, sizeof(uint32_t) * n, c->stream)))
+              hipMemcpyAsync(d_n, &nn, sizeof(uint32_t), hipMemcpyHostToDevice, c->stream)))
     rc = fail(c, SMC_E_DEVICE, "probe upload");
   if (!rc) {
     Args a{};
@@ -504,10 +510,12 @@ inline int delta_e64(smc_ctx *c, int32_t replica, uint64_t sweep, const int64_t 
     a.counters = c->d_counters;
     a.n_replicas = (int32_t)c->reps.size();
     a.probe_dE = d_out;
-    if (f.model == 0)
+    if (f.model == 0) {
       hipLaunchKernelGGL(k_recheck_net, dim3((unsigned)std::min<int64_t>((int64_t)n * kRcSplit, c->n_cu)),
-                         dim3(kR64Threads), 0, c->stream, a, (const float *)c->d_w32, d_rowe, d_done);
-    else
+                         dim3(kR64Threads), 0, c->stream, a, (const float *)c->d_w32, d_rowe);
+      hipLaunchKernelGGL(k_recheck_net_decide, dim3(net_decide_grid(c, n)), dim3(256), 0, c->stream, a,
+                         (const double *)d_rowe);
+    } else
       hipLaunchKernelGGL(k_recheck_qsro, dim3((unsigned)std::min<int64_t>(n, 2 * (int64_t)c->n_cu)),
                          dim3(kRcQsroThreads), 0, c->stream, a, (const double *)c->d_w64);
     if (hipGetLastError() != hipSuccess ||
@@ -515,7 +523,7 @@ inline int delta_e64(smc_ctx *c, int32_t replica, uint64_t sweep, const int64_t 
         hipStreamSynchronize(c->stream))
       rc = fail(c, SMC_E_DEVICE, "probe kernel");
   }
-  void *bufs[] = {d_tr, d_act, d_q, d_n, d_out, d_rowe, d_done};
+  void *bufs[] = {d_tr, d_act, d_q, d_n, d_out, d_rowe};
   for (void *p : bufs)
     if (p) (void)hipFree(p);
   return rc;
@@ -524,7 +532,7 @@ inline int delta_e64(smc_ctx *c, int32_t replica, uint64_t sweep, const int64_t 
 inline void release(smc_ctx *c) {
   FccState &f = c->fcc;
   void *bufs[] = {f.d_om,     f.d_trials, f.d_active,  f.d_e1,      f.d_queue,  f.d_counts,
-                  f.d_rowe,   f.d_done,   f.d_pack[0], f.d_pack[1], f.d_pack[2], f.d_pack[3],
+                  f.d_rowe,   f.d_pack[0], f.d_pack[1], f.d_pack[2], f.d_pack[3],
                   f.d_rq_off, f.d_rq_idx, f.d_rq_pos};
   for (void *p : bufs)
     if (p) (void)hipFree(p);
@@ -605,9 +613,7 @@ inline int create(const smc_config *cfg, uint8_t *occ_dev, const float *params_d
             hipMalloc(&f.d_e1, sizeof(float) * f.cap * f.om_n) == hipSuccess &&
             hipMalloc(&f.d_queue, sizeof(QEntry) * f.cap) == hipSuccess &&
             hipMalloc(&f.d_counts, sizeof(uint64_t) * c->colours_total) == hipSuccess &&
-            (model != 0 || (hipMalloc(&f.d_rowe, sizeof(double) * 2 * kOmMlp * f.cap) == hipSuccess &&
-                            hipMalloc(&f.d_done, sizeof(uint32_t) * f.cap) == hipSuccess &&
-                            hipMemset(f.d_done, 0, sizeof(uint32_t) * f.cap) == hipSuccess));
+            (model != 0 || hipMalloc(&f.d_rowe, sizeof(double) * 2 * kOmMlp * f.cap) == hipSuccess);
   if (!ok) return cleanup(SMC_E_NOMEM);
   const uint64_t zero = 0;
   if (hipMemcpyAsync(c->d_sweep, &zero, sizeof(uint64_t), hipMemcpyHostToDevice, c->stream) ||
