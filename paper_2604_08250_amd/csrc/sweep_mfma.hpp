@@ -3,24 +3,25 @@
 // One launch per colour index (mini-step) processes that colour of every replica whose
 // schedule has it (replicas of uneven size are independent and share the launch).  A
 // persistent block of 512 threads keeps the packed weights and the lookup tables in LDS and
-// walks groups of GROUP link cells as a pipeline:
-//   proposal (group g+2, by the first wave to run out of tiles of group g): Philox block per
+// walks its groups of GROUP link cells as a pipeline over trial buffers (buffer b: the next
+// kFill different-species trials of the block's groups in order, or one group's):
+//   proposal (buffer b+2, by the first wave to run out of tiles of buffer b): Philox block per
 //      trial, partner, species, threshold theta (FP64); same-species trials are finished here,
-//      the others compacted;
-//   gather (group g+1, issued before the energies of group g and consumed after them): the
+//      the others compacted into the buffer;
+//   gather (buffer b+1, issued before the energies of buffer b and consumed after them): the
 //      192 sites read by each trial (its affected zone Omega and their neighbours) and the
 //      cached energies of the 40 zone sites, into registers, then into LDS with the two
 //      swapped species exchanged;
-//   energy (group g): the post-swap local energies of every zone site, 32 sites per
+//   energy (buffer b): the post-swap local energies of every zone site, 32 sites per
 //      matrix-core tile (mfma_eval.hpp), tiles claimed dynamically by the eight waves; for the
 //      qSRO model (Eq. 2, P = kPQsro) 64 sites per wave tile, one per lane, each counting its
 //      neighbours' species from the staged region (the per-lane evaluator's arithmetic);
-//   decide (group g): dE = sum over the zone of (new - cached) in a fixed order; trials with
+//   decide (buffer b): dE = sum over the zone of (new - cached) in a fixed order; trials with
 //      |dE - theta| inside the guard band go to a queue re-decided in FP64, the others are
 //      accepted iff dE <= theta;
-//   apply (group g): accepted swaps write the two species and the new zone energies.
+//   apply (buffer b): accepted swaps write the two species and the new zone energies.
 // Trials of one colour never read what another trial of the colour writes (link cells of
-// at least four cells), so reads may run ahead of writes across groups.
+// at least four cells), so reads may run ahead of writes across buffers.
 #pragma once
 #include "mfma_eval.hpp"
 #include "sweep_scalar.hpp"
@@ -41,6 +42,32 @@ constexpr int smem_weight_bytes() {
   if constexpr (P == kPQsro) return (kQsroPacked * 4 + 15) / 16 * 16;
   else return pack_bytes<P>();
 }
+
+// Different-species trials per trial buffer of the colour kernel (MLP): the count n <= GROUP
+// that gives the most trials per energy-phase step, a step being one 32-row tile on each of the
+// block's kMfmaThreads / 64 waves (40 rows per trial).  The wave that runs out of tiles first
+// makes the next proposals: where tiles are short (BF16, FP8) one tile slot is kept for it
+// (GROUP 32: 31 trials, 39 tiles, 5 steps), where they are long (split BF16, FP32) the buffer is
+// full (32 trials, 40 tiles, 5 steps).  Measured on 256^3 against one buffer per group of 32
+// proposals (about 25.6 trials): split BF16 +1.5 % at 32 (+1.1 % at 31), FP8 +4.0 % at 31 (+0.6 %
+// at 32), and both lose 2 % at 24.
+template <int P, int GROUP>
+constexpr int fill_target() {
+  const int tile_rows = 32, waves = kMfmaThreads / 64, slot = (P == kPBF16 || P == kPFP8) ? 1 : 0;
+  int best = 1, best_steps = 1;
+  for (int n = 1; n <= GROUP; ++n) {
+    const int tiles = (n * kOm + tile_rows - 1) / tile_rows;
+    const int steps = (tiles + slot + waves - 1) / waves;
+    if (n * best_steps >= best * steps) {
+      best = n;
+      best_steps = steps;
+    }
+  }
+  return best;
+}
+static_assert(fill_target<kPBF16X3, 32>() == 32 && fill_target<kPFP8, 32>() == 31 &&
+                  fill_target<kPBF16, 16>() == 12 && fill_target<kPBF16X3, 16>() == 12,
+              "trial buffer fill");
 
 struct RecheckEntry {
   int64_t site;      // replica-local trial site
@@ -112,6 +139,13 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
   __shared__ float s_ec[GROUP * kOm];
   __shared__ float s_psum[GROUP * kPart];
   __shared__ TrialBuf<GROUP> s_tb[3];
+  // qSRO and FP32: one buffer per group of GROUP proposals (qSRO: its short evaluation leaves
+  // the per-buffer phases as the larger cost; packed buffers of 32 and 25 trials measured 0.5 %
+  // and 6 % slower; FP32: 1.8 % slower with packed buffers of 32)
+  constexpr bool kPack = P != kPQsro && P != kP32;
+  constexpr int kFill = kPack ? fill_target<P, GROUP>() : GROUP;
+  __shared__ TrialBuf<GROUP> s_carry;  // proposed trials that did not fit the last buffer
+  __shared__ int s_pgrp;               // the block's next group to propose
   __shared__ uint8_t s_acc[GROUP];
   __shared__ int s_tile, s_prop;
 
@@ -179,55 +213,108 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
     lgrp = grp - a.seg_start[lo];
   };
 
-  // proposal for one group into a trial buffer (wave 0)
-  auto propose = [&](int grp, TrialBuf<GROUP> &tb) {
-    int rep = 0, lgrp = 0;
-    const bool live = grp < gend;
-    if (live) locate(grp, rep, lgrp);
-    const Replica &R = a.reps[rep];
-    const uint8_t *occ = a.occ + R.site0;
-    const int64_t t = (int64_t)lgrp * GROUP + lane;
-    const int64_t i = (live && lane < GROUP && t < R.n_trials) ? trial_site(R, a.colour, t) : -1;
-    bool active = false;
-    int d = 0;
-    double theta = 0.0;
-    Pos pi{0, 0, 0};
-    int64_t n = 0;
-    uint8_t si = 0, sn = 0;
-    if (i >= 0) {
-      const U64x4 r = philox4x64_10((uint64_t)i, sweep, (uint64_t)rep, 0, a.seed, 0);
-      d = (int)(r.v[0] >> 61);
-      const double u = (double)((r.v[1] >> 11) + 1) * 0x1.0p-53;
-      theta = isinf(R.temperature) ? (double)INFINITY : -kBoltzmannEvPerK * R.temperature * log(u);
-      pi = site_pos32((int32_t)i, R.L[0], R.L[1]);
-      n = site_at32(pi, shell_dx(d), shell_dy(d), shell_dz(d), R.L[0], R.L[1], R.L[2]);
-      si = occ[i];
-      sn = occ[n];
-      active = si != sn;
-      if (!active) {
-        if (a.trace_flags) a.trace_flags[R.site0 + i] = kFlagSame;
-        if (a.trace_dE) a.trace_dE[R.site0 + i] = 0.0;
-        if (a.trace_dE_fast) a.trace_dE_fast[R.site0 + i] = 0.0;
+  // Proposals (one wave).  The block walks its groups in order and packs their different-species
+  // trials into trial buffers of kFill trials (fewer at a change of replica and at the end), so
+  // that the energy phases have the same number of tiles instead of one that varies with each
+  // group's count; trials past kFill wait in s_carry and open the next buffer.  Without kPack a
+  // buffer takes one group's trials.  The trials of a
+  // colour are independent, so the buffer a trial lands in changes nothing in its result.
+  // Stream position p of a buffer (carried trials first) goes to tb[p] below kFill, else to
+  // s_carry[p - kFill]; a wave's LDS loads precede its stores, so moving the carried trials
+  // within s_carry is safe.  Lane 0 writes s_carry's count and replica and s_pgrp at the end;
+  // a barrier separates two calls, so that no lane reads them before that write.
+  auto place = [&](TrialBuf<GROUP> &tb, int p, int32_t i, int32_t n, int x, int y, int z, double theta, uint8_t d,
+                   uint8_t si, uint8_t sn) {
+    TrialBuf<GROUP> &dst = p < kFill ? tb : s_carry;
+    const int q = p < kFill ? p : p - kFill;
+    dst.site[q] = i;
+    dst.part[q] = n;
+    dst.px[q] = x;
+    dst.py[q] = y;
+    dst.pz[q] = z;
+    dst.theta[q] = theta;
+    dst.dir[q] = d;
+    dst.si[q] = si;
+    dst.sn[q] = sn;
+  };
+  // g0: the group of this buffer without kPack
+  auto fill = [&](TrialBuf<GROUP> &tb, int g0) {
+    int cnt = 0, rep = 0, natt = 0, g = g0;
+    if constexpr (kPack) {
+      cnt = s_carry.nact;
+      rep = s_carry.rep;
+      g = s_pgrp;
+      if (lane < cnt) {
+        const int32_t ci = s_carry.site[lane], cn = s_carry.part[lane];
+        const int x = s_carry.px[lane], y = s_carry.py[lane], z = s_carry.pz[lane];
+        const double th = s_carry.theta[lane];
+        const uint8_t d = s_carry.dir[lane], si = s_carry.si[lane], sn = s_carry.sn[lane];
+        place(tb, lane, ci, cn, x, y, z, th, d, si, sn);
       }
     }
-    const unsigned long long valid = __ballot(i >= 0);
-    const unsigned long long act_mask = __ballot(active);
-    const int ca = __popcll(act_mask & ((1ull << lane) - 1ull));
-    if (active) {
-      tb.site[ca] = (int32_t)i;
-      tb.part[ca] = (int32_t)n;
-      tb.px[ca] = pi.x;
-      tb.py[ca] = pi.y;
-      tb.pz[ca] = pi.z;
-      tb.theta[ca] = theta;
-      tb.dir[ca] = (uint8_t)d;
-      tb.si[ca] = si;
-      tb.sn[ca] = sn;
+    while (cnt < kFill && g < gend) {
+      int grep = 0, lgrp = 0;
+      locate(g, grep, lgrp);
+      if ((cnt > 0 || natt > 0) && grep != rep) break;  // a buffer holds one replica
+      rep = grep;
+      const Replica &R = a.reps[rep];
+      const uint8_t *occ = a.occ + R.site0;
+      const int64_t t = (int64_t)lgrp * GROUP + lane;
+      const int64_t i = (lane < GROUP && t < R.n_trials) ? trial_site(R, a.colour, t) : -1;
+      bool active = false;
+      int d = 0;
+      double theta = 0.0;
+      Pos pi{0, 0, 0};
+      int64_t n = 0;
+      uint8_t si = 0, sn = 0;
+      if (i >= 0) {
+        const U64x4 r = philox4x64_10((uint64_t)i, sweep, (uint64_t)rep, 0, a.seed, 0);
+        d = (int)(r.v[0] >> 61);
+        const double u = (double)((r.v[1] >> 11) + 1) * 0x1.0p-53;
+        theta = isinf(R.temperature) ? (double)INFINITY : -kBoltzmannEvPerK * R.temperature * log(u);
+        pi = site_pos32((int32_t)i, R.L[0], R.L[1]);
+        n = site_at32(pi, shell_dx(d), shell_dy(d), shell_dz(d), R.L[0], R.L[1], R.L[2]);
+        si = occ[i];
+        sn = occ[n];
+        active = si != sn;
+        if (!active) {
+          if (a.trace_flags) a.trace_flags[R.site0 + i] = kFlagSame;
+          if (a.trace_dE) a.trace_dE[R.site0 + i] = 0.0;
+          if (a.trace_dE_fast) a.trace_dE_fast[R.site0 + i] = 0.0;
+        }
+      }
+      const unsigned long long valid = __ballot(i >= 0);
+      const unsigned long long act_mask = __ballot(active);
+      if (active) {
+        const int p = cnt + __popcll(act_mask & ((1ull << lane) - 1ull));
+        if constexpr (kPack) place(tb, p, (int32_t)i, (int32_t)n, pi.x, pi.y, pi.z, theta, (uint8_t)d, si, sn);
+        else {
+          tb.site[p] = (int32_t)i;
+          tb.part[p] = (int32_t)n;
+          tb.px[p] = pi.x;
+          tb.py[p] = pi.y;
+          tb.pz[p] = pi.z;
+          tb.theta[p] = theta;
+          tb.dir[p] = (uint8_t)d;
+          tb.si[p] = si;
+          tb.sn[p] = sn;
+        }
+      }
+      cnt += __popcll(act_mask);
+      natt += __popcll(valid);
+      g += gstep;
+      if (!kPack) break;  // one group (every group holds at least one trial)
     }
+    // every lane has read s_carry's count and replica above; lane 0 alone writes them
     if (lane == 0) {
-      tb.nact = __popcll(act_mask);
-      tb.nvalid = __popcll(valid);
+      tb.nact = cnt < kFill ? cnt : kFill;
+      tb.nvalid = natt;
       tb.rep = rep;
+      if constexpr (kPack) {
+        s_carry.nact = cnt > kFill ? cnt - kFill : 0;
+        s_carry.rep = rep;
+        s_pgrp = g;
+      }
     }
   };
 
@@ -289,17 +376,24 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
     }
   };
 
-  // prologue: proposals of the first two groups, gather of the first
-  __syncthreads();
-  if (wave == 0) {
-    propose(gstart, s_tb[0]);
-    propose(gstart + gstep, s_tb[1]);
+  // prologue: the first two trial buffers, gather of the first
+  if (tid == 0) {
+    s_carry.nact = 0;
+    s_carry.rep = 0;
+    s_pgrp = gstart;
   }
+  __syncthreads();
+  if (wave == 0) fill(s_tb[0], gstart);
+  __syncthreads();
+  if (wave == 0) fill(s_tb[1], gstart + gstep);
   __syncthreads();
   gather_issue(s_tb[0]);
 
   int it = 0;
-  for (int grp = gstart; grp < gend; grp += gstep, ++it) {
+  for (int grp = gstart;; grp += gstep, ++it) {
+    if constexpr (!kPack) {
+      if (grp >= gend) break;
+    }
     TrialBuf<GROUP> &cur = s_tb[it % 3];
     TrialBuf<GROUP> &nxt = s_tb[(it + 1) % 3];
     TrialBuf<GROUP> &nxt2 = s_tb[(it + 2) % 3];
@@ -308,11 +402,17 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
     if (tid == 0) s_tile = s_prop = 0;
     __syncthreads();
     const int nact = cur.nact;
+    // packed: a buffer with neither trials nor attempts (nothing gathered above) means that the
+    // block's groups are all done (filled two steps ago, barriers since; the same value in every
+    // thread)
+    if constexpr (kPack) {
+      if (nact == 0 && cur.nvalid == 0) break;
+    }
     const Replica &R = a.reps[cur.rep];
     uint8_t *occ = a.occ + R.site0;
     float *ec = a.ecache + R.site0;
     // ------------------------------------------------------------ gather (g+1) in flight
-    if (grp + gstep < gend) gather_issue(nxt);
+    if (kPack || grp + gstep < gend) gather_issue(nxt);  // nothing for an empty buffer
     // ------------------------------------------------------------ energies (g)
     const int rows = nact * kOm;
     constexpr int kTileRows = P == kPQsro ? 64 : 32;
@@ -344,7 +444,7 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
     {
       int first = 0;
       if (lane == 0) first = atomicAdd(&s_prop, 1) == 0;
-      if (__shfl(first, 0)) propose(grp + 2 * gstep, nxt2);
+      if (__shfl(first, 0)) fill(nxt2, grp + 2 * gstep);
     }
     __syncthreads();
     // ------------------------------------------------------------ decide (g)
@@ -395,19 +495,30 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
         }
         s_acc[lane] = accept;
       }
-      // fixed-order sum of the accepted dE of this group
+      // the accepted dE in fixed point: packed, converted per trial (an integer sum, the same
+      // whichever buffer holds a trial); else the group's fixed-order sum, converted once
       const unsigned long long acc_mask = __ballot(accept);
-      double v = accept ? dEd : 0.0;
-      for (int off = 1; off < 32; off <<= 1) {
-        const double o = __shfl_down(v, off);
-        v += (lane + off < 32) ? o : 0.0;
+      long long fx = 0;
+      if constexpr (kPack) {
+        fx = accept ? to_fixed(dEd) : 0;
+        for (int off = 1; off < 32; off <<= 1) {
+          const long long o = __shfl_down(fx, off);
+          fx += (lane + off < 32) ? o : 0;
+        }
+      } else {
+        double v = accept ? dEd : 0.0;
+        for (int off = 1; off < 32; off <<= 1) {
+          const double o = __shfl_down(v, off);
+          v += (lane + off < 32) ? o : 0.0;
+        }
+        if (lane == 0) fx = to_fixed(v);
       }
       if (lane == 0) {
         if (cur.rep != stat_rep) {
           flush();
           stat_rep = cur.rep;
         }
-        fixed_sum += to_fixed(v);
+        fixed_sum += fx;
         cnt_att += cur.nvalid;
         cnt_diff += nact;
         cnt_acc += __popcll(acc_mask);
