@@ -43,19 +43,20 @@ constexpr int smem_weight_bytes() {
   else return pack_bytes<P>();
 }
 
-// Different-species trials per trial buffer of the colour kernel (MLP): the count n <= GROUP
-// that gives the most trials per energy-phase step, a step being one 32-row tile on each of the
-// block's kMfmaThreads / 64 waves (40 rows per trial).  The wave that runs out of tiles first
-// makes the next proposals: where tiles are short (BF16, FP8) one tile slot is kept for it
-// (GROUP 32: 31 trials, 39 tiles, 5 steps), where they are long (split BF16, FP32) the buffer is
-// full (32 trials, 40 tiles, 5 steps).  Measured on 256^3 against one buffer per group of 32
-// proposals (about 25.6 trials): split BF16 +1.5 % at 32 (+1.1 % at 31), FP8 +4.0 % at 31 (+0.6 %
-// at 32), and both lose 2 % at 24.
-template <int P, int GROUP>
+// Different-species trials per trial buffer of the colour kernel (MLP): the count n <= CAP (the
+// buffer capacity) that gives the most trials per energy-phase step, a step being one 32-row
+// tile on each of the block's kMfmaThreads / 64 waves (40 rows per trial).  The wave that runs
+// out of tiles first makes the next proposals: where tiles are short (BF16, FP8) one tile slot
+// is kept for it (capacity 64: 63 trials, 79 tiles, 10 steps; capacity 32: 31, 39, 5), where
+// they are long (split BF16, FP32) the buffer is full (32 trials, 40 tiles, 5 steps).  Measured
+// on 256^3 against one buffer per group of 32 proposals (about 25.6 trials): split BF16 +1.5 % at
+// 32 (+1.1 % at 31), FP8 +4.0 % at 31 (+0.6 % at 32), both -2 % at 24; capacity 64 then gave
+// BF16 +5.8 % and FP8 +1.9 % over 31.
+template <int P, int CAP>
 constexpr int fill_target() {
   const int tile_rows = 32, waves = kMfmaThreads / 64, slot = (P == kPBF16 || P == kPFP8) ? 1 : 0;
   int best = 1, best_steps = 1;
-  for (int n = 1; n <= GROUP; ++n) {
+  for (int n = 1; n <= CAP; ++n) {
     const int tiles = (n * kOm + tile_rows - 1) / tile_rows;
     const int steps = (tiles + slot + waves - 1) / waves;
     if (n * best_steps >= best * steps) {
@@ -65,7 +66,7 @@ constexpr int fill_target() {
   }
   return best;
 }
-static_assert(fill_target<kPBF16X3, 32>() == 32 && fill_target<kPFP8, 32>() == 31 &&
+static_assert(fill_target<kPBF16X3, 32>() == 32 && fill_target<kPFP8, 64>() == 63 &&
                   fill_target<kPBF16, 16>() == 12 && fill_target<kPBF16X3, 16>() == 12,
               "trial buffer fill");
 
@@ -134,19 +135,22 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
   __shared__ uint16_t s_roff[8 * kReg];
   __shared__ uint16_t s_ooff[8 * kOm];
   __shared__ uint8_t s_rpos[16];
-  __shared__ uint8_t s_reg[GROUP * kReg];
-  __shared__ float s_e[GROUP * kOm];
-  __shared__ float s_ec[GROUP * kOm];
-  __shared__ float s_psum[GROUP * kPart];
-  __shared__ TrialBuf<GROUP> s_tb[3];
   // qSRO and FP32: one buffer per group of GROUP proposals (qSRO: its short evaluation leaves
   // the per-buffer phases as the larger cost; packed buffers of 32 and 25 trials measured 0.5 %
   // and 6 % slower; FP32: 1.8 % slower with packed buffers of 32)
   constexpr bool kPack = P != kPQsro && P != kP32;
-  constexpr int kFill = kPack ? fill_target<P, GROUP>() : GROUP;
-  __shared__ TrialBuf<GROUP> s_carry;  // proposed trials that did not fit the last buffer
-  __shared__ int s_pgrp;               // the block's next group to propose
-  __shared__ uint8_t s_acc[GROUP];
+  // buffer capacity: BF16 and FP8 (short tiles, small weights) take 64 trials per buffer, so
+  // that the per-buffer phases count once per 63 trials; split BF16 has no LDS left for it
+  constexpr int kCap = (P == kPBF16 || P == kPFP8) && GROUP == 32 ? 64 : GROUP;
+  constexpr int kFill = kPack ? fill_target<P, kCap>() : GROUP;
+  __shared__ uint8_t s_reg[kCap * kReg];
+  __shared__ float s_e[kCap * kOm];
+  __shared__ float s_ec[kCap * kOm];
+  __shared__ float s_psum[kCap * kPart];
+  __shared__ TrialBuf<kCap> s_tb[3];
+  __shared__ TrialBuf<kCap> s_carry;  // proposed trials that did not fit the last buffer
+  __shared__ int s_pgrp;              // the block's next group to propose
+  __shared__ uint8_t s_acc[kCap];
   __shared__ int s_tile, s_prop;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -223,9 +227,9 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
   // s_carry[p - kFill]; a wave's LDS loads precede its stores, so moving the carried trials
   // within s_carry is safe.  Lane 0 writes s_carry's count and replica and s_pgrp at the end;
   // a barrier separates two calls, so that no lane reads them before that write.
-  auto place = [&](TrialBuf<GROUP> &tb, int p, int32_t i, int32_t n, int x, int y, int z, double theta, uint8_t d,
+  auto place = [&](TrialBuf<kCap> &tb, int p, int32_t i, int32_t n, int x, int y, int z, double theta, uint8_t d,
                    uint8_t si, uint8_t sn) {
-    TrialBuf<GROUP> &dst = p < kFill ? tb : s_carry;
+    TrialBuf<kCap> &dst = p < kFill ? tb : s_carry;
     const int q = p < kFill ? p : p - kFill;
     dst.site[q] = i;
     dst.part[q] = n;
@@ -238,7 +242,7 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
     dst.sn[q] = sn;
   };
   // g0: the group of this buffer without kPack
-  auto fill = [&](TrialBuf<GROUP> &tb, int g0) {
+  auto fill = [&](TrialBuf<kCap> &tb, int g0) {
     int cnt = 0, rep = 0, natt = 0, g = g0;
     if constexpr (kPack) {
       cnt = s_carry.nact;
@@ -323,8 +327,8 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
   // packed four bytes to a register, and the cached energies of zone sites tid % 16 + 16m
   // (m < 3, below 40) of trial tid / 16, so the trial's position and partner slot are read
   // once per thread.
-  static_assert(kMfmaThreads == 16 * GROUP || GROUP == 16, "sixteen threads per trial");
-  constexpr int kTpt = kMfmaThreads / GROUP;  // threads per trial: 16 (GROUP 32) or 32 (GROUP 16)
+  static_assert(kMfmaThreads % kCap == 0 && kReg % (kMfmaThreads / kCap) == 0, "threads per trial");
+  constexpr int kTpt = kMfmaThreads / kCap;  // threads per trial: 8, 16 or 32 (kCap 64, 32, 16)
   constexpr int kPfReg = kReg / kTpt;         // region bytes per thread: 12 or 6
   constexpr int kPfOm = (kOm + kTpt - 1) / kTpt;  // cached energies per thread: 3 or 2
   // the loaded bytes stay unpacked until gather_store, so that issuing the loads never waits
@@ -332,7 +336,7 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
   uint32_t pf_reg[kPfReg];
   float pf_om[kPfOm];
   const int g_t = tid / kTpt, g_l = tid % kTpt;
-  auto gather_issue = [&](const TrialBuf<GROUP> &tb) {
+  auto gather_issue = [&](const TrialBuf<kCap> &tb) {
     const Replica &R = a.reps[tb.rep];
     const uint8_t *occ = a.occ + R.site0;
     const float *ec = a.ecache + R.site0;
@@ -356,7 +360,7 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
       }
     }
   };
-  auto gather_store = [&](const TrialBuf<GROUP> &tb) {
+  auto gather_store = [&](const TrialBuf<kCap> &tb) {
     if (g_t < tb.nact) {
       const int d = tb.dir[g_t];
       const int pi = s_rpos[2 * d], pn = s_rpos[2 * d + 1];
@@ -394,9 +398,9 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
     if constexpr (!kPack) {
       if (grp >= gend) break;
     }
-    TrialBuf<GROUP> &cur = s_tb[it % 3];
-    TrialBuf<GROUP> &nxt = s_tb[(it + 1) % 3];
-    TrialBuf<GROUP> &nxt2 = s_tb[(it + 2) % 3];
+    TrialBuf<kCap> &cur = s_tb[it % 3];
+    TrialBuf<kCap> &nxt = s_tb[(it + 1) % 3];
+    TrialBuf<kCap> &nxt2 = s_tb[(it + 2) % 3];
     // ------------------------------------------------------------ gather (g) into LDS
     gather_store(cur);
     if (tid == 0) s_tile = s_prop = 0;
@@ -499,17 +503,18 @@ __global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) 
       // whichever buffer holds a trial); else the group's fixed-order sum, converted once
       const unsigned long long acc_mask = __ballot(accept);
       long long fx = 0;
+      constexpr int kRed = kCap > 32 ? 64 : 32;  // lanes holding a buffer's trials
       if constexpr (kPack) {
         fx = accept ? to_fixed(dEd) : 0;
-        for (int off = 1; off < 32; off <<= 1) {
+        for (int off = 1; off < kRed; off <<= 1) {
           const long long o = __shfl_down(fx, off);
-          fx += (lane + off < 32) ? o : 0;
+          fx += (lane + off < kRed) ? o : 0;
         }
       } else {
         double v = accept ? dEd : 0.0;
-        for (int off = 1; off < 32; off <<= 1) {
+        for (int off = 1; off < kRed; off <<= 1) {
           const double o = __shfl_down(v, off);
-          v += (lane + off < 32) ? o : 0.0;
+          v += (lane + off < kRed) ? o : 0.0;
         }
         if (lane == 0) fx = to_fixed(v);
       }
