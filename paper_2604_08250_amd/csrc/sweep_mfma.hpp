@@ -128,21 +128,24 @@ struct TrialBuf {
 };
 
 template <int P, int GROUP>
-__global__ __launch_bounds__(kMfmaThreads) void k_sweep_colour_mfma(MfmaArgs a) {
+// qSRO: four waves per SIMD (two blocks per CU), which holds it to 128 VGPRs
+__global__ __launch_bounds__(kMfmaThreads, P == kPQsro ? 4 : 2) void k_sweep_colour_mfma(MfmaArgs a) {
   constexpr int kW = smem_weight_bytes<P>();
   __shared__ __attribute__((aligned(16))) uint8_t s_w[kW];
   __shared__ __attribute__((aligned(16))) uint8_t s_idx[8 * kOm * kIdxRow];
   __shared__ uint16_t s_roff[8 * kReg];
   __shared__ uint16_t s_ooff[8 * kOm];
   __shared__ uint8_t s_rpos[16];
-  // qSRO and FP32: one buffer per group of GROUP proposals (qSRO: its short evaluation leaves
-  // the per-buffer phases as the larger cost; packed buffers of 32 and 25 trials measured 0.5 %
-  // and 6 % slower; FP32: 1.8 % slower with packed buffers of 32)
-  constexpr bool kPack = P != kPQsro && P != kP32;
-  // buffer capacity: BF16 and FP8 (short tiles, small weights) take 64 trials per buffer, so
-  // that the per-buffer phases count once per 63 trials; split BF16 has no LDS left for it
-  constexpr int kCap = (P == kPBF16 || P == kPFP8) && GROUP == 32 ? 64 : GROUP;
-  constexpr int kFill = kPack ? fill_target<P, kCap>() : GROUP;
+  // FP32: one buffer per group of GROUP proposals (1.8 % slower with packed buffers of 32)
+  constexpr bool kPack = P != kP32;
+  // buffer capacity: BF16, FP8 (short tiles, small weights) and qSRO (no weights) take 64
+  // trials per buffer, so that the per-buffer phases count once per 63 or 64 trials; split BF16
+  // has no LDS left for it
+  constexpr int kCap = (P == kPBF16 || P == kPFP8 || P == kPQsro) && GROUP == 32 ? 64 : GROUP;
+  // qSRO fills its buffers: its short evaluation leaves the per-buffer phases as the larger cost
+  // (64 trials, 40 tiles of 64 rows; buffers of 32 and 25 trials measured 0.5 % and 6 % slower
+  // than one buffer per group, 64 trials 6 % faster)
+  constexpr int kFill = P == kPQsro ? kCap : (kPack ? fill_target<P, kCap>() : GROUP);
   __shared__ uint8_t s_reg[kCap * kReg];
   __shared__ float s_e[kCap * kOm];
   __shared__ float s_ec[kCap * kOm];
