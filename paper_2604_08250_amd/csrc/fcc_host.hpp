@@ -278,6 +278,17 @@ inline int load_params(smc_ctx *c, const float *params_dev) {
 }
 
 // Blocks of the matrix-core kernels: LDS holds one weight image per block.
+// Trials of colour col of a replica that have a site: the link cells long enough to hold the
+// colour's offset along every axis (fcc::trial_site gives -1 for the others).
+inline uint64_t colour_attempts(const Replica &R, int32_t col) {
+  int32_t rest = col >> 2;
+  const int32_t ox = rest % R.ax[0].big;
+  rest /= R.ax[0].big;
+  const int32_t oy = rest % R.ax[1].big, oz = rest / R.ax[1].big;
+  return (uint64_t)axis_cells_holding(R.ax[0], ox) * (uint64_t)axis_cells_holding(R.ax[1], oy) *
+         (uint64_t)axis_cells_holding(R.ax[2], oz);
+}
+
 // k_recheck_net_decide: one wave per queued trial (at most n of them), four waves per block, at
 // most one block per CU (the waves loop over the queue)
 inline unsigned net_decide_grid(const smc_ctx *c, int64_t n) {
@@ -409,6 +420,7 @@ inline int enqueue_sweep(smc_ctx *c, const smc_stats *st, bool trace) {
       a.e_fixed = c->d_efixed;
       a.counters = c->d_counters;
       a.n_replicas = R;
+      a.attempts = colour_attempts(rep, col);
       if (trace) {
         a.trace_dE = st->trace_dE;
         a.trace_dE_fast = st->trace_dE_fast;
