@@ -30,6 +30,7 @@ struct FccState {
   float *d_e1 = nullptr;             // [cap][om_n]
   fcc::QEntry *d_queue = nullptr;    // [cap]
   double *d_rowe = nullptr;          // [cap][56] FP64 zone energies of queued MLPNet trials
+  uint64_t *d_dpart = nullptr;       // [2][k_decide blocks] per-block accepted dE and accepts
   uint32_t *d_counts = nullptr;      // [replica colours] active trials, queued trials (one 64-bit word each)
   uint16_t *d_rq_off = nullptr;      // qSRO: [12][304] read-region offsets per partner slot
   uint16_t *d_rq_idx = nullptr;      // qSRO: [12][60][43] region position of each zone row's slots

@@ -421,6 +421,7 @@ inline int enqueue_sweep(smc_ctx *c, const smc_stats *st, bool trace) {
       a.counters = c->d_counters;
       a.n_replicas = R;
       a.attempts = colour_attempts(rep, col);
+      a.dpart = f.model == 0 ? (unsigned long long *)f.d_dpart : nullptr;
       if (trace) {
         a.trace_dE = st->trace_dE;
         a.trace_dE_fast = st->trace_dE_fast;
@@ -448,6 +449,7 @@ inline int enqueue_sweep(smc_ctx *c, const smc_stats *st, bool trace) {
         hipLaunchKernelGGL(k_decide<kOmMlp>, dg, dim3(kPhaseThreads), 0, c->stream, a);
       else
         hipLaunchKernelGGL(k_decide<kOmQsro>, dg, dim3(kPhaseThreads), 0, c->stream, a);
+      if (a.dpart) hipLaunchKernelGGL(k_decide_totals, dim3(1), dim3(kPhaseThreads), 0, c->stream, a, (int32_t)dg.x);
       // blocks loop over the queue (usually short): a few per CU
       const int ev2 = prof_begin(c);
       if (f.model == 0) {
@@ -543,7 +545,7 @@ inline int delta_e64(smc_ctx *c, int32_t replica, uint64_t sweep, const int64_t 
 
 inline void release(smc_ctx *c) {
   FccState &f = c->fcc;
-  void *bufs[] = {f.d_om,     f.d_trials, f.d_active,  f.d_e1,      f.d_queue,  f.d_counts,
+  void *bufs[] = {f.d_om,     f.d_trials, f.d_active,  f.d_e1,      f.d_queue,  f.d_counts, f.d_dpart,
                   f.d_rowe,   f.d_pack[0], f.d_pack[1], f.d_pack[2], f.d_pack[3],
                   f.d_rq_off, f.d_rq_idx, f.d_rq_pos};
   for (void *p : bufs)
@@ -625,6 +627,8 @@ inline int create(const smc_config *cfg, uint8_t *occ_dev, const float *params_d
             hipMalloc(&f.d_e1, sizeof(float) * f.cap * f.om_n) == hipSuccess &&
             hipMalloc(&f.d_queue, sizeof(QEntry) * f.cap) == hipSuccess &&
             hipMalloc(&f.d_counts, sizeof(uint64_t) * c->colours_total) == hipSuccess &&
+            hipMalloc(&f.d_dpart, sizeof(uint64_t) * 2 * grid_for(f.cap * kDecideLanes, kPhaseThreads)) ==
+                hipSuccess &&
             (model != 0 || hipMalloc(&f.d_rowe, sizeof(double) * 2 * kOmMlp * f.cap) == hipSuccess);
   if (!ok) return cleanup(SMC_E_NOMEM);
   const uint64_t zero = 0;
