@@ -517,6 +517,7 @@ struct Args {
   uint64_t attempts;       // trials of this colour that have a site (counted on the host)
   unsigned long long *dpart;  // MLPNet: [2][k_decide blocks] per-block accepted dE (fixed point)
                               // and accepts; null: k_decide adds them with atomics
+  int32_t dpart_n;            // k_decide blocks
   double *trace_dE, *trace_dE_fast;
   uint8_t *trace_flags;
   double *probe_dE;        // non-null: the re-decision kernels write dE of queue entry q to
@@ -778,7 +779,7 @@ __global__ __launch_bounds__(kPhaseThreads) void k_decide(Args a) {
     }
   }
   // the block's accepted dE (2^-32 eV units) and accept count: with dpart, partials summed by
-  // k_decide_totals (MLPNet: per-block atomics on the same two addresses cost 3-7 % of a BF16
+  // decide_totals in k_recheck_net_decide (MLPNet: per-block atomics on the same two addresses cost 3-7 % of a BF16
   // or FP8 sweep), else one atomic each (qSRO, whose longer decide spreads them out: the extra
   // launch measured 1.4 % slower)
   const unsigned long long esum = block_sum_u64((unsigned long long)fixed, s_part);
@@ -795,14 +796,14 @@ __global__ __launch_bounds__(kPhaseThreads) void k_decide(Args a) {
   }
 }
 
-// Adds the n_blocks partials of k_decide to the replica's running total and accept counter
-// (one block; exact integer sums).
-__global__ __launch_bounds__(kPhaseThreads) void k_decide_totals(Args a, int32_t n_blocks) {
-  __shared__ unsigned long long s_part[kPhaseWaves];
+// Adds the a.dpart_n partials of k_decide to the replica's running total and accept counter
+// (exact integer sums).  Every thread of a kPhaseThreads block calls it.
+__device__ __forceinline__ void decide_totals(const Args &a, unsigned long long *s_part) {
+  const int nb = a.dpart_n;
   unsigned long long e = 0, n = 0;
-  for (int b = threadIdx.x; b < n_blocks; b += blockDim.x) {
+  for (int b = threadIdx.x; b < nb; b += kPhaseThreads) {
     e += a.dpart[b];
-    n += a.dpart[n_blocks + b];
+    n += a.dpart[nb + b];
   }
   e = block_sum_u64(e, s_part);
   __syncthreads();
@@ -1022,7 +1023,13 @@ __global__ __launch_bounds__(kR64Threads) void k_recheck_net(Args a, const float
 // one wave per trial: the 56 row energies loaded by 56 lanes and summed in row order (rows
 // 0..27 after the swap, 28..55 before), the Metropolis decision and the apply (or, for a probe,
 // dE only).
-__global__ __launch_bounds__(256) void k_recheck_net_decide(Args a, const double *row_e) {
+__global__ __launch_bounds__(kPhaseThreads) void k_recheck_net_decide(Args a, const double *row_e) {
+  // the last block, which usually has no queued trial, adds k_decide's partials (a sweep's
+  // launch; probes pass none)
+  if (a.dpart && blockIdx.x == gridDim.x - 1) {
+    __shared__ unsigned long long s_part[kPhaseWaves];
+    decide_totals(a, s_part);
+  }
   const Replica R = a.reps[a.r];
   uint8_t *occ = a.occ + R.site0;
   const uint32_t nq = *a.q_count;

@@ -445,19 +445,19 @@ inline int enqueue_sweep(smc_ctx *c, const smc_stats *st, bool trace) {
       }
       prof_end(c, ev, 0);
       const dim3 dg(grid_for(nt * kDecideLanes, kPhaseThreads));
+      a.dpart_n = (int32_t)dg.x;
       if (f.model == 0)
         hipLaunchKernelGGL(k_decide<kOmMlp>, dg, dim3(kPhaseThreads), 0, c->stream, a);
       else
         hipLaunchKernelGGL(k_decide<kOmQsro>, dg, dim3(kPhaseThreads), 0, c->stream, a);
-      if (a.dpart) hipLaunchKernelGGL(k_decide_totals, dim3(1), dim3(kPhaseThreads), 0, c->stream, a, (int32_t)dg.x);
       // blocks loop over the queue (usually short): a few per CU
       const int ev2 = prof_begin(c);
       if (f.model == 0) {
         const unsigned rg = (unsigned)std::min<int64_t>(c->n_cu, nt * kRcSplit);  // LDS: one block per CU
         hipLaunchKernelGGL(k_recheck_net, dim3(rg), dim3(kR64Threads), 0, c->stream, a, (const float *)c->d_w32,
                            f.d_rowe);
-        hipLaunchKernelGGL(k_recheck_net_decide, dim3(net_decide_grid(c, nt)), dim3(256), 0, c->stream, a,
-                           (const double *)f.d_rowe);
+        hipLaunchKernelGGL(k_recheck_net_decide, dim3(net_decide_grid(c, nt)), dim3(kPhaseThreads), 0, c->stream,
+                           a, (const double *)f.d_rowe);
       } else {
         const unsigned rg = (unsigned)std::min<int64_t>(2 * (int64_t)c->n_cu, nt);
         hipLaunchKernelGGL(k_recheck_qsro, dim3(rg), dim3(kRcQsroThreads), 0, c->stream, a,
@@ -527,7 +527,7 @@ inline int delta_e64(smc_ctx *c, int32_t replica, uint64_t sweep, const int64_t 
     if (f.model == 0) {
       hipLaunchKernelGGL(k_recheck_net, dim3((unsigned)std::min<int64_t>((int64_t)n * kRcSplit, c->n_cu)),
                          dim3(kR64Threads), 0, c->stream, a, (const float *)c->d_w32, d_rowe);
-      hipLaunchKernelGGL(k_recheck_net_decide, dim3(net_decide_grid(c, n)), dim3(256), 0, c->stream, a,
+      hipLaunchKernelGGL(k_recheck_net_decide, dim3(net_decide_grid(c, n)), dim3(kPhaseThreads), 0, c->stream, a,
                          (const double *)d_rowe);
     } else
       hipLaunchKernelGGL(k_recheck_qsro, dim3((unsigned)std::min<int64_t>(n, 2 * (int64_t)c->n_cu)),
