@@ -289,10 +289,10 @@ inline uint64_t colour_attempts(const Replica &R, int32_t col) {
          (uint64_t)axis_cells_holding(R.ax[2], oz);
 }
 
-// k_recheck_net_decide: one wave per queued trial (at most n of them), four waves per block, at
-// most one block per CU (the waves loop over the queue)
+// k_recheck_net_decide: one wave per queued trial (at most n of them), kPhaseWaves waves per
+// block, at most one block per CU (the waves loop over the queue)
 inline unsigned net_decide_grid(const smc_ctx *c, int64_t n) {
-  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 3) / 4, c->n_cu));
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + kPhaseWaves - 1) / kPhaseWaves, c->n_cu));
 }
 
 inline int net_blocks(const smc_ctx *c, int P) { return (P == SMC_FP8_E4M3 ? 4 : (P == SMC_BF16 ? 3 : 1)) * c->n_cu; }
